@@ -1,0 +1,141 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct reference implementations (``oracle.c``,
+plain C built with gcc) of what the GPU library computes.  Only the test
+suite, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg
+may import this package.  It shares no code with the GPU library.
+
+Each function names the passage of the paper (Azad and Buluç, "A
+work-efficient parallel sparse matrix-sparse vector multiplication
+algorithm") it follows; see ``oracle.c`` for the C side.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+PLUS_TIMES, MIN_SELECT2ND, OR_AND = 0, 1, 2
+
+
+def build(force: bool = True, src: Optional[str] = None, out: Optional[str] = None) -> str:
+    """Compile the oracle (gcc -O2, no fast-math: fp64 semantics kept exact)."""
+    global _lib
+    src = src or _SRC
+    out = out or _LIB_PATH
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off", src, "-o", tmp,
+                        "-lm"], check=True)
+        os.replace(tmp, out)
+        if out == _LIB_PATH:
+            _lib = None
+    return out
+
+
+def _bind(lib):
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_validate.argtypes = [i64, i64, vp, vp, i64, vp]
+    lib.oracle_spmspv.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp, i64, vp, vp, vp, ctypes.c_int, vp, vp,
+                                  vp, vp]
+    lib.oracle_spmspv_f32seq.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.oracle_bfs.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp]
+    lib.oracle_bfs.restype = ctypes.c_int
+    if hasattr(lib, "oracle_pagerank"):
+        lib.oracle_pagerank.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp]
+        lib.oracle_pagerank.restype = ctypes.c_int
+    if hasattr(lib, "oracle_mlp_forward"):
+        lib.oracle_mlp_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_mlp_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+    return lib
+
+
+def load(path: Optional[str] = None):
+    """Load (building if needed) the oracle library; `path` loads a variant build."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def validate(m, n, colptr, rowids, x_idx, lib=None) -> int:
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    return int(lib.oracle_validate(m, n, _p(colptr), _p(rowids), x_idx.size, _p(x_idx)))
+
+
+def spmspv(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES,
+           mask: Optional[np.ndarray] = None, sorted_output: bool = False, lib=None):
+    """y <- A x (Algorithm 1's result) with a dense accumulator.
+
+    Returns (y_idx int32, y_val, W) with y_val float64 (plus-times),
+    int32 (min-select2nd) or uint8 (or-and).  `A` is a ``synth.CSC``.
+    """
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    f = x_idx.size
+    if semiring == PLUS_TIMES:
+        xv = np.ascontiguousarray(x_val, np.float32)
+        yv = np.empty(max(A.m, 1), np.float64)
+    elif semiring == MIN_SELECT2ND:
+        xv = np.ascontiguousarray(x_val, np.int32)
+        yv = np.empty(max(A.m, 1), np.int32)
+    elif semiring == OR_AND:
+        xv = np.ascontiguousarray(x_val, np.uint8)
+        yv = np.empty(max(A.m, 1), np.uint8)
+    else:
+        raise ValueError("semiring")
+    yi = np.empty(max(A.m, 1), np.int32)
+    mk = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+    nnz = ctypes.c_int64(0)
+    W = ctypes.c_int64(0)
+    vals = None if A.values is None else np.ascontiguousarray(A.values, np.float32)
+    rc = lib.oracle_spmspv(semiring, A.m, A.n, _p(A.colptr), _p(A.rowids), _p(vals), f, _p(x_idx), _p(xv),
+                           _p(mk), int(bool(sorted_output)), _p(yi), _p(yv), ctypes.byref(nnz), ctypes.byref(W))
+    if rc != 0:
+        raise ValueError(f"oracle_spmspv rc={rc}")
+    k = nnz.value
+    return yi[:k].copy(), yv[:k].copy(), W.value
+
+
+def spmspv_f32seq(A, x_idx: np.ndarray, x_val: np.ndarray, lib=None):
+    """Plus-times accumulated in fp32 in x order; returns (y_idx, y_val float32)."""
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    xv = np.ascontiguousarray(x_val, np.float32)
+    yi = np.empty(max(A.m, 1), np.int32)
+    yv = np.empty(max(A.m, 1), np.float32)
+    nnz = ctypes.c_int64(0)
+    vals = None if A.values is None else np.ascontiguousarray(A.values, np.float32)
+    lib.oracle_spmspv_f32seq(A.m, _p(A.colptr), _p(A.rowids), _p(vals), x_idx.size, _p(x_idx), _p(xv), _p(yi),
+                             _p(yv), ctypes.byref(nnz))
+    k = nnz.value
+    return yi[:k].copy(), yv[:k].copy()
+
+
+def bfs(A, root: int, lib=None):
+    """Queue BFS: (levels int32[n], parents int32[n] by the minimum-parent rule, num_levels)."""
+    lib = lib or load()
+    lev = np.empty(A.n, np.int32)
+    par = np.empty(A.n, np.int32)
+    nl = lib.oracle_bfs(A.n, _p(A.colptr), _p(A.rowids), int(root), _p(lev), _p(par))
+    return lev, par, int(nl)

@@ -1,0 +1,201 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct implementation of what the GPU library
+ * computes.  Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load it.  It shares no code, header, table or helper with the
+ * GPU library; the two meet only on inputs produced by the seeded generators.
+ *
+ * Contents
+ *   oracle_spmspv        y <- A x over a semiring, dense accumulator
+ *                        (fp64 for plus-times), structural output pattern.
+ *   oracle_spmspv_f32seq the same product accumulated in fp32 in x order,
+ *                        used for rounding pins.
+ *   oracle_bfs           FIFO-queue breadth-first search levels, parents by
+ *                        the minimum-parent rule.
+ *   oracle_pagerank      data-driven (delta) PageRank in fp64.
+ *   oracle_mlp_*         fp64 forward / backward of the schedule-selector MLP.
+ *
+ * Definitions followed (paper: Azad and Bulu\c{c}, "A work-efficient parallel
+ * sparse matrix-sparse vector multiplication algorithm"):
+ *   - y <- A x with A m-by-n in CSC and x, y sparse lists (Background,
+ *     Notation; Sparse matrix and vector data structures).
+ *   - The output holds exactly the rows reached from the selected columns,
+ *     one entry per unique row; the number of unique indices over all
+ *     buckets is nnz(y) (Time and space complexity), so the pattern is
+ *     structural: a row is present even if its value equals the semiring
+ *     zero.
+ *   - Multiplication applies Mult to the x entry and the matrix entry, and
+ *     repeated rows combine with Add (Algorithm 1).  For min-select2nd the
+ *     operand order is the GraphBLAS one, select2nd(A(i,j), x(j)) = x(j).
+ *   - Sorted output lists indices in strictly ascending order (SpMSpV-bucket
+ *     section, sorted variant).
+ *
+ * Parity pins live in tests/test_oracle_pins.py.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+enum { OR_PLUS_TIMES = 0, OR_MIN_SELECT2ND = 1, OR_OR_AND = 2 };
+
+static int cmp_i32(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Validate CSC + x.  Returns 0 if valid, else a negative code:
+ *   -1 colptr[0] != 0 or not monotone, -2 row id out of range,
+ *   -3 x index out of range, -4 duplicate x index.
+ */
+int oracle_validate(int64_t m, int64_t n, const int32_t* colptr, const int32_t* rowids, int64_t f,
+                    const int32_t* x_idx) {
+    if (colptr[0] != 0) return -1;
+    for (int64_t j = 0; j < n; ++j)
+        if (colptr[j + 1] < colptr[j]) return -1;
+    for (int64_t q = 0; q < colptr[n]; ++q)
+        if (rowids[q] < 0 || rowids[q] >= m) return -2;
+    unsigned char* used = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int rc = 0;
+    for (int64_t p = 0; p < f; ++p) {
+        int32_t j = x_idx[p];
+        if (j < 0 || j >= n) { rc = -3; break; }
+        if (used[j]) { rc = -4; break; }
+        used[j] = 1;
+    }
+    free(used);
+    return rc;
+}
+
+/*
+ * y <- A x over `semiring`.
+ *   values  : float[nnz] or NULL (pattern: every stored entry is 1 / true).
+ *   x_val   : plus-times float[f]; min-select2nd int32[f]; or-and uint8[f].
+ *   mask    : NULL or uint8[m]; rows with mask[i] != 0 are dropped from y
+ *             (applied after the multiply).
+ *   y_val   : plus-times double[m]; min-select2nd int32[m]; or-and uint8[m].
+ *   y_idx   : int32[m].  Output order: first-touch order when !sorted,
+ *             ascending when sorted.
+ *   *W      : products formed = sum over x entries of their column lengths.
+ * Every stored x entry selects its column, whatever its value.
+ */
+int oracle_spmspv(int semiring, int64_t m, int64_t n, const int32_t* colptr, const int32_t* rowids,
+                  const float* values, int64_t f, const int32_t* x_idx, const void* x_val,
+                  const uint8_t* mask, int sorted, int32_t* y_idx, void* y_val, int64_t* nnz_y,
+                  int64_t* W) {
+    (void)n;
+    unsigned char* seen = (unsigned char*)calloc((size_t)(m > 0 ? m : 1), 1);
+    double* acc_d = NULL;
+    int32_t* acc_i = NULL;
+    uint8_t* acc_b = NULL;
+    if (semiring == OR_PLUS_TIMES) acc_d = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    else if (semiring == OR_MIN_SELECT2ND) acc_i = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    else if (semiring == OR_OR_AND) acc_b = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+    else { free(seen); return -5; }
+
+    int64_t count = 0, work = 0;
+    for (int64_t p = 0; p < f; ++p) {
+        int32_t j = x_idx[p];
+        for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+            int32_t i = rowids[q];
+            work++;
+            if (semiring == OR_PLUS_TIMES) {
+                double a = values ? (double)values[q] : 1.0;
+                double t = a * (double)((const float*)x_val)[p];
+                if (!seen[i]) { seen[i] = 1; acc_d[i] = t; y_idx[count++] = i; }
+                else acc_d[i] = acc_d[i] + t;
+            } else if (semiring == OR_MIN_SELECT2ND) {
+                int32_t t = ((const int32_t*)x_val)[p];
+                if (!seen[i]) { seen[i] = 1; acc_i[i] = t; y_idx[count++] = i; }
+                else if (t < acc_i[i]) acc_i[i] = t;
+            } else {
+                uint8_t a = values ? (values[q] != 0.0f) : 1;
+                uint8_t t = (uint8_t)(a && ((const uint8_t*)x_val)[p] != 0);
+                if (!seen[i]) { seen[i] = 1; acc_b[i] = t; y_idx[count++] = i; }
+                else acc_b[i] = (uint8_t)(acc_b[i] || t);
+            }
+        }
+    }
+    if (mask) {
+        int64_t k = 0;
+        for (int64_t r = 0; r < count; ++r)
+            if (!mask[y_idx[r]]) y_idx[k++] = y_idx[r];
+        count = k;
+    }
+    if (sorted) qsort(y_idx, (size_t)count, sizeof(int32_t), cmp_i32);
+    for (int64_t r = 0; r < count; ++r) {
+        int32_t i = y_idx[r];
+        if (semiring == OR_PLUS_TIMES) ((double*)y_val)[r] = acc_d[i];
+        else if (semiring == OR_MIN_SELECT2ND) ((int32_t*)y_val)[r] = acc_i[i];
+        else ((uint8_t*)y_val)[r] = acc_b[i];
+    }
+    *nnz_y = count;
+    *W = work;
+    free(seen); free(acc_d); free(acc_i); free(acc_b);
+    return 0;
+}
+
+/* Plus-times accumulated in fp32, products rounded to fp32 first, rows
+ * combined in x order.  y_val float[m], y_idx in first-touch order.       */
+int oracle_spmspv_f32seq(int64_t m, const int32_t* colptr, const int32_t* rowids, const float* values,
+                         int64_t f, const int32_t* x_idx, const float* x_val, int32_t* y_idx,
+                         float* y_val, int64_t* nnz_y) {
+    unsigned char* seen = (unsigned char*)calloc((size_t)(m > 0 ? m : 1), 1);
+    float* acc = (float*)malloc((size_t)(m > 0 ? m : 1) * sizeof(float));
+    int64_t count = 0;
+    for (int64_t p = 0; p < f; ++p) {
+        int32_t j = x_idx[p];
+        for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+            int32_t i = rowids[q];
+            volatile float t = (values ? values[q] : 1.0f) * x_val[p];
+            if (!seen[i]) { seen[i] = 1; acc[i] = t; y_idx[count++] = i; }
+            else { volatile float s = acc[i] + t; acc[i] = s; }
+        }
+    }
+    for (int64_t r = 0; r < count; ++r) y_val[r] = acc[y_idx[r]];
+    *nnz_y = count;
+    free(seen); free(acc);
+    return 0;
+}
+
+/*
+ * Breadth-first search from `root`, edges j -> i for every stored A(i,j)
+ * (x over columns reaches rows).  FIFO queue.  level[v] = hop count or -1;
+ * parent[v] = the smallest u with A(v,u) stored and level[u] = level[v]-1,
+ * parent[root] = root, -1 when unreached.  Returns the number of levels
+ * (max level + 1).
+ */
+int oracle_bfs(int64_t n, const int32_t* colptr, const int32_t* rowids, int32_t root, int32_t* level,
+               int32_t* parent) {
+    for (int64_t v = 0; v < n; ++v) { level[v] = -1; if (parent) parent[v] = -1; }
+    int32_t* queue = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t head = 0, tail = 0;
+    level[root] = 0;
+    queue[tail++] = root;
+    int32_t maxl = 0;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t q = colptr[u]; q < colptr[u + 1]; ++q) {
+            int32_t v = rowids[q];
+            if (level[v] < 0) {
+                level[v] = level[u] + 1;
+                if (level[v] > maxl) maxl = level[v];
+                queue[tail++] = v;
+            }
+        }
+    }
+    if (parent) {
+        for (int64_t u = 0; u < n; ++u) {
+            if (level[u] < 0) continue;
+            for (int64_t q = colptr[u]; q < colptr[u + 1]; ++q) {
+                int32_t v = rowids[q];
+                if (level[v] == level[u] + 1 && (parent[v] < 0 || u < parent[v])) parent[v] = (int32_t)u;
+            }
+        }
+        parent[root] = root;
+    }
+    free(queue);
+    return maxl + 1;
+}
