@@ -1,0 +1,186 @@
+/*
+ * spmspv.h -- C ABI of the MI355X (gfx950) SpMSpV library.
+ *
+ * Computes y <- A x over a semiring where A is an m-by-n sparse matrix in
+ * compressed sparse column (CSC) form and x, y are sparse vectors in list
+ * form (index array + value array), following Azad and Bulu\c{c}, "A
+ * work-efficient parallel sparse matrix-sparse vector multiplication
+ * algorithm": problem statement in Background / Notation; CSC and list
+ * vectors in Background / "Sparse matrix and vector data structures"; the
+ * method is Algorithm 1 (SpMSpV-bucket) with its preprocessing step
+ * Algorithm 2 (Estimate-Buckets).
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless their name starts with h_.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     All device work is ordered on that stream.  Calls return after
+ *     enqueueing unless documented as synchronous.
+ *   - Indices are int32; colptr is int32 (nnz < 2^31); products and
+ *     offsets that can exceed 2^31 are int64.
+ *   - Status is the int return value (SPMSPV_OK = 0, negative = error).
+ *     No call throws.  A call that fails validation writes nothing to its
+ *     outputs.  spmspv_last_error() returns a thread-local detail string.
+ *   - The library never allocates device memory after spmspv_create.  The
+ *     caller owns A's arrays, x, y, BFS/PageRank outputs and the workspace;
+ *     they must outlive the handle.
+ *   - A handle is not reentrant: calls on one handle must not overlap in
+ *     time on different streams (they share the workspace).  Use one handle
+ *     per concurrent stream.
+ */
+#ifndef SPMSPV_H
+#define SPMSPV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spmspv_matrix* spmspv_handle;
+
+/* Semirings (Algorithm 1's Mult / Add pair).
+ *   PLUS_TIMES_F32     : Mult = a*x (fp32, rounded), Add = + (fp32).
+ *                        A values float, x float, y float.
+ *   MIN_SELECT2ND_I32  : Mult = select2nd(a, x) = x, Add = min.
+ *                        A values ignored, x int32, y int32.
+ *   OR_AND_BOOL        : Mult = (a != 0) AND (x != 0), Add = OR.
+ *                        A values (or pattern), x uint8, y uint8 (0/1).
+ * Output pattern is structural: y holds every row reached by a selected
+ * column, once (the unique indices of all buckets, Algorithm 1 step 2),
+ * even when its value equals the semiring zero.                          */
+enum spmspv_semiring {
+    SPMSPV_PLUS_TIMES_F32 = 0,
+    SPMSPV_MIN_SELECT2ND_I32 = 1,
+    SPMSPV_OR_AND_BOOL = 2
+};
+
+enum spmspv_status {
+    SPMSPV_OK = 0,
+    SPMSPV_EINVAL = -1,        /* bad argument or invalid input data          */
+    SPMSPV_ENOMEM = -2,        /* workspace smaller than spmspv_workspace_size */
+    SPMSPV_ECAPACITY = -3,     /* y_capacity < nnz(y); required size reported */
+    SPMSPV_EHIP = -4,          /* a HIP runtime call failed                    */
+    SPMSPV_EUNSUPPORTED = -5,  /* valid request this build cannot serve        */
+    SPMSPV_EDEVICE = -6        /* the device reported an error bit (see text)  */
+};
+
+/* Flags (bitwise OR). */
+enum spmspv_flags {
+    SPMSPV_SORTED_OUTPUT = 1,  /* y indices strictly ascending (sorted variant,
+                                  Algorithm 1 with per-bucket ordering)        */
+    SPMSPV_VALIDATE = 2,       /* check inputs on the host before launching:
+                                  synchronous, O(nnz) at create, O(f) per run */
+    SPMSPV_X_VAL_IS_INDEX = 4, /* MIN_SELECT2ND: x value of entry p is
+                                  x_idx[p]; x_val may be NULL                  */
+    SPMSPV_X_ALL_TRUE = 8,     /* OR_AND: every x value is true; x_val may be
+                                  NULL                                         */
+    SPMSPV_USE_GRAPH = 16,     /* bfs_run: replay the level loop as a captured
+                                  hipGraph                                     */
+    SPMSPV_PROFILE = 32        /* record HIP events around each kernel (see
+                                  spmspv_profile_read)                        */
+};
+
+/* Launch schedule.  Changing it never changes int / bool results or any
+ * output index set; fp32 plus-times sums may differ in rounding order.   */
+typedef struct {
+    int direction;      /* 0 = push (vector-driven, Algorithm 1)                   */
+    int tile_log2;      /* rows per bucket = 2^tile_log2; buckets = ceil(m / 2^t)  */
+    int scatter_block;  /* threads per bucketing workgroup (64..1024, power of 2)  */
+    int scatter_items;  /* products per thread per chunk (1..16, power of 2)       */
+    int merge_block;    /* threads per merge workgroup (64..1024, power of 2)      */
+    int merge_variant;  /* 0 = sparse accumulator in LDS                           */
+} spmspv_schedule;
+
+/* Bytes of device workspace spmspv_create needs for an m-by-n matrix with
+ * nnz stored entries: buckets sized for nnz entries in total (the bound in
+ * "Performance optimizations / Memory allocation"), per-call scan and bucket
+ * counters, and BFS frontier buffers.  Pure host computation.
+ * EINVAL if m, n < 1, nnz < 0, nnz >= 2^31 or bytes == NULL.            */
+int spmspv_workspace_size(int64_t m, int64_t n, int64_t nnz, int flags, size_t* h_bytes);
+
+/* Bind a CSC matrix (colptr int32[n+1], rowids int32[nnz], values float[nnz]
+ * or NULL for a pattern matrix whose entries are all 1 / true) and a
+ * workspace of ws_bytes device bytes.  Row ids inside a column may be in any
+ * order (CSC does not require sorted columns).  Duplicate (i, j) entries are
+ * combined with the semiring's Add, exactly as repeated products are.
+ * Synchronous: runs set-up kernels on `stream` (row counts that size the
+ * buckets, the maximum column length) and waits for them.  With
+ * SPMSPV_VALIDATE it also checks colptr[0] == 0, colptr monotone,
+ * colptr[n] == nnz and every row id in [0, m) on the device (EINVAL
+ * otherwise).  The matrix arrays are borrowed, not copied.
+ * Errors: EINVAL (null pointers, bad sizes, invalid CSC), ENOMEM (workspace
+ * too small), EHIP.                                                       */
+int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes, int flags,
+                  void* stream);
+
+/* y <- A x (Algorithm 1 with Algorithm 2's counting), enqueued on `stream`.
+ *   f                 : number of x entries (0 <= f <= n); indices must be
+ *                       distinct (checked only with SPMSPV_VALIDATE; with
+ *                       duplicates the device sets an error bit and y is
+ *                       unspecified, memory stays safe).
+ *   x_idx [f], x_val [f] : x in list form, any order.  x_val element type
+ *                       per semiring (see enum); may be NULL with
+ *                       X_VAL_IS_INDEX / X_ALL_TRUE.
+ *   y_idx [y_capacity], y_val [y_capacity] : output list.  Unsorted order is
+ *                       unspecified; with SPMSPV_SORTED_OUTPUT indices are
+ *                       strictly ascending.  y_val may be NULL (pattern only).
+ *   d_nnz_y           : device int64, receives nnz(y) (nullable).
+ *   h_nnz_y           : host int64 (nullable).  When non-NULL the call waits
+ *                       for the stream, stores nnz(y), and reports device
+ *                       error bits (EDEVICE) and ECAPACITY.
+ * nnz(y) <= min(m, sum of selected column lengths).  When nnz(y) exceeds
+ * y_capacity only the first y_capacity entries are written; a capacity of m
+ * always suffices.                                                        */
+int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx, const void* x_val,
+               int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
+               void* stream);
+
+/* Breadth-first search from `root` by repeated SpMSpV on the frontier
+ * (Results, "Performance of SpMSpV algorithms when used in BFS"; the
+ * frontier-expansion pattern of the Introduction), with the visited set as
+ * a mask applied to each product (the masked SpMSpV of Conclusions and
+ * Future Work).  Requires m == n.  Edges are j -> i for stored A(i, j).
+ *   semiring MIN_SELECT2ND_I32 : x value = vertex id, so a reached vertex's
+ *       parent is its smallest in-neighbour on the previous level.
+ *   semiring OR_AND_BOOL       : reachability only; parent must be NULL.
+ *   level [n]  : out, hop count from root, -1 if unreached.
+ *   parent [n] : out (nullable), parent[root] = root, -1 if unreached.
+ *   h_num_levels : out (nullable), number of non-empty levels.
+ * Synchronous (waits once per batch of levels to test for an empty
+ * frontier).  With SPMSPV_USE_GRAPH the per-level kernels are captured
+ * once in a hipGraph and replayed.                                        */
+int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* level, int32_t* parent,
+            int32_t* h_num_levels, void* stream);
+
+/* Read / replace the launch schedule (NULL restores the default). */
+int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched);
+int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
+
+/* Statistics of the most recent spmspv_run / BFS level (synchronous):
+ * h_out[0] = products W (sum of selected column lengths, the work bound of
+ * the lower-bound section), [1] = nnz(y), [2] = non-empty selected columns,
+ * [3] = maximum selected column length, [4] = device error bits.          */
+int spmspv_last_stats(spmspv_handle A, int64_t* h_out, void* stream);
+
+/* Per-kernel timing of calls made with SPMSPV_PROFILE: waits for the
+ * recorded events, writes the summed milliseconds of each phase
+ * (0 = scan, 1 = bucket scatter, 2 = merge + compaction) to h_ms[3] and the
+ * number of profiled calls to *h_calls, then clears the record.           */
+int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
+
+/* Release the handle (host memory and HIP events only; the caller frees
+ * its device arrays and workspace).                                       */
+int spmspv_destroy(spmspv_handle A);
+
+/* Static description of a status code; detail of the last error on this
+ * host thread. */
+const char* spmspv_status_string(int status);
+const char* spmspv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMSPV_H */

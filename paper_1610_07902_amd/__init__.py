@@ -1,0 +1,237 @@
+"""SpMSpV-bucket on MI355X: Python binding of libspmspv.so.
+
+The functions below have the names of the C ABI in ``include/spmspv.h`` and
+only marshal arguments: every step of the computation runs in the library's
+HIP kernels.  PyTorch provides device memory and the HIP stream.  Importing
+the binding fails loudly when the library has not been built; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmspv.so")
+
+PLUS_TIMES_F32 = 0
+MIN_SELECT2ND_I32 = 1
+OR_AND_BOOL = 2
+
+SORTED_OUTPUT = 1
+VALIDATE = 2
+X_VAL_IS_INDEX = 4
+X_ALL_TRUE = 8
+USE_GRAPH = 16
+PROFILE = 32
+
+OK, EINVAL, ENOMEM, ECAPACITY, EHIP, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTED = (
+    "spmspv_workspace_size", "spmspv_create", "spmspv_run", "bfs_run", "spmspv_get_schedule",
+    "spmspv_set_schedule", "spmspv_last_stats", "spmspv_profile_read", "spmspv_destroy",
+    "spmspv_status_string", "spmspv_last_error",
+)
+
+
+class SpmspvError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"status {status}: {message}")
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int), ("tile_log2", ctypes.c_int), ("scatter_block", ctypes.c_int),
+                ("scatter_items", ctypes.c_int), ("merge_block", ctypes.c_int), ("merge_variant", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspmspv.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    i64, vp, ci, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.spmspv_workspace_size.argtypes = [i64, i64, i64, ci, ctypes.POINTER(sz)]
+    lib.spmspv_create.argtypes = [ctypes.POINTER(vp), i64, i64, i64, vp, vp, vp, vp, sz, ci, vp]
+    lib.spmspv_run.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
+    lib.bfs_run.argtypes = [vp, ci, ctypes.c_int32, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.spmspv_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.spmspv_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.spmspv_last_stats.argtypes = [vp, ctypes.POINTER(i64), vp]
+    lib.spmspv_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.spmspv_destroy.argtypes = [vp]
+    lib.spmspv_status_string.argtypes = [ci]
+    lib.spmspv_status_string.restype = ctypes.c_char_p
+    lib.spmspv_last_error.argtypes = []
+    lib.spmspv_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load_library()
+        msg = lib.spmspv_status_string(rc).decode() + ": " + lib.spmspv_last_error().decode()
+        raise SpmspvError(rc, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------- C-ABI mirrors
+def spmspv_workspace_size(m: int, n: int, nnz: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().spmspv_workspace_size(m, n, nnz, flags, ctypes.byref(out)))
+    return out.value
+
+
+def spmspv_create(m, n, nnz, colptr, rowids, values, workspace, ws_bytes, flags=0, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p(None)
+    _check(load_library().spmspv_create(ctypes.byref(h), m, n, nnz, _ptr(colptr), _ptr(rowids), _ptr(values),
+                                        _ptr(workspace), ws_bytes, flags, _stream(stream)))
+    return h
+
+
+def spmspv_run(handle, semiring, flags, f, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y=None, sync=True,
+               stream=None) -> Optional[int]:
+    """Enqueue y <- A x; with sync=True waits and returns nnz(y)."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run(handle, semiring, flags, f, _ptr(x_idx), _ptr(x_val), _ptr(y_idx),
+                                     _ptr(y_val), y_capacity, _ptr(d_nnz_y), ctypes.byref(h) if sync else None,
+                                     _stream(stream)))
+    return h.value if sync else None
+
+
+def bfs_run(handle, semiring, root, flags, level, parent=None, stream=None) -> int:
+    nl = ctypes.c_int32(0)
+    _check(load_library().bfs_run(handle, semiring, int(root), flags, _ptr(level), _ptr(parent), ctypes.byref(nl),
+                                  _stream(stream)))
+    return nl.value
+
+
+def spmspv_get_schedule(handle) -> Schedule:
+    s = Schedule()
+    _check(load_library().spmspv_get_schedule(handle, ctypes.byref(s)))
+    return s
+
+
+def spmspv_set_schedule(handle, sched: Optional[Schedule] = None):
+    _check(load_library().spmspv_set_schedule(handle, ctypes.byref(sched) if sched is not None else None))
+
+
+def spmspv_last_stats(handle, stream=None) -> dict:
+    out = (ctypes.c_int64 * 5)()
+    _check(load_library().spmspv_last_stats(handle, out, _stream(stream)))
+    return {"W": out[0], "nnz_y": out[1], "fnz": out[2], "maxlen": out[3], "err": out[4]}
+
+
+def spmspv_profile_read(handle) -> Tuple[list, int]:
+    ms = (ctypes.c_double * 3)()
+    calls = ctypes.c_int64(0)
+    _check(load_library().spmspv_profile_read(handle, ms, ctypes.byref(calls)))
+    return [ms[0], ms[1], ms[2]], calls.value
+
+
+def spmspv_destroy(handle):
+    _check(load_library().spmspv_destroy(handle))
+
+
+# ------------------------------------------------------------ convenience
+class Matrix:
+    """A CSC matrix resident on the GPU with its library handle and workspace.
+
+    Holds torch tensors for colptr / rowids / values / workspace (the library
+    borrows them) and exposes spmspv() and bfs().
+    """
+
+    def __init__(self, m: int, n: int, colptr, rowids, values=None, flags: int = 0, device="cuda"):
+        import torch
+        self.m, self.n = int(m), int(n)
+        self.colptr = torch.as_tensor(colptr, dtype=torch.int32).to(device).contiguous()
+        self.rowids = torch.as_tensor(rowids, dtype=torch.int32).to(device).contiguous()
+        self.values = None if values is None else torch.as_tensor(values, dtype=torch.float32).to(device).contiguous()
+        self.nnz = int(self.rowids.numel())
+        self.ws_bytes = spmspv_workspace_size(self.m, self.n, self.nnz, flags)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.handle = spmspv_create(self.m, self.n, self.nnz, self.colptr, self.rowids, self.values, self.workspace,
+                                    self.ws_bytes, flags)
+        self._d_nnz = torch.zeros(1, dtype=torch.int64, device=device)
+
+    @classmethod
+    def from_csc(cls, A, flags: int = 0, device="cuda", pattern: bool = False):
+        return cls(A.m, A.n, A.colptr, A.rowids, None if pattern else A.values, flags, device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            spmspv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def schedule(self) -> Schedule:
+        return spmspv_get_schedule(self.handle)
+
+    @schedule.setter
+    def schedule(self, s: Optional[Schedule]):
+        spmspv_set_schedule(self.handle, s)
+
+    def spmspv(self, x_idx, x_val=None, semiring: int = PLUS_TIMES_F32, sorted_output: bool = False,
+               flags: int = 0, y_capacity: Optional[int] = None, out=None, sync: bool = True):
+        """y <- A x.  Returns (y_idx, y_val, nnz) trimmed to nnz when sync."""
+        import torch
+        dev = self.colptr.device
+        cap = self.m if y_capacity is None else int(y_capacity)
+        if out is None:
+            y_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            vdt = {PLUS_TIMES_F32: torch.float32, MIN_SELECT2ND_I32: torch.int32, OR_AND_BOOL: torch.uint8}[semiring]
+            y_val = torch.empty(max(cap, 1), dtype=vdt, device=dev)
+        else:
+            y_idx, y_val = out
+        fl = flags | (SORTED_OUTPUT if sorted_output else 0)
+        f = int(x_idx.numel())
+        nnz = spmspv_run(self.handle, semiring, fl, f, x_idx, x_val, y_idx, y_val, cap, self._d_nnz, sync=sync)
+        if not sync:
+            return y_idx, y_val, self._d_nnz
+        k = min(nnz, cap)
+        return y_idx[:k], y_val[:k], nnz
+
+    def bfs(self, root: int, semiring: int = MIN_SELECT2ND_I32, parents: bool = True, flags: int = 0):
+        import torch
+        dev = self.colptr.device
+        level = torch.empty(self.n, dtype=torch.int32, device=dev)
+        parent = torch.empty(self.n, dtype=torch.int32, device=dev) if (parents and semiring == MIN_SELECT2ND_I32) \
+            else None
+        nl = bfs_run(self.handle, semiring, root, flags, level, parent)
+        return level, parent, nl
+
+    def last_stats(self) -> dict:
+        return spmspv_last_stats(self.handle)

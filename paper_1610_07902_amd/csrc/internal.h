@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of the
+// SpMSpV library.  Not installed; the public interface is include/spmspv.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spv {
+
+constexpr int kWave = 64;
+
+// Device error bits (Ctrl::err), sticky until the host reads them.
+enum : uint32_t {
+    ERR_X_RANGE = 1u,          // an x index outside [0, n)
+    ERR_BUCKET_OVERFLOW = 2u,  // a bucket received more entries than its rows
+                               // hold in A (only possible with duplicate x)
+    ERR_SPIN = 4u,             // a look-back wait exceeded its bound
+    ERR_CSC = 8u,              // colptr not monotone / wrong ends (create)
+    ERR_ROW_RANGE = 16u        // a row id outside [0, m) (create)
+};
+
+enum Semiring : int { SR_PLUS_TIMES = 0, SR_MIN_SELECT2ND = 1, SR_OR_AND = 2 };
+
+// How the scan phase reads x values.
+enum XMode : int { XV_BITS32 = 0, XV_INDEX = 1, XV_U8 = 2, XV_TRUE = 3 };
+
+// Device-resident control block, one per handle (first 256 B of the workspace).
+struct alignas(256) Ctrl {
+    int32_t f;              // frontier length for device-driven loops (BFS)
+    int32_t fnz;            // selected columns with at least one entry
+    int32_t W;              // products = sum of selected column lengths
+    int32_t maxlen;         // running max selected column length (scan phase)
+    uint32_t ticket_scan;   // work tickets of the scan phase (reset by scatter)
+    uint32_t ticket_merge;  // work tickets of the merge phase (reset by scan)
+    int32_t level;          // BFS level being produced
+    uint32_t err;           // sticky error bits
+    int64_t nnz_y;          // nnz(y) of the last merge phase
+    int32_t maxlen_last;    // maxlen of the last completed scan phase
+    int32_t maxdeg;         // longest column of A (create)
+    int32_t fnz_last;
+    int32_t W_last;
+    uint32_t pad[50];
+};
+static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
+
+// Scan phase: gather the selected column ranges, prefix-sum their lengths,
+// compact the non-empty ones and mark where each product chunk starts.
+struct ScanArgs {
+    const int32_t* colptr;
+    int32_t n;
+    const int32_t* x_idx;
+    const void* x_val;
+    int xmode;
+    int32_t f_host;          // used when f_dev == nullptr
+    const int32_t* f_dev;    // device frontier length (BFS)
+    Ctrl* ctrl;
+    int32_t* cstart;         // [fnz] first entry of each non-empty column
+    int32_t* coff;           // [fnz+1] exclusive prefix of lengths
+    uint32_t* cxv;           // [fnz] x value bits
+    int32_t* chunk_col;      // [nchunks] first column of each product chunk
+    int chunk_log2;          // products per chunk = 2^chunk_log2
+    uint64_t* lb1;           // look-back words of this phase (zero on entry):
+                             // [lb1_n] product sums, then [lb1_n] column counts
+    int32_t lb1_n;
+    int64_t nnz;             // products above this mean duplicate x indices
+    int64_t chunk_n;         // entries of chunk_col
+    int32_t* cursor;         // bucket fill counters, cleared here for scatter
+    uint64_t* lb3;           // merge look-back words, cleared here
+    int32_t nb;              // buckets of the current schedule
+    int bump_level;          // BFS: advance ctrl->level when f > 0
+};
+
+// Scatter phase: products -> row-range buckets.
+struct ScatterArgs {
+    const int32_t* rowids;
+    const float* values;     // nullable (pattern)
+    Ctrl* ctrl;
+    const int32_t* cstart;
+    const int32_t* coff;
+    const uint32_t* cxv;
+    const int32_t* chunk_col;
+    int chunk_log2;
+    int tile_log2;
+    int32_t nb;
+    int32_t m;
+    const int32_t* rcp;      // [m+1] prefix of row counts of A = bucket bases
+    int32_t* cursor;         // [nb]
+    uint2* buckets;          // [nnz] (row, value bits)
+    const uint32_t* mask;    // nullable visited bitmap: drop rows whose bit is set
+    uint64_t* lb1;           // scan look-back words to clear (two halves of lb1_n)
+    int32_t lb1_n;
+    int32_t lb1_clear;       // how many of each half to clear
+    int32_t f_host;
+    const int32_t* f_dev;
+};
+
+// Merge + compaction phase: one workgroup per bucket.
+struct MergeArgs {
+    Ctrl* ctrl;
+    const int32_t* cursor;
+    const uint2* buckets;
+    const int32_t* rcp;
+    int32_t m;
+    int tile_log2;
+    int32_t nb;
+    uint64_t* lb3;
+    int32_t* y_idx;
+    void* y_val;             // nullable
+    int64_t y_cap;
+    int64_t* d_nnz_y;        // nullable
+    uint32_t* visited;       // BFS: visited bitmap, updated with new vertices
+    int32_t* level;          // BFS
+    int32_t* parent;         // BFS, nullable
+    int set_f;               // BFS: publish nnz(y) as the next frontier length
+};
+
+size_t merge_lds_bytes(int tile_log2, bool sorted);
+size_t scatter_lds_bytes(int nb, int chunk);
+
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s);
+hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool sorted, bool bfs, hipStream_t s);
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kMergeItems = 8;
+
+// Set-up kernels (spmspv_create, bfs_run).
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl,
+                             hipStream_t s);
+hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
+hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
+                           int32_t* frontier, Ctrl* ctrl, hipStream_t s);
+
+}  // namespace spv

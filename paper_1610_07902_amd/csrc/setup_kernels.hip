@@ -1,0 +1,169 @@
+// Set-up kernels: run once per matrix (spmspv_create) or once per BFS.
+// Not on the per-multiply path.
+
+#include "internal.h"
+
+namespace spv {
+
+namespace {
+
+constexpr int kSetupBlock = 256;
+constexpr int kScanBlk = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanSpan = kScanBlk * kScanPer;
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// counts[r] += 1 for every row id r (counts has m+1 zeroed entries).
+__global__ void k_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rowids[q];
+        if (r >= 0 && r < m) atomicAdd(&counts[r], 1);
+        else atomicOr(&ctrl->err, ERR_ROW_RANGE);
+    }
+}
+
+// colptr[0] == 0, colptr monotone, colptr[n] == nnz; also the longest column.
+__global__ void k_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl) {
+    int lmax = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = colptr[j], b = colptr[j + 1];
+        if (b < a) atomicOr(&ctrl->err, ERR_CSC);
+        lmax = max(lmax, b - a);
+        if (j == 0 && a != 0) atomicOr(&ctrl->err, ERR_CSC);
+        if (j == n - 1 && (int64_t)b != nnz) atomicOr(&ctrl->err, ERR_CSC);
+    }
+    if (lmax > 0) atomicMax(&ctrl->maxdeg, lmax);
+}
+
+__device__ int block_scan_excl(int v, int* s) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            const int t = s[w];
+            s[w] = acc;
+            acc += t;
+        }
+        s[16] = acc;
+    }
+    __syncthreads();
+    const int r = s[wid] + x - v;
+    return r;
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_span_sums(const int32_t* data, int64_t count, int32_t* partials) {
+    __shared__ int s[17];
+    const int64_t base = (int64_t)blockIdx.x * kScanSpan + threadIdx.x * kScanPer;
+    int v = 0;
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < count) v += data[base + i];
+    block_scan_excl(v, s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[16];
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_partials(int32_t* partials, int64_t np) {
+    __shared__ int s[17];
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < np; b0 += kScanBlk) {
+        const int64_t i = b0 + threadIdx.x;
+        const int v = i < np ? partials[i] : 0;
+        const int e = block_scan_excl(v, s);
+        const int tot = s[16];
+        if (i < np) partials[i] = carry + e;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_span_apply(int32_t* data, int64_t count, const int32_t* partials) {
+    __shared__ int s[17];
+    const int64_t base = (int64_t)blockIdx.x * kScanSpan + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        v[i] = base + i < count ? data[base + i] : 0;
+        sum += v[i];
+    }
+    int run = block_scan_excl(sum, s) + partials[blockIdx.x];
+    for (int i = 0; i < kScanPer; ++i) {
+        if (base + i < count) data[base + i] = run;
+        run += v[i];
+    }
+}
+
+__global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
+                           int32_t* frontier, Ctrl* ctrl) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+        level[v] = (v == root) ? 0 : -1;
+        if (parent) parent[v] = (v == root) ? root : -1;
+    }
+    const int64_t nw = ((int64_t)n + 31) >> 5;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += stride)
+        visited[w] = (w == (root >> 5)) ? (1u << (root & 31)) : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        frontier[0] = root;
+        ctrl->f = 1;
+        ctrl->level = 0;
+    }
+}
+
+inline int grid_for(int64_t count, int block, int cap = 4096) {
+    int64_t g = (count + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, kSetupBlock)), dim3(kSetupBlock), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl,
+                             hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_counts, dim3(grid_for(nnz, kSetupBlock)), dim3(kSetupBlock), 0, s, rowids, nnz, m,
+                       counts, ctrl);
+    return hipGetLastError();
+}
+
+// In-place exclusive scan of `count` int32 values; `partials` needs
+// ceil(count / 4096) entries.
+hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t np = (count + kScanSpan - 1) / kScanSpan;
+    hipLaunchKernelGGL(k_span_sums, dim3((unsigned)np), dim3(kScanBlk), 0, s, data, count, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlk), 0, s, partials, np);
+    hipLaunchKernelGGL(k_span_apply, dim3((unsigned)np), dim3(kScanBlk), 0, s, data, count, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_colptr, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, colptr, n, nnz,
+                       ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
+                           int32_t* frontier, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, n, root, level, parent,
+                       visited, frontier, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace spv

@@ -1,0 +1,558 @@
+// C ABI of the SpMSpV library (include/spmspv.h): handle, workspace layout,
+// schedule, validation and the per-call launch sequence.
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spmspv.h"
+#include "internal.h"
+
+using namespace spv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return SPMSPV_EHIP;
+}
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+    } while (0)
+
+constexpr int kTileLog2Min = 8;
+constexpr int kTileLog2Max = 14;
+constexpr int kChunkMin = 256;
+constexpr size_t kAlign = 256;
+constexpr int kProfileSlots = 1024;
+constexpr int kGraphLevels = 16;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline int ceil_log2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+// Offsets of every region inside the caller's workspace.
+struct Layout {
+    size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
+        total;
+    int64_t nb_max, lb1_n, chunk_n;
+};
+
+Layout make_layout(int64_t m, int64_t n, int64_t nnz) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    L.nb_max = (m + (1 << kTileLog2Min) - 1) >> kTileLog2Min;
+    L.lb1_n = (n + kScanTile - 1) / kScanTile + 1;
+    L.chunk_n = nnz / kChunkMin + 2;
+    L.ctrl = take(sizeof(Ctrl));
+    L.rcp = take(size_t(m + 1) * 4);
+    L.partials = take(size_t((m + 1) / 4096 + 2) * 4);
+    L.cstart = take(size_t(n) * 4);
+    L.coff = take(size_t(n + 1) * 4);
+    L.cxv = take(size_t(n) * 4);
+    L.chunk_col = take(size_t(L.chunk_n) * 4);
+    L.lb1 = take(size_t(L.lb1_n) * 16);
+    L.cursor = take(size_t(L.nb_max) * 4);
+    L.lb3 = take(size_t(L.nb_max) * 8);
+    L.buckets = take(size_t(nnz) * 8);
+    L.visited = take(size_t((m + 31) / 32) * 4);
+    L.front0 = take(size_t(m) * 4);
+    L.front1 = take(size_t(m) * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct spmspv_matrix {
+    int64_t m = 0, n = 0, nnz = 0;
+    const int32_t* colptr = nullptr;
+    const int32_t* rowids = nullptr;
+    const float* values = nullptr;
+    Layout L{};
+    char* ws = nullptr;
+    Ctrl* ctrl = nullptr;
+    int32_t* rcp = nullptr;
+    int32_t* cstart = nullptr;
+    int32_t* coff = nullptr;
+    uint32_t* cxv = nullptr;
+    int32_t* chunk_col = nullptr;
+    uint64_t* lb1 = nullptr;
+    int32_t* cursor = nullptr;
+    uint64_t* lb3 = nullptr;
+    uint2* buckets = nullptr;
+    uint32_t* visited = nullptr;
+    int32_t* front[2] = {nullptr, nullptr};
+    int32_t maxdeg = 0;
+    int device = 0;
+    int num_cu = 256;
+    size_t lds_max = 65536;
+    spmspv_schedule sched{};
+    // profiling ring
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used = 0;
+    // BFS graph cache
+    hipGraphExec_t graph = nullptr;
+    int graph_key = -1;
+};
+
+namespace {
+
+int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
+    int tl = ceil_log2(A->m) - 10;
+    if (tl < kTileLog2Min) tl = kTileLog2Min;
+    if (tl > kTileLog2Max) tl = kTileLog2Max;
+    while (tl > kTileLog2Min && merge_lds_bytes(tl, false) + 1024 > A->lds_max) --tl;
+    s->direction = 0;
+    s->tile_log2 = tl;
+    s->scatter_block = 256;
+    s->scatter_items = 8;
+    s->merge_block = 256;
+    s->merge_variant = 0;
+    return SPMSPV_OK;
+}
+
+int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
+    if (s->direction != 0) return fail(SPMSPV_EUNSUPPORTED, "only the push direction is built");
+    if (s->tile_log2 < kTileLog2Min || s->tile_log2 > kTileLog2Max)
+        return fail(SPMSPV_EINVAL, "tile_log2 out of [8, 14]");
+    const int64_t nb = (A->m + (int64_t(1) << s->tile_log2) - 1) >> s->tile_log2;
+    const int sb = s->scatter_block, si = s->scatter_items;
+    const bool ok_scatter = (sb == 256 && (si == 4 || si == 8 || si == 16)) || (sb == 512 && (si == 4 || si == 8)) ||
+                            (sb == 1024 && si == 4);
+    if (!ok_scatter) return fail(SPMSPV_EINVAL, "unsupported scatter_block / scatter_items pair");
+    if (s->merge_block != 256 && s->merge_block != 512) return fail(SPMSPV_EINVAL, "merge_block must be 256 or 512");
+    if (s->merge_variant != 0) return fail(SPMSPV_EUNSUPPORTED, "only the LDS merge variant is built");
+    if (merge_lds_bytes(s->tile_log2, false) + 1024 > A->lds_max) return fail(SPMSPV_EINVAL, "tile exceeds LDS");
+    if (scatter_lds_bytes((int)nb, sb * si) + 1024 > A->lds_max)
+        return fail(SPMSPV_EINVAL, "too many buckets for the scatter LDS histogram");
+    return SPMSPV_OK;
+}
+
+inline int64_t num_buckets(const spmspv_matrix* A) {
+    return (A->m + (int64_t(1) << A->sched.tile_log2) - 1) >> A->sched.tile_log2;
+}
+
+// Enqueue the three phases of one y <- A x.
+int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_host, const int32_t* f_dev,
+            const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y,
+            bool bfs, int32_t* level, int32_t* parent, hipStream_t s, hipEvent_t* ev) {
+    const spmspv_schedule& sc = A->sched;
+    const int nb = (int)num_buckets(A);
+    const int chunk = sc.scatter_block * sc.scatter_items;
+    const int chunk_log2 = ceil_log2(chunk);
+    const int64_t f_bound = f_dev ? A->n : f_host;
+
+    ScanArgs sa{};
+    sa.colptr = A->colptr;
+    sa.n = (int32_t)A->n;
+    sa.x_idx = x_idx;
+    sa.x_val = x_val;
+    sa.xmode = xmode;
+    sa.f_host = (int32_t)f_host;
+    sa.f_dev = f_dev;
+    sa.ctrl = A->ctrl;
+    sa.cstart = A->cstart;
+    sa.coff = A->coff;
+    sa.cxv = A->cxv;
+    sa.chunk_col = A->chunk_col;
+    sa.chunk_log2 = chunk_log2;
+    sa.lb1 = A->lb1;
+    sa.lb1_n = (int32_t)A->L.lb1_n;
+    sa.nnz = A->nnz;
+    sa.chunk_n = A->L.chunk_n;
+    sa.cursor = A->cursor;
+    sa.lb3 = A->lb3;
+    sa.nb = nb;
+    sa.bump_level = bfs ? 1 : 0;
+    int64_t g1 = (f_bound + kScanTile - 1) / kScanTile;
+    if (g1 < 1) g1 = 1;
+    if (g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;
+
+    ScatterArgs ca{};
+    ca.rowids = A->rowids;
+    ca.values = A->values;
+    ca.ctrl = A->ctrl;
+    ca.cstart = A->cstart;
+    ca.coff = A->coff;
+    ca.cxv = A->cxv;
+    ca.chunk_col = A->chunk_col;
+    ca.chunk_log2 = chunk_log2;
+    ca.tile_log2 = sc.tile_log2;
+    ca.nb = nb;
+    ca.m = (int32_t)A->m;
+    ca.rcp = A->rcp;
+    ca.cursor = A->cursor;
+    ca.buckets = A->buckets;
+    ca.mask = bfs ? A->visited : nullptr;
+    ca.lb1 = A->lb1;
+    ca.lb1_n = (int32_t)A->L.lb1_n;
+    ca.lb1_clear = (int32_t)((f_bound + kScanTile - 1) / kScanTile + 1);
+    if (ca.lb1_clear > ca.lb1_n) ca.lb1_clear = ca.lb1_n;
+    ca.f_host = (int32_t)f_host;
+    ca.f_dev = f_dev;
+    int64_t wbound = f_dev ? A->nnz : f_host * (int64_t)A->maxdeg;
+    if (wbound > A->nnz) wbound = A->nnz;
+    int64_t g2 = (wbound + chunk - 1) / chunk;
+    if (g2 < 1) g2 = 1;
+    if (g2 > 8 * A->num_cu) g2 = 8 * A->num_cu;
+
+    MergeArgs ma{};
+    ma.ctrl = A->ctrl;
+    ma.cursor = A->cursor;
+    ma.buckets = A->buckets;
+    ma.rcp = A->rcp;
+    ma.m = (int32_t)A->m;
+    ma.tile_log2 = sc.tile_log2;
+    ma.nb = nb;
+    ma.lb3 = A->lb3;
+    ma.y_idx = y_idx;
+    ma.y_val = y_val;
+    ma.y_cap = y_cap;
+    ma.d_nnz_y = d_nnz_y;
+    ma.visited = A->visited;
+    ma.level = level;
+    ma.parent = parent;
+    ma.set_f = bfs ? 1 : 0;
+
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_scan(sa, (int)g1, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(launch_merge(ma, semiring, sc.merge_block, sorted, bfs, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return SPMSPV_OK;
+}
+
+hipEvent_t* profile_slot(spmspv_matrix* A) {
+    if (A->prof_ev.empty()) {
+        A->prof_ev.resize(size_t(kProfileSlots) * 4);
+        for (auto& e : A->prof_ev)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    }
+    if (A->prof_used >= kProfileSlots) return nullptr;
+    return &A->prof_ev[size_t(A->prof_used++) * 4];
+}
+
+int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SPMSPV_OK;
+}
+
+int clear_err(spmspv_matrix* A, hipStream_t s) {
+    HIP_TRY(launch_fill_u32(&A->ctrl->err, 0u, 1, s));
+    return SPMSPV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spmspv_status_string(int status) {
+    switch (status) {
+        case SPMSPV_OK: return "ok";
+        case SPMSPV_EINVAL: return "invalid argument or input";
+        case SPMSPV_ENOMEM: return "workspace too small";
+        case SPMSPV_ECAPACITY: return "output capacity too small";
+        case SPMSPV_EHIP: return "HIP runtime error";
+        case SPMSPV_EUNSUPPORTED: return "unsupported request";
+        case SPMSPV_EDEVICE: return "device reported an error";
+        default: return "unknown status";
+    }
+}
+
+const char* spmspv_last_error(void) { return g_last_error.c_str(); }
+
+int spmspv_workspace_size(int64_t m, int64_t n, int64_t nnz, int flags, size_t* h_bytes) {
+    (void)flags;
+    if (!h_bytes) return fail(SPMSPV_EINVAL, "h_bytes is NULL");
+    if (m < 1 || n < 1 || nnz < 0 || nnz >= (int64_t(1) << 31) || m >= (int64_t(1) << 31) ||
+        n >= (int64_t(1) << 31))
+        return fail(SPMSPV_EINVAL, "sizes out of range (need 1 <= m, n < 2^31, 0 <= nnz < 2^31)");
+    *h_bytes = make_layout(m, n, nnz).total;
+    return SPMSPV_OK;
+}
+
+int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes, int flags,
+                  void* stream) {
+    if (!h_out) return fail(SPMSPV_EINVAL, "h_out is NULL");
+    *h_out = nullptr;
+    size_t need = 0;
+    int rc = spmspv_workspace_size(m, n, nnz, flags, &need);
+    if (rc) return rc;
+    if (!colptr || (nnz > 0 && !rowids) || !workspace) return fail(SPMSPV_EINVAL, "NULL matrix or workspace");
+    if (ws_bytes < need) return fail(SPMSPV_ENOMEM, "workspace smaller than spmspv_workspace_size");
+    if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+        return fail(SPMSPV_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    auto* A = new spmspv_matrix();
+    A->m = m;
+    A->n = n;
+    A->nnz = nnz;
+    A->colptr = colptr;
+    A->rowids = rowids;
+    A->values = values;
+    A->L = make_layout(m, n, nnz);
+    A->ws = static_cast<char*>(workspace);
+    const Layout& L = A->L;
+    A->ctrl = reinterpret_cast<Ctrl*>(A->ws + L.ctrl);
+    A->rcp = reinterpret_cast<int32_t*>(A->ws + L.rcp);
+    A->cstart = reinterpret_cast<int32_t*>(A->ws + L.cstart);
+    A->coff = reinterpret_cast<int32_t*>(A->ws + L.coff);
+    A->cxv = reinterpret_cast<uint32_t*>(A->ws + L.cxv);
+    A->chunk_col = reinterpret_cast<int32_t*>(A->ws + L.chunk_col);
+    A->lb1 = reinterpret_cast<uint64_t*>(A->ws + L.lb1);
+    A->cursor = reinterpret_cast<int32_t*>(A->ws + L.cursor);
+    A->lb3 = reinterpret_cast<uint64_t*>(A->ws + L.lb3);
+    A->buckets = reinterpret_cast<uint2*>(A->ws + L.buckets);
+    A->visited = reinterpret_cast<uint32_t*>(A->ws + L.visited);
+    A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
+    A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
+
+    auto bail = [&](int status) {
+        delete A;
+        return status;
+    };
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, A->device) == hipSuccess && v > 0)
+        A->num_cu = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, A->device) == hipSuccess && v > 0)
+        A->lds_max = (size_t)v;
+    if (A->lds_max > 65536) A->lds_max = 65536;
+
+    // Zero the control block and the per-call look-back / counter state.
+    const size_t zero_end = L.buckets;
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws), 0u, int64_t(zero_end / 4), s)) != hipSuccess)
+        return bail(hip_fail(e, "zero workspace"));
+    if ((e = launch_validate_colptr(colptr, (int32_t)n, nnz, A->ctrl, s)) != hipSuccess)
+        return bail(hip_fail(e, "validate colptr"));
+    if ((e = launch_row_counts(rowids, nnz, (int32_t)m, A->rcp, A->ctrl, s)) != hipSuccess)
+        return bail(hip_fail(e, "row counts"));
+    if ((e = launch_exclusive_scan_i32(A->rcp, m + 1, reinterpret_cast<int32_t*>(A->ws + L.partials), s)) !=
+        hipSuccess)
+        return bail(hip_fail(e, "row count scan"));
+    Ctrl h{};
+    if ((e = hipMemcpyAsync(&h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return bail(hip_fail(e, "read control block"));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "create sync"));
+    if (h.err & (ERR_CSC | ERR_ROW_RANGE)) {
+        if (flags & SPMSPV_VALIDATE) return bail(fail(SPMSPV_EINVAL, "invalid CSC (colptr or row ids)"));
+        // Without validation an invalid matrix is still refused: bucket
+        // sizing depends on it.
+        return bail(fail(SPMSPV_EINVAL, "invalid CSC detected while sizing buckets"));
+    }
+    A->maxdeg = h.maxdeg;
+    default_schedule(A, &A->sched);
+    if (check_schedule(A, &A->sched) != SPMSPV_OK)
+        return bail(fail(SPMSPV_EUNSUPPORTED, "matrix too tall for the LDS bucket layout"));
+    *h_out = A;
+    return SPMSPV_OK;
+}
+
+int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched) {
+    if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    *h_sched = A->sched;
+    return SPMSPV_OK;
+}
+
+int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    spmspv_schedule s{};
+    if (h_sched) s = *h_sched;
+    else default_schedule(A, &s);
+    const int rc = check_schedule(A, &s);
+    if (rc) return rc;
+    A->sched = s;
+    if (A->graph) {
+        (void)hipGraphExecDestroy(A->graph);
+        A->graph = nullptr;
+        A->graph_key = -1;
+    }
+    return SPMSPV_OK;
+}
+
+int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx, const void* x_val,
+               int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y, void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    if (f > 0 && !x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
+    if (y_capacity < 0 || (y_capacity > 0 && !y_idx)) return fail(SPMSPV_EINVAL, "bad y buffer");
+    int xmode = XV_BITS32;
+    if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
+    else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
+    if (f > 0 && !x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    if (flags & SPMSPV_VALIDATE) {
+        std::vector<int32_t> hx((size_t)f);
+        if (f) HIP_TRY(hipMemcpyAsync(hx.data(), x_idx, size_t(f) * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<uint8_t> seen((size_t)A->n, 0);
+        for (int64_t p = 0; p < f; ++p) {
+            const int32_t j = hx[(size_t)p];
+            if (j < 0 || j >= A->n) return fail(SPMSPV_EINVAL, "x index out of range");
+            if (seen[(size_t)j]) return fail(SPMSPV_EINVAL, "duplicate x index");
+            seen[(size_t)j] = 1;
+        }
+    }
+    hipEvent_t* ev = (flags & SPMSPV_PROFILE) ? profile_slot(A) : nullptr;
+    int rc = enqueue(A, semiring, xmode, (flags & SPMSPV_SORTED_OUTPUT) != 0, f, nullptr, x_idx, x_val, y_idx, y_val,
+                     y_capacity, d_nnz_y, false, nullptr, nullptr, s, ev);
+    if (rc) return rc;
+    if (h_nnz_y) {
+        Ctrl h{};
+        rc = read_ctrl(A, &h, s);
+        if (rc) return rc;
+        *h_nnz_y = h.nnz_y;
+        if (h.err) {
+            clear_err(A, s);
+            return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
+                                            " (1 = x index range, 2 = duplicate x index, 4 = look-back bound)");
+        }
+        if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
+    }
+    return SPMSPV_OK;
+}
+
+int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* level, int32_t* parent,
+            int32_t* h_num_levels, void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (A->m != A->n) return fail(SPMSPV_EINVAL, "BFS needs a square matrix");
+    if (semiring != SR_MIN_SELECT2ND && semiring != SR_OR_AND)
+        return fail(SPMSPV_EINVAL, "BFS semiring must be MIN_SELECT2ND_I32 or OR_AND_BOOL");
+    if (semiring == SR_OR_AND && parent) return fail(SPMSPV_EINVAL, "OR_AND BFS has no parents");
+    if (!level) return fail(SPMSPV_EINVAL, "level is NULL");
+    if (root < 0 || root >= A->n) return fail(SPMSPV_EINVAL, "root out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
+    const bool sorted = true;
+
+
+    auto enqueue_levels = [&](int count) -> int {
+        for (int l = 0; l < count; ++l) {
+            int32_t* x = A->front[l & 1];
+            int32_t* y = A->front[(l + 1) & 1];
+            const int rc = enqueue(A, semiring, xmode, sorted, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr,
+                                   true, level, parent, s, nullptr);
+            if (rc) return rc;
+        }
+        return SPMSPV_OK;
+    };
+
+    const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
+    const int key = semiring * 4 + (parent ? 2 : 0) + 1;
+    if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
+        if (A->graph) {
+            (void)hipGraphExecDestroy(A->graph);
+            A->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_levels(kGraphLevels);
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&A->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            A->graph = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        A->graph_key = key;
+    }
+    HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, s));
+    // Level loop: kGraphLevels levels per batch, then one host check of the
+    // frontier length.  Levels after the frontier empties are no-ops.
+    int32_t hf = 1;
+    for (int64_t batch = 0; hf > 0; ++batch) {
+        if (batch * kGraphLevels > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+        if (use_graph) HIP_TRY(hipGraphLaunch(A->graph, s));
+        else {
+            const int rc = enqueue_levels(kGraphLevels);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    Ctrl h{};
+    int rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    if (h.err) {
+        clear_err(A, s);
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (h_num_levels) *h_num_levels = h.level;
+    return SPMSPV_OK;
+}
+
+int spmspv_last_stats(spmspv_handle A, int64_t* h_out, void* stream) {
+    if (!A || !h_out) return fail(SPMSPV_EINVAL, "NULL argument");
+    Ctrl h{};
+    const int rc = read_ctrl(A, &h, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    h_out[0] = h.W_last;
+    h_out[1] = h.nnz_y;
+    h_out[2] = h.fnz_last;
+    h_out[3] = h.maxlen_last;
+    h_out[4] = h.err;
+    return SPMSPV_OK;
+}
+
+int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls) {
+    if (!A || !h_ms || !h_calls) return fail(SPMSPV_EINVAL, "NULL argument");
+    h_ms[0] = h_ms[1] = h_ms[2] = 0.0;
+    for (int c = 0; c < A->prof_used; ++c) {
+        hipEvent_t* ev = &A->prof_ev[size_t(c) * 4];
+        HIP_TRY(hipEventSynchronize(ev[3]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            h_ms[k] += ms;
+        }
+    }
+    *h_calls = A->prof_used;
+    A->prof_used = 0;
+    return SPMSPV_OK;
+}
+
+int spmspv_destroy(spmspv_handle A) {
+    if (!A) return SPMSPV_OK;
+    for (auto& e : A->prof_ev) (void)hipEventDestroy(e);
+    if (A->graph) (void)hipGraphExecDestroy(A->graph);
+    delete A;
+    return SPMSPV_OK;
+}
+
+}  // extern "C"

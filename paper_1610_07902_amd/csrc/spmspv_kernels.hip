@@ -1,0 +1,673 @@
+// Hot-path kernels of SpMSpV-bucket for gfx950 (CDNA4, wave64).
+//
+// One y <- A x is three launches on one stream:
+//   k_scan    (step a) gathers the selected columns' [colptr[j], colptr[j+1])
+//             ranges, prefix-sums their lengths with a single-pass
+//             decoupled look-back scan, compacts the non-empty columns and
+//             records the first column of every fixed-size product chunk.
+//             This is the exact work estimate of Algorithm 2
+//             (Estimate-Buckets): W = sum of selected column lengths.
+//   k_scatter (step b) walks the W products in equal chunks (merge-path
+//             over nonzeros: every workgroup gets the same number of
+//             products however the column lengths vary), reads row ids and
+//             values coalesced, applies Mult, and appends (row, value) to
+//             the row-range bucket of the row (Algorithm 1, step 1).  Bucket
+//             counts of the chunk are kept in LDS; each bucket's slot range
+//             is reserved with one atomic per (chunk, bucket), which plays
+//             the role of Algorithm 2's per-thread Boffset prefix.
+//   k_merge   (steps c, d) gives each bucket one workgroup and an LDS-resident
+//             sparse accumulator over the bucket's rows.  First touch of a
+//             row is found with an LDS atomic on a row bitmap and counted by
+//             wavefront ballot; only touched accumulator cells are
+//             initialised (Algorithm 1, step 2).  The per-bucket unique
+//             counts are prefix-summed across workgroups by decoupled
+//             look-back, and each workgroup writes its rows straight to y
+//             (Algorithm 1, step 3), ascending when sorted output is asked
+//             for (walk of the row bitmap in order).
+//
+// Bucket storage: bucket k covers rows [k*T, (k+1)*T) with T = 2^tile_log2.
+// Its slots start at rcp[k*T], the number of stored entries of A in rows
+// before k*T, and it has rcp[(k+1)*T] - rcp[k*T] slots.  With distinct x
+// indices each product (i, j) is a distinct stored entry of A, so a bucket
+// never receives more entries than its rows hold: total bucket space is
+// nnz(A), the bound of "Performance optimizations / Memory allocation".
+
+#include "internal.h"
+
+namespace spv {
+
+namespace {
+
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+constexpr int kSpinMax = 1 << 20;
+
+__device__ __forceinline__ uint64_t ld_acquire64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Decoupled look-back over per-tile state words (status in bits 63:62,
+// value in 61:0).  Called by all 64 lanes of one wave.  Publishes `agg` for
+// `tile`, returns the exclusive prefix and publishes the inclusive one.
+// A wait that exceeds kSpinMax polls sets ERR_SPIN and returns a partial
+// prefix rather than hanging.
+__device__ uint64_t lookback(uint64_t* st, int tile, uint64_t agg, uint32_t* err) {
+    const int lane = threadIdx.x & (kWave - 1);
+    if (tile == 0) {
+        if (lane == 0) st_release64(&st[0], LB_INC | (agg & LB_VAL));
+        return 0;
+    }
+    if (lane == 0) st_release64(&st[tile], LB_AGG | (agg & LB_VAL));
+    uint64_t excl = 0;
+    int base = tile - 1;
+    int spins = 0;
+    for (;;) {
+        const int idx = base - lane;
+        const uint64_t w = idx >= 0 ? ld_acquire64(&st[idx]) : LB_INC;
+        const uint64_t status = w >> 62;
+        const uint64_t inc_mask = __ballot(status == 2);
+        const uint64_t empty_mask = __ballot(status == 0);
+        const uint64_t need = inc_mask ? (((inc_mask & (~inc_mask + 1)) << 1) - 1) : ~0ull;
+        if (empty_mask & need) {
+            if (++spins > kSpinMax) {
+                if (lane == 0) atomicOr(err, ERR_SPIN);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        const uint64_t v = ((need >> lane) & 1ull) ? (w & LB_VAL) : 0ull;
+        excl += wave_sum_u64(v);
+        if (inc_mask) break;
+        base -= kWave;
+    }
+    if (lane == 0) st_release64(&st[tile], LB_INC | ((excl + agg) & LB_VAL));
+    return excl;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* s_tmp, uint64_t& total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) s_tmp[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (int w = 0; w < BLOCK / kWave; ++w) {
+            const uint64_t t = s_tmp[w];
+            s_tmp[w] = acc;
+            acc += t;
+        }
+        s_tmp[BLOCK / kWave] = acc;
+    }
+    __syncthreads();
+    const uint64_t r = s_tmp[wid] + x - v;
+    total = s_tmp[BLOCK / kWave];
+    __syncthreads();
+    return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ int block_exclusive_i32(int v, int* s_tmp, int& total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) s_tmp[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < BLOCK / kWave; ++w) {
+            const int t = s_tmp[w];
+            s_tmp[w] = acc;
+            acc += t;
+        }
+        s_tmp[BLOCK / kWave] = acc;
+    }
+    __syncthreads();
+    const int r = s_tmp[wid] + x - v;
+    total = s_tmp[BLOCK / kWave];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ step (a)
+// Two look-back chains per tile, one for the product count (sum of column
+// lengths) and one for the number of non-empty columns, each with a 62-bit
+// value: no input, valid or not, can make one overflow into the other.
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
+    constexpr int TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_tmp[BLOCK / kWave + 1];
+    __shared__ int s_tile;
+    __shared__ uint64_t s_excl_sum, s_excl_cnt;
+    __shared__ int s_max;
+    const int tid = threadIdx.x;
+    const int f = a.f_dev ? *a.f_dev : a.f_host;
+    uint64_t* lb_sum = a.lb1;
+    uint64_t* lb_cnt = a.lb1 + a.lb1_n;
+
+    // Clear the scatter counters and merge look-back words of this call.
+    for (int i = blockIdx.x * BLOCK + tid; i < a.nb; i += gridDim.x * BLOCK) {
+        a.cursor[i] = 0;
+        a.lb3[i] = 0;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        a.ctrl->ticket_merge = 0;
+        if (a.bump_level && f > 0) a.ctrl->level += 1;
+        if (f <= 0) {
+            a.ctrl->W = 0;
+            a.ctrl->fnz = 0;
+            a.coff[0] = 0;
+        }
+    }
+    if (tid == 0) s_max = 0;
+    const int ntiles = (f + TILE - 1) / TILE;
+    const int64_t chunk = 1ll << a.chunk_log2;
+    int lmax = 0;
+    for (;;) {
+        if (tid == 0) s_tile = (int)atomicAdd(&a.ctrl->ticket_scan, 1u);
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile >= ntiles) break;
+        const int p0 = tile * TILE + tid * ITEMS;
+        int32_t st[ITEMS], ln[ITEMS];
+        uint32_t xv[ITEMS];
+        uint64_t lsum = 0, lcnt = 0;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int p = p0 + i;
+            ln[i] = 0;
+            st[i] = 0;
+            xv[i] = 0;
+            if (p < f) {
+                const int32_t j = a.x_idx[p];
+                if (j >= 0 && j < a.n) {
+                    st[i] = a.colptr[j];
+                    ln[i] = a.colptr[j + 1] - st[i];
+                } else {
+                    atomicOr(&a.ctrl->err, ERR_X_RANGE);
+                }
+                switch (a.xmode) {
+                    case XV_BITS32: xv[i] = reinterpret_cast<const uint32_t*>(a.x_val)[p]; break;
+                    case XV_INDEX: xv[i] = (uint32_t)j; break;
+                    case XV_U8: xv[i] = reinterpret_cast<const uint8_t*>(a.x_val)[p] ? 1u : 0u; break;
+                    default: xv[i] = 1u; break;
+                }
+            }
+            lmax = max(lmax, ln[i]);
+            lsum += (uint64_t)ln[i];
+            lcnt += ln[i] > 0 ? 1u : 0u;
+        }
+        uint64_t tile_sum, tile_cnt;
+        const uint64_t tex_sum = block_exclusive_u64<BLOCK>(lsum, s_tmp, tile_sum);
+        const uint64_t tex_cnt = block_exclusive_u64<BLOCK>(lcnt, s_tmp, tile_cnt);
+        if (tid < kWave) {
+            const uint64_t es = lookback(lb_sum, tile, tile_sum, &a.ctrl->err);
+            const uint64_t ec = lookback(lb_cnt, tile, tile_cnt, &a.ctrl->err);
+            if (tid == 0) {
+                s_excl_sum = es;
+                s_excl_cnt = ec;
+            }
+        }
+        __syncthreads();
+        uint64_t off = s_excl_sum + tex_sum;
+        uint64_t c = s_excl_cnt + tex_cnt;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (ln[i] > 0) {
+                a.cstart[c] = st[i];
+                a.coff[c] = (int32_t)off;   // exact whenever the total is valid (<= nnz)
+                a.cxv[c] = xv[i];
+                for (int64_t k = ((int64_t)off + chunk - 1) >> a.chunk_log2;
+                     (k << a.chunk_log2) < (int64_t)off + ln[i] && k < a.chunk_n; ++k)
+                    a.chunk_col[k] = (int32_t)c;
+                off += (uint64_t)ln[i];
+                c += 1;
+            }
+        }
+        if (tile == ntiles - 1 && tid == BLOCK - 1) {
+            if (off > (uint64_t)a.nnz) {
+                // More products than stored entries: x has duplicate indices.
+                atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                a.ctrl->W = 0;
+                a.ctrl->fnz = 0;
+                a.coff[0] = 0;
+            } else {
+                a.ctrl->W = (int32_t)off;
+                a.ctrl->fnz = (int32_t)c;
+                a.coff[c] = (int32_t)off;
+            }
+        }
+        __syncthreads();
+    }
+    atomicMax(&s_max, lmax);
+    __syncthreads();
+    if (tid == 0 && s_max > 0) atomicMax(&a.ctrl->maxlen, s_max);
+}
+
+// ------------------------------------------------------------------ step (b)
+template <int SR>
+__device__ __forceinline__ uint32_t mult(const float* values, int32_t q, uint32_t xbits) {
+    if constexpr (SR == SR_PLUS_TIMES) {
+        const float av = values ? values[q] : 1.0f;
+        return __float_as_uint(__fmul_rn(av, __uint_as_float(xbits)));
+    } else if constexpr (SR == SR_MIN_SELECT2ND) {
+        return xbits;
+    } else {
+        const uint32_t av = values ? (values[q] != 0.0f ? 1u : 0u) : 1u;
+        return av & (xbits != 0u ? 1u : 0u);
+    }
+}
+
+template <int BLOCK, int ITEMS, int SR>
+__global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
+    constexpr int C = BLOCK * ITEMS;
+    extern __shared__ int32_t lds_scatter[];
+    int32_t* hist = lds_scatter;                               // [nb]
+    int32_t* s_off = hist + a.nb;                      // [C+1]
+    int32_t* s_start = s_off + (C + 1);                // [C+1]
+    uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));  // [C+1]
+    const int tid = threadIdx.x;
+
+    if (blockIdx.x == 0 && tid == 0) {
+        a.ctrl->ticket_scan = 0;
+        a.ctrl->maxlen_last = a.ctrl->maxlen;
+        a.ctrl->maxlen = 0;
+        a.ctrl->fnz_last = a.ctrl->fnz;
+        a.ctrl->W_last = a.ctrl->W;
+    }
+    for (int i = blockIdx.x * BLOCK + tid; i < a.lb1_clear; i += gridDim.x * BLOCK) {
+        a.lb1[i] = 0;
+        a.lb1[a.lb1_n + i] = 0;
+    }
+
+    const int W = a.ctrl->W;
+    const int fnz = a.ctrl->fnz;
+    const int nchunks = (int)(((int64_t)W + C - 1) / C);
+    if ((int)blockIdx.x >= nchunks) return;
+
+    for (int i = tid; i < a.nb; i += BLOCK) hist[i] = 0;
+    const int tl = a.tile_log2;
+
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int q0 = c * C;
+        const int cnt = min(C, W - q0);
+        const int p0 = a.chunk_col[c];
+        const int pend = (c + 1 < nchunks) ? a.chunk_col[c + 1] : fnz - 1;
+        const int ncols = pend - p0 + 1;
+        __syncthreads();  // previous chunk finished with the column arrays and hist
+        for (int k = tid; k < ncols; k += BLOCK) {
+            s_off[k] = a.coff[p0 + k] - q0;
+            s_start[k] = a.cstart[p0 + k];
+            s_xv[k] = a.cxv[p0 + k];
+        }
+        __syncthreads();
+
+        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS];
+        uint32_t val[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int rq = i * BLOCK + tid;
+            bk[i] = -1;
+            rank[i] = 0;
+            row[i] = 0;
+            val[i] = 0;
+            if (rq < cnt) {
+                int lo = 0, hi = ncols - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= rq) lo = mid; else hi = mid - 1;
+                }
+                const int32_t q = s_start[lo] + (rq - s_off[lo]);
+                const int32_t r = a.rowids[q];
+                row[i] = r;
+                val[i] = mult<SR>(a.values, q, s_xv[lo]);
+                bool keep = true;
+                if (a.mask) keep = ((a.mask[r >> 5] >> (r & 31)) & 1u) == 0u;
+                if (keep) {
+                    bk[i] = r >> tl;
+                    rank[i] = atomicAdd(&hist[bk[i]], 1);
+                }
+            }
+        }
+        __syncthreads();
+        // One slot-range reservation per (chunk, bucket): the first entry of
+        // each bucket in this chunk reserves hist[k] slots.
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (bk[i] >= 0 && rank[i] == 0) {
+                const int k = bk[i];
+                const int n = hist[k];
+                const int r0 = k << tl;
+                const int base = a.rcp[r0];
+                const int cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
+                const int g = atomicAdd(&a.cursor[k], n);
+                if (g + n > cap) {
+                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                    hist[k] = -1;
+                } else {
+                    hist[k] = base + g;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (bk[i] >= 0) {
+                const int pos = hist[bk[i]];
+                if (pos >= 0) a.buckets[pos + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (bk[i] >= 0 && rank[i] == 0) hist[bk[i]] = 0;
+    }
+}
+
+// ---------------------------------------------------------------- steps (c, d)
+template <int SR>
+__device__ __forceinline__ uint32_t identity() {
+    if constexpr (SR == SR_PLUS_TIMES) return 0u;            // +0.0f
+    else if constexpr (SR == SR_MIN_SELECT2ND) return 0x7fffffffu;
+    else return 0u;
+}
+
+template <int SR>
+__device__ __forceinline__ void accumulate(uint32_t* cell, uint32_t v) {
+    if constexpr (SR == SR_PLUS_TIMES) atomicAdd(reinterpret_cast<float*>(cell), __uint_as_float(v));
+    else if constexpr (SR == SR_MIN_SELECT2ND) atomicMin(reinterpret_cast<int*>(cell), (int)v);
+    else atomicOr(cell, v);
+}
+
+template <int SR>
+__device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) {
+    if constexpr (SR == SR_OR_AND) reinterpret_cast<uint8_t*>(y_val)[o] = (uint8_t)(v != 0u);
+    else reinterpret_cast<uint32_t*>(y_val)[o] = v;
+}
+
+template <int BLOCK, int ITEMS, int SR, bool SORTED, bool BFS>
+__global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
+    extern __shared__ uint32_t lds_merge[];
+    const int tl = a.tile_log2;
+    const int T = 1 << tl;
+    uint32_t* spa = lds_merge;                                   // [T] accumulator
+    uint32_t* bm = spa + T;                                // [T/32] touched rows
+    uint16_t* uind = reinterpret_cast<uint16_t*>(bm + (T >> 5));  // [T] unique rows (unsorted)
+    __shared__ int s_b, s_ucnt;
+    __shared__ int64_t s_excl;
+    __shared__ int s_tmp[BLOCK / kWave + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+
+    if (tid == 0) {
+        s_b = (int)atomicAdd(&a.ctrl->ticket_merge, 1u);
+        s_ucnt = 0;
+    }
+    __syncthreads();
+    const int b = s_b;
+    const int W = a.ctrl->W;
+    if (W == 0) {
+        // Nothing was multiplied: y is empty.
+        if (b == a.nb - 1 && tid == 0) {
+            a.ctrl->nnz_y = 0;
+            if (a.d_nnz_y) *a.d_nnz_y = 0;
+            if (a.set_f) a.ctrl->f = 0;
+        }
+        return;
+    }
+    const int row0 = b << tl;
+    const int rows = min(T, a.m - row0);
+    const int cnt_raw = a.cursor[b];
+    if (cnt_raw == 0 && b != a.nb - 1) {
+        if (tid == 0) st_release64(&a.lb3[b], (b == 0 ? LB_INC : LB_AGG));
+        return;
+    }
+    const int base = a.rcp[row0];
+    // Entries beyond the bucket's slot count only exist after an overflow
+    // (duplicate x indices); never read past the bucket.
+    const int cnt = min(cnt_raw, a.rcp[min(row0 + T, a.m)] - base);
+    const int nw = (rows + 31) >> 5;
+    for (int w = tid; w < nw; w += BLOCK) bm[w] = 0u;
+
+    if (cnt <= BLOCK * ITEMS) {
+        // Entries fit in registers: initialise only the touched cells, then
+        // accumulate (two passes over registers, Algorithm 1 step 2).
+        uint32_t rr[ITEMS], vv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int e = i * BLOCK + tid;
+            rr[i] = 0xffffffffu;
+            vv[i] = 0u;
+            if (e < cnt) {
+                const uint2 ent = a.buckets[base + e];
+                rr[i] = ent.x - (uint32_t)row0;
+                vv[i] = ent.y;
+                if (rr[i] >= (uint32_t)rows) {  // unwritten slot after an overflow
+                    rr[i] = 0xffffffffu;
+                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            bool first = false;
+            if (rr[i] != 0xffffffffu) {
+                const uint32_t bit = 1u << (rr[i] & 31u);
+                const uint32_t old = atomicOr(&bm[rr[i] >> 5], bit);
+                first = (old & bit) == 0u;
+                if (first) spa[rr[i]] = identity<SR>();
+            }
+            const uint64_t fm = __ballot(first);
+            if (fm) {
+                int wbase = 0;
+                if (lane == 0) wbase = atomicAdd(&s_ucnt, (int)__popcll(fm));
+                wbase = __shfl(wbase, 0, kWave);
+                if (!SORTED && first) uind[wbase + (int)lanes_below(fm)] = (uint16_t)rr[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (rr[i] != 0xffffffffu) accumulate<SR>(&spa[rr[i]], vv[i]);
+    } else {
+        // Large bucket: initialise the whole tile once, then one streaming
+        // pass does first-touch detection and accumulation together.
+        for (int r = tid; r < rows; r += BLOCK) spa[r] = identity<SR>();
+        __syncthreads();
+        for (int e0 = 0; e0 < cnt; e0 += BLOCK) {
+            const int e = e0 + tid;
+            bool first = false;
+            uint32_t r = 0, v = 0;
+            bool valid = e < cnt;
+            if (valid) {
+                const uint2 ent = a.buckets[base + e];
+                r = ent.x - (uint32_t)row0;
+                v = ent.y;
+                if (r >= (uint32_t)rows) {  // unwritten slot after an overflow
+                    valid = false;
+                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                }
+            }
+            if (valid) {
+                const uint32_t bit = 1u << (r & 31u);
+                const uint32_t old = atomicOr(&bm[r >> 5], bit);
+                first = (old & bit) == 0u;
+            }
+            const uint64_t fm = __ballot(first);
+            if (fm) {
+                int wbase = 0;
+                if (lane == 0) wbase = atomicAdd(&s_ucnt, (int)__popcll(fm));
+                wbase = __shfl(wbase, 0, kWave);
+                if (!SORTED && first) uind[wbase + (int)lanes_below(fm)] = (uint16_t)r;
+            }
+            if (valid) accumulate<SR>(&spa[r], v);
+        }
+    }
+    __syncthreads();
+    const int ucnt = s_ucnt;
+    if (tid < kWave) {
+        const uint64_t e = lookback(a.lb3, b, (uint64_t)ucnt, &a.ctrl->err);
+        if (tid == 0) {
+            s_excl = (int64_t)e;
+            if (b == a.nb - 1) {
+                const int64_t total = (int64_t)e + ucnt;
+                a.ctrl->nnz_y = total;
+                if (a.d_nnz_y) *a.d_nnz_y = total;
+                if (a.set_f) a.ctrl->f = (int32_t)total;
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t excl = s_excl;
+    const int lvl = BFS ? a.ctrl->level : 0;
+
+    if constexpr (SORTED) {
+        int carry = 0;
+        for (int w0 = 0; w0 < nw; w0 += BLOCK) {
+            const int w = w0 + tid;
+            uint32_t bits = w < nw ? bm[w] : 0u;
+            int tot;
+            const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
+            if (BFS && w < nw && bits) a.visited[(row0 >> 5) + w] |= bits;
+            int k = 0;
+            while (bits) {
+                const int bitpos = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                const int r = (w << 5) + bitpos;
+                const int64_t o = excl + carry + pos + k;
+                ++k;
+                if (o < a.y_cap) {
+                    a.y_idx[o] = row0 + r;
+                    if (a.y_val) store_value<SR>(a.y_val, o, spa[r]);
+                }
+                if (BFS) {
+                    a.level[row0 + r] = lvl;
+                    if (a.parent) a.parent[row0 + r] = (int32_t)spa[r];
+                }
+            }
+            carry += tot;
+        }
+    } else {
+        for (int t = tid; t < ucnt; t += BLOCK) {
+            const int r = uind[t];
+            const int64_t o = excl + t;
+            if (o < a.y_cap) {
+                a.y_idx[o] = row0 + r;
+                if (a.y_val) store_value<SR>(a.y_val, o, spa[r]);
+            }
+            if (BFS) {
+                a.level[row0 + r] = lvl;
+                if (a.parent) a.parent[row0 + r] = (int32_t)spa[r];
+            }
+        }
+        if (BFS)
+            for (int w = tid; w < nw; w += BLOCK)
+                if (bm[w]) a.visited[(row0 >> 5) + w] |= bm[w];
+    }
+}
+
+}  // namespace
+
+size_t merge_lds_bytes(int tile_log2, bool sorted) {
+    const size_t T = size_t(1) << tile_log2;
+    return T * 4 + (T / 32) * 4 + (sorted ? 0 : T * 2);
+}
+
+size_t scatter_lds_bytes(int nb, int chunk) { return size_t(nb) * 4 + size_t(chunk + 1) * 12; }
+
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems>), dim3(grid), dim3(kScanBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int ITEMS>
+static hipError_t scatter_sr(const ScatterArgs& a, int semiring, int grid, hipStream_t s) {
+    const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS);
+    switch (semiring) {
+        case SR_PLUS_TIMES:
+            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_PLUS_TIMES>), dim3(grid), dim3(BLOCK), lds, s, a);
+            break;
+        case SR_MIN_SELECT2ND:
+            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_MIN_SELECT2ND>), dim3(grid), dim3(BLOCK), lds, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_OR_AND>), dim3(grid), dim3(BLOCK), lds, s, a);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
+    if (block == 256) {
+        if (items == 4) return scatter_sr<256, 4>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<256, 8>(a, semiring, grid, s);
+        if (items == 16) return scatter_sr<256, 16>(a, semiring, grid, s);
+    } else if (block == 512) {
+        if (items == 4) return scatter_sr<512, 4>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<512, 8>(a, semiring, grid, s);
+    } else if (block == 1024) {
+        if (items == 4) return scatter_sr<1024, 4>(a, semiring, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int BLOCK, int SR>
+static hipError_t merge_mode(const MergeArgs& a, bool sorted, bool bfs, hipStream_t s) {
+    const size_t lds = merge_lds_bytes(a.tile_log2, sorted);
+    const dim3 grid(a.nb), blk(BLOCK);
+    if (bfs) {
+        if constexpr (SR == SR_PLUS_TIMES) return hipErrorInvalidValue;
+        else {
+            if (sorted) hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, true, true>), grid, blk, lds, s, a);
+            else hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, false, true>), grid, blk, lds, s, a);
+        }
+    } else {
+        if (sorted) hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, true, false>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, false, false>), grid, blk, lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int BLOCK>
+static hipError_t merge_block(const MergeArgs& a, int semiring, bool sorted, bool bfs, hipStream_t s) {
+    switch (semiring) {
+        case SR_PLUS_TIMES: return merge_mode<BLOCK, SR_PLUS_TIMES>(a, sorted, bfs, s);
+        case SR_MIN_SELECT2ND: return merge_mode<BLOCK, SR_MIN_SELECT2ND>(a, sorted, bfs, s);
+        default: return merge_mode<BLOCK, SR_OR_AND>(a, sorted, bfs, s);
+    }
+}
+
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool sorted, bool bfs, hipStream_t s) {
+    if (block == 256) return merge_block<256>(a, semiring, sorted, bfs, s);
+    if (block == 512) return merge_block<512>(a, semiring, sorted, bfs, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace spv

@@ -1,0 +1,64 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spmspv.h")
+
+
+def _lib():
+    import paper_1610_07902_amd as spv
+    if not os.path.exists(spv.LIB_PATH):
+        pytest.skip("libspmspv.so not built")
+    return spv, spv.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|const char\*)\s+(\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("spmspv_create", "spmspv_run", "bfs_run", "spmspv_workspace_size", "spmspv_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    spv, lib = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", spv.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(spv.EXPORTED) <= exported
+
+
+def test_workspace_size_host_only():
+    spv, lib = _lib()
+    b1 = spv.spmspv_workspace_size(1000, 1000, 5000)
+    b2 = spv.spmspv_workspace_size(1000, 1000, 50000)
+    assert b2 - b1 >= 8 * 45000          # buckets hold nnz (row, value) pairs
+    with pytest.raises(spv.SpmspvError) as e:
+        spv.spmspv_workspace_size(0, 10, 10)
+    assert e.value.status == spv.EINVAL
+    with pytest.raises(spv.SpmspvError):
+        spv.spmspv_workspace_size(10, 10, 1 << 31)
+
+
+def test_null_arguments_rejected_without_gpu():
+    spv, lib = _lib()
+    h = ctypes.c_void_p(None)
+    rc = lib.spmspv_create(ctypes.byref(h), 10, 10, 5, None, None, None, None, 0, 0, None)
+    assert rc == spv.EINVAL and h.value is None
+    assert lib.spmspv_run(None, 0, 0, 0, None, None, None, None, 0, None, None, None) == spv.EINVAL
+    assert lib.bfs_run(None, 1, 0, 0, None, None, None, None) == spv.EINVAL
+    assert lib.spmspv_destroy(None) == spv.OK
+    assert lib.spmspv_status_string(spv.ECAPACITY).decode() == "output capacity too small"
+    assert lib.spmspv_last_error().decode() != ""
