@@ -39,7 +39,9 @@ struct alignas(256) Ctrl {
     int32_t maxdeg;         // longest column of A (create)
     int32_t fnz_last;
     int32_t W_last;
-    uint32_t pad[50];
+    int32_t* bfs_level;     // BFS output arrays, set by the BFS init kernel so a
+    int32_t* bfs_parent;    // captured level graph does not bake them in
+    uint32_t pad[46];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -68,6 +70,7 @@ struct ScanArgs {
     uint64_t* lb3;           // merge look-back words, cleared here
     int32_t nb;              // buckets of the current schedule
     int bump_level;          // BFS: advance ctrl->level when f > 0
+    int single_tile;         // each workgroup processes exactly one tile
 };
 
 // Scatter phase: products -> row-range buckets.
@@ -109,22 +112,22 @@ struct MergeArgs {
     int64_t y_cap;
     int64_t* d_nnz_y;        // nullable
     uint32_t* visited;       // BFS: visited bitmap, updated with new vertices
-    int32_t* level;          // BFS
-    int32_t* parent;         // BFS, nullable
     int set_f;               // BFS: publish nnz(y) as the next frontier length
 };
 
-size_t merge_lds_bytes(int tile_log2, bool sorted);
+size_t merge_lds_bytes(int tile_log2);
 size_t scatter_lds_bytes(int nb, int chunk);
+bool scatter_shape_supported(int block, int items);
 
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s);
 hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s);
-hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool sorted, bool bfs, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kMergeItems = 8;
+constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk
 
 // Set-up kernels (spmspv_create, bfs_run).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);

@@ -116,6 +116,8 @@ __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
         frontier[0] = root;
         ctrl->f = 1;
         ctrl->level = 0;
+        ctrl->bfs_level = level;
+        ctrl->bfs_parent = parent;
     }
 }
 

@@ -34,7 +34,7 @@ int hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 constexpr int kTileLog2Min = 8;
-constexpr int kTileLog2Max = 14;
+constexpr int kTileLog2Max = 15;
 constexpr int kChunkMin = 256;
 constexpr size_t kAlign = 256;
 constexpr int kProfileSlots = 1024;
@@ -116,36 +116,40 @@ struct spmspv_matrix {
     // BFS graph cache
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
 };
 
 namespace {
 
 int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
-    int tl = ceil_log2(A->m) - 10;
+    // Buckets as wide as LDS allows, but at least ~256 of them when the
+    // matrix is tall enough (one merge workgroup per bucket).
+    int tl = ceil_log2(A->m) - 8;
     if (tl < kTileLog2Min) tl = kTileLog2Min;
     if (tl > kTileLog2Max) tl = kTileLog2Max;
-    while (tl > kTileLog2Min && merge_lds_bytes(tl, false) + 1024 > A->lds_max) --tl;
+    while (tl > kTileLog2Min && merge_lds_bytes(tl) + 1024 > A->lds_max) --tl;
     s->direction = 0;
     s->tile_log2 = tl;
-    s->scatter_block = 256;
+    s->scatter_block = 1024;
     s->scatter_items = 8;
-    s->merge_block = 256;
+    s->merge_block = 1024;
     s->merge_variant = 0;
+    const int64_t nb = (A->m + (int64_t(1) << tl) - 1) >> tl;
+    if (scatter_lds_bytes((int)nb, 8192) + 1024 > A->lds_max) s->scatter_items = 4;
     return SPMSPV_OK;
 }
 
 int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
     if (s->direction != 0) return fail(SPMSPV_EUNSUPPORTED, "only the push direction is built");
     if (s->tile_log2 < kTileLog2Min || s->tile_log2 > kTileLog2Max)
-        return fail(SPMSPV_EINVAL, "tile_log2 out of [8, 14]");
+        return fail(SPMSPV_EINVAL, "tile_log2 out of [8, 15]");
     const int64_t nb = (A->m + (int64_t(1) << s->tile_log2) - 1) >> s->tile_log2;
     const int sb = s->scatter_block, si = s->scatter_items;
-    const bool ok_scatter = (sb == 256 && (si == 4 || si == 8 || si == 16)) || (sb == 512 && (si == 4 || si == 8)) ||
-                            (sb == 1024 && si == 4);
-    if (!ok_scatter) return fail(SPMSPV_EINVAL, "unsupported scatter_block / scatter_items pair");
-    if (s->merge_block != 256 && s->merge_block != 512) return fail(SPMSPV_EINVAL, "merge_block must be 256 or 512");
+    if (!scatter_shape_supported(sb, si)) return fail(SPMSPV_EINVAL, "unsupported scatter_block / scatter_items pair");
+    if (s->merge_block != 256 && s->merge_block != 512 && s->merge_block != 1024)
+        return fail(SPMSPV_EINVAL, "merge_block must be 256, 512 or 1024");
     if (s->merge_variant != 0) return fail(SPMSPV_EUNSUPPORTED, "only the LDS merge variant is built");
-    if (merge_lds_bytes(s->tile_log2, false) + 1024 > A->lds_max) return fail(SPMSPV_EINVAL, "tile exceeds LDS");
+    if (merge_lds_bytes(s->tile_log2) + 1024 > A->lds_max) return fail(SPMSPV_EINVAL, "tile exceeds LDS");
     if (scatter_lds_bytes((int)nb, sb * si) + 1024 > A->lds_max)
         return fail(SPMSPV_EINVAL, "too many buckets for the scatter LDS histogram");
     return SPMSPV_OK;
@@ -189,7 +193,10 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     sa.bump_level = bfs ? 1 : 0;
     int64_t g1 = (f_bound + kScanTile - 1) / kScanTile;
     if (g1 < 1) g1 = 1;
-    if (g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;
+    // f known on the host: one workgroup per tile, one ticket each.  f on
+    // the device (BFS): a fixed grid loops over tickets.
+    sa.single_tile = f_dev ? 0 : 1;
+    if (f_dev && g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;
 
     ScatterArgs ca{};
     ca.rowids = A->rowids;
@@ -217,7 +224,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     if (wbound > A->nnz) wbound = A->nnz;
     int64_t g2 = (wbound + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
-    if (g2 > 8 * A->num_cu) g2 = 8 * A->num_cu;
+    if (g2 > A->num_cu) g2 = A->num_cu;
 
     MergeArgs ma{};
     ma.ctrl = A->ctrl;
@@ -233,8 +240,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     ma.y_cap = y_cap;
     ma.d_nnz_y = d_nnz_y;
     ma.visited = A->visited;
-    ma.level = level;
-    ma.parent = parent;
+    (void)level;
+    (void)parent;
     ma.set_f = bfs ? 1 : 0;
 
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
@@ -242,7 +249,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_merge(ma, semiring, sc.merge_block, sorted, bfs, s));
+    HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return SPMSPV_OK;
 }
@@ -346,7 +353,6 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         A->num_cu = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, A->device) == hipSuccess && v > 0)
         A->lds_max = (size_t)v;
-    if (A->lds_max > 65536) A->lds_max = 65536;
 
     // Zero the control block and the per-call look-back / counter state.
     const size_t zero_end = L.buckets;
@@ -457,28 +463,31 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     const bool sorted = true;
 
 
-    auto enqueue_levels = [&](int count) -> int {
+    auto enqueue_levels = [&](int count, hipStream_t st) -> int {
         for (int l = 0; l < count; ++l) {
             int32_t* x = A->front[l & 1];
             int32_t* y = A->front[(l + 1) & 1];
             const int rc = enqueue(A, semiring, xmode, sorted, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr,
-                                   true, level, parent, s, nullptr);
+                                   true, level, parent, st, nullptr);
             if (rc) return rc;
         }
         return SPMSPV_OK;
     };
 
     const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
-    const int key = semiring * 4 + (parent ? 2 : 0) + 1;
+    const int key = semiring + 1;
     if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
         if (A->graph) {
             (void)hipGraphExecDestroy(A->graph);
             A->graph = nullptr;
         }
+        // Capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph is then launched on `s`.
+        if (!A->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&A->cap_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_levels(kGraphLevels);
-        hipError_t e = hipStreamEndCapture(s, &g);
+        HIP_TRY(hipStreamBeginCapture(A->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_levels(kGraphLevels, A->cap_stream);
+        hipError_t e = hipStreamEndCapture(A->cap_stream, &g);
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
             return rc;
@@ -500,7 +509,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         if (batch * kGraphLevels > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
         if (use_graph) HIP_TRY(hipGraphLaunch(A->graph, s));
         else {
-            const int rc = enqueue_levels(kGraphLevels);
+            const int rc = enqueue_levels(kGraphLevels, s);
             if (rc) return rc;
         }
         HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -551,6 +560,7 @@ int spmspv_destroy(spmspv_handle A) {
     if (!A) return SPMSPV_OK;
     for (auto& e : A->prof_ev) (void)hipEventDestroy(e);
     if (A->graph) (void)hipGraphExecDestroy(A->graph);
+    if (A->cap_stream) (void)hipStreamDestroy(A->cap_stream);
     delete A;
     return SPMSPV_OK;
 }

@@ -50,14 +50,26 @@ __device__ __forceinline__ void st_release64(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Control words written by an earlier kernel (plain stores or atomics) are
+// read with agent-scope atomic loads, never through the scalar cache.
+__device__ __forceinline__ int32_t ld_ctrl(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t* ld_ctrl_ptr(int32_t* const* p) {
+    return reinterpret_cast<int32_t*>(__hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_ctrl(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_ctrl_u(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
-}
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 // Decoupled look-back over per-tile state words (status in bits 63:62,
@@ -159,7 +171,15 @@ __device__ __forceinline__ int block_exclusive_i32(int v, int* s_tmp, int& total
 // Two look-back chains per tile, one for the product count (sum of column
 // lengths) and one for the number of non-empty columns, each with a 62-bit
 // value: no input, valid or not, can make one overflow into the other.
-template <int BLOCK, int ITEMS>
+template <int XMODE>
+__device__ __forceinline__ uint32_t x_value(const void* x_val, int p, int32_t j) {
+    if constexpr (XMODE == XV_BITS32) return reinterpret_cast<const uint32_t*>(x_val)[p];
+    else if constexpr (XMODE == XV_INDEX) return (uint32_t)j;
+    else if constexpr (XMODE == XV_U8) return reinterpret_cast<const uint8_t*>(x_val)[p] ? 1u : 0u;
+    else return 1u;
+}
+
+template <int BLOCK, int ITEMS, int XMODE>
 __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     constexpr int TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_tmp[BLOCK / kWave + 1];
@@ -167,7 +187,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     __shared__ uint64_t s_excl_sum, s_excl_cnt;
     __shared__ int s_max;
     const int tid = threadIdx.x;
-    const int f = a.f_dev ? *a.f_dev : a.f_host;
+    const int f = a.f_dev ? ld_ctrl(a.f_dev) : a.f_host;
     uint64_t* lb_sum = a.lb1;
     uint64_t* lb_cnt = a.lb1 + a.lb1_n;
 
@@ -177,11 +197,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         a.lb3[i] = 0;
     }
     if (blockIdx.x == 0 && tid == 0) {
-        a.ctrl->ticket_merge = 0;
-        if (a.bump_level && f > 0) a.ctrl->level += 1;
+        st_ctrl_u(&a.ctrl->ticket_merge, 0u);
+        if (a.bump_level && f > 0) st_ctrl(&a.ctrl->level, ld_ctrl(&a.ctrl->level) + 1);
         if (f <= 0) {
-            a.ctrl->W = 0;
-            a.ctrl->fnz = 0;
+            st_ctrl(&a.ctrl->W, 0);
+            st_ctrl(&a.ctrl->fnz, 0);
             a.coff[0] = 0;
         }
     }
@@ -212,12 +232,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
                 } else {
                     atomicOr(&a.ctrl->err, ERR_X_RANGE);
                 }
-                switch (a.xmode) {
-                    case XV_BITS32: xv[i] = reinterpret_cast<const uint32_t*>(a.x_val)[p]; break;
-                    case XV_INDEX: xv[i] = (uint32_t)j; break;
-                    case XV_U8: xv[i] = reinterpret_cast<const uint8_t*>(a.x_val)[p] ? 1u : 0u; break;
-                    default: xv[i] = 1u; break;
-                }
+                xv[i] = x_value<XMODE>(a.x_val, p, j);
             }
             lmax = max(lmax, ln[i]);
             lsum += (uint64_t)ln[i];
@@ -254,16 +269,17 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
             if (off > (uint64_t)a.nnz) {
                 // More products than stored entries: x has duplicate indices.
                 atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
-                a.ctrl->W = 0;
-                a.ctrl->fnz = 0;
+                st_ctrl(&a.ctrl->W, 0);
+                st_ctrl(&a.ctrl->fnz, 0);
                 a.coff[0] = 0;
             } else {
-                a.ctrl->W = (int32_t)off;
-                a.ctrl->fnz = (int32_t)c;
+                st_ctrl(&a.ctrl->W, (int32_t)off);
+                st_ctrl(&a.ctrl->fnz, (int32_t)c);
                 a.coff[c] = (int32_t)off;
             }
         }
         __syncthreads();
+        if (a.single_tile) break;
     }
     atomicMax(&s_max, lmax);
     __syncthreads();
@@ -284,34 +300,48 @@ __device__ __forceinline__ uint32_t mult(const float* values, int32_t q, uint32_
     }
 }
 
+// One workgroup turns chunks of C = BLOCK * ITEMS consecutive products into
+// bucket runs.  Per chunk: (1) each thread gathers ITEMS products (row id,
+// Mult value) and takes a rank in its bucket from an LDS histogram; (2) the
+// histogram is prefix-summed in LDS and every bucket touched by the chunk
+// reserves one slot range with a single global atomic; (3) the products are
+// counting-sorted by bucket into LDS (this private buffer is the thread-local
+// buffer of "Performance optimizations / Cache efficiency" on a workgroup
+// scale) and (4) streamed out so consecutive lanes write consecutive slots.
+// The LDS region holding the chunk's column table during (1) is reused as
+// the sort buffer in (3).
 template <int BLOCK, int ITEMS, int SR>
 __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     constexpr int C = BLOCK * ITEMS;
-    extern __shared__ int32_t lds_scatter[];
-    int32_t* hist = lds_scatter;                               // [nb]
-    int32_t* s_off = hist + a.nb;                      // [C+1]
-    int32_t* s_start = s_off + (C + 1);                // [C+1]
-    uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));  // [C+1]
+    extern __shared__ uint32_t lds_scatter[];
+    const int nb = a.nb;
+    int32_t* hist = reinterpret_cast<int32_t*>(lds_scatter);   // [nb] counts, then global slot base
+    int32_t* loff = hist + nb;                                  // [nb] chunk-local bucket offsets
+    uint32_t* region = lds_scatter + 2 * nb + 2;                // 8-byte aligned
+    int32_t* s_off = reinterpret_cast<int32_t*>(region);        // [C+1] column table (phase 1)
+    int32_t* s_start = s_off + (C + 1);
+    uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));
+    uint2* stage = reinterpret_cast<uint2*>(region);            // [C] sort buffer (phase 3)
+    __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
 
     if (blockIdx.x == 0 && tid == 0) {
-        a.ctrl->ticket_scan = 0;
-        a.ctrl->maxlen_last = a.ctrl->maxlen;
-        a.ctrl->maxlen = 0;
-        a.ctrl->fnz_last = a.ctrl->fnz;
-        a.ctrl->W_last = a.ctrl->W;
+        st_ctrl_u(&a.ctrl->ticket_scan, 0u);
+        st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
+        st_ctrl(&a.ctrl->fnz_last, ld_ctrl(&a.ctrl->fnz));
+        st_ctrl(&a.ctrl->W_last, ld_ctrl(&a.ctrl->W));
     }
     for (int i = blockIdx.x * BLOCK + tid; i < a.lb1_clear; i += gridDim.x * BLOCK) {
         a.lb1[i] = 0;
         a.lb1[a.lb1_n + i] = 0;
     }
 
-    const int W = a.ctrl->W;
-    const int fnz = a.ctrl->fnz;
+    const int W = ld_ctrl(&a.ctrl->W);
+    const int fnz = ld_ctrl(&a.ctrl->fnz);
     const int nchunks = (int)(((int64_t)W + C - 1) / C);
     if ((int)blockIdx.x >= nchunks) return;
 
-    for (int i = tid; i < a.nb; i += BLOCK) hist[i] = 0;
+    for (int i = tid; i < nb; i += BLOCK) hist[i] = 0;
     const int tl = a.tile_log2;
 
     for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
@@ -320,7 +350,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         const int p0 = a.chunk_col[c];
         const int pend = (c + 1 < nchunks) ? a.chunk_col[c + 1] : fnz - 1;
         const int ncols = pend - p0 + 1;
-        __syncthreads();  // previous chunk finished with the column arrays and hist
+        __syncthreads();  // the previous chunk is done with hist, loff and the shared region
         for (int k = tid; k < ncols; k += BLOCK) {
             s_off[k] = a.coff[p0 + k] - q0;
             s_start[k] = a.cstart[p0 + k];
@@ -328,6 +358,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         }
         __syncthreads();
 
+        // (1) gather + rank
         int32_t row[ITEMS], bk[ITEMS], rank[ITEMS];
         uint32_t val[ITEMS];
 #pragma unroll
@@ -356,32 +387,43 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             }
         }
         __syncthreads();
-        // One slot-range reservation per (chunk, bucket): the first entry of
-        // each bucket in this chunk reserves hist[k] slots.
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            if (bk[i] >= 0 && rank[i] == 0) {
-                const int k = bk[i];
-                const int n = hist[k];
-                const int r0 = k << tl;
-                const int base = a.rcp[r0];
-                const int cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
-                const int g = atomicAdd(&a.cursor[k], n);
-                if (g + n > cap) {
-                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
-                    hist[k] = -1;
-                } else {
-                    hist[k] = base + g;
+        // (2) chunk-local offsets and one slot reservation per touched bucket
+        int carry = 0;
+        for (int b0 = 0; b0 < nb; b0 += BLOCK) {
+            const int b = b0 + tid;
+            const int n = b < nb ? hist[b] : 0;
+            int tot;
+            const int e = block_exclusive_i32<BLOCK>(n, s_tmp, tot);
+            if (b < nb) {
+                loff[b] = carry + e;
+                if (n > 0) {
+                    const int r0 = b << tl;
+                    const int base = a.rcp[r0];
+                    const int cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
+                    const int g = atomicAdd(&a.cursor[b], n);
+                    if (g + n > cap) {
+                        atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                        hist[b] = -1;
+                    } else {
+                        hist[b] = base + g;
+                    }
                 }
             }
+            carry += tot;
         }
+        const int kept = carry;
         __syncthreads();
+        // (3) counting sort into the LDS buffer
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            if (bk[i] >= 0) {
-                const int pos = hist[bk[i]];
-                if (pos >= 0) a.buckets[pos + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
-            }
+        for (int i = 0; i < ITEMS; ++i)
+            if (bk[i] >= 0) stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+        __syncthreads();
+        // (4) coalesced write-out of the bucket runs
+        for (int t = tid; t < kept; t += BLOCK) {
+            const uint2 e = stage[t];
+            const int b = (int)e.x >> tl;
+            const int gb = hist[b];
+            if (gb >= 0) a.buckets[gb + (t - loff[b])] = e;
         }
         __syncthreads();
 #pragma unroll
@@ -411,19 +453,34 @@ __device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) 
     else reinterpret_cast<uint32_t*>(y_val)[o] = v;
 }
 
-template <int BLOCK, int ITEMS, int SR, bool SORTED, bool BFS>
+// Counts first touches of a wave: one LDS atomic per wave (ballot + popcount).
+__device__ __forceinline__ void count_first(bool first, int* s_ucnt) {
+    const uint64_t fm = __ballot(first);
+    if (fm && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(s_ucnt, (int)__popcll(fm));
+}
+
+// One workgroup per bucket.  The bucket's rows [row0, row0 + T) get an LDS
+// sparse accumulator (T values) and a T-bit touched bitmap.  A row's first
+// touch is the atomicOr on the bitmap that finds its bit clear; first
+// touches are counted per wave by ballot.  Only touched accumulator cells are
+// initialised (Algorithm 1, step 2), unless the bucket holds more entries
+// than the registers cache, where the whole tile is initialised once and a
+// single streaming pass does both.  The unique count joins a decoupled
+// look-back across buckets to give the bucket's offset in y (Algorithm 1,
+// step 3) and the bitmap is walked in order, so y comes out ascending; the
+// walk compacts rows through a small LDS list for coalesced y writes.
+template <int BLOCK, int ITEMS, int SR, bool BFS>
 __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     extern __shared__ uint32_t lds_merge[];
     const int tl = a.tile_log2;
     const int T = 1 << tl;
-    uint32_t* spa = lds_merge;                                   // [T] accumulator
-    uint32_t* bm = spa + T;                                // [T/32] touched rows
-    uint16_t* uind = reinterpret_cast<uint16_t*>(bm + (T >> 5));  // [T] unique rows (unsorted)
+    uint32_t* spa = lds_merge;                                       // [T]
+    uint32_t* bm = spa + T;                                          // [T/32]
+    uint16_t* list = reinterpret_cast<uint16_t*>(bm + (T >> 5));     // [kMergeList]
     __shared__ int s_b, s_ucnt;
     __shared__ int64_t s_excl;
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
 
     if (tid == 0) {
         s_b = (int)atomicAdd(&a.ctrl->ticket_merge, 1u);
@@ -431,33 +488,30 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     }
     __syncthreads();
     const int b = s_b;
-    const int W = a.ctrl->W;
+    const int W = ld_ctrl(&a.ctrl->W);
     if (W == 0) {
-        // Nothing was multiplied: y is empty.
         if (b == a.nb - 1 && tid == 0) {
             a.ctrl->nnz_y = 0;
             if (a.d_nnz_y) *a.d_nnz_y = 0;
-            if (a.set_f) a.ctrl->f = 0;
+            if (a.set_f) st_ctrl(&a.ctrl->f, 0);
         }
         return;
     }
     const int row0 = b << tl;
     const int rows = min(T, a.m - row0);
-    const int cnt_raw = a.cursor[b];
+    const int cnt_raw = ld_ctrl(&a.cursor[b]);
     if (cnt_raw == 0 && b != a.nb - 1) {
         if (tid == 0) st_release64(&a.lb3[b], (b == 0 ? LB_INC : LB_AGG));
         return;
     }
     const int base = a.rcp[row0];
-    // Entries beyond the bucket's slot count only exist after an overflow
+    // Slots past the bucket's capacity exist only after an overflow
     // (duplicate x indices); never read past the bucket.
     const int cnt = min(cnt_raw, a.rcp[min(row0 + T, a.m)] - base);
     const int nw = (rows + 31) >> 5;
     for (int w = tid; w < nw; w += BLOCK) bm[w] = 0u;
 
     if (cnt <= BLOCK * ITEMS) {
-        // Entries fit in registers: initialise only the touched cells, then
-        // accumulate (two passes over registers, Algorithm 1 step 2).
         uint32_t rr[ITEMS], vv[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -480,54 +534,33 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
             bool first = false;
             if (rr[i] != 0xffffffffu) {
                 const uint32_t bit = 1u << (rr[i] & 31u);
-                const uint32_t old = atomicOr(&bm[rr[i] >> 5], bit);
-                first = (old & bit) == 0u;
+                first = (atomicOr(&bm[rr[i] >> 5], bit) & bit) == 0u;
                 if (first) spa[rr[i]] = identity<SR>();
             }
-            const uint64_t fm = __ballot(first);
-            if (fm) {
-                int wbase = 0;
-                if (lane == 0) wbase = atomicAdd(&s_ucnt, (int)__popcll(fm));
-                wbase = __shfl(wbase, 0, kWave);
-                if (!SORTED && first) uind[wbase + (int)lanes_below(fm)] = (uint16_t)rr[i];
-            }
+            count_first(first, &s_ucnt);
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
             if (rr[i] != 0xffffffffu) accumulate<SR>(&spa[rr[i]], vv[i]);
     } else {
-        // Large bucket: initialise the whole tile once, then one streaming
-        // pass does first-touch detection and accumulation together.
         for (int r = tid; r < rows; r += BLOCK) spa[r] = identity<SR>();
         __syncthreads();
         for (int e0 = 0; e0 < cnt; e0 += BLOCK) {
             const int e = e0 + tid;
             bool first = false;
-            uint32_t r = 0, v = 0;
-            bool valid = e < cnt;
-            if (valid) {
+            if (e < cnt) {
                 const uint2 ent = a.buckets[base + e];
-                r = ent.x - (uint32_t)row0;
-                v = ent.y;
-                if (r >= (uint32_t)rows) {  // unwritten slot after an overflow
-                    valid = false;
+                const uint32_t r = ent.x - (uint32_t)row0;
+                if (r < (uint32_t)rows) {
+                    const uint32_t bit = 1u << (r & 31u);
+                    first = (atomicOr(&bm[r >> 5], bit) & bit) == 0u;
+                    accumulate<SR>(&spa[r], ent.y);
+                } else {
                     atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
                 }
             }
-            if (valid) {
-                const uint32_t bit = 1u << (r & 31u);
-                const uint32_t old = atomicOr(&bm[r >> 5], bit);
-                first = (old & bit) == 0u;
-            }
-            const uint64_t fm = __ballot(first);
-            if (fm) {
-                int wbase = 0;
-                if (lane == 0) wbase = atomicAdd(&s_ucnt, (int)__popcll(fm));
-                wbase = __shfl(wbase, 0, kWave);
-                if (!SORTED && first) uind[wbase + (int)lanes_below(fm)] = (uint16_t)r;
-            }
-            if (valid) accumulate<SR>(&spa[r], v);
+            count_first(first, &s_ucnt);
         }
     }
     __syncthreads();
@@ -540,88 +573,114 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                 const int64_t total = (int64_t)e + ucnt;
                 a.ctrl->nnz_y = total;
                 if (a.d_nnz_y) *a.d_nnz_y = total;
-                if (a.set_f) a.ctrl->f = (int32_t)total;
+                if (a.set_f) st_ctrl(&a.ctrl->f, (int32_t)total);
             }
         }
     }
     __syncthreads();
     const int64_t excl = s_excl;
-    const int lvl = BFS ? a.ctrl->level : 0;
+    const int lvl = BFS ? ld_ctrl(&a.ctrl->level) : 0;
+    int32_t* const level = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_level) : nullptr;
+    int32_t* const parent = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_parent) : nullptr;
 
-    if constexpr (SORTED) {
-        int carry = 0;
-        for (int w0 = 0; w0 < nw; w0 += BLOCK) {
-            const int w = w0 + tid;
-            uint32_t bits = w < nw ? bm[w] : 0u;
-            int tot;
-            const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
-            if (BFS && w < nw && bits) a.visited[(row0 >> 5) + w] |= bits;
-            int k = 0;
-            while (bits) {
-                const int bitpos = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                const int r = (w << 5) + bitpos;
-                const int64_t o = excl + carry + pos + k;
-                ++k;
-                if (o < a.y_cap) {
-                    a.y_idx[o] = row0 + r;
-                    if (a.y_val) store_value<SR>(a.y_val, o, spa[r]);
-                }
-                if (BFS) {
-                    a.level[row0 + r] = lvl;
-                    if (a.parent) a.parent[row0 + r] = (int32_t)spa[r];
-                }
-            }
-            carry += tot;
+    // In-order walk of the bitmap, kMergeList / 32 words per round.
+    constexpr int kRoundWords = kMergeList / 32;
+    int64_t carry = 0;
+    for (int w0 = 0; w0 < nw; w0 += kRoundWords) {
+        const int w = w0 + tid;
+        const bool mine = tid < kRoundWords && w < nw;
+        const uint32_t bits = mine ? bm[w] : 0u;
+        int tot;
+        const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
+        if (BFS && bits) a.visited[(row0 >> 5) + w] |= bits;
+        uint32_t rest = bits;
+        int k = 0;
+        while (rest) {
+            const int bitpos = __ffs(rest) - 1;
+            rest &= rest - 1u;
+            list[pos + k] = (uint16_t)((w << 5) + bitpos);
+            ++k;
         }
-    } else {
-        for (int t = tid; t < ucnt; t += BLOCK) {
-            const int r = uind[t];
-            const int64_t o = excl + t;
+        __syncthreads();
+        for (int t = tid; t < tot; t += BLOCK) {
+            const int r = list[t];
+            const int64_t o = excl + carry + t;
+            const uint32_t v = spa[r];
             if (o < a.y_cap) {
                 a.y_idx[o] = row0 + r;
-                if (a.y_val) store_value<SR>(a.y_val, o, spa[r]);
+                if (a.y_val) store_value<SR>(a.y_val, o, v);
             }
             if (BFS) {
-                a.level[row0 + r] = lvl;
-                if (a.parent) a.parent[row0 + r] = (int32_t)spa[r];
+                level[row0 + r] = lvl;
+                if (parent) parent[row0 + r] = (int32_t)v;
             }
         }
-        if (BFS)
-            for (int w = tid; w < nw; w += BLOCK)
-                if (bm[w]) a.visited[(row0 >> 5) + w] |= bm[w];
+        carry += tot;
+        __syncthreads();
     }
 }
 
 }  // namespace
 
-size_t merge_lds_bytes(int tile_log2, bool sorted) {
+size_t merge_lds_bytes(int tile_log2) {
     const size_t T = size_t(1) << tile_log2;
-    return T * 4 + (T / 32) * 4 + (sorted ? 0 : T * 2);
+    return T * 4 + (T / 32) * 4 + size_t(kMergeList) * 2;
 }
 
-size_t scatter_lds_bytes(int nb, int chunk) { return size_t(nb) * 4 + size_t(chunk + 1) * 12; }
+size_t scatter_lds_bytes(int nb, int chunk) {
+    const size_t table = size_t(chunk + 1) * 12, sortbuf = size_t(chunk) * 8;
+    return size_t(2 * nb + 2) * 4 + (table > sortbuf ? table : sortbuf);
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
 
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems>), dim3(grid), dim3(kScanBlock), 0, s, a);
+    switch (a.xmode) {
+        case XV_BITS32:
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_BITS32>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            break;
+        case XV_INDEX:
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_INDEX>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            break;
+        case XV_U8:
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_U8>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            break;
+        case XV_TRUE:
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_TRUE>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int BLOCK, int ITEMS, int SR>
+static hipError_t scatter_one(const ScatterArgs& a, int grid, hipStream_t s) {
+    const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS);
+    auto kern = k_scatter<BLOCK, ITEMS, SR>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
     return hipGetLastError();
 }
 
 template <int BLOCK, int ITEMS>
 static hipError_t scatter_sr(const ScatterArgs& a, int semiring, int grid, hipStream_t s) {
-    const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS);
     switch (semiring) {
-        case SR_PLUS_TIMES:
-            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_PLUS_TIMES>), dim3(grid), dim3(BLOCK), lds, s, a);
-            break;
-        case SR_MIN_SELECT2ND:
-            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_MIN_SELECT2ND>), dim3(grid), dim3(BLOCK), lds, s, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_scatter<BLOCK, ITEMS, SR_OR_AND>), dim3(grid), dim3(BLOCK), lds, s, a);
-            break;
+        case SR_PLUS_TIMES: return scatter_one<BLOCK, ITEMS, SR_PLUS_TIMES>(a, grid, s);
+        case SR_MIN_SELECT2ND: return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND>(a, grid, s);
+        default: return scatter_one<BLOCK, ITEMS, SR_OR_AND>(a, grid, s);
     }
-    return hipGetLastError();
+}
+
+bool scatter_shape_supported(int block, int items) {
+    return (block == 256 && (items == 4 || items == 8 || items == 16)) ||
+           (block == 512 && (items == 4 || items == 8)) || (block == 1024 && (items == 4 || items == 8));
 }
 
 hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
@@ -634,39 +693,38 @@ hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int ite
         if (items == 8) return scatter_sr<512, 8>(a, semiring, grid, s);
     } else if (block == 1024) {
         if (items == 4) return scatter_sr<1024, 4>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<1024, 8>(a, semiring, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int BLOCK, int SR>
-static hipError_t merge_mode(const MergeArgs& a, bool sorted, bool bfs, hipStream_t s) {
-    const size_t lds = merge_lds_bytes(a.tile_log2, sorted);
-    const dim3 grid(a.nb), blk(BLOCK);
-    if (bfs) {
-        if constexpr (SR == SR_PLUS_TIMES) return hipErrorInvalidValue;
-        else {
-            if (sorted) hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, true, true>), grid, blk, lds, s, a);
-            else hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, false, true>), grid, blk, lds, s, a);
-        }
-    } else {
-        if (sorted) hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, true, false>), grid, blk, lds, s, a);
-        else hipLaunchKernelGGL((k_merge<BLOCK, kMergeItems, SR, false, false>), grid, blk, lds, s, a);
-    }
+template <int BLOCK, int SR, bool BFS>
+static hipError_t merge_one(const MergeArgs& a, hipStream_t s) {
+    const size_t lds = merge_lds_bytes(a.tile_log2);
+    auto kern = k_merge<BLOCK, kMergeItems, SR, BFS>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.nb), dim3(BLOCK), lds, s, a);
     return hipGetLastError();
 }
 
 template <int BLOCK>
-static hipError_t merge_block(const MergeArgs& a, int semiring, bool sorted, bool bfs, hipStream_t s) {
+static hipError_t merge_block(const MergeArgs& a, int semiring, bool bfs, hipStream_t s) {
     switch (semiring) {
-        case SR_PLUS_TIMES: return merge_mode<BLOCK, SR_PLUS_TIMES>(a, sorted, bfs, s);
-        case SR_MIN_SELECT2ND: return merge_mode<BLOCK, SR_MIN_SELECT2ND>(a, sorted, bfs, s);
-        default: return merge_mode<BLOCK, SR_OR_AND>(a, sorted, bfs, s);
+        case SR_PLUS_TIMES:
+            if (bfs) return hipErrorInvalidValue;
+            return merge_one<BLOCK, SR_PLUS_TIMES, false>(a, s);
+        case SR_MIN_SELECT2ND:
+            return bfs ? merge_one<BLOCK, SR_MIN_SELECT2ND, true>(a, s) : merge_one<BLOCK, SR_MIN_SELECT2ND, false>(a, s);
+        default:
+            return bfs ? merge_one<BLOCK, SR_OR_AND, true>(a, s) : merge_one<BLOCK, SR_OR_AND, false>(a, s);
     }
 }
 
-hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool sorted, bool bfs, hipStream_t s) {
-    if (block == 256) return merge_block<256>(a, semiring, sorted, bfs, s);
-    if (block == 512) return merge_block<512>(a, semiring, sorted, bfs, s);
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
+    if (block == 256) return merge_block<256>(a, semiring, bfs, s);
+    if (block == 512) return merge_block<512>(a, semiring, bfs, s);
+    if (block == 1024) return merge_block<1024>(a, semiring, bfs, s);
     return hipErrorInvalidValue;
 }
 

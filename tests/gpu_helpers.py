@@ -32,6 +32,8 @@ def compare(semiring, g_idx, g_val, o_idx, o_val, sorted_output=False, terms_abs
         bad = np.nonzero(err > bound)[0]
         assert bad.size == 0, f"{bad.size} values outside tolerance, worst rel {np.max(err / np.maximum(np.abs(ref), 1e-300))}"
     elif semiring == 1:
-        assert np.array_equal(gv.astype(np.int64), ov.astype(np.int64)), "int32 values differ"
+        bad = np.nonzero(gv.astype(np.int64) != ov.astype(np.int64))[0]
+        assert bad.size == 0, f"{bad.size} int32 values differ, e.g. rows {gi[bad[:5]]} gpu {gv[bad[:5]]} oracle {ov[bad[:5]]}"
     else:
-        assert np.array_equal(gv.astype(np.uint8), ov.astype(np.uint8)), "bool values differ"
+        bad = np.nonzero(gv.astype(np.uint8) != ov.astype(np.uint8))[0]
+        assert bad.size == 0, f"{bad.size} bool values differ, e.g. rows {gi[bad[:5]]} gpu {gv[bad[:5]]} oracle {ov[bad[:5]]}"
