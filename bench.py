@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only the timed headline loop (for rocprofv3)")
+    ap.add_argument("--schedules", action="store_true", help="also time a grid of launch schedules")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -177,10 +178,58 @@ def main():
                                         f"fp64 dense-accumulator oracle, one host thread"}
     log(f"cpu oracle: {result['cpu_baseline']['value']} GTEPS over {done} calls")
 
+    if args.schedules:
+        result["schedules"] = schedule_sweep(spv, M, A, deg, dev, stream)
     if not args.no_extras:
         result["sweep"] = sweep(spv, M, A, deg, dev, stream)
         result["bfs"] = bfs_bench(spv, M, A, dev)
     print(json.dumps(result))
+
+
+def time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, m, steps, stream):
+    import torch
+    nx = len(xi)
+    for i in range(4):
+        spv.spmspv_run(M.handle, sr, 0, f, xi[i % nx], xv[i % nx], y_idx, y_val, m, sync=False, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        spv.spmspv_run(M.handle, sr, 0, f, xi[i % nx], xv[i % nx], y_idx, y_val, m, sync=False, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def schedule_sweep(spv, M, A, deg, dev, stream):
+    import torch
+    import synth
+    out = {}
+    y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
+    y_val = torch.empty(A.m, dtype=torch.float32, device=dev)
+    for dens in (1e-3, 1e-2, 1e-1):
+        f = synth.density_f(A.n, dens)
+        xs = [synth.sparse_x(A.n, f, seed=4000 + r) for r in range(8)]
+        W = float(np.mean([int(deg[x[0]].sum()) for x in xs]))
+        xi = [torch.as_tensor(x[0]).to(dev) for x in xs]
+        xv = [torch.as_tensor(x[1]).to(dev) for x in xs]
+        for tl in (12, 13, 14, 15):
+            for sb, si in ((1024, 8), (1024, 4), (512, 4)):
+                for mb in (1024, 512):
+                    try:
+                        M.schedule = spv.Schedule(0, tl, sb, si, mb, 0)
+                    except spv.SpmspvError:
+                        continue
+                    ms = time_calls(spv, M, 0, f, xi, xv, y_idx, y_val, A.m, 32, stream)
+                    out[f"d{dens:g}/t{tl}/s{sb}x{si}/m{mb}"] = round(W / (ms * 1e-3) / 1e9, 2)
+    M.schedule = None
+    best = {}
+    for k, v in out.items():
+        d = k.split("/")[0]
+        if d not in best or v > best[d][1]:
+            best[d] = (k, v)
+    log(f"schedule sweep best: {best}")
+    return {"GTEPS": out, "best": best}
 
 
 def sweep(spv, M, A, deg, dev, stream):

@@ -112,6 +112,7 @@ struct MergeArgs {
     int64_t y_cap;
     int64_t* d_nnz_y;        // nullable
     uint32_t* visited;       // BFS: visited bitmap, updated with new vertices
+    const uint32_t* heavy;   // [m/32] rows with at least kHeavyRow stored entries
     int set_f;               // BFS: publish nnz(y) as the next frontier length
 };
 
@@ -124,9 +125,10 @@ hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int ite
 hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 2;
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kMergeItems = 8;
+constexpr int kHeavyRow = 2048;    // rows with this many stored entries may be collapsed per wave
 constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk
 
 // Set-up kernels (spmspv_create, bfs_run).
@@ -135,6 +137,7 @@ hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int3
                              hipStream_t s);
 hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
                            int32_t* frontier, Ctrl* ctrl, hipStream_t s);
 

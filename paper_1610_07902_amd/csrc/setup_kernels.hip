@@ -121,6 +121,19 @@ __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
     }
 }
 
+// heavy bit of row r = (rcp[r+1] - rcp[r] >= thresh); one thread per 32-row word.
+__global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy) {
+    const int64_t nw = ((int64_t)m + 31) >> 5;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t bits = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int64_t r = w * 32 + b;
+            if (r < m && rcp[r + 1] - rcp[r] >= thresh) bits |= 1u << b;
+        }
+        heavy[w] = bits;
+    }
+}
+
 inline int grid_for(int64_t count, int block, int cap = 4096) {
     int64_t g = (count + block - 1) / block;
     if (g < 1) g = 1;
@@ -158,6 +171,12 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(k_validate_colptr, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, colptr, n, nnz,
                        ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s) {
+    hipLaunchKernelGGL(k_heavy_rows, dim3(grid_for((m + 31) / 32, kSetupBlock)), dim3(kSetupBlock), 0, s, rcp, m,
+                       thresh, heavy);
     return hipGetLastError();
 }
 

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/spmspv.h"
+#include "spmspv.h"
 #include "internal.h"
 
 using namespace spv;
@@ -51,7 +51,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
-        total;
+        heavy, total;
     int64_t nb_max, lb1_n, chunk_n;
 };
 
@@ -76,10 +76,11 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz) {
     L.lb1 = take(size_t(L.lb1_n) * 16);
     L.cursor = take(size_t(L.nb_max) * 4);
     L.lb3 = take(size_t(L.nb_max) * 8);
-    L.buckets = take(size_t(nnz) * 8);
+    L.buckets = take(size_t(nnz + 1) * 8);
     L.visited = take(size_t((m + 31) / 32) * 4);
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
+    L.heavy = take(size_t((m + 31) / 32) * 4);
     L.total = o;
     return L;
 }
@@ -104,6 +105,7 @@ struct spmspv_matrix {
     uint64_t* lb3 = nullptr;
     uint2* buckets = nullptr;
     uint32_t* visited = nullptr;
+    uint32_t* heavy = nullptr;
     int32_t* front[2] = {nullptr, nullptr};
     int32_t maxdeg = 0;
     int device = 0;
@@ -240,6 +242,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     ma.y_cap = y_cap;
     ma.d_nnz_y = d_nnz_y;
     ma.visited = A->visited;
+    ma.heavy = A->heavy;
     (void)level;
     (void)parent;
     ma.set_f = bfs ? 1 : 0;
@@ -341,6 +344,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->visited = reinterpret_cast<uint32_t*>(A->ws + L.visited);
     A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
     A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
+    A->heavy = reinterpret_cast<uint32_t*>(A->ws + L.heavy);
 
     auto bail = [&](int status) {
         delete A;
@@ -365,6 +369,8 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     if ((e = launch_exclusive_scan_i32(A->rcp, m + 1, reinterpret_cast<int32_t*>(A->ws + L.partials), s)) !=
         hipSuccess)
         return bail(hip_fail(e, "row count scan"));
+    if ((e = launch_heavy_rows(A->rcp, (int32_t)m, kHeavyRow, A->heavy, s)) != hipSuccess)
+        return bail(hip_fail(e, "heavy rows"));
     Ctrl h{};
     if ((e = hipMemcpyAsync(&h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return bail(hip_fail(e, "read control block"));

@@ -183,7 +183,6 @@ template <int BLOCK, int ITEMS, int XMODE>
 __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     constexpr int TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_tmp[BLOCK / kWave + 1];
-    __shared__ int s_tile;
     __shared__ uint64_t s_excl_sum, s_excl_cnt;
     __shared__ int s_max;
     const int tid = threadIdx.x;
@@ -209,31 +208,41 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     const int ntiles = (f + TILE - 1) / TILE;
     const int64_t chunk = 1ll << a.chunk_log2;
     int lmax = 0;
-    for (;;) {
-        if (tid == 0) s_tile = (int)atomicAdd(&a.ctrl->ticket_scan, 1u);
-        __syncthreads();
-        const int tile = s_tile;
+    // Tiles are taken in blockIdx order (tile = blockIdx.x + k * gridDim.x), so
+    // every tile's predecessors belong to workgroups dispatched no later than
+    // its own; the look-back wait is bounded in any case.
+    for (int tile = blockIdx.x;; tile += gridDim.x) {
         if (tile >= ntiles) break;
         const int p0 = tile * TILE + tid * ITEMS;
-        int32_t st[ITEMS], ln[ITEMS];
+        int32_t st[ITEMS], ln[ITEMS], jj[ITEMS];
         uint32_t xv[ITEMS];
         uint64_t lsum = 0, lcnt = 0;
+        // Independent loads first (x indices, then both colptr ends, then x
+        // values) so every thread has all its gathers in flight at once.
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) jj[i] = (p0 + i < f) ? a.x_idx[p0 + i] : -1;
+        bool bad = false;
+        int32_t b0[ITEMS], b1[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int p = p0 + i;
-            ln[i] = 0;
-            st[i] = 0;
-            xv[i] = 0;
-            if (p < f) {
-                const int32_t j = a.x_idx[p];
-                if (j >= 0 && j < a.n) {
-                    st[i] = a.colptr[j];
-                    ln[i] = a.colptr[j + 1] - st[i];
-                } else {
-                    atomicOr(&a.ctrl->err, ERR_X_RANGE);
-                }
-                xv[i] = x_value<XMODE>(a.x_val, p, j);
-            }
+            // Clamp to a valid column so all gathers issue unconditionally.
+            const int32_t jc = (jj[i] >= 0 && jj[i] < a.n) ? jj[i] : 0;
+            b0[i] = a.colptr[jc];
+            b1[i] = a.colptr[jc + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool valid = p0 + i < f;
+            const bool inr = jj[i] >= 0 && jj[i] < a.n;
+            bad |= valid && !inr;
+            st[i] = (valid && inr) ? b0[i] : 0;
+            ln[i] = (valid && inr) ? b1[i] - b0[i] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) xv[i] = (p0 + i < f) ? x_value<XMODE>(a.x_val, p0 + i, jj[i]) : 0u;
+        if (bad) atomicOr(&a.ctrl->err, ERR_X_RANGE);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
             lmax = max(lmax, ln[i]);
             lsum += (uint64_t)ln[i];
             lcnt += ln[i] > 0 ? 1u : 0u;
@@ -241,13 +250,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         uint64_t tile_sum, tile_cnt;
         const uint64_t tex_sum = block_exclusive_u64<BLOCK>(lsum, s_tmp, tile_sum);
         const uint64_t tex_cnt = block_exclusive_u64<BLOCK>(lcnt, s_tmp, tile_cnt);
+        // The two chains run concurrently in waves 0 and 1.
         if (tid < kWave) {
             const uint64_t es = lookback(lb_sum, tile, tile_sum, &a.ctrl->err);
+            if (tid == 0) s_excl_sum = es;
+        } else if (tid < 2 * kWave) {
             const uint64_t ec = lookback(lb_cnt, tile, tile_cnt, &a.ctrl->err);
-            if (tid == 0) {
-                s_excl_sum = es;
-                s_excl_cnt = ec;
-            }
+            if (tid == kWave) s_excl_cnt = ec;
         }
         __syncthreads();
         uint64_t off = s_excl_sum + tex_sum;
@@ -279,7 +288,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
             }
         }
         __syncthreads();
-        if (a.single_tile) break;
     }
     atomicMax(&s_max, lmax);
     __syncthreads();
@@ -358,32 +366,46 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         }
         __syncthreads();
 
-        // (1) gather + rank
-        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS];
+        // (1) gather + rank.  Each thread owns ITEMS consecutive products:
+        // one binary search finds the column of the first, the rest walk
+        // forward.  All row-id / value / mask loads are then issued together
+        // (indices clamped into range), and ranks are taken in LDS.
+        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS], qq[ITEMS];
+        uint32_t xcol[ITEMS];
+        {
+            const int rq0 = tid * ITEMS;
+            int lo = 0, hi = ncols - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= rq0) lo = mid; else hi = mid - 1;
+            }
+            int next = lo + 1 < ncols ? s_off[lo + 1] : 0x7fffffff;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int rq = rq0 + i;
+                while (rq >= next) {
+                    ++lo;
+                    next = lo + 1 < ncols ? s_off[lo + 1] : 0x7fffffff;
+                }
+                qq[i] = rq < cnt ? s_start[lo] + (rq - s_off[lo]) : -1;
+                xcol[i] = s_xv[lo];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) row[i] = a.rowids[qq[i] >= 0 ? qq[i] : 0];
         uint32_t val[ITEMS];
 #pragma unroll
+        for (int i = 0; i < ITEMS; ++i) val[i] = mult<SR>(a.values, qq[i] >= 0 ? qq[i] : 0, xcol[i]);
+        uint32_t mw[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) mw[i] = a.mask ? a.mask[(uint32_t)row[i] >> 5] : 0u;
+#pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int rq = i * BLOCK + tid;
             bk[i] = -1;
             rank[i] = 0;
-            row[i] = 0;
-            val[i] = 0;
-            if (rq < cnt) {
-                int lo = 0, hi = ncols - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_off[mid] <= rq) lo = mid; else hi = mid - 1;
-                }
-                const int32_t q = s_start[lo] + (rq - s_off[lo]);
-                const int32_t r = a.rowids[q];
-                row[i] = r;
-                val[i] = mult<SR>(a.values, q, s_xv[lo]);
-                bool keep = true;
-                if (a.mask) keep = ((a.mask[r >> 5] >> (r & 31)) & 1u) == 0u;
-                if (keep) {
-                    bk[i] = r >> tl;
-                    rank[i] = atomicAdd(&hist[bk[i]], 1);
-                }
+            if (qq[i] >= 0 && ((mw[i] >> (row[i] & 31)) & 1u) == 0u) {
+                bk[i] = row[i] >> tl;
+                rank[i] = atomicAdd(&hist[bk[i]], 1);
             }
         }
         __syncthreads();
@@ -459,6 +481,70 @@ __device__ __forceinline__ void count_first(bool first, int* s_ucnt) {
     if (fm && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(s_ucnt, (int)__popcll(fm));
 }
 
+template <int SR>
+__device__ __forceinline__ uint32_t combine(uint32_t x, uint32_t y) {
+    if constexpr (SR == SR_PLUS_TIMES) return __float_as_uint(__uint_as_float(x) + __uint_as_float(y));
+    else if constexpr (SR == SR_MIN_SELECT2ND) return (uint32_t)min((int)x, (int)y);
+    else return x | y;
+}
+
+template <int SR>
+__device__ __forceinline__ uint32_t wave_reduce(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = combine<SR>(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+    return v;
+}
+
+// Hub rows: when at least kPeelMin lanes of a wave carry the row of the
+// wave's first heavy-row entry (rows with many stored entries, flagged once
+// per matrix), those lanes are collapsed into one LDS operation.  At most one
+// row is collapsed per wave instruction; all other entries go straight to
+// LDS atomics.  This keeps a hub row hit by a large share of a bucket's
+// entries from serialising a whole wave on one LDS address.
+constexpr int kPeelMin = 4;
+
+__device__ __forceinline__ uint64_t peel_mask(uint32_t r, bool valid, bool heavy, uint32_t& key, int& src) {
+    const uint64_t hm = __ballot(valid && heavy);
+    if (__popcll(hm) < kPeelMin) return 0ull;
+    src = __ffsll((unsigned long long)hm) - 1;
+    key = (uint32_t)__shfl((int)r, src, kWave);
+    const uint64_t km = __ballot(valid && heavy && r == key);
+    return __popcll(km) >= kPeelMin ? km : 0ull;
+}
+
+template <int SR>
+__device__ __forceinline__ bool touch_row(uint32_t r, bool valid, bool heavy, uint32_t* bm, uint32_t* spa,
+                                          bool init) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t key = 0;
+    int src = 0;
+    const uint64_t km = peel_mask(r, valid, heavy, key, src);
+    const bool peeled = (km >> lane) & 1ull;
+    bool first = false;
+    if (valid && (!peeled || lane == src)) {
+        const uint32_t bit = 1u << (r & 31u);
+        first = (atomicOr(&bm[r >> 5], bit) & bit) == 0u;
+        if (first && init) spa[r] = identity<SR>();
+    }
+    return first;
+}
+
+template <int SR>
+__device__ __forceinline__ void add_row(uint32_t r, uint32_t v, bool valid, bool heavy, uint32_t* spa) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t key = 0;
+    int src = 0;
+    const uint64_t km = peel_mask(r, valid, heavy, key, src);
+    if (km) {
+        const bool peeled = (km >> lane) & 1ull;
+        const uint32_t sum = wave_reduce<SR>(peeled ? v : identity<SR>());
+        if (valid && !peeled) accumulate<SR>(&spa[r], v);
+        if (lane == src) accumulate<SR>(&spa[key], sum);
+    } else if (valid) {
+        accumulate<SR>(&spa[r], v);
+    }
+}
+
 // One workgroup per bucket.  The bucket's rows [row0, row0 + T) get an LDS
 // sparse accumulator (T values) and a T-bit touched bitmap.  A row's first
 // touch is the atomicOr on the bitmap that finds its bit clear; first
@@ -476,19 +562,23 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     const int T = 1 << tl;
     uint32_t* spa = lds_merge;                                       // [T]
     uint32_t* bm = spa + T;                                          // [T/32]
-    uint16_t* list = reinterpret_cast<uint16_t*>(bm + (T >> 5));     // [kMergeList]
-    __shared__ int s_b, s_ucnt;
+    uint32_t* hb = bm + (T >> 5);                                    // [T/32] heavy rows
+    uint16_t* list = reinterpret_cast<uint16_t*>(hb + (T >> 5));     // [kMergeList]
+    __shared__ int s_ucnt;
     __shared__ int64_t s_excl;
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
 
-    if (tid == 0) {
-        s_b = (int)atomicAdd(&a.ctrl->ticket_merge, 1u);
-        s_ucnt = 0;
-    }
-    __syncthreads();
-    const int b = s_b;
+    // Buckets in blockIdx order: a bucket's look-back predecessors belong to
+    // workgroups dispatched no later than its own (the wait is bounded).
+    if (tid == 0) s_ucnt = 0;
+    const int b = blockIdx.x;
     const int W = ld_ctrl(&a.ctrl->W);
+    const int row0 = b << tl;
+    const int cnt_raw = ld_ctrl(&a.cursor[b]);
+    const int base = a.rcp[row0];
+    const int cap = a.rcp[min(row0 + T, a.m)] - base;
+    __syncthreads();
     if (W == 0) {
         if (b == a.nb - 1 && tid == 0) {
             a.ctrl->nnz_y = 0;
@@ -497,71 +587,78 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         }
         return;
     }
-    const int row0 = b << tl;
     const int rows = min(T, a.m - row0);
-    const int cnt_raw = ld_ctrl(&a.cursor[b]);
     if (cnt_raw == 0 && b != a.nb - 1) {
         if (tid == 0) st_release64(&a.lb3[b], (b == 0 ? LB_INC : LB_AGG));
         return;
     }
-    const int base = a.rcp[row0];
     // Slots past the bucket's capacity exist only after an overflow
     // (duplicate x indices); never read past the bucket.
-    const int cnt = min(cnt_raw, a.rcp[min(row0 + T, a.m)] - base);
+    const int cnt = min(cnt_raw, cap);
     const int nw = (rows + 31) >> 5;
-    for (int w = tid; w < nw; w += BLOCK) bm[w] = 0u;
+    for (int w = tid; w < nw; w += BLOCK) {
+        bm[w] = 0u;
+        hb[w] = a.heavy[(row0 >> 5) + w];
+    }
 
     if (cnt <= BLOCK * ITEMS) {
         uint32_t rr[ITEMS], vv[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const int e = i * BLOCK + tid;
-            rr[i] = 0xffffffffu;
-            vv[i] = 0u;
-            if (e < cnt) {
-                const uint2 ent = a.buckets[base + e];
-                rr[i] = ent.x - (uint32_t)row0;
-                vv[i] = ent.y;
+            const uint2 ent = a.buckets[base + (e < cnt ? e : 0)];
+            rr[i] = e < cnt ? ent.x : 0xffffffffu;
+            vv[i] = ent.y;
+        }
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i * BLOCK + tid < cnt) {
+                rr[i] -= (uint32_t)row0;
                 if (rr[i] >= (uint32_t)rows) {  // unwritten slot after an overflow
                     rr[i] = 0xffffffffu;
-                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                    bad = true;
                 }
             }
         }
+        if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            bool first = false;
-            if (rr[i] != 0xffffffffu) {
-                const uint32_t bit = 1u << (rr[i] & 31u);
-                first = (atomicOr(&bm[rr[i] >> 5], bit) & bit) == 0u;
-                if (first) spa[rr[i]] = identity<SR>();
-            }
-            count_first(first, &s_ucnt);
-        }
-        __syncthreads();
+        bool hv[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (rr[i] != 0xffffffffu) accumulate<SR>(&spa[rr[i]], vv[i]);
+            hv[i] = rr[i] != 0xffffffffu && ((hb[rr[i] >> 5] >> (rr[i] & 31u)) & 1u);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            count_first(touch_row<SR>(rr[i], rr[i] != 0xffffffffu, hv[i], bm, spa, true), &s_ucnt);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) add_row<SR>(rr[i], vv[i], rr[i] != 0xffffffffu, hv[i], spa);
     } else {
         for (int r = tid; r < rows; r += BLOCK) spa[r] = identity<SR>();
         __syncthreads();
-        for (int e0 = 0; e0 < cnt; e0 += BLOCK) {
-            const int e = e0 + tid;
-            bool first = false;
-            if (e < cnt) {
-                const uint2 ent = a.buckets[base + e];
-                const uint32_t r = ent.x - (uint32_t)row0;
-                if (r < (uint32_t)rows) {
-                    const uint32_t bit = 1u << (r & 31u);
-                    first = (atomicOr(&bm[r >> 5], bit) & bit) == 0u;
-                    accumulate<SR>(&spa[r], ent.y);
-                } else {
-                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
-                }
+        constexpr int kBatch = 4;   // entries per thread in flight per step
+        bool bad = false;
+        for (int e0 = 0; e0 < cnt; e0 += BLOCK * kBatch) {
+            uint2 ent[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + u * BLOCK + tid;
+                ent[u] = e < cnt ? a.buckets[base + e] : make_uint2(0xffffffffu, 0u);
             }
-            count_first(first, &s_ucnt);
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const uint32_t r = ent[u].x - (uint32_t)row0;
+                bool valid = e0 + u * BLOCK + tid < cnt;
+                if (valid && r >= (uint32_t)rows) {
+                    valid = false;
+                    bad = true;
+                }
+                const bool heavy = valid && ((hb[r >> 5] >> (r & 31u)) & 1u);
+                count_first(touch_row<SR>(r, valid, heavy, bm, spa, false), &s_ucnt);
+                add_row<SR>(r, ent[u].y, valid, heavy, spa);
+            }
         }
+        if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
     }
     __syncthreads();
     const int ucnt = s_ucnt;
@@ -624,7 +721,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
 
 size_t merge_lds_bytes(int tile_log2) {
     const size_t T = size_t(1) << tile_log2;
-    return T * 4 + (T / 32) * 4 + size_t(kMergeList) * 2;
+    return T * 4 + (T / 32) * 8 + size_t(kMergeList) * 2;
 }
 
 size_t scatter_lds_bytes(int nb, int chunk) {
