@@ -77,14 +77,25 @@ enum spmspv_flags {
                                   NULL                                         */
     SPMSPV_USE_GRAPH = 16,     /* bfs_run: replay the level loop as a captured
                                   hipGraph                                     */
-    SPMSPV_PROFILE = 32        /* record HIP events around each kernel (see
+    SPMSPV_PROFILE = 32,       /* record HIP events around each kernel (see
                                   spmspv_profile_read)                        */
+    SPMSPV_WITH_TRANSPOSE = 64,/* create: also build the CSR form of A so the
+                                  pull direction is available                 */
+    SPMSPV_SYMMETRIC = 128,    /* create: caller states A == A^T (pattern and
+                                  values); the pull direction reads A's
+                                  columns as rows, no transpose is built      */
+    SPMSPV_DIRECTION_OPT = 256 /* bfs_run: choose push or pull per level
+                                  (Beamer's frontier-edge heuristic); needs a
+                                  handle created with one of the two flags
+                                  above                                       */
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any
  * output index set; fp32 plus-times sums may differ in rounding order.   */
 typedef struct {
-    int direction;      /* 0 = push (vector-driven, Algorithm 1)                   */
+    int direction;      /* 0 = push (vector-driven, Algorithm 1); 1 = pull
+                           (matrix-driven: scan every row of A against x;
+                           needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)  */
     int tile_log2;      /* rows per bucket = 2^tile_log2; buckets = ceil(m / 2^t)  */
     int scatter_block;  /* threads per bucketing workgroup (64..1024, power of 2)  */
     int scatter_items;  /* products per thread per chunk (1..16, power of 2)       */

@@ -25,6 +25,9 @@ X_VAL_IS_INDEX = 4
 X_ALL_TRUE = 8
 USE_GRAPH = 16
 PROFILE = 32
+WITH_TRANSPOSE = 64
+SYMMETRIC = 128
+DIRECTION_OPT = 256
 
 OK, EINVAL, ENOMEM, ECAPACITY, EHIP, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 

@@ -41,7 +41,11 @@ struct alignas(256) Ctrl {
     int32_t W_last;
     int32_t* bfs_level;     // BFS output arrays, set by the BFS init kernel so a
     int32_t* bfs_parent;    // captured level graph does not bake them in
-    uint32_t pad[46];
+    int32_t dir;            // direction of the current BFS level: 0 push, 1 pull
+    int32_t policy;         // BFS direction policy: 0 push only, 1 frontier-edge heuristic
+    int64_t edges_left;     // stored entries in columns of unvisited vertices
+    uint32_t unsorted;      // set at create when some column's row ids are not ascending
+    uint32_t pad[39];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -95,6 +99,7 @@ struct ScatterArgs {
     int32_t lb1_clear;       // how many of each half to clear
     int32_t f_host;
     const int32_t* f_dev;
+    int gate;                // 1: skip the work when ctrl->dir selects pull
 };
 
 // Merge + compaction phase: one workgroup per bucket.
@@ -114,7 +119,52 @@ struct MergeArgs {
     uint32_t* visited;       // BFS: visited bitmap, updated with new vertices
     const uint32_t* heavy;   // [m/32] rows with at least kHeavyRow stored entries
     int set_f;               // BFS: publish nnz(y) as the next frontier length
+    int gate;                // 1: skip when ctrl->dir selects pull
 };
+
+// Pull (matrix-driven) direction over the CSR form of A.
+struct PullArgs {
+    Ctrl* ctrl;
+    int32_t m, n;
+    int64_t nnz;
+    const int32_t* rowptr;   // [m+1]
+    const uint32_t* colids;  // [nnz]
+    const float* values;     // [nnz] CSR values, nullable
+    const int32_t* part;     // [pull_blocks+1] merge-path partition
+    int pull_blocks;
+    const int32_t* x_idx;
+    const void* x_val;
+    int32_t f_host;
+    const int32_t* f_dev;
+    uint32_t* xbits;         // [n/32] zero between calls
+    uint32_t* xdense;        // [n]
+    uint32_t* ybits;         // [m/32] zero between calls
+    uint32_t* ydense;        // [m] semiring identity between calls
+    const uint32_t* mask;    // nullable: rows to skip (BFS visited)
+    uint64_t* lbp;           // [emit_blocks] look-back words
+    int emit_blocks;
+    int32_t* y_idx;
+    void* y_val;
+    int64_t y_cap;
+    int64_t* d_nnz_y;
+    uint32_t* visited;
+    int set_f;
+    int bump_level;
+    int gate;                // 1: skip when ctrl->dir selects push
+};
+
+constexpr int kPullBlock = 256;
+constexpr int kPullItems = 8;
+constexpr int kPullChunk = kPullBlock * kPullItems;
+
+hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, hipStream_t s);
+hipError_t launch_pull_setup(const int32_t* colptr, const int32_t* rowids, const float* values, int32_t m,
+                             int32_t n, int64_t nnz, const int32_t* rowptr, int32_t* cursor, int32_t* colids,
+                             float* tvalues, int32_t* part, uint32_t* unsorted, hipStream_t s);
+hipError_t launch_clear_u64(uint64_t* p, int n, hipStream_t s);
+hipError_t launch_fill_ident(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+int pull_emit_blocks(int32_t m);
+int pull_blocks(int32_t m, int64_t nnz);
 
 size_t merge_lds_bytes(int tile_log2);
 size_t scatter_lds_bytes(int nb, int chunk);
@@ -138,7 +188,8 @@ hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int3
 hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s);
+hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl, hipStream_t s);
+                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
 
 }  // namespace spv

@@ -1,0 +1,423 @@
+// Pull (matrix-driven) direction: y(i) = Add over the stored entries A(i, j)
+// of row i whose column j is selected by x.  This is the other class of
+// SpMSpV algorithms in the paper's Background ("Classes of SpMSpV
+// algorithms"): it touches every stored entry of the rows it scans, so its
+// cost is O(m + nnz(A)) rather than the vector-driven O(df), and it wins when
+// x is dense; switching between the two is the paper's stated future work
+// (Conclusions).  Rows are read in CSR form: the transpose built at create,
+// or A itself when the caller declares A symmetric.
+//
+// Three launches: k_pull_prep scatters x into a bitmap + dense values;
+// k_pull walks a merge-path partition of (row ends + stored entries) so every
+// workgroup gets the same number of steps whatever the row lengths; k_emit
+// walks the result bitmap in order (decoupled look-back across workgroups),
+// writes y ascending and restores the zeroed / identity state of the dense
+// buffers for the next call.
+
+#include "internal.h"
+
+namespace spv {
+
+namespace {
+
+constexpr uint64_t LBP_AGG = 1ull << 62;
+constexpr uint64_t LBP_INC = 2ull << 62;
+constexpr uint64_t LBP_VAL = (1ull << 62) - 1;
+constexpr int kSpinMaxP = 1 << 20;
+
+__device__ __forceinline__ int32_t ldc(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t* ldc_ptr(int32_t* const* p) {
+    return reinterpret_cast<int32_t*>(__hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <int SR>
+__device__ __forceinline__ uint32_t ident() {
+    if constexpr (SR == SR_PLUS_TIMES) return 0u;
+    else if constexpr (SR == SR_MIN_SELECT2ND) return 0x7fffffffu;
+    else return 0u;
+}
+
+template <int SR>
+__device__ __forceinline__ uint32_t comb(uint32_t x, uint32_t y) {
+    if constexpr (SR == SR_PLUS_TIMES) return __float_as_uint(__uint_as_float(x) + __uint_as_float(y));
+    else if constexpr (SR == SR_MIN_SELECT2ND) return (uint32_t)min((int)x, (int)y);
+    else return x | y;
+}
+
+template <int SR>
+__device__ __forceinline__ void comb_global(uint32_t* cell, uint32_t v) {
+    if constexpr (SR == SR_PLUS_TIMES) atomicAdd(reinterpret_cast<float*>(cell), __uint_as_float(v));
+    else if constexpr (SR == SR_MIN_SELECT2ND) atomicMin(reinterpret_cast<int*>(cell), (int)v);
+    else atomicOr(cell, v);
+}
+
+// ---------------------------------------------------------------- x -> dense
+template <int XMODE>
+__global__ __launch_bounds__(256) void k_pull_prep(PullArgs a) {
+    if (a.gate && ldc(&a.ctrl->dir) != 1) return;   // this BFS level runs push
+    const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.bump_level && f > 0) stc(&a.ctrl->level, ldc(&a.ctrl->level) + 1);
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < f; p += gridDim.x * 256) {
+        const int32_t j = a.x_idx[p];
+        if (j < 0 || j >= a.n) {
+            atomicOr(&a.ctrl->err, ERR_X_RANGE);
+            continue;
+        }
+        uint32_t v;
+        if constexpr (XMODE == XV_BITS32) v = reinterpret_cast<const uint32_t*>(a.x_val)[p];
+        else if constexpr (XMODE == XV_INDEX) v = (uint32_t)j;
+        else if constexpr (XMODE == XV_U8) v = reinterpret_cast<const uint8_t*>(a.x_val)[p] ? 1u : 0u;
+        else v = 1u;
+        a.xdense[j] = v;
+        atomicOr(&a.xbits[j >> 5], 1u << (j & 31));
+    }
+}
+
+// ------------------------------------------------------------- row walk
+// Workgroup c covers merge-path diagonals [c*C, (c+1)*C) of the sequence
+// "stored entries of row 0, end of row 0, entries of row 1, ...".  part[c] =
+// rows ended before diagonal c*C (computed once per matrix).  Each thread
+// walks ITEMS consecutive diagonals; a row wholly inside one thread is
+// written directly, a row split across threads or workgroups is combined
+// with one global atomic per piece.
+template <int BLOCK, int ITEMS, int SR, bool EARLY>
+__global__ __launch_bounds__(BLOCK) void k_pull(PullArgs a) {
+    constexpr int C = BLOCK * ITEMS;
+    __shared__ int32_t s_re[C + 2];   // diagonal index of each row end touched by this workgroup
+    const int tid = threadIdx.x;
+    if (a.gate && ldc(&a.ctrl->dir) != 1) return;
+    const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
+    if (f <= 0) return;
+    const int64_t total = (int64_t)a.m + a.nnz;
+    const int64_t d0 = (int64_t)blockIdx.x * C;
+    if (d0 >= total) return;
+    const int64_t d1 = min(d0 + C, total);
+    const int r0 = a.part[blockIdx.x];
+    const int r1 = a.part[blockIdx.x + 1];
+    const int rlast = min(r1, a.m - 1);
+    for (int k = tid; k <= rlast - r0; k += BLOCK) s_re[k] = (r0 + k) + a.rowptr[r0 + k + 1];
+    __syncthreads();
+
+    int64_t dt = d0 + (int64_t)tid * ITEMS;
+    const int64_t dend = min(dt + ITEMS, d1);
+    if (dt >= dend) return;
+    // rows ended before dt: count of s_re[k] < dt among rows r0..rlast
+    int lo = 0, hi = rlast - r0 + 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)s_re[mid] < dt) lo = mid + 1; else hi = mid;
+    }
+    int r = r0 + lo;
+    int64_t q = dt - r;
+    const uint32_t* __restrict__ colids = a.colids;
+    bool whole = r < a.m && q == a.rowptr[r];   // the thread holds row r from its first entry
+    bool hit = false, done = false, skip = false;
+    uint32_t acc = ident<SR>();
+    if (r < a.m && a.mask) skip = (a.mask[r >> 5] >> (r & 31)) & 1u;
+    for (; dt < dend; ++dt) {
+        if (r >= a.m) break;
+        const int64_t rend = (int64_t)s_re[r - r0] - r;   // rowptr[r + 1]
+        if (q < rend) {
+            if (!skip && !done) {
+                const uint32_t j = colids[q];
+                if ((a.xbits[j >> 5] >> (j & 31)) & 1u) {
+                    uint32_t t;
+                    if constexpr (SR == SR_PLUS_TIMES) {
+                        const float av = a.values ? a.values[q] : 1.0f;
+                        t = __float_as_uint(__fmul_rn(av, __uint_as_float(a.xdense[j])));
+                    } else if constexpr (SR == SR_MIN_SELECT2ND) {
+                        t = a.xdense[j];
+                    } else {
+                        const uint32_t av = a.values ? (a.values[q] != 0.0f ? 1u : 0u) : 1u;
+                        t = av & a.xdense[j];
+                    }
+                    acc = hit ? comb<SR>(acc, t) : t;
+                    hit = true;
+                    // or-and: nothing can change a true row; min-select2nd with
+                    // ascending column ids and x value = column id: the first hit
+                    // of this piece of the row is its minimum.
+                    if (EARLY) done = (SR == SR_OR_AND) ? (acc != 0u) : true;
+                }
+            }
+            ++q;
+        } else {
+            // end of row r
+            if (hit) {
+                if (whole) a.ydense[r] = acc;
+                else comb_global<SR>(&a.ydense[r], acc);
+                atomicOr(&a.ybits[r >> 5], 1u << (r & 31));
+            }
+            ++r;
+            hit = false;
+            done = false;
+            whole = true;
+            acc = ident<SR>();
+            skip = (r < a.m && a.mask) ? ((a.mask[r >> 5] >> (r & 31)) & 1u) : false;
+        }
+    }
+    if (hit && r < a.m) {   // row continues past this thread
+        comb_global<SR>(&a.ydense[r], acc);
+        atomicOr(&a.ybits[r >> 5], 1u << (r & 31));
+    }
+}
+
+// -------------------------------------------------------------- emit y
+// Walks ybits in order, kEmitWords words per workgroup, and writes y with a
+// decoupled look-back for the offsets.  Resets ybits / ydense for the next
+// call and clears the x bits this call set.
+constexpr int kEmitBlock = 256;
+constexpr int kEmitWords = 1024;
+
+__device__ uint64_t lookback_p(uint64_t* st, int tile, uint64_t agg, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    if (tile == 0) {
+        if (lane == 0) __hip_atomic_store(&st[0], LBP_INC | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    if (lane == 0) __hip_atomic_store(&st[tile], LBP_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    int base = tile - 1, spins = 0;
+    for (;;) {
+        const int idx = base - lane;
+        const uint64_t w = idx >= 0 ? __hip_atomic_load(&st[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LBP_INC;
+        const uint64_t status = w >> 62;
+        const uint64_t inc = __ballot(status == 2), emp = __ballot(status == 0);
+        const uint64_t need = inc ? (((inc & (~inc + 1)) << 1) - 1) : ~0ull;
+        if (emp & need) {
+            if (++spins > kSpinMaxP) {
+                if (lane == 0) atomicOr(err, ERR_SPIN);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = ((need >> lane) & 1ull) ? (w & LBP_VAL) : 0ull;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        excl += v;
+        if (inc) break;
+        base -= 64;
+    }
+    if (lane == 0) __hip_atomic_store(&st[tile], LBP_INC | ((excl + agg) & LBP_VAL), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+template <int SR, bool BFS>
+__global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
+    __shared__ int s_tmp[kEmitBlock / 64 + 1];
+    __shared__ int64_t s_excl;
+    const int tid = threadIdx.x;
+    if (a.gate && ldc(&a.ctrl->dir) != 1) return;
+    const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
+    const int nw = (a.m + 31) >> 5;
+    const int w0 = blockIdx.x * kEmitWords;
+    // clear this call's x bits (every workgroup shares the work)
+    for (int p = blockIdx.x * kEmitBlock + tid; p < f; p += gridDim.x * kEmitBlock) {
+        const int32_t j = a.x_idx[p];
+        if (j >= 0 && j < a.n) a.xbits[j >> 5] = 0u;
+    }
+    constexpr int PER = kEmitWords / kEmitBlock;
+    uint32_t bits[PER];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int w = w0 + tid * PER + k;
+        bits[k] = w < nw ? a.ybits[w] : 0u;
+        cnt += __popc(bits[k]);
+    }
+    // block exclusive scan of cnt
+    const int lane = tid & 63, wid = tid >> 6;
+    int x = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_tmp[wid] = x;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < kEmitBlock / 64; ++w) {
+            const int t = s_tmp[w];
+            s_tmp[w] = acc;
+            acc += t;
+        }
+        s_tmp[kEmitBlock / 64] = acc;
+    }
+    __syncthreads();
+    const int pos = s_tmp[wid] + x - cnt;
+    const int tot = s_tmp[kEmitBlock / 64];
+    if (tid < 64) {
+        const uint64_t e = lookback_p(a.lbp, blockIdx.x, (uint64_t)tot, &a.ctrl->err);
+        if (tid == 0) {
+            s_excl = (int64_t)e;
+            if (blockIdx.x == gridDim.x - 1) {
+                const int64_t total = (int64_t)e + tot;
+                a.ctrl->nnz_y = total;
+                if (a.d_nnz_y) *a.d_nnz_y = total;
+                if (a.set_f) stc(&a.ctrl->f, (int32_t)total);
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t excl = s_excl;
+    const int lvl = BFS ? ldc(&a.ctrl->level) : 0;
+    int32_t* const level = BFS ? ldc_ptr(&a.ctrl->bfs_level) : nullptr;
+    int32_t* const parent = BFS ? ldc_ptr(&a.ctrl->bfs_parent) : nullptr;
+    int64_t o = excl + pos;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int w = w0 + tid * PER + k;
+        uint32_t b = bits[k];
+        if (b) {
+            a.ybits[w] = 0u;
+            if (BFS) a.visited[w] |= b;
+        }
+        while (b) {
+            const int bit = __ffs(b) - 1;
+            b &= b - 1u;
+            const int r = (w << 5) + bit;
+            const uint32_t v = a.ydense[r];
+            a.ydense[r] = ident<SR>();
+            if (o < a.y_cap) {
+                a.y_idx[o] = r;
+                if (a.y_val) {
+                    if (SR == SR_OR_AND) reinterpret_cast<uint8_t*>(a.y_val)[o] = (uint8_t)(v != 0u);
+                    else reinterpret_cast<uint32_t*>(a.y_val)[o] = v;
+                }
+            }
+            if (BFS) {
+                level[r] = lvl;
+                if (parent) parent[r] = (int32_t)v;
+            }
+            ++o;
+        }
+    }
+    // the look-back words of this call are cleared by the next k_pull_prep
+}
+
+__global__ void k_lbp_clear(uint64_t* lbp, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) lbp[i] = 0;
+}
+
+__global__ void k_fill32(uint32_t* p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// part[c] = rows ended before diagonal c*C of the (row ends + entries) merge path.
+__global__ void k_pull_partition(const int32_t* rowptr, int32_t m, int64_t nnz, int C, int32_t* part, int nparts) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nparts; c += gridDim.x * blockDim.x) {
+        const int64_t d = min((int64_t)c * C, (int64_t)m + nnz);
+        // smallest r in [0, m] with r + rowptr[r + 1] >= d (row r's end token at or after d)
+        int lo = 0, hi = m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int64_t)mid + rowptr[mid + 1] < d) lo = mid + 1; else hi = mid;
+        }
+        part[c] = lo;
+    }
+}
+
+// Transpose: CSR column ids / values from CSC, slot order within a row is
+// the order of atomic arrival.
+__global__ void k_transpose(const int32_t* colptr, const int32_t* rowids, const float* values, int32_t n,
+                            const int32_t* rowptr, int32_t* cursor, int32_t* colids, float* tvalues) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        for (int q = colptr[j]; q < colptr[j + 1]; ++q) {
+            const int32_t i = rowids[q];
+            const int32_t slot = rowptr[i] + atomicAdd(&cursor[i], 1);
+            colids[slot] = j;
+            if (tvalues) tvalues[slot] = values ? values[q] : 1.0f;
+        }
+    }
+}
+
+// Row ids ascending inside every column (enables the first-hit exit of the
+// pull min-select2nd BFS on a symmetric matrix).
+__global__ void k_check_sorted(const int32_t* colptr, const int32_t* rowids, int32_t n, uint32_t* unsorted) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        for (int q = colptr[j] + 1; q < colptr[j + 1]; ++q)
+            if (rowids[q] <= rowids[q - 1]) {
+                atomicOr(unsorted, 1u);
+                break;
+            }
+}
+
+}  // namespace
+
+hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, hipStream_t s) {
+    int64_t fg = (a.f_host + 255) / 256 + 1;
+    if (a.f_dev || fg > 1024) fg = 1024;
+    const int f_grid = (int)fg;
+    hipLaunchKernelGGL(k_lbp_clear, dim3(64), dim3(256), 0, s, a.lbp, a.emit_blocks);
+    switch (xmode) {
+        case XV_BITS32: hipLaunchKernelGGL(k_pull_prep<XV_BITS32>, dim3(f_grid), dim3(256), 0, s, a); break;
+        case XV_INDEX: hipLaunchKernelGGL(k_pull_prep<XV_INDEX>, dim3(f_grid), dim3(256), 0, s, a); break;
+        case XV_U8: hipLaunchKernelGGL(k_pull_prep<XV_U8>, dim3(f_grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_pull_prep<XV_TRUE>, dim3(f_grid), dim3(256), 0, s, a); break;
+    }
+    const dim3 g(a.pull_blocks), b(kPullBlock);
+    switch (semiring) {
+        case SR_PLUS_TIMES: hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_PLUS_TIMES, false>), g, b, 0, s, a); break;
+        case SR_MIN_SELECT2ND:
+            if (early) hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_MIN_SELECT2ND, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_MIN_SELECT2ND, false>), g, b, 0, s, a);
+            break;
+        default:
+            if (early) hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, false>), g, b, 0, s, a);
+            break;
+    }
+    const dim3 ge(a.emit_blocks), be(kEmitBlock);
+    switch (semiring) {
+        case SR_PLUS_TIMES: hipLaunchKernelGGL((k_emit<SR_PLUS_TIMES, false>), ge, be, 0, s, a); break;
+        case SR_MIN_SELECT2ND:
+            if (bfs) hipLaunchKernelGGL((k_emit<SR_MIN_SELECT2ND, true>), ge, be, 0, s, a);
+            else hipLaunchKernelGGL((k_emit<SR_MIN_SELECT2ND, false>), ge, be, 0, s, a);
+            break;
+        default:
+            if (bfs) hipLaunchKernelGGL((k_emit<SR_OR_AND, true>), ge, be, 0, s, a);
+            else hipLaunchKernelGGL((k_emit<SR_OR_AND, false>), ge, be, 0, s, a);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u64(uint64_t* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lbp_clear, dim3(64), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_ident(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill32, dim3(2048), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+int pull_emit_blocks(int32_t m) { return ((m + 31) / 32 + kEmitWords - 1) / kEmitWords; }
+int pull_blocks(int32_t m, int64_t nnz) { return (int)(((int64_t)m + nnz + kPullChunk - 1) / kPullChunk); }
+
+hipError_t launch_pull_setup(const int32_t* colptr, const int32_t* rowids, const float* values, int32_t m,
+                             int32_t n, int64_t nnz, const int32_t* rowptr, int32_t* cursor, int32_t* colids,
+                             float* tvalues, int32_t* part, uint32_t* unsorted, hipStream_t s) {
+    if (colids) {
+        hipLaunchKernelGGL(k_transpose, dim3(1024), dim3(256), 0, s, colptr, rowids, values, n, rowptr, cursor, colids,
+                           tvalues);
+    } else if (unsorted) {
+        hipLaunchKernelGGL(k_check_sorted, dim3(1024), dim3(256), 0, s, colptr, rowids, n, unsorted);
+    }
+    const int nparts = pull_blocks(m, nnz) + 1;
+    hipLaunchKernelGGL(k_pull_partition, dim3((nparts + 255) / 256), dim3(256), 0, s, colids ? rowptr : colptr, m,
+                       nnz, kPullChunk, part, nparts);
+    return hipGetLastError();
+}
+
+}  // namespace spv

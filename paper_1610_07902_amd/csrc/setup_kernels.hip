@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kScanBlk) void k_span_apply(int32_t* data, int64_t 
 }
 
 __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl) {
+                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
         level[v] = (v == root) ? 0 : -1;
@@ -118,6 +118,9 @@ __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
         ctrl->level = 0;
         ctrl->bfs_level = level;
         ctrl->bfs_parent = parent;
+        ctrl->dir = 0;
+        ctrl->policy = policy;
+        ctrl->edges_left = nnz;
     }
 }
 
@@ -132,6 +135,29 @@ __global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint
         }
         heavy[w] = bits;
     }
+}
+
+// Direction of the next BFS level from the frontier just scanned (Beamer,
+// Asanovic and Patterson's direction-optimizing rule): switch push -> pull
+// when the frontier's stored entries exceed edges_left / 14, pull -> push
+// when the frontier holds fewer than n / 24 vertices.
+__global__ void k_decide(Ctrl* ctrl, int32_t n, int64_t nnz) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t W = __hip_atomic_load(&ctrl->W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t prev = __hip_atomic_load(&ctrl->dir, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t policy = __hip_atomic_load(&ctrl->policy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t left = __hip_atomic_load(&ctrl->edges_left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int dir = 0;
+    if (policy == 1) {
+        if (prev == 0) dir = ((int64_t)W * 14 > left) ? 1 : 0;
+        else dir = ((int64_t)f * 24 < (int64_t)n) ? 0 : 1;
+    }
+    left -= W;
+    if (left < 0) left = 0;
+    __hip_atomic_store(&ctrl->edges_left, left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctrl->dir, dir, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    (void)nnz;
 }
 
 inline int grid_for(int64_t count, int block, int cap = 4096) {
@@ -180,10 +206,15 @@ hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint
     return hipGetLastError();
 }
 
+hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, ctrl, n, nnz);
+    return hipGetLastError();
+}
+
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl, hipStream_t s) {
+                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, n, root, level, parent,
-                       visited, frontier, ctrl);
+                       visited, frontier, ctrl, nnz, policy);
     return hipGetLastError();
 }
 

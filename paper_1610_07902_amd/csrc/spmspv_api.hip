@@ -52,10 +52,13 @@ inline int ceil_log2(int64_t v) {
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
         heavy, total;
+    // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
+    size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values;
+    bool pull, transpose;
     int64_t nb_max, lb1_n, chunk_n;
 };
 
-Layout make_layout(int64_t m, int64_t n, int64_t nnz) {
+Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -81,6 +84,20 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz) {
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
     L.heavy = take(size_t((m + 31) / 32) * 4);
+    L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
+    L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
+    if (L.pull) {
+        L.p_xbits = take(size_t((n + 31) / 32) * 4);
+        L.p_xdense = take(size_t(n) * 4);
+        L.p_ybits = take(size_t((m + 31) / 32) * 4);
+        L.p_ydense = take(size_t(m) * 4);
+        L.p_lbp = take(size_t(pull_emit_blocks((int32_t)m) + 1) * 8);
+        L.p_part = take(size_t(pull_blocks((int32_t)m, nnz) + 2) * 4);
+    }
+    if (L.transpose) {
+        L.t_colids = take(size_t(nnz + 1) * 4);
+        L.t_values = take(size_t(nnz + 1) * 4);
+    }
     L.total = o;
     return L;
 }
@@ -119,6 +136,19 @@ struct spmspv_matrix {
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    // pull direction
+    bool pull = false;
+    bool rows_sorted = false;           // CSR rows have ascending column ids
+    const int32_t* rowptr = nullptr;
+    const uint32_t* colids = nullptr;
+    const float* rvalues = nullptr;
+    uint32_t* p_xbits = nullptr;
+    uint32_t* p_xdense = nullptr;
+    uint32_t* p_ybits = nullptr;
+    uint32_t* p_ydense = nullptr;
+    uint64_t* p_lbp = nullptr;
+    int32_t* p_part = nullptr;
+    uint32_t ydense_ident = 0;
 };
 
 namespace {
@@ -142,7 +172,9 @@ int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
 }
 
 int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
-    if (s->direction != 0) return fail(SPMSPV_EUNSUPPORTED, "only the push direction is built");
+    if (s->direction != 0 && s->direction != 1) return fail(SPMSPV_EINVAL, "direction must be 0 (push) or 1 (pull)");
+    if (s->direction == 1 && !A->pull)
+        return fail(SPMSPV_EUNSUPPORTED, "pull needs a handle created with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
     if (s->tile_log2 < kTileLog2Min || s->tile_log2 > kTileLog2Max)
         return fail(SPMSPV_EINVAL, "tile_log2 out of [8, 15]");
     const int64_t nb = (A->m + (int64_t(1) << s->tile_log2) - 1) >> s->tile_log2;
@@ -164,7 +196,7 @@ inline int64_t num_buckets(const spmspv_matrix* A) {
 // Enqueue the three phases of one y <- A x.
 int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_host, const int32_t* f_dev,
             const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y,
-            bool bfs, int32_t* level, int32_t* parent, hipStream_t s, hipEvent_t* ev) {
+            bool bfs, int32_t* level, int32_t* parent, hipStream_t s, hipEvent_t* ev, bool diropt = false) {
     const spmspv_schedule& sc = A->sched;
     const int nb = (int)num_buckets(A);
     const int chunk = sc.scatter_block * sc.scatter_items;
@@ -222,6 +254,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     if (ca.lb1_clear > ca.lb1_n) ca.lb1_clear = ca.lb1_n;
     ca.f_host = (int32_t)f_host;
     ca.f_dev = f_dev;
+    ca.gate = diropt ? 1 : 0;
     int64_t wbound = f_dev ? A->nnz : f_host * (int64_t)A->maxdeg;
     if (wbound > A->nnz) wbound = A->nnz;
     int64_t g2 = (wbound + chunk - 1) / chunk;
@@ -246,14 +279,65 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     (void)level;
     (void)parent;
     ma.set_f = bfs ? 1 : 0;
+    ma.gate = diropt ? 1 : 0;
 
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_scan(sa, (int)g1, s));
+    if (diropt) HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return SPMSPV_OK;
+}
+
+// Enqueue one pull-direction multiply (three launches).
+int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
+                 const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
+                 int64_t* d_nnz_y, bool bfs, bool bump, bool gate, hipStream_t s, hipEvent_t* ev) {
+    const uint32_t ident = semiring == SR_MIN_SELECT2ND ? 0x7fffffffu : 0u;
+    if (A->ydense_ident != ident) {
+        HIP_TRY(launch_fill_ident(A->p_ydense, ident, A->m, s));
+        A->ydense_ident = ident;
+    }
+    PullArgs pa{};
+    pa.ctrl = A->ctrl;
+    pa.m = (int32_t)A->m;
+    pa.n = (int32_t)A->n;
+    pa.nnz = A->nnz;
+    pa.rowptr = A->rowptr;
+    pa.colids = A->colids;
+    pa.values = A->rvalues;
+    pa.part = A->p_part;
+    pa.pull_blocks = pull_blocks((int32_t)A->m, A->nnz);
+    pa.x_idx = x_idx;
+    pa.x_val = x_val;
+    pa.f_host = (int32_t)f_host;
+    pa.f_dev = f_dev;
+    pa.xbits = A->p_xbits;
+    pa.xdense = A->p_xdense;
+    pa.ybits = A->p_ybits;
+    pa.ydense = A->p_ydense;
+    pa.mask = bfs ? A->visited : nullptr;
+    pa.lbp = A->p_lbp;
+    pa.emit_blocks = pull_emit_blocks((int32_t)A->m);
+    pa.y_idx = y_idx;
+    pa.y_val = y_val;
+    pa.y_cap = y_cap;
+    pa.d_nnz_y = d_nnz_y;
+    pa.visited = A->visited;
+    pa.set_f = bfs ? 1 : 0;
+    pa.bump_level = bump ? 1 : 0;
+    pa.gate = gate ? 1 : 0;
+    const bool early = semiring == SR_OR_AND || (semiring == SR_MIN_SELECT2ND && xmode == XV_INDEX && A->rows_sorted);
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_pull(pa, semiring, xmode, bfs, early, s));
+    if (ev) {
+        HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(hipEventRecord(ev[3], s));
+    }
     return SPMSPV_OK;
 }
 
@@ -303,7 +387,8 @@ int spmspv_workspace_size(int64_t m, int64_t n, int64_t nnz, int flags, size_t* 
     if (m < 1 || n < 1 || nnz < 0 || nnz >= (int64_t(1) << 31) || m >= (int64_t(1) << 31) ||
         n >= (int64_t(1) << 31))
         return fail(SPMSPV_EINVAL, "sizes out of range (need 1 <= m, n < 2^31, 0 <= nnz < 2^31)");
-    *h_bytes = make_layout(m, n, nnz).total;
+    if ((flags & SPMSPV_SYMMETRIC) && m != n) return fail(SPMSPV_EINVAL, "SPMSPV_SYMMETRIC needs m == n");
+    *h_bytes = make_layout(m, n, nnz, flags).total;
     return SPMSPV_OK;
 }
 
@@ -328,7 +413,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->colptr = colptr;
     A->rowids = rowids;
     A->values = values;
-    A->L = make_layout(m, n, nnz);
+    A->L = make_layout(m, n, nnz, flags);
     A->ws = static_cast<char*>(workspace);
     const Layout& L = A->L;
     A->ctrl = reinterpret_cast<Ctrl*>(A->ws + L.ctrl);
@@ -371,6 +456,39 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         return bail(hip_fail(e, "row count scan"));
     if ((e = launch_heavy_rows(A->rcp, (int32_t)m, kHeavyRow, A->heavy, s)) != hipSuccess)
         return bail(hip_fail(e, "heavy rows"));
+    if (L.pull) {
+        A->pull = true;
+        A->p_xbits = reinterpret_cast<uint32_t*>(A->ws + L.p_xbits);
+        A->p_xdense = reinterpret_cast<uint32_t*>(A->ws + L.p_xdense);
+        A->p_ybits = reinterpret_cast<uint32_t*>(A->ws + L.p_ybits);
+        A->p_ydense = reinterpret_cast<uint32_t*>(A->ws + L.p_ydense);
+        A->p_lbp = reinterpret_cast<uint64_t*>(A->ws + L.p_lbp);
+        A->p_part = reinterpret_cast<int32_t*>(A->ws + L.p_part);
+        // every pull region up to the transpose starts at zero (ydense = identity of + and or)
+        const size_t zb = L.p_xbits, ze = L.transpose ? L.t_colids : L.total;
+        if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + zb), 0u, int64_t((ze - zb) / 4), s)) != hipSuccess)
+            return bail(hip_fail(e, "zero pull buffers"));
+        A->ydense_ident = 0;
+        int32_t* colids_t = nullptr;
+        float* tvalues = nullptr;
+        if (L.transpose) {
+            colids_t = reinterpret_cast<int32_t*>(A->ws + L.t_colids);
+            tvalues = values ? reinterpret_cast<float*>(A->ws + L.t_values) : nullptr;
+            if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->front[0]), 0u, m, s)) != hipSuccess)
+                return bail(hip_fail(e, "zero transpose cursors"));
+            A->rowptr = A->rcp;
+            A->colids = reinterpret_cast<const uint32_t*>(colids_t);
+            A->rvalues = tvalues;
+        } else {
+            A->rowptr = colptr;
+            A->colids = reinterpret_cast<const uint32_t*>(rowids);
+            A->rvalues = values;
+        }
+        if ((e = launch_pull_setup(colptr, rowids, values, (int32_t)m, (int32_t)n, nnz, A->rowptr, A->front[0],
+                                   colids_t, tvalues, A->p_part, L.transpose ? nullptr : &A->ctrl->unsorted, s)) !=
+            hipSuccess)
+            return bail(hip_fail(e, "pull set-up"));
+    }
     Ctrl h{};
     if ((e = hipMemcpyAsync(&h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return bail(hip_fail(e, "read control block"));
@@ -382,6 +500,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         return bail(fail(SPMSPV_EINVAL, "invalid CSC detected while sizing buckets"));
     }
     A->maxdeg = h.maxdeg;
+    A->rows_sorted = A->pull && !L.transpose && h.unsorted == 0;
     default_schedule(A, &A->sched);
     if (check_schedule(A, &A->sched) != SPMSPV_OK)
         return bail(fail(SPMSPV_EUNSUPPORTED, "matrix too tall for the LDS bucket layout"));
@@ -437,8 +556,11 @@ int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_
         }
     }
     hipEvent_t* ev = (flags & SPMSPV_PROFILE) ? profile_slot(A) : nullptr;
-    int rc = enqueue(A, semiring, xmode, (flags & SPMSPV_SORTED_OUTPUT) != 0, f, nullptr, x_idx, x_val, y_idx, y_val,
-                     y_capacity, d_nnz_y, false, nullptr, nullptr, s, ev);
+    int rc = A->sched.direction == 1
+                 ? enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y,
+                                false, false, false, s, ev)
+                 : enqueue(A, semiring, xmode, (flags & SPMSPV_SORTED_OUTPUT) != 0, f, nullptr, x_idx, x_val, y_idx,
+                           y_val, y_capacity, d_nnz_y, false, nullptr, nullptr, s, ev);
     if (rc) return rc;
     if (h_nnz_y) {
         Ctrl h{};
@@ -467,21 +589,30 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
     const bool sorted = true;
+    const bool diropt = (flags & SPMSPV_DIRECTION_OPT) != 0;
+    if (diropt && !A->pull)
+        return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DIRECTION_OPT needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
 
 
     auto enqueue_levels = [&](int count, hipStream_t st) -> int {
         for (int l = 0; l < count; ++l) {
             int32_t* x = A->front[l & 1];
             int32_t* y = A->front[(l + 1) & 1];
-            const int rc = enqueue(A, semiring, xmode, sorted, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr,
-                                   true, level, parent, st, nullptr);
+            int rc = enqueue(A, semiring, xmode, sorted, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
+                             level, parent, st, nullptr, diropt);
             if (rc) return rc;
+            if (diropt) {
+                // pull kernels for the same level; they run only when k_decide chose pull
+                rc = enqueue_pull(A, semiring, xmode, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
+                                  false, true, st, nullptr);
+                if (rc) return rc;
+            }
         }
         return SPMSPV_OK;
     };
 
     const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
-    const int key = semiring + 1;
+    const int key = semiring + 1 + (diropt ? 8 : 0);
     if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
         if (A->graph) {
             (void)hipGraphExecDestroy(A->graph);
@@ -507,7 +638,8 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         }
         A->graph_key = key;
     }
-    HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, s));
+    HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz,
+                            diropt ? 1 : 0, s));
     // Level loop: kGraphLevels levels per batch, then one host check of the
     // frontier length.  Levels after the frontier empties are no-ops.
     int32_t hf = 1;

@@ -344,6 +344,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         a.lb1[a.lb1_n + i] = 0;
     }
 
+    if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
     const int W = ld_ctrl(&a.ctrl->W);
     const int fnz = ld_ctrl(&a.ctrl->fnz);
     const int nchunks = (int)(((int64_t)W + C - 1) / C);
@@ -571,6 +572,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
 
     // Buckets in blockIdx order: a bucket's look-back predecessors belong to
     // workgroups dispatched no later than its own (the wait is bounded).
+    if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
     if (tid == 0) s_ucnt = 0;
     const int b = blockIdx.x;
     const int W = ld_ctrl(&a.ctrl->W);

@@ -1,0 +1,122 @@
+"""GPU parity of the pull (matrix-driven) direction and of the
+direction-optimizing BFS, against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_07902_amd as spv
+    spv.load_library()
+    oracle.build(force=False)
+    synth.build(force=False)
+    return spv
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def pull_schedule(spv, M):
+    s = M.schedule
+    s.direction = 1
+    M.schedule = s
+
+
+def run_pair(spv, M, A, S, semiring, xval, flags=0):
+    gi, gv, nnz = M.spmspv(dev(S), None if xval is None else dev(xval), semiring=semiring, flags=flags)
+    if semiring == 1 and xval is None:
+        oxv = S.astype(np.int32)
+    elif semiring == 2 and xval is None:
+        oxv = np.ones(S.size, np.uint8)
+    else:
+        oxv = xval
+    oi, ov, W = oracle.spmspv(A, S, oxv, semiring, sorted_output=True)
+    compare(semiring, gi, gv, oi, ov, sorted_output=True)
+    assert M.last_stats()["err"] == 0
+
+
+@pytest.mark.parametrize("shape", [(5000, 3000), (1200, 4000), (4096, 4096)])
+def test_pull_with_transpose_all_semirings(spv, shape):
+    m, n = shape
+    rng = np.random.default_rng(m + n)
+    nt = 10 * max(m, n)
+    rows = np.concatenate([rng.integers(0, m, nt), np.full(n, 7)]).astype(np.int32)        # row 7: a hub
+    cols = np.concatenate([rng.integers(0, n, nt), np.arange(n)]).astype(np.int32)
+    colptr, rowids = synth.coo_to_csc(m, n, rows, cols, drop_self=False)
+    A = synth.CSC(m, n, colptr, rowids, synth.values(rowids.size, 5))
+    M = spv.Matrix.from_csc(A, flags=spv.WITH_TRANSPOSE)
+    pull_schedule(spv, M)
+    assert M.schedule.direction == 1
+    for f in (1, n // 50, n // 3, n):
+        S, xv = synth.sparse_x(n, f, seed=f)
+        run_pair(spv, M, A, S, 0, xv)
+        run_pair(spv, M, A, S, 1, rng.integers(-500, 500, f).astype(np.int32))
+        run_pair(spv, M, A, S, 1, None, flags=spv.X_VAL_IS_INDEX)
+        run_pair(spv, M, A, S, 2, (rng.random(f) < 0.6).astype(np.uint8))
+        run_pair(spv, M, A, S, 2, None, flags=spv.X_ALL_TRUE)
+
+
+def test_pull_symmetric_pattern(spv):
+    A = synth.rmat(15, seed=3, symmetrize=True, with_values=False)
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC)
+    pull_schedule(spv, M)
+    for f in (10, 3000, 30000):
+        S, xv = synth.sparse_x(A.n, f, seed=f + 1)
+        run_pair(spv, M, A, S, 0, xv)
+        run_pair(spv, M, A, S, 1, None, flags=spv.X_VAL_IS_INDEX)
+        run_pair(spv, M, A, S, 2, None, flags=spv.X_ALL_TRUE)
+    # push and pull give the same bits for int / bool
+    S, _ = synth.sparse_x(A.n, 5000, seed=9)
+    a = M.spmspv(dev(S), None, semiring=1, flags=spv.X_VAL_IS_INDEX)
+    M.schedule = None
+    b = M.spmspv(dev(S), None, semiring=1, flags=spv.X_VAL_IS_INDEX, sorted_output=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_pull_rejected_without_rows(spv):
+    A = synth.rmat(10, seed=1)
+    M = spv.Matrix.from_csc(A)
+    s = M.schedule
+    s.direction = 1
+    with pytest.raises(spv.SpmspvError):
+        M.schedule = s
+
+
+@pytest.mark.parametrize("create_flag", ["SYMMETRIC", "WITH_TRANSPOSE"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_direction_optimizing_bfs(spv, create_flag, graph):
+    A = synth.rmat(16, seed=1, symmetrize=True, with_values=False)
+    M = spv.Matrix.from_csc(A, flags=getattr(spv, create_flag))
+    fl = spv.DIRECTION_OPT | (spv.USE_GRAPH if graph else 0)
+    for root in synth.roots(A, 3, seed=2000):
+        lev, par, nl = M.bfs(int(root), spv.MIN_SELECT2ND_I32, flags=fl)
+        olev, opar, onl = oracle.bfs(A, int(root))
+        assert nl == onl
+        assert np.array_equal(lev.cpu().numpy(), olev)
+        assert np.array_equal(par.cpu().numpy(), opar)
+        lev2, _, nl2 = M.bfs(int(root), spv.OR_AND_BOOL, flags=fl)
+        assert nl2 == onl and np.array_equal(lev2.cpu().numpy(), olev)
+
+
+def test_direction_optimizing_grid(spv):
+    nx = 48
+    G = synth.grid(nx, nx, nx, diag=True)
+    M = spv.Matrix.from_csc(G, flags=spv.SYMMETRIC)
+    lev, par, nl = M.bfs(0, spv.MIN_SELECT2ND_I32, flags=spv.DIRECTION_OPT | spv.USE_GRAPH)
+    v = np.arange(G.n)
+    x, y, z = v % nx, (v // nx) % nx, v // (nx * nx)
+    assert nl == 3 * (nx - 1) + 1 and np.array_equal(lev.cpu().numpy(), x + y + z)
+    ep = np.where(z > 0, v - nx * nx, np.where(y > 0, v - nx, v - 1))
+    ep[0] = 0
+    assert np.array_equal(par.cpu().numpy(), ep)
