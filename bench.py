@@ -79,7 +79,7 @@ def main():
     t0 = time.time()
     A = synth.rmat(args.scale, 16, seed=1, symmetrize=True)
     log(f"generated {A.name}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
-    M = spv.Matrix.from_csc(A, device=dev)
+    M = spv.Matrix.from_csc(A, device=dev, flags=spv.WITH_TRANSPOSE)
     deg = A.degrees()
     f = synth.density_f(A.n, args.density)
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in range(args.nx)]
@@ -241,49 +241,53 @@ def sweep(spv, M, A, deg, dev, stream):
             f = synth.density_f(A.n, dens)
             nx = 16
             xs = [synth.sparse_x(A.n, f, seed=3000 + r) for r in range(nx)]
-            W = np.array([int(deg[x[0]].sum()) for x in xs])
+            W = float(np.mean([int(deg[x[0]].sum()) for x in xs]))
             xi = [torch.as_tensor(x[0]).to(dev) for x in xs]
             xv = [torch.as_tensor(x[1] if sr == 0 else x[0]).to(dev) for x in xs]
             y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
             y_val = torch.empty(A.m, dtype=torch.float32 if sr == 0 else torch.int32, device=dev)
-            steps = 64
-            for i in range(8):
-                spv.spmspv_run(M.handle, sr, 0, f, xi[i % nx], xv[i % nx], y_idx, y_val, A.m, sync=False,
-                               stream=stream)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for i in range(steps):
-                spv.spmspv_run(M.handle, sr, 0, f, xi[i % nx], xv[i % nx], y_idx, y_val, A.m, sync=False,
-                               stream=stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
-            prod = float(np.mean([W[i % nx] for i in range(steps)]))
-            out[f"{name}@{dens:g}"] = {"f": f, "us": round(ms * 1e3, 2), "GTEPS": round(prod / (ms * 1e-3) / 1e9, 3)}
-            log(f"sweep {name} density {dens:g}: {ms * 1e3:.1f} us, {out[f'{name}@{dens:g}']['GTEPS']} GTEPS")
+            rec = {"f": f}
+            for direction in (0, 1):
+                s = M.schedule
+                s.direction = direction
+                M.schedule = s
+                ms = time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, A.m, 64, stream)
+                key = "push" if direction == 0 else "pull"
+                rec[key + "_us"] = round(ms * 1e3, 2)
+                rec[key + "_GTEPS"] = round(W / (ms * 1e-3) / 1e9, 3)
+            M.schedule = None
+            out[f"{name}@{dens:g}"] = rec
+            log(f"sweep {name} density {dens:g}: {rec}")
     return out
 
 
 def bfs_bench(spv, M, A, dev):
+    """BFS from 16 roots on the pattern of A: push only vs direction-optimizing."""
     import torch
     import synth
+    P = spv.Matrix(A.m, A.n, M.colptr, M.rowids, None, flags=spv.SYMMETRIC, device=dev)
     roots = synth.roots(A, 16, seed=2000)
     deg = A.degrees()
-    total_ms, total_w, levels = 0.0, 0, []
-    for flags in (spv.USE_GRAPH,):
-        M.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, flags=flags)   # warm (graph capture)
+    out = {"roots": 16}
+    for name, flags in (("push", spv.USE_GRAPH), ("diropt", spv.USE_GRAPH | spv.DIRECTION_OPT)):
+        P.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, flags=flags)   # warm (graph capture)
+        total_ms, total_w, levels = 0.0, 0, []
         for r in roots:
             torch.cuda.synchronize()
             t = time.perf_counter()
-            lev, par, nl = M.bfs(int(r), spv.MIN_SELECT2ND_I32, flags=flags)
+            lev, par, nl = P.bfs(int(r), spv.MIN_SELECT2ND_I32, flags=flags)
             torch.cuda.synchronize()
             total_ms += (time.perf_counter() - t) * 1e3
             lv = lev.cpu().numpy()
             total_w += int(deg[lv >= 0].sum())
             levels.append(nl)
-    return {"roots": 16, "total_ms": round(total_ms, 2), "GTEPS": round(total_w / (total_ms * 1e-3) / 1e9, 3),
-            "levels": levels, "note": "push-only, per-level three kernels in a replayed hipGraph"}
+        out[name] = {"total_ms": round(total_ms, 2), "GTEPS": round(total_w / (total_ms * 1e-3) / 1e9, 3),
+                     "levels": levels}
+        log(f"bfs {name}: {out[name]}")
+    out["note"] = ("GTEPS = sum over reached vertices of their column length (push-equivalent products) / time; "
+                   "min-select2nd semiring (parents = smallest in-neighbour on the previous level)")
+    P.close()
+    return out
 
 
 if __name__ == "__main__":

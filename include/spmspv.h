@@ -84,10 +84,16 @@ enum spmspv_flags {
     SPMSPV_SYMMETRIC = 128,    /* create: caller states A == A^T (pattern and
                                   values); the pull direction reads A's
                                   columns as rows, no transpose is built      */
-    SPMSPV_DIRECTION_OPT = 256 /* bfs_run: choose push or pull per level
+    SPMSPV_DIRECTION_OPT = 256,/* bfs_run: choose push or pull per level
                                   (Beamer's frontier-edge heuristic); needs a
                                   handle created with one of the two flags
                                   above                                       */
+    SPMSPV_USE_SELECTOR = 512  /* spmspv_run / bfs_run: a small MLP loaded with
+                                  spmspv_selector_load picks the bucket count
+                                  (or the pull direction) per call from
+                                  features the scan computes on the device;
+                                  one extra host synchronisation per call or
+                                  BFS level                                   */
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any
@@ -148,6 +154,14 @@ int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_
                int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
                void* stream);
 
+/* spmspv_run with an output mask (the masked SpMSpV of Conclusions and
+ * Future Work): `mask` is a device bitmap of ceil(m / 32) uint32 words; row
+ * i is excluded from y when bit (i & 31) of word i >> 5 is set, and its
+ * products are dropped before bucketing.  NULL mask = spmspv_run.       */
+int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx,
+                      const void* x_val, const uint32_t* mask, int32_t* y_idx, void* y_val, int64_t y_capacity,
+                      int64_t* d_nnz_y, int64_t* h_nnz_y, void* stream);
+
 /* Breadth-first search from `root` by repeated SpMSpV on the frontier
  * (Results, "Performance of SpMSpV algorithms when used in BFS"; the
  * frontier-expansion pattern of the Introduction), with the visited set as
@@ -172,7 +186,9 @@ int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
 /* Statistics of the most recent spmspv_run / BFS level (synchronous):
  * h_out[0] = products W (sum of selected column lengths, the work bound of
  * the lower-bound section), [1] = nnz(y), [2] = non-empty selected columns,
- * [3] = maximum selected column length, [4] = device error bits.          */
+ * [3] = maximum selected column length, [4] = device error bits,
+ * [5] = selector class of the last SPMSPV_USE_SELECTOR call.  h_out holds
+ * 6 entries.                                                              */
 int spmspv_last_stats(spmspv_handle A, int64_t* h_out, void* stream);
 
 /* Per-kernel timing of calls made with SPMSPV_PROFILE: waits for the
@@ -184,6 +200,45 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
 /* Release the handle (host memory and HIP events only; the caller frees
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
+
+/* ---- schedule selector (a learned replacement for the fixed bucket count
+ * of "Performance optimizations"; see the bucket-count discussion there).
+ * The selector is a fully connected network 6 -> 64 -> 64 -> 10 with ReLU
+ * after both hidden layers, fp32.  Parameter layout (5258 floats):
+ *   W1[64][6], b1[64], W2[64][64], b2[64], W3[10][64], b3[10].
+ * Inputs are log2(1 + v) of six per-call quantities the scan produces --
+ * f, W (products), max selected column length, n, nnz/n, unvisited rows
+ * (BFS; n otherwise) -- each standardised as (v - mean[c]) / std[c].
+ * Output class c in 0..8 = push with 2^(c+4) buckets (tile clamped to what
+ * LDS holds); 9 = pull direction (push tile of class 8 when the handle has
+ * no row form).                                                           */
+
+/* Copy host weights and feature standardisation to the handle (synchronous).
+ * EINVAL for non-finite weights or std <= 0 (the selector is then disabled). */
+int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_mean, const float* h_std,
+                         void* stream);
+
+/* Classes chosen per level by the most recent bfs_run with
+ * SPMSPV_USE_SELECTOR: writes min(cap, count) entries, *h_count = count.  */
+int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count);
+
+/* tile_log2 that class `cls` (0..8) runs with on this handle; -1 for 9.   */
+int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2);
+
+/* Number of selector parameters (5258). */
+int spmspv_mlp_param_count(void);
+
+/* logits[batch][10] <- MLP(params, X[batch][6]) on the device.          */
+int spmspv_mlp_forward(const float* params, const float* X, int batch, float* logits, void* stream);
+
+/* One training step on the device: mean softmax cross-entropy of
+ * (X[batch][6], labels[batch] in 0..9), its gradient by backpropagation,
+ * then (lr > 0) one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction with `step` >= 1) of params / adam_m / adam_v in place.
+ * grad [5258] and d_loss [1] receive the gradient and loss (nullable).
+ * 1 <= batch <= 128; one workgroup; sums in a fixed order.               */
+int spmspv_mlp_train_step(float* params, float* adam_m, float* adam_v, int step, float lr, const float* X,
+                          const int32_t* labels, int batch, float* grad, float* d_loss, void* stream);
 
 /* Static description of a status code; detail of the last error on this
  * host thread. */

@@ -53,10 +53,9 @@ def _bind(lib):
         lib.oracle_pagerank.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp]
         lib.oracle_pagerank.restype = ctypes.c_int
     if hasattr(lib, "oracle_mlp_forward"):
-        lib.oracle_mlp_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                           vp, vp, vp, vp, vp, vp, vp, vp]
-        lib.oracle_mlp_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                             ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        ci = ctypes.c_int
+        lib.oracle_mlp_forward.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp]
+        lib.oracle_mlp_loss_grad.argtypes = [ci, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_mlp_loss_grad.restype = ctypes.c_double
     return lib
 
@@ -139,3 +138,36 @@ def bfs(A, root: int, lib=None):
     par = np.empty(A.n, np.int32)
     nl = lib.oracle_bfs(A.n, _p(A.colptr), _p(A.rowids), int(root), _p(lev), _p(par))
     return lev, par, int(nl)
+
+
+# ------------------------------------------------------------ selector MLP
+MLP_SHAPE = (6, 64, 64, 10)
+
+
+def mlp_param_count(shape=MLP_SHAPE) -> int:
+    i, h1, h2, o = shape
+    return h1 * i + h1 + h2 * h1 + h2 + o * h2 + o
+
+
+def mlp_forward(params, X, shape=MLP_SHAPE, lib=None):
+    """fp64 logits [B][out] of the selector MLP (6 -> 64 ReLU -> 64 ReLU -> 10)."""
+    lib = lib or load()
+    i, h1, h2, o = shape
+    p = np.ascontiguousarray(params, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    B = X.shape[0]
+    out = np.empty((B, o), np.float64)
+    lib.oracle_mlp_forward(i, h1, h2, o, B, _p(p), _p(X), _p(out), None, None, None, None)
+    return out
+
+
+def mlp_loss_grad(params, X, labels, shape=MLP_SHAPE, lib=None):
+    """(mean softmax cross-entropy, gradient in the parameter layout), fp64."""
+    lib = lib or load()
+    i, h1, h2, o = shape
+    p = np.ascontiguousarray(params, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    y = np.ascontiguousarray(labels, np.int32)
+    g = np.empty(mlp_param_count(shape), np.float64)
+    loss = lib.oracle_mlp_loss_grad(i, h1, h2, o, X.shape[0], _p(p), _p(X), _p(y), _p(g), None, None, None, None)
+    return float(loss), g

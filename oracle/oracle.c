@@ -199,3 +199,103 @@ int oracle_bfs(int64_t n, const int32_t* colptr, const int32_t* rowids, int32_t 
     free(queue);
     return maxl + 1;
 }
+
+/*
+ * Schedule-selector MLP in fp64: 6 inputs -> 64 ReLU -> 64 ReLU -> 10 logits,
+ * softmax cross-entropy, mean over the batch.  Parameter layout (flat):
+ *   W1[h1][in], b1[h1], W2[h2][h1], b2[h2], W3[out][h2], b3[out].
+ * oracle_mlp_forward writes logits[B][out]; oracle_mlp_loss_grad writes the
+ * gradient of the mean loss (same layout as the parameters) and returns the
+ * mean loss.  Plain loops, no blocking.
+ */
+static void mlp_layers(int in, int h1, int h2, int out, const double* p, const double* x, double* a1, double* a2,
+                       double* z3) {
+    const double* W1 = p;
+    const double* b1 = W1 + h1 * in;
+    const double* W2 = b1 + h1;
+    const double* b2 = W2 + h2 * h1;
+    const double* W3 = b2 + h2;
+    const double* b3 = W3 + out * h2;
+    for (int i = 0; i < h1; ++i) {
+        double z = b1[i];
+        for (int c = 0; c < in; ++c) z += W1[i * in + c] * x[c];
+        a1[i] = z > 0 ? z : 0;
+    }
+    for (int j = 0; j < h2; ++j) {
+        double z = b2[j];
+        for (int i = 0; i < h1; ++i) z += W2[j * h1 + i] * a1[i];
+        a2[j] = z > 0 ? z : 0;
+    }
+    for (int k = 0; k < out; ++k) {
+        double z = b3[k];
+        for (int j = 0; j < h2; ++j) z += W3[k * h2 + j] * a2[j];
+        z3[k] = z;
+    }
+}
+
+void oracle_mlp_forward(int in, int h1, int h2, int out, int B, const double* p, const double* X, double* logits,
+                        double* unused0, double* unused1, double* unused2, double* unused3) {
+    (void)unused0; (void)unused1; (void)unused2; (void)unused3;
+    double* a1 = (double*)malloc(sizeof(double) * h1);
+    double* a2 = (double*)malloc(sizeof(double) * h2);
+    for (int s = 0; s < B; ++s) mlp_layers(in, h1, h2, out, p, X + s * in, a1, a2, logits + s * out);
+    free(a1); free(a2);
+}
+
+double oracle_mlp_loss_grad(int in, int h1, int h2, int out, int B, const double* p, const double* X,
+                            const int* labels, double* grad, double* unused0, double* unused1, double* unused2,
+                            double* unused3) {
+    (void)unused0; (void)unused1; (void)unused2; (void)unused3;
+    const int np = h1 * in + h1 + h2 * h1 + h2 + out * h2 + out;
+    for (int q = 0; q < np; ++q) grad[q] = 0;
+    const double* W2 = p + h1 * in + h1;
+    const double* W3 = W2 + h2 * h1 + h2;
+    double* gW1 = grad;
+    double* gb1 = gW1 + h1 * in;
+    double* gW2 = gb1 + h1;
+    double* gb2 = gW2 + h2 * h1;
+    double* gW3 = gb2 + h2;
+    double* gb3 = gW3 + out * h2;
+    double* a1 = (double*)malloc(sizeof(double) * h1);
+    double* a2 = (double*)malloc(sizeof(double) * h2);
+    double* z3 = (double*)malloc(sizeof(double) * out);
+    double* d3 = (double*)malloc(sizeof(double) * out);
+    double* d2 = (double*)malloc(sizeof(double) * h2);
+    double* d1 = (double*)malloc(sizeof(double) * h1);
+    double loss = 0;
+    for (int s = 0; s < B; ++s) {
+        const double* x = X + s * in;
+        mlp_layers(in, h1, h2, out, p, x, a1, a2, z3);
+        double mx = z3[0];
+        for (int k = 1; k < out; ++k) if (z3[k] > mx) mx = z3[k];
+        double se = 0;
+        for (int k = 0; k < out; ++k) se += exp(z3[k] - mx);
+        loss += -(z3[labels[s]] - mx - log(se));
+        /* d(mean loss)/d z3 = (softmax - onehot) / B */
+        for (int k = 0; k < out; ++k) d3[k] = (exp(z3[k] - mx) / se - (k == labels[s] ? 1.0 : 0.0)) / B;
+        for (int k = 0; k < out; ++k) {
+            gb3[k] += d3[k];
+            for (int j = 0; j < h2; ++j) gW3[k * h2 + j] += d3[k] * a2[j];
+        }
+        for (int j = 0; j < h2; ++j) {
+            double t = 0;
+            for (int k = 0; k < out; ++k) t += W3[k * h2 + j] * d3[k];
+            d2[j] = a2[j] > 0 ? t : 0;
+        }
+        for (int j = 0; j < h2; ++j) {
+            gb2[j] += d2[j];
+            for (int i = 0; i < h1; ++i) gW2[j * h1 + i] += d2[j] * a1[i];
+        }
+        for (int i = 0; i < h1; ++i) {
+            double t = 0;
+            for (int j = 0; j < h2; ++j) t += W2[j * h1 + i] * d2[j];
+            d1[i] = a1[i] > 0 ? t : 0;
+        }
+        for (int i = 0; i < h1; ++i) {
+            gb1[i] += d1[i];
+            for (int c = 0; c < in; ++c) gW1[i * in + c] += d1[i] * x[c];
+        }
+    }
+    free(a1); free(a2); free(z3); free(d3); free(d2); free(d1);
+    return loss / B;
+}

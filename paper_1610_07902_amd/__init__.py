@@ -28,13 +28,19 @@ PROFILE = 32
 WITH_TRANSPOSE = 64
 SYMMETRIC = 128
 DIRECTION_OPT = 256
+USE_SELECTOR = 512
+
+MLP_PARAMS = 5258
+NUM_CLASSES = 10
 
 OK, EINVAL, ENOMEM, ECAPACITY, EHIP, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = (
     "spmspv_workspace_size", "spmspv_create", "spmspv_run", "bfs_run", "spmspv_get_schedule",
     "spmspv_set_schedule", "spmspv_last_stats", "spmspv_profile_read", "spmspv_destroy",
-    "spmspv_status_string", "spmspv_last_error",
+    "spmspv_status_string", "spmspv_last_error", "spmspv_run_masked", "spmspv_selector_load",
+    "spmspv_selector_classes", "spmspv_class_tile", "spmspv_mlp_param_count", "spmspv_mlp_forward",
+    "spmspv_mlp_train_step",
 )
 
 
@@ -75,6 +81,13 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_destroy.argtypes = [vp]
     lib.spmspv_status_string.argtypes = [ci]
     lib.spmspv_status_string.restype = ctypes.c_char_p
+    lib.spmspv_run_masked.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
+    lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
+    lib.spmspv_selector_classes.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.spmspv_class_tile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int32)]
+    lib.spmspv_mlp_param_count.argtypes = []
+    lib.spmspv_mlp_forward.argtypes = [vp, vp, ci, vp, vp]
+    lib.spmspv_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp, vp, ci, vp, vp, vp]
     lib.spmspv_last_error.argtypes = []
     lib.spmspv_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -129,6 +142,58 @@ def spmspv_run(handle, semiring, flags, f, x_idx, x_val, y_idx, y_val, y_capacit
     return h.value if sync else None
 
 
+def spmspv_run_masked(handle, semiring, flags, f, x_idx, x_val, mask, y_idx, y_val, y_capacity, d_nnz_y=None,
+                      sync=True, stream=None) -> Optional[int]:
+    """y <- A x with rows whose mask bit is set excluded (mask: int32/uint32 words)."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run_masked(handle, semiring, flags, f, _ptr(x_idx), _ptr(x_val), _ptr(mask),
+                                            _ptr(y_idx), _ptr(y_val), y_capacity, _ptr(d_nnz_y),
+                                            ctypes.byref(h) if sync else None, _stream(stream)))
+    return h.value if sync else None
+
+
+def spmspv_selector_load(handle, params, mean, std, stream=None):
+    """params / mean / std: host float32 numpy arrays (5258, 6, 6)."""
+    import numpy as np
+    p = np.ascontiguousarray(params, np.float32)
+    mu = np.ascontiguousarray(mean, np.float32)
+    sd = np.ascontiguousarray(std, np.float32)
+    if p.size != MLP_PARAMS or mu.size != 6 or sd.size != 6:
+        raise ValueError("selector weights must be 5258 + 6 + 6 floats")
+    _check(load_library().spmspv_selector_load(handle, p.ctypes.data, mu.ctypes.data, sd.ctypes.data,
+                                               _stream(stream)))
+
+
+def spmspv_selector_classes(handle) -> list:
+    cnt = ctypes.c_int32(0)
+    _check(load_library().spmspv_selector_classes(handle, None, 0, ctypes.byref(cnt)))
+    buf = (ctypes.c_int32 * max(cnt.value, 1))()
+    _check(load_library().spmspv_selector_classes(handle, buf, cnt.value, ctypes.byref(cnt)))
+    return list(buf[:cnt.value])
+
+
+def spmspv_class_tile(handle, cls: int) -> int:
+    t = ctypes.c_int32(0)
+    _check(load_library().spmspv_class_tile(handle, int(cls), ctypes.byref(t)))
+    return t.value
+
+
+def spmspv_mlp_param_count() -> int:
+    return int(load_library().spmspv_mlp_param_count())
+
+
+def spmspv_mlp_forward(params, X, logits, stream=None):
+    """logits[B][10] <- MLP(params, X[B][6]); device float32 tensors."""
+    _check(load_library().spmspv_mlp_forward(_ptr(params), _ptr(X), int(X.shape[0]), _ptr(logits),
+                                             _stream(stream)))
+
+
+def spmspv_mlp_train_step(params, adam_m, adam_v, step, lr, X, labels, grad=None, loss=None, stream=None):
+    _check(load_library().spmspv_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                                                _ptr(X), _ptr(labels), int(X.shape[0]), _ptr(grad), _ptr(loss),
+                                                _stream(stream)))
+
+
 def bfs_run(handle, semiring, root, flags, level, parent=None, stream=None) -> int:
     nl = ctypes.c_int32(0)
     _check(load_library().bfs_run(handle, semiring, int(root), flags, _ptr(level), _ptr(parent), ctypes.byref(nl),
@@ -147,9 +212,9 @@ def spmspv_set_schedule(handle, sched: Optional[Schedule] = None):
 
 
 def spmspv_last_stats(handle, stream=None) -> dict:
-    out = (ctypes.c_int64 * 5)()
+    out = (ctypes.c_int64 * 6)()
     _check(load_library().spmspv_last_stats(handle, out, _stream(stream)))
-    return {"W": out[0], "nnz_y": out[1], "fnz": out[2], "maxlen": out[3], "err": out[4]}
+    return {"W": out[0], "nnz_y": out[1], "fnz": out[2], "maxlen": out[3], "err": out[4], "cls": out[5]}
 
 
 def spmspv_profile_read(handle) -> Tuple[list, int]:
@@ -208,8 +273,8 @@ class Matrix:
         spmspv_set_schedule(self.handle, s)
 
     def spmspv(self, x_idx, x_val=None, semiring: int = PLUS_TIMES_F32, sorted_output: bool = False,
-               flags: int = 0, y_capacity: Optional[int] = None, out=None, sync: bool = True):
-        """y <- A x.  Returns (y_idx, y_val, nnz) trimmed to nnz when sync."""
+               flags: int = 0, y_capacity: Optional[int] = None, out=None, sync: bool = True, mask=None):
+        """y <- A x (rows with a set `mask` bit excluded).  Returns (y_idx, y_val, nnz), trimmed when sync."""
         import torch
         dev = self.colptr.device
         cap = self.m if y_capacity is None else int(y_capacity)
@@ -221,7 +286,8 @@ class Matrix:
             y_idx, y_val = out
         fl = flags | (SORTED_OUTPUT if sorted_output else 0)
         f = int(x_idx.numel())
-        nnz = spmspv_run(self.handle, semiring, fl, f, x_idx, x_val, y_idx, y_val, cap, self._d_nnz, sync=sync)
+        nnz = spmspv_run_masked(self.handle, semiring, fl, f, x_idx, x_val, mask, y_idx, y_val, cap, self._d_nnz,
+                                sync=sync)
         if not sync:
             return y_idx, y_val, self._d_nnz
         k = min(nnz, cap)
@@ -238,3 +304,12 @@ class Matrix:
 
     def last_stats(self) -> dict:
         return spmspv_last_stats(self.handle)
+
+    def load_selector(self, params, mean, std):
+        spmspv_selector_load(self.handle, params, mean, std)
+
+    def selector_classes(self) -> list:
+        return spmspv_selector_classes(self.handle)
+
+    def class_tile(self, cls: int) -> int:
+        return spmspv_class_tile(self.handle, cls)

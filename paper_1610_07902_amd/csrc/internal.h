@@ -45,7 +45,12 @@ struct alignas(256) Ctrl {
     int32_t policy;         // BFS direction policy: 0 push only, 1 frontier-edge heuristic
     int64_t edges_left;     // stored entries in columns of unvisited vertices
     uint32_t unsorted;      // set at create when some column's row ids are not ascending
-    uint32_t pad[39];
+    uint32_t pad0;
+    int64_t seen;           // BFS: vertices reached so far (selector feature)
+    int32_t bfs_mode;       // the selector runs inside a BFS
+    int32_t cls;            // class chosen by the selector for the current multiply
+    float features[6];      // standardised selector features of the current multiply
+    uint32_t pad[30];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -189,6 +194,15 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s);
 hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
+
+// Schedule-selector MLP (6 -> 64 -> 64 -> 10).
+constexpr int kMlpIn = 6, kMlpH1 = 64, kMlpH2 = 64, kMlpOut = 10;
+constexpr int kMlpParams = kMlpH1 * kMlpIn + kMlpH1 + kMlpH2 * kMlpH1 + kMlpH2 + kMlpOut * kMlpH2 + kMlpOut;
+constexpr int kMlpBatchMax = 128;
+hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* logits, hipStream_t s);
+hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float lr, const float* X,
+                                 const int32_t* labels, int B, float* grad_out, float* loss_out, hipStream_t s);
+hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
                            int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
 

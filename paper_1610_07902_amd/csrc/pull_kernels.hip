@@ -113,57 +113,136 @@ __global__ __launch_bounds__(BLOCK) void k_pull(PullArgs a) {
         const int mid = (lo + hi) >> 1;
         if ((int64_t)s_re[mid] < dt) lo = mid + 1; else hi = mid;
     }
+    // Phase 1 (LDS only): classify each of the thread's steps as a stored
+    // entry or the end of a row.  Phases 2-4 issue every column-id load, then
+    // every x-bitmap probe, then the value loads, so a thread keeps all its
+    // memory traffic in flight at once; phase 5 folds in order.
+    const int nsteps = (int)(dend - dt);
+    const uint32_t* __restrict__ colids = a.colids;
     int r = r0 + lo;
     int64_t q = dt - r;
-    const uint32_t* __restrict__ colids = a.colids;
-    bool whole = r < a.m && q == a.rowptr[r];   // the thread holds row r from its first entry
-    bool hit = false, done = false, skip = false;
-    uint32_t acc = ident<SR>();
-    if (r < a.m && a.mask) skip = (a.mask[r >> 5] >> (r & 31)) & 1u;
-    for (; dt < dend; ++dt) {
-        if (r >= a.m) break;
-        const int64_t rend = (int64_t)s_re[r - r0] - r;   // rowptr[r + 1]
-        if (q < rend) {
-            if (!skip && !done) {
-                const uint32_t j = colids[q];
-                if ((a.xbits[j >> 5] >> (j & 31)) & 1u) {
-                    uint32_t t;
-                    if constexpr (SR == SR_PLUS_TIMES) {
-                        const float av = a.values ? a.values[q] : 1.0f;
-                        t = __float_as_uint(__fmul_rn(av, __uint_as_float(a.xdense[j])));
-                    } else if constexpr (SR == SR_MIN_SELECT2ND) {
-                        t = a.xdense[j];
-                    } else {
-                        const uint32_t av = a.values ? (a.values[q] != 0.0f ? 1u : 0u) : 1u;
-                        t = av & a.xdense[j];
-                    }
-                    acc = hit ? comb<SR>(acc, t) : t;
-                    hit = true;
-                    // or-and: nothing can change a true row; min-select2nd with
-                    // ascending column ids and x value = column id: the first hit
-                    // of this piece of the row is its minimum.
-                    if (EARLY) done = (SR == SR_OR_AND) ? (acc != 0u) : true;
-                }
+    const bool whole0 = r < a.m && q == a.rowptr[r];   // the thread holds its first row from the start
+    int32_t qs[ITEMS], rs[ITEMS];
+    uint8_t kind[ITEMS];   // 0 none, 1 stored entry, 2 end of row rs[i]
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        qs[i] = 0;
+        rs[i] = r;
+        kind[i] = 0;
+        if (i < nsteps && r < a.m) {
+            const int64_t rend = (int64_t)s_re[r - r0] - r;   // rowptr[r + 1]
+            if (q < rend) {
+                kind[i] = 1;
+                qs[i] = (int32_t)q;
+                ++q;
+            } else {
+                kind[i] = 2;
+                ++r;
             }
-            ++q;
-        } else {
-            // end of row r
-            if (hit) {
-                if (whole) a.ydense[r] = acc;
-                else comb_global<SR>(&a.ydense[r], acc);
-                atomicOr(&a.ybits[r >> 5], 1u << (r & 31));
-            }
-            ++r;
-            hit = false;
-            done = false;
-            whole = true;
-            acc = ident<SR>();
-            skip = (r < a.m && a.mask) ? ((a.mask[r >> 5] >> (r & 31)) & 1u) : false;
         }
     }
-    if (hit && r < a.m) {   // row continues past this thread
+    // Phase 2: entries of masked (visited) rows are skipped; column ids.
+    bool use[ITEMS];
+    uint32_t cj[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        use[i] = kind[i] == 1;
+        if (use[i] && a.mask) use[i] = ((a.mask[rs[i] >> 5] >> (rs[i] & 31)) & 1u) == 0u;
+        cj[i] = use[i] ? colids[qs[i]] : 0u;
+    }
+    // Phase 3: probe x.
+    bool hitv[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) hitv[i] = use[i] && ((a.xbits[cj[i] >> 5] >> (cj[i] & 31)) & 1u);
+    // Phase 4: Mult for the hits.
+    uint32_t tv[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        tv[i] = 0u;
+        if (hitv[i]) {
+            if constexpr (SR == SR_PLUS_TIMES) {
+                const float av = a.values ? a.values[qs[i]] : 1.0f;
+                tv[i] = __float_as_uint(__fmul_rn(av, __uint_as_float(a.xdense[cj[i]])));
+            } else if constexpr (SR == SR_MIN_SELECT2ND) {
+                tv[i] = a.xdense[cj[i]];
+            } else {
+                const uint32_t av = a.values ? (a.values[qs[i]] != 0.0f ? 1u : 0u) : 1u;
+                tv[i] = av & a.xdense[cj[i]];
+            }
+        }
+    }
+    // Phase 5: fold per row; a row wholly inside this thread is written
+    // directly, a piece of a longer row is combined with a global atomic.
+    bool whole = whole0, hit = false;
+    uint32_t acc = ident<SR>();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (kind[i] == 1) {
+            if (hitv[i]) {
+                acc = hit ? comb<SR>(acc, tv[i]) : tv[i];
+                hit = true;
+            }
+        } else if (kind[i] == 2) {
+            if (hit) {
+                if (whole) a.ydense[rs[i]] = acc;
+                else comb_global<SR>(&a.ydense[rs[i]], acc);
+                atomicOr(&a.ybits[rs[i] >> 5], 1u << (rs[i] & 31));
+            }
+            hit = false;
+            whole = true;
+            acc = ident<SR>();
+        }
+    }
+    if (hit && r < a.m) {   // row r continues past this thread
         comb_global<SR>(&a.ydense[r], acc);
         atomicOr(&a.ybits[r >> 5], 1u << (r & 31));
+    }
+}
+
+// Bottom-up BFS step: one thread per row, unvisited rows only, stopping at
+// the first selected column (or-and: the row is reached; min-select2nd with
+// ascending column ids and x value = column id: the first hit is the
+// minimum).  Four column ids and four bitmap probes are in flight at a time.
+template <int SR, bool FIRST_HIT>
+__global__ __launch_bounds__(256) void k_pull_bfs(PullArgs a) {
+    if (a.gate && ldc(&a.ctrl->dir) != 1) return;
+    const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
+    if (f <= 0) return;
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * 256;
+    for (int r0 = blockIdx.x * 256 + (threadIdx.x & ~63); r0 < a.m; r0 += stride) {
+        const int r = r0 + lane;
+        bool hit = false;
+        uint32_t acc = ident<SR>();
+        if (r < a.m && !(a.mask && ((a.mask[r >> 5] >> (r & 31)) & 1u))) {
+            const int q1 = a.rowptr[r + 1];
+            for (int q = a.rowptr[r]; q < q1; q += 4) {
+                uint32_t j[4];
+                bool in[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    in[u] = q + u < q1;
+                    j[u] = in[u] ? a.colids[q + u] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) in[u] = in[u] && ((a.xbits[j[u] >> 5] >> (j[u] & 31)) & 1u);
+                bool stop = false;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (in[u] && !stop) {
+                        const uint32_t t = SR == SR_MIN_SELECT2ND ? a.xdense[j[u]] : 1u;
+                        acc = hit ? comb<SR>(acc, t) : t;
+                        hit = true;
+                        if (FIRST_HIT || SR == SR_OR_AND) stop = true;
+                    }
+                }
+                if (stop) break;
+            }
+        }
+        if (hit) a.ydense[r] = acc;
+        const uint64_t hm = __ballot(hit);
+        if (lane == 0 && (uint32_t)hm) atomicOr(&a.ybits[r0 >> 5], (uint32_t)hm);
+        if (lane == 32 && (uint32_t)(hm >> 32)) atomicOr(&a.ybits[(r0 >> 5) + 1], (uint32_t)(hm >> 32));
     }
 }
 
@@ -364,6 +443,16 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
         case XV_U8: hipLaunchKernelGGL(k_pull_prep<XV_U8>, dim3(f_grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_pull_prep<XV_TRUE>, dim3(f_grid), dim3(256), 0, s, a); break;
     }
+    if (bfs) {
+        // bottom-up step: one thread per row, first-hit exit
+        const dim3 gb((a.m + 255) / 256 < 8192 ? (a.m + 255) / 256 : 8192), bb(256);
+        if (semiring == SR_MIN_SELECT2ND) {
+            if (early) hipLaunchKernelGGL((k_pull_bfs<SR_MIN_SELECT2ND, true>), gb, bb, 0, s, a);
+            else hipLaunchKernelGGL((k_pull_bfs<SR_MIN_SELECT2ND, false>), gb, bb, 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_pull_bfs<SR_OR_AND, true>), gb, bb, 0, s, a);
+        }
+    } else {
     const dim3 g(a.pull_blocks), b(kPullBlock);
     switch (semiring) {
         case SR_PLUS_TIMES: hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_PLUS_TIMES, false>), g, b, 0, s, a); break;
@@ -375,6 +464,7 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
             if (early) hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, true>), g, b, 0, s, a);
             else hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, false>), g, b, 0, s, a);
             break;
+    }
     }
     const dim3 ge(a.emit_blocks), be(kEmitBlock);
     switch (semiring) {

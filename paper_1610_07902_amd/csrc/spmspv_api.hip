@@ -53,7 +53,7 @@ struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
         heavy, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
-    size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values;
+    size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values, selector;
     bool pull, transpose;
     int64_t nb_max, lb1_n, chunk_n;
 };
@@ -84,6 +84,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
     L.heavy = take(size_t((m + 31) / 32) * 4);
+    L.selector = take(size_t(kMlpParams + 2 * kMlpIn) * 4);
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
     if (L.pull) {
@@ -149,6 +150,10 @@ struct spmspv_matrix {
     uint64_t* p_lbp = nullptr;
     int32_t* p_part = nullptr;
     uint32_t ydense_ident = 0;
+    // schedule selector: MLP parameters, then feature mean[6] and std[6]
+    float* selector = nullptr;
+    bool selector_loaded = false;
+    std::vector<int> level_classes;     // classes the selector chose in the last BFS
 };
 
 namespace {
@@ -189,16 +194,18 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
     return SPMSPV_OK;
 }
 
-inline int64_t num_buckets(const spmspv_matrix* A) {
-    return (A->m + (int64_t(1) << A->sched.tile_log2) - 1) >> A->sched.tile_log2;
-}
 
 // Enqueue the three phases of one y <- A x.
-int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_host, const int32_t* f_dev,
-            const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y,
-            bool bfs, int32_t* level, int32_t* parent, hipStream_t s, hipEvent_t* ev, bool diropt = false) {
-    const spmspv_schedule& sc = A->sched;
-    const int nb = (int)num_buckets(A);
+// phases: 1 = scan only, 2 = scatter + merge only, 3 = all.  tile_log2 < 0
+// uses the handle's schedule.  clear_nb > 0 makes the scan clear that many
+// bucket counters (so a later scatter may use a narrower tile).
+int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev, const int32_t* x_idx,
+            const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
+            const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
+            int phases = 3, int clear_nb = 0) {
+    spmspv_schedule sc = A->sched;
+    if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
+    const int nb = (int)((A->m + (int64_t(1) << sc.tile_log2) - 1) >> sc.tile_log2);
     const int chunk = sc.scatter_block * sc.scatter_items;
     const int chunk_log2 = ceil_log2(chunk);
     const int64_t f_bound = f_dev ? A->n : f_host;
@@ -223,7 +230,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     sa.chunk_n = A->L.chunk_n;
     sa.cursor = A->cursor;
     sa.lb3 = A->lb3;
-    sa.nb = nb;
+    sa.nb = clear_nb > nb ? clear_nb : nb;
     sa.bump_level = bfs ? 1 : 0;
     int64_t g1 = (f_bound + kScanTile - 1) / kScanTile;
     if (g1 < 1) g1 = 1;
@@ -247,7 +254,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     ca.rcp = A->rcp;
     ca.cursor = A->cursor;
     ca.buckets = A->buckets;
-    ca.mask = bfs ? A->visited : nullptr;
+    ca.mask = mask;
     ca.lb1 = A->lb1;
     ca.lb1_n = (int32_t)A->L.lb1_n;
     ca.lb1_clear = (int32_t)((f_bound + kScanTile - 1) / kScanTile + 1);
@@ -276,26 +283,29 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, bool sorted, int64_t f_ho
     ma.d_nnz_y = d_nnz_y;
     ma.visited = A->visited;
     ma.heavy = A->heavy;
-    (void)level;
-    (void)parent;
     ma.set_f = bfs ? 1 : 0;
     ma.gate = diropt ? 1 : 0;
 
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_scan(sa, (int)g1, s));
-    if (diropt) HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    if (phases & 1) {
+        if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(launch_scan(sa, (int)g1, s));
+        if (diropt) HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    }
+    if (phases & 2) {
+        HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    }
     return SPMSPV_OK;
 }
 
 // Enqueue one pull-direction multiply (three launches).
 int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
                  const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
-                 int64_t* d_nnz_y, bool bfs, bool bump, bool gate, hipStream_t s, hipEvent_t* ev) {
+                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, bool bump, bool gate, hipStream_t s,
+                 hipEvent_t* ev) {
     const uint32_t ident = semiring == SR_MIN_SELECT2ND ? 0x7fffffffu : 0u;
     if (A->ydense_ident != ident) {
         HIP_TRY(launch_fill_ident(A->p_ydense, ident, A->m, s));
@@ -319,7 +329,7 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     pa.xdense = A->p_xdense;
     pa.ybits = A->p_ybits;
     pa.ydense = A->p_ydense;
-    pa.mask = bfs ? A->visited : nullptr;
+    pa.mask = mask;
     pa.lbp = A->p_lbp;
     pa.emit_blocks = pull_emit_blocks((int32_t)A->m);
     pa.y_idx = y_idx;
@@ -339,6 +349,49 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
         HIP_TRY(hipEventRecord(ev[3], s));
     }
     return SPMSPV_OK;
+}
+
+int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s);
+
+// Tile of a selector class c < 9: 2^(c+4) buckets over m rows, clamped to
+// what LDS and the scatter histogram can hold.
+int class_tile(const spmspv_matrix* A, int c) {
+    int tl = ceil_log2(A->m) - (c + 4);
+    if (tl < kTileLog2Min) tl = kTileLog2Min;
+    if (tl > kTileLog2Max) tl = kTileLog2Max;
+    while (tl < kTileLog2Max && scatter_lds_bytes((int)((A->m + (int64_t(1) << tl) - 1) >> tl),
+                                                 A->sched.scatter_block * A->sched.scatter_items) + 1024 >
+                                   A->lds_max)
+        ++tl;
+    while (tl > kTileLog2Min && merge_lds_bytes(tl) + 1024 > A->lds_max) --tl;
+    return tl;
+}
+
+// One multiply whose schedule the selector MLP picks: scan, selector
+// inference on the device, one host read of the class, then the chosen
+// push tile or the pull direction.  Returns the class in *cls.
+int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
+                 const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
+                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, hipStream_t s, int* cls, int32_t* f_now) {
+    const int clear_nb = (int)((A->m + (int64_t(1) << kTileLog2Min) - 1) >> kTileLog2Min);
+    int rc = enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
+                     nullptr, false, -1, 1, clear_nb);
+    if (rc) return rc;
+    HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, s));
+    Ctrl h{};
+    rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    *cls = h.cls;
+    if (f_now) *f_now = h.f;
+    if (h.cls == 9 && A->pull && h.f > 0) {
+        // the scatter that normally clears the scan's look-back words is skipped
+        HIP_TRY(launch_clear_u64(A->lb1, (int)A->L.lb1_n * 2, s));
+        return enqueue_pull(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs,
+                            mask, false, false, s, nullptr);
+    }
+    const int tl = class_tile(A, h.cls < 9 ? h.cls : 8);
+    return enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
+                   nullptr, false, tl, 2, 0);
 }
 
 hipEvent_t* profile_slot(spmspv_matrix* A) {
@@ -430,6 +483,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
     A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
     A->heavy = reinterpret_cast<uint32_t*>(A->ws + L.heavy);
+    A->selector = reinterpret_cast<float*>(A->ws + L.selector);
 
     auto bail = [&](int status) {
         delete A;
@@ -532,6 +586,13 @@ int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
 
 int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx, const void* x_val,
                int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y, void* stream) {
+    return spmspv_run_masked(A, semiring, flags, f, x_idx, x_val, nullptr, y_idx, y_val, y_capacity, d_nnz_y, h_nnz_y,
+                             stream);
+}
+
+int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx, const void* x_val,
+                      const uint32_t* mask, int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y,
+                      int64_t* h_nnz_y, void* stream) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
     if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
@@ -556,11 +617,20 @@ int spmspv_run(spmspv_handle A, int semiring, int flags, int64_t f, const int32_
         }
     }
     hipEvent_t* ev = (flags & SPMSPV_PROFILE) ? profile_slot(A) : nullptr;
-    int rc = A->sched.direction == 1
-                 ? enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y,
-                                false, false, false, s, ev)
-                 : enqueue(A, semiring, xmode, (flags & SPMSPV_SORTED_OUTPUT) != 0, f, nullptr, x_idx, x_val, y_idx,
-                           y_val, y_capacity, d_nnz_y, false, nullptr, nullptr, s, ev);
+    int rc;
+    if (flags & SPMSPV_USE_SELECTOR) {
+        if (!A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
+        int cls = 0;
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 0u, 1, s));
+        rc = run_selected(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
+                          mask, s, &cls, nullptr);
+    } else if (A->sched.direction == 1) {
+        rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
+                          mask, false, false, s, ev);
+    } else {
+        rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask, s,
+                     ev);
+    }
     if (rc) return rc;
     if (h_nnz_y) {
         Ctrl h{};
@@ -588,8 +658,9 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     if (root < 0 || root >= A->n) return fail(SPMSPV_EINVAL, "root out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
-    const bool sorted = true;
     const bool diropt = (flags & SPMSPV_DIRECTION_OPT) != 0;
+    const bool selector = (flags & SPMSPV_USE_SELECTOR) != 0;
+    if (selector && !A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
     if (diropt && !A->pull)
         return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DIRECTION_OPT needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
 
@@ -598,19 +669,46 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         for (int l = 0; l < count; ++l) {
             int32_t* x = A->front[l & 1];
             int32_t* y = A->front[(l + 1) & 1];
-            int rc = enqueue(A, semiring, xmode, sorted, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
-                             level, parent, st, nullptr, diropt);
+            int rc = enqueue(A, semiring, xmode, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
+                             A->visited, st, nullptr, diropt);
             if (rc) return rc;
             if (diropt) {
                 // pull kernels for the same level; they run only when k_decide chose pull
                 rc = enqueue_pull(A, semiring, xmode, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
-                                  false, true, st, nullptr);
+                                  A->visited, false, true, st, nullptr);
                 if (rc) return rc;
             }
         }
         return SPMSPV_OK;
     };
 
+    if (selector) {
+        // One host read per level: scan, device-side inference, chosen path.
+        HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz, 0, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->seen), 0u, 2, s));
+        A->level_classes.clear();
+        for (int64_t l = 0;; ++l) {
+            if (l > A->n + 1) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+            int cls = 0;
+            int32_t fnow = 0;
+            const int rc = run_selected(A, semiring, xmode, 0, &A->ctrl->f, A->front[l & 1], nullptr,
+                                        A->front[(l + 1) & 1], nullptr, A->m, nullptr, true, A->visited, s, &cls,
+                                        &fnow);
+            if (rc) return rc;
+            if (fnow == 0) break;
+            A->level_classes.push_back(cls);
+        }
+        Ctrl h{};
+        int rc = read_ctrl(A, &h, s);
+        if (rc) return rc;
+        if (h.err) {
+            clear_err(A, s);
+            return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+        }
+        if (h_num_levels) *h_num_levels = h.level;
+        return SPMSPV_OK;
+    }
     const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
     const int key = semiring + 1 + (diropt ? 8 : 0);
     if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
@@ -674,6 +772,64 @@ int spmspv_last_stats(spmspv_handle A, int64_t* h_out, void* stream) {
     h_out[2] = h.fnz_last;
     h_out[3] = h.maxlen_last;
     h_out[4] = h.err;
+    h_out[5] = h.cls;
+    return SPMSPV_OK;
+}
+
+int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_mean, const float* h_std,
+                         void* stream) {
+    if (!A || !h_params || !h_mean || !h_std) return fail(SPMSPV_EINVAL, "NULL argument");
+    std::vector<float> buf((size_t)kMlpParams + 2 * kMlpIn);
+    for (int q = 0; q < kMlpParams; ++q) {
+        if (!(h_params[q] == h_params[q]) || h_params[q] > 1e30f || h_params[q] < -1e30f) {
+            A->selector_loaded = false;
+            return fail(SPMSPV_EINVAL, "selector weights are not finite; selector disabled");
+        }
+        buf[(size_t)q] = h_params[q];
+    }
+    for (int c = 0; c < kMlpIn; ++c) {
+        if (!(h_std[c] > 0.f)) {
+            A->selector_loaded = false;
+            return fail(SPMSPV_EINVAL, "feature std must be positive; selector disabled");
+        }
+        buf[(size_t)kMlpParams + c] = h_mean[c];
+        buf[(size_t)kMlpParams + kMlpIn + c] = h_std[c];
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(A->selector, buf.data(), buf.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    A->selector_loaded = true;
+    return SPMSPV_OK;
+}
+
+int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count) {
+    if (!A || !h_count) return fail(SPMSPV_EINVAL, "NULL argument");
+    *h_count = (int32_t)A->level_classes.size();
+    for (int32_t k = 0; k < cap && k < *h_count; ++k) h_out[k] = A->level_classes[(size_t)k];
+    return SPMSPV_OK;
+}
+
+int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2) {
+    if (!A || !h_tile_log2 || cls < 0 || cls > 9) return fail(SPMSPV_EINVAL, "bad argument");
+    *h_tile_log2 = cls == 9 ? -1 : class_tile(A, cls);
+    return SPMSPV_OK;
+}
+
+int spmspv_mlp_param_count(void) { return kMlpParams; }
+
+int spmspv_mlp_forward(const float* params, const float* X, int batch, float* logits, void* stream) {
+    if (!params || batch < 0 || (batch > 0 && (!X || !logits))) return fail(SPMSPV_EINVAL, "bad argument");
+    HIP_TRY(launch_mlp_forward(params, X, batch, logits, static_cast<hipStream_t>(stream)));
+    return SPMSPV_OK;
+}
+
+int spmspv_mlp_train_step(float* params, float* adam_m, float* adam_v, int step, float lr, const float* X,
+                          const int32_t* labels, int batch, float* grad, float* d_loss, void* stream) {
+    if (!params || !X || !labels || batch < 1 || batch > kMlpBatchMax || step < 1 || lr < 0.f ||
+        (lr > 0.f && (!adam_m || !adam_v)))
+        return fail(SPMSPV_EINVAL, "bad argument (1 <= batch <= 128, step >= 1, lr >= 0)");
+    HIP_TRY(launch_mlp_train_step(params, adam_m, adam_v, step, lr, X, labels, batch, grad, d_loss,
+                                  static_cast<hipStream_t>(stream)));
     return SPMSPV_OK;
 }
 
