@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only the timed headline loop (for rocprofv3)")
     ap.add_argument("--schedules", action="store_true", help="also time a grid of launch schedules")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 256 MiB device copies (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -69,6 +71,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import synth
     import paper_1610_07902_amd as spv
 
@@ -154,7 +159,9 @@ def main():
                    "scale": args.scale, "nnz": A.nnz, "f": f, "mean_products": float(W.mean()),
                    "mean_nnz_y": float(nnz_y.mean()), "schedule": M.schedule.as_dict()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(dom, args),
+                     "algorithmic_bytes_per_launch": round(avg_bytes[dom]),
                      "per_kernel_us": {p: round(avg_ms[p] * 1e3, 2) for p in phases},
                      "per_kernel_gbs": {p: round(avg_bytes[p] / (avg_ms[p] * 1e-3) / 1e9, 1) for p in phases},
                      "whole_step_method_gbs": round(method_bytes / (ms / args.steps * 1e-3) / 1e9, 1)},
@@ -184,6 +191,49 @@ def main():
         result["sweep"] = sweep(spv, M, A, deg, dev, stream)
         result["bfs"] = bfs_bench(spv, M, A, dev)
     print(json.dumps(result))
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration(torch):
+    """Ten plain device-to-device copies of 256 MiB: each reads and writes
+    exactly COPY_BYTES, so FETCH_SIZE / WRITE_SIZE per dispatch of this copy
+    kernel convert the counters' units to bytes."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 10}))
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("spmspv_kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1610_07902_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, args):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing, is for another workload, or was
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != kernel_source_digest() or rec.get("scale") != args.scale or \
+            rec.get("density") != args.density:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, m, steps, stream):
