@@ -100,7 +100,8 @@ __global__ __launch_bounds__(TB) void k_mlp_train_step(float* p, float* am, floa
         for (int k = 1; k < MO; ++k) mx = fmaxf(mx, z[k]);
         float se = 0.f;
         for (int k = 0; k < MO; ++k) se += expf(z[k] - mx);
-        const int y = labels[tid];
+        int y = labels[tid];
+        y = y < 0 ? 0 : (y >= MO ? MO - 1 : y);   // out-of-range labels are clamped (memory safety)
         ls[tid] = -(z[y] - mx - logf(se));
         for (int k = 0; k < MO; ++k) z[k] = (expf(z[k] - mx) / se - (k == y ? 1.f : 0.f)) / (float)B;
     }
