@@ -88,6 +88,9 @@ enum spmspv_flags {
                                   (Beamer's frontier-edge heuristic); needs a
                                   handle created with one of the two flags
                                   above                                       */
+    SPMSPV_MSBFS = 1024,       /* spmspv_batch_workspace_size / _attach: also
+                                  hold per-source frontiers and visited
+                                  bitmaps for msbfs_run                       */
     SPMSPV_USE_SELECTOR = 512  /* spmspv_run / bfs_run: a small MLP loaded with
                                   spmspv_selector_load picks the bucket count
                                   (or the pull direction) per call from
@@ -200,6 +203,58 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
 /* Release the handle (host memory and HIP events only; the caller frees
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
+
+/* ---- batched calls (many x against one A in one launch sequence).
+ * x is the concatenation of nbatch vectors: vector b occupies positions
+ * [x_off[b], x_off[b+1]) of x_idx / x_val (x_off int64, device, x_off[0]
+ * = 0).  Its products are bucketed by key (b, row range), with exact bucket
+ * sizes from a counting pass (Algorithm 2's role), and merged per key; the
+ * results come out one vector after another, each ascending, vector b at
+ * [y_off[b], y_off[b+1]) of y_idx / y_val.  Every x, y and offset array is
+ * device memory.  The batch workspace is a second caller-owned buffer. */
+
+/* Bytes of the batch workspace for up to max_batch vectors (<= 1024) with
+ * at most max_f x entries and max_products products (sum of selected column
+ * lengths, < 2^31) in one call.  With SPMSPV_MSBFS max_f is taken as
+ * max_batch * n and max_products <= 0 as max_batch * nnz (the most one BFS
+ * level can produce), plus frontier and visited buffers; needs m == n and
+ * max_batch * n < 2^31.                                                   */
+int spmspv_batch_workspace_size(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
+                                size_t* h_bytes);
+
+/* Bind a batch workspace of ws_bytes device bytes (owned by the caller,
+ * borrowed until the handle is destroyed or another is attached). */
+int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
+                        void* workspace, size_t ws_bytes);
+
+/* y_b <- A x_b for b < nbatch, one scan, two bucketing passes and one merge
+ * launch for the whole batch.  Flags: SPMSPV_X_VAL_IS_INDEX, X_ALL_TRUE
+ * and SPMSPV_VALIDATE (host check of x_off and of distinct in-range indices
+ * per vector; synchronous) as for spmspv_run.  Without VALIDATE, duplicate
+ * indices inside one vector are combined like repeated products.  y is
+ * always ascending within a vector.  y_off [nbatch+1] receives the output
+ * offsets.  With h_nnz_total non-NULL the call waits and reports the total
+ * (ECAPACITY when it exceeds y_capacity, or when the products exceed the
+ * workspace's max_products; then y is unspecified).  The bucket tile is the
+ * narrowest at or above the schedule's for which nbatch * ceil(m / tile)
+ * <= 8192 (EUNSUPPORTED if none).                                        */
+int spmspv_run_batch(spmspv_handle A, int semiring, int flags, int nbatch, const int64_t* x_off,
+                     const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,
+                     int64_t y_capacity, int64_t* h_nnz_total, void* stream);
+
+/* Schedule for batched calls (tile_log2 is the starting tile; NULL restores
+ * the handle's schedule) and the effective one for nbatch vectors.       */
+int spmspv_set_batch_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
+int spmspv_get_batch_schedule(spmspv_handle A, int nbatch, spmspv_schedule* h_sched);
+
+/* Multi-source BFS: nsrc independent searches from h_roots[0..nsrc) run as
+ * one batched SpMSpV per level (the frontiers of all sources form one
+ * batch; source x's visited bitmap masks its own products).  level and
+ * parent are [nsrc][n] int32 (parent nullable; NULL for OR_AND), with the
+ * conventions of bfs_run per source.  Needs a batch workspace attached with
+ * SPMSPV_MSBFS and max_batch >= nsrc.  Synchronous.                      */
+int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, int flags, int32_t* level,
+              int32_t* parent, int32_t* h_num_levels, void* stream);
 
 /* ---- schedule selector (a learned replacement for the fixed bucket count
  * of "Performance optimizations"; see the bucket-count discussion there).

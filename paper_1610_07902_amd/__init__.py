@@ -29,6 +29,7 @@ WITH_TRANSPOSE = 64
 SYMMETRIC = 128
 DIRECTION_OPT = 256
 USE_SELECTOR = 512
+MSBFS = 1024
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10
@@ -40,7 +41,8 @@ EXPORTED = (
     "spmspv_set_schedule", "spmspv_last_stats", "spmspv_profile_read", "spmspv_destroy",
     "spmspv_status_string", "spmspv_last_error", "spmspv_run_masked", "spmspv_selector_load",
     "spmspv_selector_classes", "spmspv_class_tile", "spmspv_mlp_param_count", "spmspv_mlp_forward",
-    "spmspv_mlp_train_step",
+    "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
+    "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run",
 )
 
 
@@ -88,6 +90,12 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_mlp_param_count.argtypes = []
     lib.spmspv_mlp_forward.argtypes = [vp, vp, ci, vp, vp]
     lib.spmspv_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp, vp, ci, vp, vp, vp]
+    lib.spmspv_batch_workspace_size.argtypes = [vp, ci, i64, i64, ci, ctypes.POINTER(sz)]
+    lib.spmspv_batch_attach.argtypes = [vp, ci, i64, i64, ci, vp, sz]
+    lib.spmspv_run_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+    lib.spmspv_set_batch_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.spmspv_get_batch_schedule.argtypes = [vp, ci, ctypes.POINTER(Schedule)]
+    lib.msbfs_run.argtypes = [vp, ci, ci, vp, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_last_error.argtypes = []
     lib.spmspv_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -192,6 +200,47 @@ def spmspv_mlp_train_step(params, adam_m, adam_v, step, lr, X, labels, grad=None
     _check(load_library().spmspv_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
                                                 _ptr(X), _ptr(labels), int(X.shape[0]), _ptr(grad), _ptr(loss),
                                                 _stream(stream)))
+
+
+def spmspv_batch_workspace_size(handle, max_batch, max_f=0, max_products=0, flags=0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().spmspv_batch_workspace_size(handle, int(max_batch), int(max_f), int(max_products),
+                                                      int(flags), ctypes.byref(out)))
+    return out.value
+
+
+def spmspv_batch_attach(handle, max_batch, max_f, max_products, flags, workspace, ws_bytes):
+    _check(load_library().spmspv_batch_attach(handle, int(max_batch), int(max_f), int(max_products), int(flags),
+                                              _ptr(workspace), int(ws_bytes)))
+
+
+def spmspv_run_batch(handle, semiring, flags, nbatch, x_off, x_idx, x_val, y_off, y_idx, y_val, y_capacity,
+                     sync=True, stream=None) -> Optional[int]:
+    """Batched y_b <- A x_b; with sync=True waits and returns the total nnz."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run_batch(handle, semiring, flags, int(nbatch), _ptr(x_off), _ptr(x_idx),
+                                           _ptr(x_val), _ptr(y_off), _ptr(y_idx), _ptr(y_val), int(y_capacity),
+                                           ctypes.byref(h) if sync else None, _stream(stream)))
+    return h.value if sync else None
+
+
+def spmspv_set_batch_schedule(handle, sched: Optional[Schedule] = None):
+    _check(load_library().spmspv_set_batch_schedule(handle, ctypes.byref(sched) if sched is not None else None))
+
+
+def spmspv_get_batch_schedule(handle, nbatch) -> Schedule:
+    sc = Schedule()
+    _check(load_library().spmspv_get_batch_schedule(handle, int(nbatch), ctypes.byref(sc)))
+    return sc
+
+
+def msbfs_run(handle, semiring, roots, flags, level, parent=None, stream=None) -> int:
+    import numpy as np
+    r = np.ascontiguousarray(roots, np.int32)
+    nl = ctypes.c_int32(0)
+    _check(load_library().msbfs_run(handle, semiring, int(r.size), r.ctypes.data, flags, _ptr(level), _ptr(parent),
+                                    ctypes.byref(nl), _stream(stream)))
+    return nl.value
 
 
 def bfs_run(handle, semiring, root, flags, level, parent=None, stream=None) -> int:
@@ -304,6 +353,44 @@ class Matrix:
 
     def last_stats(self) -> dict:
         return spmspv_last_stats(self.handle)
+
+    def attach_batch(self, max_batch: int, max_f: int = 0, max_products: int = 0, msbfs: bool = False):
+        """Allocate and bind the batch workspace (torch uint8 tensor held here)."""
+        import torch
+        fl = MSBFS if msbfs else 0
+        nbytes = spmspv_batch_workspace_size(self.handle, max_batch, max_f, max_products, fl)
+        self.batch_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.colptr.device)
+        spmspv_batch_attach(self.handle, max_batch, max_f, max_products, fl, self.batch_ws, nbytes)
+        return nbytes
+
+    def spmspv_batch(self, x_off, x_idx, x_val=None, semiring: int = PLUS_TIMES_F32, flags: int = 0,
+                     y_capacity: Optional[int] = None, out=None, sync: bool = True):
+        """Batched multiply; x_off int64 [B+1], x_idx / x_val concatenated (device tensors).
+        Returns (y_off, y_idx, y_val, total)."""
+        import torch
+        dev = self.colptr.device
+        nb = int(x_off.numel()) - 1
+        cap = int(y_capacity) if y_capacity is not None else nb * self.m
+        if out is None:
+            vdt = {PLUS_TIMES_F32: torch.float32, MIN_SELECT2ND_I32: torch.int32, OR_AND_BOOL: torch.uint8}[semiring]
+            y_off = torch.empty(nb + 1, dtype=torch.int64, device=dev)
+            y_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            y_val = torch.empty(max(cap, 1), dtype=vdt, device=dev)
+        else:
+            y_off, y_idx, y_val = out
+        total = spmspv_run_batch(self.handle, semiring, flags, nb, x_off, x_idx, x_val, y_off, y_idx, y_val, cap,
+                                 sync=sync)
+        return y_off, y_idx, y_val, total
+
+    def msbfs(self, roots, semiring: int = MIN_SELECT2ND_I32, parents: bool = True, flags: int = 0):
+        import torch
+        dev = self.colptr.device
+        k = len(roots)
+        level = torch.empty((k, self.n), dtype=torch.int32, device=dev)
+        parent = torch.empty((k, self.n), dtype=torch.int32, device=dev) \
+            if (parents and semiring == MIN_SELECT2ND_I32) else None
+        nl = msbfs_run(self.handle, semiring, roots, flags, level, parent)
+        return level, parent, nl
 
     def load_selector(self, params, mean, std):
         spmspv_selector_load(self.handle, params, mean, std)

@@ -80,6 +80,14 @@ struct ScanArgs {
     int32_t nb;              // buckets of the current schedule
     int bump_level;          // BFS: advance ctrl->level when f > 0
     int single_tile;         // each workgroup processes exactly one tile
+    // Batched calls: x is the concatenation of nbatch vectors, vector b at
+    // positions [xoff[b], xoff[b+1]); xoff[nbatch] (read on the device) is the
+    // total length and must not exceed f_cap.
+    const int64_t* xoff;     // nullable: single-vector call
+    int32_t nbatch;
+    int64_t f_cap;
+    int32_t* cxid;           // [fnz] vector of each non-empty column
+    int32_t* kcount;         // [nb+1] per-key product counts, cleared here
 };
 
 // Scatter phase: products -> row-range buckets.
@@ -97,6 +105,13 @@ struct ScatterArgs {
     int32_t m;
     const int32_t* rcp;      // [m+1] prefix of row counts of A = bucket bases
     int32_t* cursor;         // [nb]
+    // Batched calls: key = vector * nbx + (row >> tile_log2); bases come from
+    // an exact count pass (kcount, then its exclusive scan kbase).
+    const int32_t* cxid;
+    int32_t* kcount;         // [nb] count pass output
+    const int32_t* kbase;    // [nb+1] bucket bases of the batched scatter
+    int32_t nbx;             // buckets per vector
+    int32_t mask_words;      // words per vector in a batched mask
     uint2* buckets;          // [nnz] (row, value bits)
     const uint32_t* mask;    // nullable visited bitmap: drop rows whose bit is set
     uint64_t* lb1;           // scan look-back words to clear (two halves of lb1_n)
@@ -125,6 +140,13 @@ struct MergeArgs {
     const uint32_t* heavy;   // [m/32] rows with at least kHeavyRow stored entries
     int set_f;               // BFS: publish nnz(y) as the next frontier length
     int gate;                // 1: skip when ctrl->dir selects pull
+    // Batched calls (key = vector * nbx + bucket)
+    const int32_t* kbase;    // [nb+1]
+    int32_t nbx;
+    int32_t nbatch;
+    int64_t* yoff;           // [nbatch+1] out: start of each vector's y
+    int64_t n_stride;        // BFS: level / parent entries per vector
+    int32_t mask_words;      // BFS: visited words per vector
 };
 
 // Pull (matrix-driven) direction over the CSR form of A.
@@ -172,7 +194,14 @@ int pull_emit_blocks(int32_t m);
 int pull_blocks(int32_t m, int64_t nnz);
 
 size_t merge_lds_bytes(int tile_log2);
-size_t scatter_lds_bytes(int nb, int chunk);
+size_t scatter_lds_bytes(int nb, int chunk, bool batch = false);
+constexpr int kMaxBatch = 1024;    // vectors per batched call
+hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
+                                hipStream_t s);
+hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
+hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
+                             uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl,
+                             hipStream_t s);
 bool scatter_shape_supported(int block, int items);
 
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s);

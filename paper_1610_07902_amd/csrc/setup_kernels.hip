@@ -124,6 +124,41 @@ __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
     }
 }
 
+// Multi-source BFS start: source x owns level / parent entries
+// [x * n, (x + 1) * n) and visited words [x * mask_words, ...); its frontier
+// is its root, so the first batched frontier is roots[0 .. nsrc).
+__global__ void k_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
+                             uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t total = (int64_t)nsrc * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t x = i / n;
+        const int32_t v = (int32_t)(i - x * n);
+        const int32_t r = roots[x];
+        level[i] = v == r ? 0 : -1;
+        if (parent) parent[i] = v == r ? r : -1;
+    }
+    const int64_t words = (int64_t)nsrc * mask_words;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += stride) {
+        const int64_t x = i / mask_words;
+        const int64_t w = i - x * mask_words;
+        const int32_t r = roots[x];
+        visited[i] = w == (r >> 5) ? (1u << (r & 31)) : 0u;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nsrc; i += stride) {
+        if (i < nsrc) frontier[i] = roots[i];
+        xoff[i] = i;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->f = nsrc;
+        ctrl->level = 0;
+        ctrl->bfs_level = level;
+        ctrl->bfs_parent = parent;
+        ctrl->dir = 0;
+        ctrl->policy = 0;
+    }
+}
+
 // heavy bit of row r = (rcp[r+1] - rcp[r] >= thresh); one thread per 32-row word.
 __global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy) {
     const int64_t nw = ((int64_t)m + 31) >> 5;
@@ -215,6 +250,15 @@ hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
                            int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, n, root, level, parent,
                        visited, frontier, ctrl, nnz, policy);
+    return hipGetLastError();
+}
+
+hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
+                             uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl,
+                             hipStream_t s) {
+    const int64_t total = (int64_t)nsrc * n;
+    hipLaunchKernelGGL(k_msbfs_init, dim3(grid_for(total, kSetupBlock)), dim3(kSetupBlock), 0, s, n, nsrc, roots,
+                       level, parent, visited, mask_words, frontier, xoff, ctrl);
     return hipGetLastError();
 }
 

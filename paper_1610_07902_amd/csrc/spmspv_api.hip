@@ -103,6 +103,68 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     return L;
 }
 
+// Batched calls: caller-provided second workspace.
+constexpr int kMaxKeys = 8192;   // (vector, bucket) keys per batched call
+
+struct BatchLayout {
+    size_t cstart, coff, cxid, cxv, chunk_col, lb1, kcount, partials, cursor, lb3, buckets, visited, front0, front1,
+        xoff0, xoff1, roots, total;
+    int64_t max_f, max_products, chunk_n, lb1_n;
+    int32_t mask_words;
+};
+
+BatchLayout make_batch_layout(int64_t m, int64_t n, int64_t nnz, int max_batch, int64_t max_f,
+                              int64_t max_products, bool bfs) {
+    BatchLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    if (bfs) {
+        // every source's frontier holds at most n vertices and one level at
+        // most nnz products per source
+        max_f = (int64_t)max_batch * n;
+        if (max_products <= 0) max_products = (int64_t)max_batch * nnz;
+    }
+    if (max_products > INT32_MAX - 1) max_products = INT32_MAX - 1;
+    L.max_f = max_f;
+    L.max_products = max_products;
+    L.chunk_n = max_products / kChunkMin + 2;
+    L.lb1_n = (max_f + kScanTile - 1) / kScanTile + 1;
+    L.mask_words = (int32_t)((m + 31) / 32);
+    L.cstart = take(size_t(max_f + 1) * 4);
+    L.coff = take(size_t(max_f + 1) * 4);
+    L.cxid = take(size_t(max_f + 1) * 4);
+    L.cxv = take(size_t(max_f + 1) * 4);
+    L.chunk_col = take(size_t(L.chunk_n) * 4);
+    L.lb1 = take(size_t(L.lb1_n) * 16);
+    L.kcount = take(size_t(kMaxKeys + 1) * 4);
+    L.partials = take(size_t(kMaxKeys / 4096 + 2) * 4);
+    L.cursor = take(size_t(kMaxKeys) * 4);
+    L.lb3 = take(size_t(kMaxKeys) * 8);
+    L.buckets = take(size_t(max_products + 1) * 8);
+    if (bfs) {
+        L.visited = take(size_t(max_batch) * L.mask_words * 4);
+        L.front0 = take(size_t(max_f) * 4);
+        L.front1 = take(size_t(max_f) * 4);
+        L.xoff0 = take(size_t(max_batch + 1) * 8);
+        L.xoff1 = take(size_t(max_batch + 1) * 8);
+        L.roots = take(size_t(max_batch) * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+struct BatchCtx {
+    bool bound = false;
+    bool bfs = false;
+    int max_batch = 0;
+    BatchLayout L{};
+    char* ws = nullptr;
+};
+
 }  // namespace
 
 struct spmspv_matrix {
@@ -154,6 +216,8 @@ struct spmspv_matrix {
     float* selector = nullptr;
     bool selector_loaded = false;
     std::vector<int> level_classes;     // classes the selector chose in the last BFS
+    BatchCtx batch;                     // second workspace for batched calls
+    spmspv_schedule batch_sched{};      // batched-call schedule (tile_log2 0 = derive)
 };
 
 namespace {
@@ -392,6 +456,138 @@ int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     const int tl = class_tile(A, h.cls < 9 ? h.cls : 8);
     return enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
                    nullptr, false, tl, 2, 0);
+}
+
+// Shape of a batched call: the narrowest tile at or above the handle's whose
+// nbatch * buckets keys fit the key limit and whose scatter histogram fits
+// LDS with one of the candidate workgroup shapes.
+int batch_shape(const spmspv_matrix* A, int nbatch, spmspv_schedule* out) {
+    spmspv_schedule sc = A->sched;
+    if (A->batch_sched.tile_log2 > 0) sc = A->batch_sched;
+    const int shapes[4][2] = {{sc.scatter_block, sc.scatter_items}, {1024, 4}, {512, 4}, {256, 4}};
+    for (int tl = sc.tile_log2; tl <= kTileLog2Max; ++tl) {
+        if (merge_lds_bytes(tl) + 1024 > A->lds_max) break;
+        const int64_t nbx = (A->m + (int64_t(1) << tl) - 1) >> tl;
+        const int64_t K = nbx * nbatch;
+        if (K > kMaxKeys) continue;
+        for (const auto& sh : shapes) {
+            if (!scatter_shape_supported(sh[0], sh[1])) continue;
+            if (scatter_lds_bytes((int)K, sh[0] * sh[1], true) + 1024 > A->lds_max) continue;
+            *out = sc;
+            out->tile_log2 = tl;
+            out->scatter_block = sh[0];
+            out->scatter_items = sh[1];
+            return SPMSPV_OK;
+        }
+    }
+    return fail(SPMSPV_EUNSUPPORTED, "batch too large for the key limit: nbatch * ceil(m / 2^15) must be <= " +
+                                         std::to_string(kMaxKeys));
+}
+
+int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const int64_t* x_off, const int32_t* x_idx,
+                  const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val, int64_t y_cap, bool bfs,
+                  hipStream_t s) {
+    BatchCtx& B = A->batch;
+    char* w = B.ws;
+    const BatchLayout& L = B.L;
+    spmspv_schedule sc{};
+    int rc = batch_shape(A, nbatch, &sc);
+    if (rc) return rc;
+    const int tl = sc.tile_log2;
+    const int nbx = (int)((A->m + (int64_t(1) << tl) - 1) >> tl);
+    const int K = nbx * nbatch;
+    const int chunk = sc.scatter_block * sc.scatter_items;
+    const int chunk_log2 = ceil_log2(chunk);
+    auto i32 = [&](size_t off) { return reinterpret_cast<int32_t*>(w + off); };
+    int32_t* kcount = i32(L.kcount);
+    uint32_t* visited = bfs ? reinterpret_cast<uint32_t*>(w + L.visited) : nullptr;
+
+    ScanArgs sa{};
+    sa.colptr = A->colptr;
+    sa.n = (int32_t)A->n;
+    sa.x_idx = x_idx;
+    sa.x_val = x_val;
+    sa.xmode = xmode;
+    sa.ctrl = A->ctrl;
+    sa.cstart = i32(L.cstart);
+    sa.coff = i32(L.coff);
+    sa.cxv = reinterpret_cast<uint32_t*>(w + L.cxv);
+    sa.chunk_col = i32(L.chunk_col);
+    sa.chunk_log2 = chunk_log2;
+    sa.lb1 = reinterpret_cast<uint64_t*>(w + L.lb1);
+    sa.lb1_n = (int32_t)L.lb1_n;
+    sa.nnz = L.max_products;
+    sa.chunk_n = L.chunk_n;
+    sa.cursor = i32(L.cursor);
+    sa.lb3 = reinterpret_cast<uint64_t*>(w + L.lb3);
+    sa.nb = K;
+    sa.bump_level = bfs ? 1 : 0;
+    sa.xoff = x_off;
+    sa.nbatch = nbatch;
+    sa.f_cap = L.max_f;
+    sa.cxid = i32(L.cxid);
+    sa.kcount = kcount;
+    int64_t g1 = (L.max_f + kScanTile - 1) / kScanTile;
+    if (g1 < 1) g1 = 1;
+    if (g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;   // co-resident: look-back waits stay bounded
+
+    ScatterArgs ca{};
+    ca.rowids = A->rowids;
+    ca.values = A->values;
+    ca.ctrl = A->ctrl;
+    ca.cstart = sa.cstart;
+    ca.coff = sa.coff;
+    ca.cxv = sa.cxv;
+    ca.chunk_col = sa.chunk_col;
+    ca.chunk_log2 = chunk_log2;
+    ca.tile_log2 = tl;
+    ca.nb = K;
+    ca.m = (int32_t)A->m;
+    ca.rcp = A->rcp;
+    ca.cursor = sa.cursor;
+    ca.buckets = reinterpret_cast<uint2*>(w + L.buckets);
+    ca.mask = visited;
+    ca.lb1 = sa.lb1;
+    ca.lb1_n = sa.lb1_n;
+    ca.lb1_clear = (int32_t)L.lb1_n;
+    ca.cxid = sa.cxid;
+    ca.kcount = kcount;
+    ca.kbase = kcount;   // scanned in place between the two passes
+    ca.nbx = nbx;
+    ca.mask_words = L.mask_words;
+    int64_t g2 = (L.max_products + chunk - 1) / chunk;
+    if (g2 < 1) g2 = 1;
+    if (g2 > 2 * A->num_cu) g2 = 2 * A->num_cu;
+
+    MergeArgs ma{};
+    ma.ctrl = A->ctrl;
+    ma.cursor = sa.cursor;
+    ma.buckets = ca.buckets;
+    ma.rcp = A->rcp;
+    ma.m = (int32_t)A->m;
+    ma.tile_log2 = tl;
+    ma.nb = K;
+    ma.lb3 = sa.lb3;
+    ma.y_idx = y_idx;
+    ma.y_val = y_val;
+    ma.y_cap = y_cap;
+    ma.d_nnz_y = nullptr;
+    ma.visited = visited;
+    ma.heavy = A->heavy;
+    ma.set_f = bfs ? 1 : 0;
+    ma.kbase = kcount;
+    ma.nbx = nbx;
+    ma.nbatch = nbatch;
+    ma.yoff = y_off;
+    ma.n_stride = A->n;
+    ma.mask_words = L.mask_words;
+
+    HIP_TRY(launch_scan(sa, (int)g1, s));
+    HIP_TRY(launch_scatter_batch(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, true, s));
+    HIP_TRY(launch_exclusive_scan_i32(kcount, K + 1, i32(L.partials), s));
+    HIP_TRY(launch_scatter_batch(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, false, s));
+    HIP_TRY(launch_merge_batch(ma, semiring, sc.merge_block, bfs, s));
+    return SPMSPV_OK;
 }
 
 hipEvent_t* profile_slot(spmspv_matrix* A) {
@@ -812,6 +1008,176 @@ int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_
 int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2) {
     if (!A || !h_tile_log2 || cls < 0 || cls > 9) return fail(SPMSPV_EINVAL, "bad argument");
     *h_tile_log2 = cls == 9 ? -1 : class_tile(A, cls);
+    return SPMSPV_OK;
+}
+
+int spmspv_batch_workspace_size(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
+                                size_t* h_bytes) {
+    if (!A || !h_bytes) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (max_batch < 1 || max_batch > kMaxBatch) return fail(SPMSPV_EINVAL, "max_batch must be in [1, 1024]");
+    const bool bfs = (flags & SPMSPV_MSBFS) != 0;
+    if (bfs && A->m != A->n) return fail(SPMSPV_EINVAL, "multi-source BFS needs a square matrix");
+    if (bfs && (int64_t)max_batch * A->n >= INT32_MAX)
+        return fail(SPMSPV_EUNSUPPORTED, "max_batch * n must stay below 2^31");
+    if (!bfs && (max_f < 0 || max_f >= INT32_MAX || max_products < 0))
+        return fail(SPMSPV_EINVAL, "max_f must be in [0, 2^31) and max_products >= 0");
+    *h_bytes = make_batch_layout(A->m, A->n, A->nnz, max_batch, max_f, max_products, bfs).total;
+    return SPMSPV_OK;
+}
+
+int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
+                        void* workspace, size_t ws_bytes) {
+    size_t need = 0;
+    const int rc = spmspv_batch_workspace_size(A, max_batch, max_f, max_products, flags, &need);
+    if (rc) return rc;
+    if (!workspace) return fail(SPMSPV_EINVAL, "NULL workspace");
+    if (ws_bytes < need) return fail(SPMSPV_ENOMEM, "batch workspace needs " + std::to_string(need) + " bytes");
+    const bool bfs = (flags & SPMSPV_MSBFS) != 0;
+    A->batch.bound = true;
+    A->batch.bfs = bfs;
+    A->batch.max_batch = max_batch;
+    A->batch.L = make_batch_layout(A->m, A->n, A->nnz, max_batch, max_f, max_products, bfs);
+    A->batch.ws = static_cast<char*>(workspace);
+    return SPMSPV_OK;
+}
+
+int spmspv_set_batch_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (!h_sched) {
+        A->batch_sched = spmspv_schedule{};
+        return SPMSPV_OK;
+    }
+    const int rc = check_schedule(A, h_sched);
+    if (rc) return rc;
+    if (h_sched->direction != 0) return fail(SPMSPV_EINVAL, "batched calls run the push direction");
+    A->batch_sched = *h_sched;
+    return SPMSPV_OK;
+}
+
+int spmspv_get_batch_schedule(spmspv_handle A, int nbatch, spmspv_schedule* h_sched) {
+    if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (nbatch < 1 || nbatch > kMaxBatch) return fail(SPMSPV_EINVAL, "nbatch must be in [1, 1024]");
+    return batch_shape(A, nbatch, h_sched);
+}
+
+namespace {
+int batch_status(spmspv_matrix* A, hipStream_t s, int64_t* total) {
+    Ctrl h{};
+    int rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    if (h.err) {
+        clear_err(A, s);
+        if (h.err & ERR_X_RANGE) return fail(SPMSPV_EINVAL, "x index or vector offset out of range");
+        if (h.err & ERR_BUCKET_OVERFLOW)
+            return fail(SPMSPV_ECAPACITY, "products exceed the batch workspace's max_products");
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (total) *total = h.nnz_y;
+    return SPMSPV_OK;
+}
+}  // namespace
+
+int spmspv_run_batch(spmspv_handle A, int semiring, int flags, int nbatch, const int64_t* x_off,
+                     const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,
+                     int64_t y_capacity, int64_t* h_nnz_total, void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (!A->batch.bound) return fail(SPMSPV_EINVAL, "no batch workspace attached (spmspv_batch_attach)");
+    if (nbatch < 1 || nbatch > A->batch.max_batch) return fail(SPMSPV_EINVAL, "nbatch out of range");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (!x_off || !y_off || !y_idx || y_capacity < 0) return fail(SPMSPV_EINVAL, "NULL or negative argument");
+    int xmode = XV_BITS32;
+    if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
+    else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
+    if (xmode != XV_INDEX && xmode != XV_TRUE && !x_val) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & SPMSPV_VALIDATE) {
+        std::vector<int64_t> off((size_t)nbatch + 1);
+        HIP_TRY(hipMemcpyAsync(off.data(), x_off, off.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (off[0] != 0) return fail(SPMSPV_EINVAL, "x_off[0] must be 0");
+        for (int b = 0; b < nbatch; ++b)
+            if (off[(size_t)b + 1] < off[(size_t)b]) return fail(SPMSPV_EINVAL, "x_off must be non-decreasing");
+        if (off[(size_t)nbatch] > A->batch.L.max_f) return fail(SPMSPV_EINVAL, "total x length exceeds max_f");
+        std::vector<int32_t> xi((size_t)off[(size_t)nbatch]);
+        if (!xi.empty()) {
+            if (!x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
+            HIP_TRY(hipMemcpyAsync(xi.data(), x_idx, xi.size() * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        std::vector<int32_t> stamp((size_t)A->n, -1);
+        for (int b = 0; b < nbatch; ++b)
+            for (int64_t p = off[(size_t)b]; p < off[(size_t)b + 1]; ++p) {
+                const int32_t j = xi[(size_t)p];
+                if (j < 0 || j >= A->n) return fail(SPMSPV_EINVAL, "x index out of range");
+                if (stamp[(size_t)j] == b) return fail(SPMSPV_EINVAL, "duplicate x index within a vector");
+                stamp[(size_t)j] = b;
+            }
+    }
+    const int rc = enqueue_batch(A, semiring, xmode, nbatch, x_off, x_idx, x_val, y_off, y_idx, y_val, y_capacity,
+                                 false, s);
+    if (rc) return rc;
+    if (h_nnz_total) {
+        int64_t total = 0;
+        const int st = batch_status(A, s, &total);
+        if (st) return st;
+        *h_nnz_total = total;
+        if (total > y_capacity)
+            return fail(SPMSPV_ECAPACITY, "nnz(y) total " + std::to_string(total) + " exceeds y_capacity");
+    }
+    return SPMSPV_OK;
+}
+
+int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, int flags, int32_t* level,
+              int32_t* parent, int32_t* h_num_levels, void* stream) {
+    (void)flags;
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (!A->batch.bound || !A->batch.bfs)
+        return fail(SPMSPV_EINVAL, "no batch workspace attached with SPMSPV_MSBFS");
+    if (A->m != A->n) return fail(SPMSPV_EINVAL, "BFS needs a square matrix");
+    if (semiring != SR_MIN_SELECT2ND && semiring != SR_OR_AND)
+        return fail(SPMSPV_EINVAL, "BFS semiring must be MIN_SELECT2ND_I32 or OR_AND_BOOL");
+    if (semiring == SR_OR_AND && parent) return fail(SPMSPV_EINVAL, "OR_AND BFS has no parents");
+    if (nsrc < 1 || nsrc > A->batch.max_batch) return fail(SPMSPV_EINVAL, "nsrc out of range");
+    if (!h_roots || !level) return fail(SPMSPV_EINVAL, "NULL argument");
+    for (int x = 0; x < nsrc; ++x)
+        if (h_roots[x] < 0 || h_roots[x] >= A->n) return fail(SPMSPV_EINVAL, "root out of range");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchCtx& B = A->batch;
+    const BatchLayout& L = B.L;
+    spmspv_schedule sc{};
+    int rc = batch_shape(A, nsrc, &sc);
+    if (rc) return rc;
+    int32_t* roots = reinterpret_cast<int32_t*>(B.ws + L.roots);
+    int32_t* front[2] = {reinterpret_cast<int32_t*>(B.ws + L.front0), reinterpret_cast<int32_t*>(B.ws + L.front1)};
+    int64_t* xoff[2] = {reinterpret_cast<int64_t*>(B.ws + L.xoff0), reinterpret_cast<int64_t*>(B.ws + L.xoff1)};
+    HIP_TRY(hipMemcpyAsync(roots, h_roots, size_t(nsrc) * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_msbfs_init((int32_t)A->n, nsrc, roots, level, parent, reinterpret_cast<uint32_t*>(B.ws + L.visited),
+                              L.mask_words, front[0], xoff[0], A->ctrl, s));
+    const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
+    // Levels are enqueued kGraphLevels at a time; levels after the frontiers
+    // empty are no-ops.  One host check of the total frontier per batch.
+    int32_t hf = nsrc;
+    for (int64_t l = 0; hf > 0; l += kGraphLevels) {
+        if (l > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+        for (int k = 0; k < kGraphLevels; ++k) {
+            const int64_t lv = l + k;
+            rc = enqueue_batch(A, semiring, xmode, nsrc, xoff[lv & 1], front[lv & 1], nullptr, xoff[(lv + 1) & 1],
+                               front[(lv + 1) & 1], nullptr, L.max_f, true, s);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    Ctrl h{};
+    rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    if (h.err) {
+        clear_err(A, s);
+        if (h.err & ERR_BUCKET_OVERFLOW)
+            return fail(SPMSPV_ECAPACITY, "a level's products exceed the batch workspace's max_products");
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (h_num_levels) *h_num_levels = h.level;
     return SPMSPV_OK;
 }
 

@@ -179,14 +179,27 @@ __device__ __forceinline__ uint32_t x_value(const void* x_val, int p, int32_t j)
     else return 1u;
 }
 
-template <int BLOCK, int ITEMS, int XMODE>
+template <int BLOCK, int ITEMS, int XMODE, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     constexpr int TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_tmp[BLOCK / kWave + 1];
     __shared__ uint64_t s_excl_sum, s_excl_cnt;
     __shared__ int s_max;
+    __shared__ int64_t s_xoff[BATCH ? kMaxBatch + 1 : 1];
     const int tid = threadIdx.x;
-    const int f = a.f_dev ? ld_ctrl(a.f_dev) : a.f_host;
+    int f;
+    if constexpr (BATCH) {
+        // Vector offsets come from the caller or the previous BFS level.
+        for (int i = tid; i <= a.nbatch; i += BLOCK)
+            s_xoff[i] = __hip_atomic_load(&a.xoff[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int64_t F = s_xoff[a.nbatch];
+        const bool ok = F >= 0 && F <= a.f_cap && s_xoff[0] == 0;
+        if (!ok && blockIdx.x == 0 && tid == 0) atomicOr(&a.ctrl->err, ERR_X_RANGE);
+        f = ok ? (int)F : 0;
+    } else {
+        f = a.f_dev ? ld_ctrl(a.f_dev) : a.f_host;
+    }
     uint64_t* lb_sum = a.lb1;
     uint64_t* lb_cnt = a.lb1 + a.lb1_n;
 
@@ -195,6 +208,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         a.cursor[i] = 0;
         a.lb3[i] = 0;
     }
+    if constexpr (BATCH)
+        for (int i = blockIdx.x * BLOCK + tid; i <= a.nb; i += gridDim.x * BLOCK) a.kcount[i] = 0;
     if (blockIdx.x == 0 && tid == 0) {
         st_ctrl_u(&a.ctrl->ticket_merge, 0u);
         if (a.bump_level && f > 0) st_ctrl(&a.ctrl->level, ld_ctrl(&a.ctrl->level) + 1);
@@ -267,6 +282,16 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
                 a.cstart[c] = st[i];
                 a.coff[c] = (int32_t)off;   // exact whenever the total is valid (<= nnz)
                 a.cxv[c] = xv[i];
+                if constexpr (BATCH) {
+                    // vector of position p: the last b with xoff[b] <= p
+                    const int64_t p = p0 + i;
+                    int lo = 0, hi = a.nbatch - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_xoff[mid] <= p) lo = mid; else hi = mid - 1;
+                    }
+                    a.cxid[c] = lo;
+                }
                 for (int64_t k = ((int64_t)off + chunk - 1) >> a.chunk_log2;
                      (k << a.chunk_log2) < (int64_t)off + ln[i] && k < a.chunk_n; ++k)
                     a.chunk_col[k] = (int32_t)c;
@@ -276,7 +301,9 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         }
         if (tile == ntiles - 1 && tid == BLOCK - 1) {
             if (off > (uint64_t)a.nnz) {
-                // More products than stored entries: x has duplicate indices.
+                // Single vector: more products than stored entries means x
+                // has duplicate indices.  Batched: more products than the
+                // bucket storage holds.
                 atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
                 st_ctrl(&a.ctrl->W, 0);
                 st_ctrl(&a.ctrl->fnz, 0);
@@ -318,7 +345,15 @@ __device__ __forceinline__ uint32_t mult(const float* values, int32_t q, uint32_
 // scale) and (4) streamed out so consecutive lanes write consecutive slots.
 // The LDS region holding the chunk's column table during (1) is reused as
 // the sort buffer in (3).
-template <int BLOCK, int ITEMS, int SR>
+//
+// MODE 0: one vector, bucket = row >> tile_log2, bases from the row-count
+// prefix of A.  Batched calls (x is several vectors; key = vector * nbx +
+// bucket) run twice: MODE 1 only counts products per key (Algorithm 2's
+// counting, per workgroup in LDS, then one global add per touched key) and
+// MODE 2 scatters with bases from the exclusive scan of those counts.
+enum { SC_SINGLE = 0, SC_COUNT = 1, SC_BATCH = 2 };
+
+template <int BLOCK, int ITEMS, int SR, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     constexpr int C = BLOCK * ITEMS;
     extern __shared__ uint32_t lds_scatter[];
@@ -329,19 +364,23 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     int32_t* s_off = reinterpret_cast<int32_t*>(region);        // [C+1] column table (phase 1)
     int32_t* s_start = s_off + (C + 1);
     uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));
+    int32_t* s_xid = reinterpret_cast<int32_t*>(s_xv + (C + 1)); // batched: vector of each column
     uint2* stage = reinterpret_cast<uint2*>(region);            // [C] sort buffer (phase 3)
+    int32_t* skey = reinterpret_cast<int32_t*>(stage + C);      // batched: [C] key of each staged entry
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
 
-    if (blockIdx.x == 0 && tid == 0) {
-        st_ctrl_u(&a.ctrl->ticket_scan, 0u);
-        st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
-        st_ctrl(&a.ctrl->fnz_last, ld_ctrl(&a.ctrl->fnz));
-        st_ctrl(&a.ctrl->W_last, ld_ctrl(&a.ctrl->W));
-    }
-    for (int i = blockIdx.x * BLOCK + tid; i < a.lb1_clear; i += gridDim.x * BLOCK) {
-        a.lb1[i] = 0;
-        a.lb1[a.lb1_n + i] = 0;
+    if (MODE != SC_BATCH) {   // the first pass over the products of this call
+        if (blockIdx.x == 0 && tid == 0) {
+            st_ctrl_u(&a.ctrl->ticket_scan, 0u);
+            st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
+            st_ctrl(&a.ctrl->fnz_last, ld_ctrl(&a.ctrl->fnz));
+            st_ctrl(&a.ctrl->W_last, ld_ctrl(&a.ctrl->W));
+        }
+        for (int i = blockIdx.x * BLOCK + tid; i < a.lb1_clear; i += gridDim.x * BLOCK) {
+            a.lb1[i] = 0;
+            a.lb1[a.lb1_n + i] = 0;
+        }
     }
 
     if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
@@ -364,6 +403,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             s_off[k] = a.coff[p0 + k] - q0;
             s_start[k] = a.cstart[p0 + k];
             s_xv[k] = a.cxv[p0 + k];
+            if constexpr (MODE != SC_SINGLE) s_xid[k] = a.cxid[p0 + k];
         }
         __syncthreads();
 
@@ -371,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         // one binary search finds the column of the first, the rest walk
         // forward.  All row-id / value / mask loads are then issued together
         // (indices clamped into range), and ranks are taken in LDS.
-        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS], qq[ITEMS];
+        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS], qq[ITEMS], xid[ITEMS];
         uint32_t xcol[ITEMS];
         {
             const int rq0 = tid * ITEMS;
@@ -390,26 +430,41 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
                 }
                 qq[i] = rq < cnt ? s_start[lo] + (rq - s_off[lo]) : -1;
                 xcol[i] = s_xv[lo];
+                xid[i] = MODE != SC_SINGLE ? s_xid[lo] : 0;
             }
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) row[i] = a.rowids[qq[i] >= 0 ? qq[i] : 0];
         uint32_t val[ITEMS];
+        if constexpr (MODE != SC_COUNT) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) val[i] = mult<SR>(a.values, qq[i] >= 0 ? qq[i] : 0, xcol[i]);
+            for (int i = 0; i < ITEMS; ++i) val[i] = mult<SR>(a.values, qq[i] >= 0 ? qq[i] : 0, xcol[i]);
+        }
         uint32_t mw[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) mw[i] = a.mask ? a.mask[(uint32_t)row[i] >> 5] : 0u;
+        for (int i = 0; i < ITEMS; ++i)
+            mw[i] = a.mask ? a.mask[(int64_t)xid[i] * a.mask_words + ((uint32_t)row[i] >> 5)] : 0u;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             bk[i] = -1;
             rank[i] = 0;
             if (qq[i] >= 0 && ((mw[i] >> (row[i] & 31)) & 1u) == 0u) {
-                bk[i] = row[i] >> tl;
+                bk[i] = MODE != SC_SINGLE ? xid[i] * a.nbx + (row[i] >> tl) : row[i] >> tl;
                 rank[i] = atomicAdd(&hist[bk[i]], 1);
             }
         }
         __syncthreads();
+        if constexpr (MODE == SC_COUNT) {
+            // Algorithm 2's per-bucket counts, accumulated over workgroups.
+            for (int b = tid; b < nb; b += BLOCK) {
+                const int n = hist[b];
+                if (n) {
+                    atomicAdd(&a.kcount[b], n);
+                    hist[b] = 0;
+                }
+            }
+            continue;   // the loop head synchronises before hist is reused
+        }
         // (2) chunk-local offsets and one slot reservation per touched bucket
         int carry = 0;
         for (int b0 = 0; b0 < nb; b0 += BLOCK) {
@@ -420,9 +475,15 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             if (b < nb) {
                 loff[b] = carry + e;
                 if (n > 0) {
-                    const int r0 = b << tl;
-                    const int base = a.rcp[r0];
-                    const int cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
+                    int base, cap;
+                    if constexpr (MODE == SC_BATCH) {
+                        base = a.kbase[b];
+                        cap = a.kbase[b + 1] - base;
+                    } else {
+                        const int r0 = b << tl;
+                        base = a.rcp[r0];
+                        cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
+                    }
                     const int g = atomicAdd(&a.cursor[b], n);
                     if (g + n > cap) {
                         atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
@@ -439,12 +500,15 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         // (3) counting sort into the LDS buffer
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (bk[i] >= 0) stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+            if (bk[i] >= 0) {
+                stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+                if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+            }
         __syncthreads();
         // (4) coalesced write-out of the bucket runs
         for (int t = tid; t < kept; t += BLOCK) {
             const uint2 e = stage[t];
-            const int b = (int)e.x >> tl;
+            const int b = MODE == SC_BATCH ? skey[t] : (int)e.x >> tl;
             const int gb = hist[b];
             if (gb >= 0) a.buckets[gb + (t - loff[b])] = e;
         }
@@ -556,7 +620,12 @@ __device__ __forceinline__ void add_row(uint32_t r, uint32_t v, bool valid, bool
 // look-back across buckets to give the bucket's offset in y (Algorithm 1,
 // step 3) and the bitmap is walked in order, so y comes out ascending; the
 // walk compacts rows through a small LDS list for coalesced y writes.
-template <int BLOCK, int ITEMS, int SR, bool BFS>
+//
+// Batched calls (BATCH): workgroup k merges key k = vector * nbx + bucket;
+// the look-back runs over all keys, so y holds the vectors' results one
+// after another (each ascending) and the first bucket of each vector
+// publishes where its part starts (yoff).
+template <int BLOCK, int ITEMS, int SR, bool BFS, bool BATCH>
 __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     extern __shared__ uint32_t lds_merge[];
     const int tl = a.tile_log2;
@@ -576,21 +645,36 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     if (tid == 0) s_ucnt = 0;
     const int b = blockIdx.x;
     const int W = ld_ctrl(&a.ctrl->W);
-    const int row0 = b << tl;
+    int xb = 0, bt = b;   // vector and bucket within it
+    if constexpr (BATCH) {
+        xb = b / a.nbx;
+        bt = b - xb * a.nbx;
+    }
+    const int row0 = bt << tl;
     const int cnt_raw = ld_ctrl(&a.cursor[b]);
-    const int base = a.rcp[row0];
-    const int cap = a.rcp[min(row0 + T, a.m)] - base;
+    int base, cap;
+    if constexpr (BATCH) {
+        base = a.kbase[b];
+        cap = a.kbase[b + 1] - base;
+    } else {
+        base = a.rcp[row0];
+        cap = a.rcp[min(row0 + T, a.m)] - base;
+    }
     __syncthreads();
     if (W == 0) {
-        if (b == a.nb - 1 && tid == 0) {
-            a.ctrl->nnz_y = 0;
-            if (a.d_nnz_y) *a.d_nnz_y = 0;
-            if (a.set_f) st_ctrl(&a.ctrl->f, 0);
+        if (tid == 0) {
+            if (BATCH && bt == 0) a.yoff[xb] = 0;
+            if (b == a.nb - 1) {
+                a.ctrl->nnz_y = 0;
+                if (a.d_nnz_y) *a.d_nnz_y = 0;
+                if (a.set_f) st_ctrl(&a.ctrl->f, 0);
+                if (BATCH) a.yoff[a.nbatch] = 0;
+            }
         }
         return;
     }
     const int rows = min(T, a.m - row0);
-    if (cnt_raw == 0 && b != a.nb - 1) {
+    if (cnt_raw == 0 && b != a.nb - 1 && (!BATCH || bt != 0)) {
         if (tid == 0) st_release64(&a.lb3[b], (b == 0 ? LB_INC : LB_AGG));
         return;
     }
@@ -668,19 +752,27 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         const uint64_t e = lookback(a.lb3, b, (uint64_t)ucnt, &a.ctrl->err);
         if (tid == 0) {
             s_excl = (int64_t)e;
+            if (BATCH && bt == 0) a.yoff[xb] = (int64_t)e;
             if (b == a.nb - 1) {
                 const int64_t total = (int64_t)e + ucnt;
                 a.ctrl->nnz_y = total;
                 if (a.d_nnz_y) *a.d_nnz_y = total;
                 if (a.set_f) st_ctrl(&a.ctrl->f, (int32_t)total);
+                if (BATCH) a.yoff[a.nbatch] = total;
             }
         }
     }
     __syncthreads();
     const int64_t excl = s_excl;
     const int lvl = BFS ? ld_ctrl(&a.ctrl->level) : 0;
-    int32_t* const level = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_level) : nullptr;
-    int32_t* const parent = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_parent) : nullptr;
+    int32_t* level = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_level) : nullptr;
+    int32_t* parent = BFS ? ld_ctrl_ptr(&a.ctrl->bfs_parent) : nullptr;
+    uint32_t* visited = a.visited;
+    if (BATCH && BFS) {
+        level += (int64_t)xb * a.n_stride;
+        if (parent) parent += (int64_t)xb * a.n_stride;
+        visited += (int64_t)xb * a.mask_words;
+    }
 
     // In-order walk of the bitmap, kMergeList / 32 words per round.
     constexpr int kRoundWords = kMergeList / 32;
@@ -691,7 +783,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         const uint32_t bits = mine ? bm[w] : 0u;
         int tot;
         const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
-        if (BFS && bits) a.visited[(row0 >> 5) + w] |= bits;
+        if (BFS && bits) visited[(row0 >> 5) + w] |= bits;
         uint32_t rest = bits;
         int k = 0;
         while (rest) {
@@ -726,8 +818,8 @@ size_t merge_lds_bytes(int tile_log2) {
     return T * 4 + (T / 32) * 8 + size_t(kMergeList) * 2;
 }
 
-size_t scatter_lds_bytes(int nb, int chunk) {
-    const size_t table = size_t(chunk + 1) * 12, sortbuf = size_t(chunk) * 8;
+size_t scatter_lds_bytes(int nb, int chunk, bool batch) {
+    const size_t table = size_t(chunk + 1) * (batch ? 16 : 12), sortbuf = size_t(chunk) * (batch ? 12 : 8);
     return size_t(2 * nb + 2) * 4 + (table > sortbuf ? table : sortbuf);
 }
 
@@ -738,19 +830,24 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                                (int)bytes);
 }
 
-hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
+template <bool BATCH>
+static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s) {
     switch (a.xmode) {
         case XV_BITS32:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_BITS32>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_BITS32, BATCH>), dim3(grid), dim3(kScanBlock), 0,
+                               s, a);
             break;
         case XV_INDEX:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_INDEX>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_INDEX, BATCH>), dim3(grid), dim3(kScanBlock), 0,
+                               s, a);
             break;
         case XV_U8:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_U8>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_U8, BATCH>), dim3(grid), dim3(kScanBlock), 0, s,
+                               a);
             break;
         case XV_TRUE:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_TRUE>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_TRUE, BATCH>), dim3(grid), dim3(kScanBlock), 0,
+                               s, a);
             break;
         default:
             return hipErrorInvalidValue;
@@ -758,22 +855,31 @@ hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int BLOCK, int ITEMS, int SR>
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
+    if (a.xoff) {
+        if (a.nbatch < 1 || a.nbatch > kMaxBatch || !a.cxid || !a.kcount) return hipErrorInvalidValue;
+        return scan_mode<true>(a, grid, s);
+    }
+    return scan_mode<false>(a, grid, s);
+}
+
+template <int BLOCK, int ITEMS, int SR, int MODE>
 static hipError_t scatter_one(const ScatterArgs& a, int grid, hipStream_t s) {
-    const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS);
-    auto kern = k_scatter<BLOCK, ITEMS, SR>;
+    const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS, MODE != SC_SINGLE);
+    auto kern = k_scatter<BLOCK, ITEMS, SR, MODE>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
     return hipGetLastError();
 }
 
-template <int BLOCK, int ITEMS>
+template <int BLOCK, int ITEMS, int MODE>
 static hipError_t scatter_sr(const ScatterArgs& a, int semiring, int grid, hipStream_t s) {
+    if constexpr (MODE == SC_COUNT) return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s);
     switch (semiring) {
-        case SR_PLUS_TIMES: return scatter_one<BLOCK, ITEMS, SR_PLUS_TIMES>(a, grid, s);
-        case SR_MIN_SELECT2ND: return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND>(a, grid, s);
-        default: return scatter_one<BLOCK, ITEMS, SR_OR_AND>(a, grid, s);
+        case SR_PLUS_TIMES: return scatter_one<BLOCK, ITEMS, SR_PLUS_TIMES, MODE>(a, grid, s);
+        case SR_MIN_SELECT2ND: return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s);
+        default: return scatter_one<BLOCK, ITEMS, SR_OR_AND, MODE>(a, grid, s);
     }
 }
 
@@ -782,49 +888,74 @@ bool scatter_shape_supported(int block, int items) {
            (block == 512 && (items == 4 || items == 8)) || (block == 1024 && (items == 4 || items == 8));
 }
 
-hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
+template <int MODE>
+static hipError_t scatter_shape(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
     if (block == 256) {
-        if (items == 4) return scatter_sr<256, 4>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<256, 8>(a, semiring, grid, s);
-        if (items == 16) return scatter_sr<256, 16>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<256, 4, MODE>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<256, 8, MODE>(a, semiring, grid, s);
+        if (items == 16) return scatter_sr<256, 16, MODE>(a, semiring, grid, s);
     } else if (block == 512) {
-        if (items == 4) return scatter_sr<512, 4>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<512, 8>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<512, 4, MODE>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<512, 8, MODE>(a, semiring, grid, s);
     } else if (block == 1024) {
-        if (items == 4) return scatter_sr<1024, 4>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<1024, 8>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<1024, 4, MODE>(a, semiring, grid, s);
+        if (items == 8) return scatter_sr<1024, 8, MODE>(a, semiring, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int BLOCK, int SR, bool BFS>
+hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
+    return scatter_shape<SC_SINGLE>(a, semiring, block, items, grid, s);
+}
+
+hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
+                                hipStream_t s) {
+    if (!a.cxid || a.nbx < 1 || (count && !a.kcount) || (!count && !a.kbase)) return hipErrorInvalidValue;
+    return count ? scatter_shape<SC_COUNT>(a, semiring, block, items, grid, s)
+                 : scatter_shape<SC_BATCH>(a, semiring, block, items, grid, s);
+}
+
+template <int BLOCK, int SR, bool BFS, bool BATCH>
 static hipError_t merge_one(const MergeArgs& a, hipStream_t s) {
     const size_t lds = merge_lds_bytes(a.tile_log2);
-    auto kern = k_merge<BLOCK, kMergeItems, SR, BFS>;
+    auto kern = k_merge<BLOCK, kMergeItems, SR, BFS, BATCH>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.nb), dim3(BLOCK), lds, s, a);
     return hipGetLastError();
 }
 
-template <int BLOCK>
+template <int BLOCK, bool BATCH>
 static hipError_t merge_block(const MergeArgs& a, int semiring, bool bfs, hipStream_t s) {
     switch (semiring) {
         case SR_PLUS_TIMES:
             if (bfs) return hipErrorInvalidValue;
-            return merge_one<BLOCK, SR_PLUS_TIMES, false>(a, s);
+            return merge_one<BLOCK, SR_PLUS_TIMES, false, BATCH>(a, s);
         case SR_MIN_SELECT2ND:
-            return bfs ? merge_one<BLOCK, SR_MIN_SELECT2ND, true>(a, s) : merge_one<BLOCK, SR_MIN_SELECT2ND, false>(a, s);
+            return bfs ? merge_one<BLOCK, SR_MIN_SELECT2ND, true, BATCH>(a, s)
+                       : merge_one<BLOCK, SR_MIN_SELECT2ND, false, BATCH>(a, s);
         default:
-            return bfs ? merge_one<BLOCK, SR_OR_AND, true>(a, s) : merge_one<BLOCK, SR_OR_AND, false>(a, s);
+            return bfs ? merge_one<BLOCK, SR_OR_AND, true, BATCH>(a, s)
+                       : merge_one<BLOCK, SR_OR_AND, false, BATCH>(a, s);
     }
 }
 
-hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
-    if (block == 256) return merge_block<256>(a, semiring, bfs, s);
-    if (block == 512) return merge_block<512>(a, semiring, bfs, s);
-    if (block == 1024) return merge_block<1024>(a, semiring, bfs, s);
+template <bool BATCH>
+static hipError_t merge_dispatch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
+    if (block == 256) return merge_block<256, BATCH>(a, semiring, bfs, s);
+    if (block == 512) return merge_block<512, BATCH>(a, semiring, bfs, s);
+    if (block == 1024) return merge_block<1024, BATCH>(a, semiring, bfs, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
+    return merge_dispatch<false>(a, semiring, block, bfs, s);
+}
+
+hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
+    if (!a.kbase || !a.yoff || a.nbx < 1 || a.nbatch < 1 || (int64_t)a.nbx * a.nbatch != a.nb)
+        return hipErrorInvalidValue;
+    return merge_dispatch<true>(a, semiring, block, bfs, s);
 }
 
 }  // namespace spv
