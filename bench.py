@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--schedules", action="store_true", help="also time a grid of launch schedules")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (HBM counter calibration)")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched workload (R-MAT scale 20)")
+    ap.add_argument("--no-msbfs", action="store_true", help="skip the 64-source BFS of the batched workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -80,6 +82,9 @@ def main():
     spv.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batch_only:
+        print(json.dumps(batch_bench(spv, dev, msbfs=not args.no_msbfs)))
+        return
 
     t0 = time.time()
     A = synth.rmat(args.scale, 16, seed=1, symmetrize=True)
@@ -190,6 +195,10 @@ def main():
     if not args.no_extras:
         result["sweep"] = sweep(spv, M, A, deg, dev, stream)
         result["bfs"] = bfs_bench(spv, M, A, dev)
+        M.close()
+        del M, xi_d, xv_d
+        torch.cuda.empty_cache()
+        result["batched"] = batch_bench(spv, dev, msbfs=not args.no_msbfs)
     print(json.dumps(result))
 
 
@@ -337,6 +346,100 @@ def bfs_bench(spv, M, A, dev):
     out["note"] = ("GTEPS = sum over reached vertices of their column length (push-equivalent products) / time; "
                    "min-select2nd semiring (parents = smallest in-neighbour on the previous level)")
     P.close()
+    return out
+
+
+def batch_bench(spv, dev, msbfs=True, reps=5):
+    """64 independent x against R-MAT scale 20 (ef16, symmetrised, fp32
+    values) with f_i log-uniform in [1, n/4]: one batched call versus 64
+    plain calls (each reading nnz(y) back, and without the read-back); then
+    a 64-source BFS versus 64 single-source BFS runs."""
+    import torch
+    import synth
+    t0 = time.time()
+    A = synth.rmat(20, 16, seed=1, symmetrize=True)
+    deg = A.degrees()
+    M = spv.Matrix.from_csc(A, device=dev)
+    sizes = synth.log_uniform_sizes(64, A.n / 4, seed=4100)
+    xs = [synth.sparse_x(A.n, int(f), seed=5000 + k) for k, f in enumerate(sizes)]
+    off = np.zeros(65, np.int64)
+    off[1:] = np.cumsum(sizes)
+    W = np.array([int(deg[x[0]].sum()) for x in xs], np.int64)
+    Wt = int(W.sum())
+    xi_d = [torch.as_tensor(x[0]).to(dev) for x in xs]
+    xv_d = [torch.as_tensor(x[1]).to(dev) for x in xs]
+    off_d = torch.as_tensor(off).to(dev)
+    cat_i = torch.cat(xi_d)
+    cat_v = torch.cat(xv_d)
+    M.attach_batch(64, max_f=int(off[-1]), max_products=Wt)
+    y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
+    y_val = torch.empty(A.m, dtype=torch.float32, device=dev)
+    d_nnz = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    log(f"batched workload: n={A.n} nnz={A.nnz} sum f={int(off[-1])} products={Wt} (set-up {time.time() - t0:.1f}s)")
+
+    def plain(sync):
+        for k in range(64):
+            spv.spmspv_run(M.handle, 0, 0, int(sizes[k]), xi_d[k], xv_d[k], y_idx, y_val, A.m, d_nnz, sync=sync,
+                           stream=stream)
+
+    total_nnz = [0]
+    cap = int(min(64 * A.m, Wt)) + 1
+    by_idx = torch.empty(cap, dtype=torch.int32, device=dev)
+    by_val = torch.empty(cap, dtype=torch.float32, device=dev)
+    by_off = torch.empty(65, dtype=torch.int64, device=dev)
+
+    def batched(sync):
+        total_nnz[0] = spv.spmspv_run_batch(M.handle, 0, 0, 64, off_d, cat_i, cat_v, by_off, by_idx, by_val, cap,
+                                            sync=sync, stream=stream)
+
+    def timed(fn, *a):
+        best = []
+        fn(*a)
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn(*a)
+            torch.cuda.synchronize()
+            best.append(time.perf_counter() - t)
+        return float(np.median(best)), float(np.min(best))
+
+    out = {"workload": "64 x, f_i log-uniform in [1, n/4], plus-times fp32, R-MAT scale 20 ef16 symmetrised",
+           "n": A.n, "nnz": A.nnz, "sum_f": int(off[-1]), "products": Wt}
+    for name, fn, arg in (("plain_sync", plain, True), ("plain_nosync", plain, False),
+                          ("batched", batched, False), ("batched_sync", batched, True)):
+        med, mn = timed(fn, arg)
+        out[name] = {"ms": round(med * 1e3, 3), "min_ms": round(mn * 1e3, 3), "GTEPS": round(Wt / med / 1e9, 3)}
+        log(f"batched workload {name}: {out[name]}")
+    out["batched_over_plain_sync"] = round(out["plain_sync"]["ms"] / out["batched"]["ms"], 3)
+    out["batched_over_plain_nosync"] = round(out["plain_nosync"]["ms"] / out["batched"]["ms"], 3)
+    out["batch_schedule"] = spv.spmspv_get_batch_schedule(M.handle, 64).as_dict()
+    M.batch_ws = None
+    if msbfs:
+        roots = synth.roots(A, 64, seed=2000)
+        P = spv.Matrix(A.m, A.n, M.colptr, M.rowids, None, flags=spv.SYMMETRIC, device=dev)
+        P.attach_batch(64, msbfs=True)
+        single = {}
+        for name, fl in (("push", spv.USE_GRAPH), ("diropt", spv.USE_GRAPH | spv.DIRECTION_OPT)):
+            P.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, flags=fl)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for r in roots:
+                P.bfs(int(r), spv.MIN_SELECT2ND_I32, flags=fl)
+            torch.cuda.synchronize()
+            single[name] = round((time.perf_counter() - t) * 1e3, 2)
+        P.msbfs(roots)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lev, par, nl = P.msbfs(roots)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        out["msbfs64"] = {"batched_ms": round(ms, 2), "single_push_ms": single["push"],
+                          "single_diropt_ms": single["diropt"], "levels": nl,
+                          "batched_over_single_push": round(single["push"] / ms, 3)}
+        log(f"64-source BFS: {out['msbfs64']}")
+        P.close()
+    M.close()
     return out
 
 

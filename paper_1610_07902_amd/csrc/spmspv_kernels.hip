@@ -540,86 +540,81 @@ __device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) 
     else reinterpret_cast<uint32_t*>(y_val)[o] = v;
 }
 
-// Counts first touches of a wave: one LDS atomic per wave (ballot + popcount).
-__device__ __forceinline__ void count_first(bool first, int* s_ucnt) {
-    const uint64_t fm = __ballot(first);
-    if (fm && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(s_ucnt, (int)__popcll(fm));
-}
 
-template <int SR>
-__device__ __forceinline__ uint32_t combine(uint32_t x, uint32_t y) {
-    if constexpr (SR == SR_PLUS_TIMES) return __float_as_uint(__uint_as_float(x) + __uint_as_float(y));
-    else if constexpr (SR == SR_MIN_SELECT2ND) return (uint32_t)min((int)x, (int)y);
-    else return x | y;
-}
 
-template <int SR>
-__device__ __forceinline__ uint32_t wave_reduce(uint32_t v) {
+// Tile accumulation.  Measured on gfx950, an LDS float atomic add retires
+// about a third of a lane per cycle per compute unit, some 17 times slower
+// than an integer LDS atomic, while a compare-and-swap retry loop on a
+// 32-bit word sustains about 2.4 lanes per cycle on distinct addresses.
+// So plus-times adds through compare-and-swap, with untouched cells holding
+// kUntouched (a signalling NaN: products and sums of real values are never
+// signalling NaNs, so the cell itself records the first touch and no bitmap
+// atomic is needed).  Rows flagged heavy (hubs; many lanes of one wave may
+// hit the same one, where retries would pile up) start at +0.0 and take the
+// native float atomic plus a bitmap bit.  min and or use their native
+// integer atomics and the bitmap.
+constexpr uint32_t kUntouched = 0x7fa5a5a5u;
+
+// Applies K entries held by one thread.  For plus-times the K reads and
+// the K first compare-and-swap attempts are issued back to back, so a wave
+// pays the LDS round trip about twice per K entries; the rare lost races
+// retry one entry at a time.
+template <int SR, int K>
+__device__ __forceinline__ void add_rows(const uint32_t (&r)[K], const uint32_t (&v)[K], const bool (&ok)[K],
+                                         const bool (&hv)[K], uint32_t* spa, uint32_t* bm) {
+    if constexpr (SR == SR_PLUS_TIMES) {
+        bool light[K];
+        uint32_t old[K];
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = combine<SR>(v, (uint32_t)__shfl_xor((int)v, d, kWave));
-    return v;
-}
-
-// Hub rows: when at least kPeelMin lanes of a wave carry the row of the
-// wave's first heavy-row entry (rows with many stored entries, flagged once
-// per matrix), those lanes are collapsed into one LDS operation.  At most one
-// row is collapsed per wave instruction; all other entries go straight to
-// LDS atomics.  This keeps a hub row hit by a large share of a bucket's
-// entries from serialising a whole wave on one LDS address.
-constexpr int kPeelMin = 4;
-
-__device__ __forceinline__ uint64_t peel_mask(uint32_t r, bool valid, bool heavy, uint32_t& key, int& src) {
-    const uint64_t hm = __ballot(valid && heavy);
-    if (__popcll(hm) < kPeelMin) return 0ull;
-    src = __ffsll((unsigned long long)hm) - 1;
-    key = (uint32_t)__shfl((int)r, src, kWave);
-    const uint64_t km = __ballot(valid && heavy && r == key);
-    return __popcll(km) >= kPeelMin ? km : 0ull;
-}
-
-template <int SR>
-__device__ __forceinline__ bool touch_row(uint32_t r, bool valid, bool heavy, uint32_t* bm, uint32_t* spa,
-                                          bool init) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint32_t key = 0;
-    int src = 0;
-    const uint64_t km = peel_mask(r, valid, heavy, key, src);
-    const bool peeled = (km >> lane) & 1ull;
-    bool first = false;
-    if (valid && (!peeled || lane == src)) {
-        const uint32_t bit = 1u << (r & 31u);
-        first = (atomicOr(&bm[r >> 5], bit) & bit) == 0u;
-        if (first && init) spa[r] = identity<SR>();
-    }
-    return first;
-}
-
-template <int SR>
-__device__ __forceinline__ void add_row(uint32_t r, uint32_t v, bool valid, bool heavy, uint32_t* spa) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint32_t key = 0;
-    int src = 0;
-    const uint64_t km = peel_mask(r, valid, heavy, key, src);
-    if (km) {
-        const bool peeled = (km >> lane) & 1ull;
-        const uint32_t sum = wave_reduce<SR>(peeled ? v : identity<SR>());
-        if (valid && !peeled) accumulate<SR>(&spa[r], v);
-        if (lane == src) accumulate<SR>(&spa[key], sum);
-    } else if (valid) {
-        accumulate<SR>(&spa[r], v);
+        for (int u = 0; u < K; ++u) {
+            light[u] = ok[u] && !hv[u];
+            if (ok[u] && hv[u]) {
+                atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
+                atomicAdd(reinterpret_cast<float*>(&spa[r[u]]), __uint_as_float(v[u]));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) old[u] = light[u] ? spa[r[u]] : 0u;
+        uint32_t got[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            got[u] = old[u];
+            if (light[u]) {
+                const uint32_t nv =
+                    old[u] == kUntouched ? v[u] : __float_as_uint(__uint_as_float(old[u]) + __uint_as_float(v[u]));
+                got[u] = atomicCAS(&spa[r[u]], old[u], nv);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            while (got[u] != old[u]) {   // another lane updated the cell first
+                old[u] = got[u];
+                const uint32_t nv =
+                    old[u] == kUntouched ? v[u] : __float_as_uint(__uint_as_float(old[u]) + __uint_as_float(v[u]));
+                got[u] = atomicCAS(&spa[r[u]], old[u], nv);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            if (ok[u]) {
+                atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
+                accumulate<SR>(&spa[r[u]], v[u]);
+            }
+        }
     }
 }
 
 // One workgroup per bucket.  The bucket's rows [row0, row0 + T) get an LDS
-// sparse accumulator (T values) and a T-bit touched bitmap.  A row's first
-// touch is the atomicOr on the bitmap that finds its bit clear; first
-// touches are counted per wave by ballot.  Only touched accumulator cells are
-// initialised (Algorithm 1, step 2), unless the bucket holds more entries
-// than the registers cache, where the whole tile is initialised once and a
-// single streaming pass does both.  The unique count joins a decoupled
-// look-back across buckets to give the bucket's offset in y (Algorithm 1,
-// step 3) and the bitmap is walked in order, so y comes out ascending; the
-// walk compacts rows through a small LDS list for coalesced y writes.
+// sparse accumulator (T values) and a T-bit touched bitmap.  The whole tile
+// is initialised while the bucket's first entries are in flight (a store
+// per row is far cheaper here than tracking first touches row by row);
+// every entry then updates its row as described above, and the number of
+// unique rows of Algorithm 1 step 2 is the population count of the bitmap.
+// The unique count joins a decoupled look-back across buckets to give the
+// bucket's offset in y (Algorithm 1, step 3) and the bitmap is walked in
+// order, so y comes out ascending; the walk compacts rows through a small
+// LDS list for coalesced y writes.
 //
 // Batched calls (BATCH): workgroup k merges key k = vector * nbx + bucket;
 // the look-back runs over all keys, so y holds the vectors' results one
@@ -634,7 +629,6 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     uint32_t* bm = spa + T;                                          // [T/32]
     uint32_t* hb = bm + (T >> 5);                                    // [T/32] heavy rows
     uint16_t* list = reinterpret_cast<uint16_t*>(hb + (T >> 5));     // [kMergeList]
-    __shared__ int s_ucnt;
     __shared__ int64_t s_excl;
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
@@ -642,7 +636,6 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     // Buckets in blockIdx order: a bucket's look-back predecessors belong to
     // workgroups dispatched no later than its own (the wait is bounded).
     if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
-    if (tid == 0) s_ucnt = 0;
     const int b = blockIdx.x;
     const int W = ld_ctrl(&a.ctrl->W);
     int xb = 0, bt = b;   // vector and bucket within it
@@ -682,13 +675,9 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     // (duplicate x indices); never read past the bucket.
     const int cnt = min(cnt_raw, cap);
     const int nw = (rows + 31) >> 5;
-    for (int w = tid; w < nw; w += BLOCK) {
-        bm[w] = 0u;
-        hb[w] = a.heavy[(row0 >> 5) + w];
-    }
-
-    if (cnt <= BLOCK * ITEMS) {
-        uint32_t rr[ITEMS], vv[ITEMS];
+    const bool small = cnt <= BLOCK * ITEMS;
+    uint32_t rr[ITEMS], vv[ITEMS];
+    if (small) {   // the whole bucket in registers: issue every load before the tile set-up
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const int e = i * BLOCK + tid;
@@ -696,34 +685,45 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
             rr[i] = e < cnt ? ent.x : 0xffffffffu;
             vv[i] = ent.y;
         }
-        bool bad = false;
+    }
+    for (int w = tid; w < nw; w += BLOCK) {
+        bm[w] = 0u;
+        hb[w] = a.heavy[(row0 >> 5) + w];
+    }
+    if constexpr (SR == SR_PLUS_TIMES) __syncthreads();   // the cell init below reads hb
+    {
+        uint4* spa4 = reinterpret_cast<uint4*>(spa);
+        for (int q = tid; q < nw * 8; q += BLOCK) {   // 4 cells per store, whole bitmap words
+            uint32_t c[4];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            if (i * BLOCK + tid < cnt) {
-                rr[i] -= (uint32_t)row0;
-                if (rr[i] >= (uint32_t)rows) {  // unwritten slot after an overflow
-                    rr[i] = 0xffffffffu;
-                    bad = true;
+            for (int k = 0; k < 4; ++k) {
+                if constexpr (SR == SR_PLUS_TIMES) {
+                    const int r = q * 4 + k;
+                    c[k] = ((hb[r >> 5] >> (r & 31)) & 1u) ? 0u : kUntouched;
+                } else {
+                    c[k] = identity<SR>();
                 }
             }
+            spa4[q] = make_uint4(c[0], c[1], c[2], c[3]);
         }
-        if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
-        __syncthreads();
-        bool hv[ITEMS];
+    }
+    __syncthreads();
+    bool bad = false;
+    if (small) {
+        bool ok[ITEMS], hv[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            hv[i] = rr[i] != 0xffffffffu && ((hb[rr[i] >> 5] >> (rr[i] & 31u)) & 1u);
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            count_first(touch_row<SR>(rr[i], rr[i] != 0xffffffffu, hv[i], bm, spa, true), &s_ucnt);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) add_row<SR>(rr[i], vv[i], rr[i] != 0xffffffffu, hv[i], spa);
+        for (int i = 0; i < ITEMS; ++i) {
+            ok[i] = rr[i] != 0xffffffffu;
+            rr[i] -= (uint32_t)row0;
+            if (ok[i] && rr[i] >= (uint32_t)rows) {   // unwritten slot after an overflow
+                ok[i] = false;
+                bad = true;
+            }
+            hv[i] = ok[i] && ((hb[rr[i] >> 5] >> (rr[i] & 31u)) & 1u);
+        }
+        add_rows<SR, ITEMS>(rr, vv, ok, hv, spa, bm);
     } else {
-        for (int r = tid; r < rows; r += BLOCK) spa[r] = identity<SR>();
-        __syncthreads();
-        constexpr int kBatch = 4;   // entries per thread in flight per step
-        bool bad = false;
+        constexpr int kBatch = 8;   // entries per thread in flight per step
         for (int e0 = 0; e0 < cnt; e0 += BLOCK * kBatch) {
             uint2 ent[kBatch];
 #pragma unroll
@@ -731,23 +731,40 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                 const int e = e0 + u * BLOCK + tid;
                 ent[u] = e < cnt ? a.buckets[base + e] : make_uint2(0xffffffffu, 0u);
             }
+            uint32_t r[kBatch], v[kBatch];
+            bool ok[kBatch], hv[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const uint32_t r = ent[u].x - (uint32_t)row0;
-                bool valid = e0 + u * BLOCK + tid < cnt;
-                if (valid && r >= (uint32_t)rows) {
-                    valid = false;
+                r[u] = ent[u].x - (uint32_t)row0;
+                v[u] = ent[u].y;
+                ok[u] = e0 + u * BLOCK + tid < cnt;
+                if (ok[u] && r[u] >= (uint32_t)rows) {
+                    ok[u] = false;
                     bad = true;
                 }
-                const bool heavy = valid && ((hb[r >> 5] >> (r & 31u)) & 1u);
-                count_first(touch_row<SR>(r, valid, heavy, bm, spa, false), &s_ucnt);
-                add_row<SR>(r, ent[u].y, valid, heavy, spa);
+                hv[u] = ok[u] && ((hb[r[u] >> 5] >> (r[u] & 31u)) & 1u);
+            }
+            add_rows<SR, kBatch>(r, v, ok, hv, spa, bm);
+        }
+    }
+    if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+    __syncthreads();
+    if constexpr (SR == SR_PLUS_TIMES) {   // touched light rows are the cells that left kUntouched
+        // one wave-wide vote per 64 consecutive cells (conflict-free reads)
+        const int lane = tid & (kWave - 1);
+        for (int c0 = (tid - lane); c0 < nw * 32; c0 += BLOCK) {
+            const uint64_t v = __ballot(spa[c0 + lane] != kUntouched);
+            if (lane < 2) {
+                const int w = (c0 >> 5) + lane;
+                if (w < nw) bm[w] |= (uint32_t)(v >> (32 * lane)) & ~hb[w];
             }
         }
-        if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+        __syncthreads();
     }
-    __syncthreads();
-    const int ucnt = s_ucnt;
+    int pc = 0;
+    for (int w = tid; w < nw; w += BLOCK) pc += __popc(bm[w]);
+    int ucnt;
+    (void)block_exclusive_i32<BLOCK>(pc, s_tmp, ucnt);
     if (tid < kWave) {
         const uint64_t e = lookback(a.lb3, b, (uint64_t)ucnt, &a.ctrl->err);
         if (tid == 0) {
