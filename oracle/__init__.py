@@ -140,6 +140,16 @@ def bfs(A, root: int, lib=None):
     return lev, par, int(nl)
 
 
+def pagerank(A, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 100, lib=None):
+    """Data-driven (delta) PageRank in fp64: (rank float64[n], multiplies, active counts per step)."""
+    lib = lib or load()
+    rank = np.empty(A.n, np.float64)
+    act = np.zeros(max_iter + 1, np.int32)
+    it = lib.oracle_pagerank(A.n, _p(A.colptr), _p(A.rowids), float(damping), float(tol), int(max_iter), _p(rank),
+                             _p(act))
+    return rank, int(it), act[:it + 1].copy()
+
+
 # ------------------------------------------------------------ selector MLP
 MLP_SHAPE = (6, 64, 64, 10)
 

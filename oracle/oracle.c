@@ -299,3 +299,65 @@ double oracle_mlp_loss_grad(int in, int h1, int h2, int out, int B, const double
     free(a1); free(a2); free(z3); free(d3); free(d2); free(d1);
     return loss / B;
 }
+
+/*
+ * Data-driven (delta) PageRank in fp64.  The paper cites PageRank as a
+ * data-driven SpMSpV customer whose vertices stop sending updates once
+ * their value has converged (Introduction); it gives no formula, so this
+ * is the reading the GPU library implements:
+ *   outdeg(j) = stored entries of column j; A_n(i, j) = 1 / outdeg(j) for
+ *   every stored A(i, j) (edge j -> i); columns with no entries send
+ *   nothing (their mass is dropped).
+ *   p = 0; delta = (1 - d) / n at every vertex; every vertex active.
+ *   repeat:  p += delta;
+ *            stop when no vertex is active or max_iter multiplies are done;
+ *            delta' = d * A_n * (delta restricted to active vertices), as a
+ *              sparse product: its pattern is the rows reached (structural);
+ *            active = { v in pattern(delta') : delta'(v) > tol * p(v) }
+ *              (p before adding delta'); delta = delta'.
+ * rank[n] receives p.  active_counts (nullable, max_iter + 1 entries)
+ * receives the number of active vertices before each multiply.  Returns
+ * the number of multiplies performed.
+ */
+int oracle_pagerank(int64_t n, const int32_t* colptr, const int32_t* rowids, double damping, double tol,
+                    int max_iter, double* rank, int32_t* active_counts) {
+    double* delta = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double* next = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    unsigned char* active = (unsigned char*)malloc((size_t)(n > 0 ? n : 1));
+    unsigned char* reached = (unsigned char*)malloc((size_t)(n > 0 ? n : 1));
+    for (int64_t v = 0; v < n; ++v) {
+        rank[v] = 0.0;
+        delta[v] = (1.0 - damping) / (double)n;
+        active[v] = 1;
+    }
+    int it = 0;
+    for (;;) {
+        int64_t nact = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            rank[v] += delta[v];
+            nact += active[v];
+        }
+        if (active_counts) active_counts[it] = (int32_t)nact;
+        if (nact == 0 || it == max_iter) break;
+        for (int64_t v = 0; v < n; ++v) {
+            next[v] = 0.0;
+            reached[v] = 0;
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t len = colptr[j + 1] - colptr[j];
+            if (!active[j] || len == 0) continue;
+            const double c = damping * delta[j] / (double)len;
+            for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+                next[rowids[q]] += c;
+                reached[rowids[q]] = 1;
+            }
+        }
+        for (int64_t v = 0; v < n; ++v) {
+            active[v] = reached[v] && next[v] > tol * rank[v];
+            delta[v] = next[v];
+        }
+        ++it;
+    }
+    free(delta); free(next); free(active); free(reached);
+    return it;
+}
