@@ -88,6 +88,8 @@ enum spmspv_flags {
                                   (Beamer's frontier-edge heuristic); needs a
                                   handle created with one of the two flags
                                   above                                       */
+    SPMSPV_AUTO_SCHEDULE = 2048,/* spmspv_run: use the schedule spmspv_autotune
+                                  found for the density band nearest f / n  */
     SPMSPV_MSBFS = 1024,       /* spmspv_batch_workspace_size / _attach: also
                                   hold per-source frontiers and visited
                                   bitmaps for msbfs_run                       */
@@ -182,6 +184,41 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
 int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* level, int32_t* parent,
             int32_t* h_num_levels, void* stream);
 
+/* ---- autotuner.  Bucket count (tile_log2), bucketing workgroup shape,
+ * merge workgroup size and direction are searched by timing the library's
+ * own calls (coordinate descent, two passes, then the pull direction when
+ * the handle has it), per density band, on inputs drawn on the device
+ * (each column with probability `density`, values in (0, 1]).  The paper's
+ * CPU choice of 4t buckets ("Performance optimizations") is the analogue
+ * this replaces.  The best schedule of each band is kept in the handle and
+ * used by spmspv_run with SPMSPV_AUTO_SCHEDULE.  Never changes int / bool
+ * results or index sets.                                                 */
+typedef struct {
+    double density;           /* band                                      */
+    int64_t f;                /* x entries drawn for it                    */
+    spmspv_schedule sched;    /* fastest schedule found                    */
+    double us;                /* its time per call (microseconds)          */
+    double default_us;        /* the default schedule's time per call      */
+} spmspv_tune_entry;
+
+/* Synchronous.  x_idx [n], x_val [n] (float, plus-times only; NULL
+ * otherwise), y_idx [m], y_val [m] (4 bytes per entry) are caller scratch.
+ * reps timed calls per candidate.  h_out [ndens] (nullable).  1 <= ndens
+ * <= 64, densities in (0, 1].                                            */
+int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, int ndens, int reps, int32_t* x_idx,
+                    void* x_val, int32_t* y_idx, void* y_val, spmspv_tune_entry* h_out, void* stream);
+
+/* The tuned schedule spmspv_run would use for f x entries (EINVAL before
+ * spmspv_autotune).                                                       */
+int spmspv_tuned_schedule(spmspv_handle A, int64_t f, spmspv_schedule* h_sched);
+
+/* Tune the batched-call schedule on one given batch (arguments as for
+ * spmspv_run_batch), keep the fastest with spmspv_set_batch_schedule's
+ * effect, and report it and its time per call.  Synchronous.             */
+int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, const int64_t* x_off,
+                          const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,
+                          int64_t y_capacity, int reps, spmspv_schedule* h_best, double* h_us, void* stream);
+
 /* Read / replace the launch schedule (NULL restores the default). */
 int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched);
 int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
@@ -203,6 +240,28 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
 /* Release the handle (host memory and HIP events only; the caller frees
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
+
+/* ---- data-driven PageRank (the Introduction names PageRank among the
+ * data-driven SpMSpV uses, where a vertex stops sending updates once its
+ * value has converged; the paper gives no formula, this is the delta form):
+ *   rank = 0, delta = (1 - d) / n everywhere, every vertex active;
+ *   each step: rank += delta; x = { (j, d * delta(j) / outdeg(j)) : j active,
+ *   outdeg(j) > 0 } with outdeg(j) the stored entries of column j (edge
+ *   j -> i for stored A(i, j)); delta = A x (plus-times SpMSpV); vertex j
+ *   stays active when delta(j) > tol * rank(j) (rank before adding);
+ *   stop when no vertex is active or after max_iter multiplies.
+ * Mass of columns without entries is dropped.  fp32 on the device.       */
+
+/* Scratch bytes pagerank_run needs (16 n + 256). */
+int pagerank_scratch_size(spmspv_handle A, size_t* h_bytes);
+
+/* Needs m == n and a pattern handle (values NULL): A_n's entries are
+ * 1 / outdeg.  rank [n] (device float) receives the result.  Flags:
+ * SPMSPV_USE_SELECTOR picks each multiply's schedule with the loaded
+ * selector (one host synchronisation per step; without it the host checks
+ * every 16 steps).  *h_iters = multiplies performed.  Synchronous.       */
+int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int flags, float* rank, void* scratch,
+                 size_t scratch_bytes, int32_t* h_iters, void* stream);
 
 /* ---- batched calls (many x against one A in one launch sequence).
  * x is the concatenation of nbatch vectors: vector b occupies positions
@@ -273,7 +332,7 @@ int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, i
 int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_mean, const float* h_std,
                          void* stream);
 
-/* Classes chosen per level by the most recent bfs_run with
+/* Classes chosen per step by the most recent bfs_run or pagerank_run with
  * SPMSPV_USE_SELECTOR: writes min(cap, count) entries, *h_count = count.  */
 int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count);
 

@@ -30,6 +30,7 @@ SYMMETRIC = 128
 DIRECTION_OPT = 256
 USE_SELECTOR = 512
 MSBFS = 1024
+AUTO_SCHEDULE = 2048
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10
@@ -42,7 +43,8 @@ EXPORTED = (
     "spmspv_status_string", "spmspv_last_error", "spmspv_run_masked", "spmspv_selector_load",
     "spmspv_selector_classes", "spmspv_class_tile", "spmspv_mlp_param_count", "spmspv_mlp_forward",
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
-    "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run",
+    "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
+    "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
 )
 
 
@@ -58,6 +60,15 @@ class Schedule(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("density", ctypes.c_double), ("f", ctypes.c_int64), ("sched", Schedule), ("us", ctypes.c_double),
+                ("default_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"density": self.density, "f": self.f, "sched": self.sched.as_dict(), "us": self.us,
+                "default_us": self.default_us}
 
 
 _lib = None
@@ -96,6 +107,14 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_set_batch_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.spmspv_get_batch_schedule.argtypes = [vp, ci, ctypes.POINTER(Schedule)]
     lib.msbfs_run.argtypes = [vp, ci, ci, vp, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.spmspv_autotune.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_double), ci, ci, vp, vp, vp, vp,
+                                    ctypes.POINTER(TuneEntry), vp]
+    lib.spmspv_tuned_schedule.argtypes = [vp, i64, ctypes.POINTER(Schedule)]
+    lib.spmspv_autotune_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ci, ctypes.POINTER(Schedule),
+                                          ctypes.POINTER(ctypes.c_double), vp]
+    lib.pagerank_scratch_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.pagerank_run.argtypes = [vp, ctypes.c_float, ctypes.c_float, ci, ci, vp, vp, sz,
+                                 ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_last_error.argtypes = []
     lib.spmspv_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -241,6 +260,43 @@ def msbfs_run(handle, semiring, roots, flags, level, parent=None, stream=None) -
     _check(load_library().msbfs_run(handle, semiring, int(r.size), r.ctypes.data, flags, _ptr(level), _ptr(parent),
                                     ctypes.byref(nl), _stream(stream)))
     return nl.value
+
+
+def spmspv_autotune(handle, semiring, densities, reps, x_idx, x_val, y_idx, y_val, stream=None) -> list:
+    d = (ctypes.c_double * len(densities))(*[float(v) for v in densities])
+    out = (TuneEntry * len(densities))()
+    _check(load_library().spmspv_autotune(handle, semiring, d, len(densities), int(reps), _ptr(x_idx), _ptr(x_val),
+                                          _ptr(y_idx), _ptr(y_val), out, _stream(stream)))
+    return [e.as_dict() for e in out]
+
+
+def spmspv_tuned_schedule(handle, f) -> Schedule:
+    sc = Schedule()
+    _check(load_library().spmspv_tuned_schedule(handle, int(f), ctypes.byref(sc)))
+    return sc
+
+
+def spmspv_autotune_batch(handle, semiring, flags, nbatch, x_off, x_idx, x_val, y_off, y_idx, y_val, y_capacity,
+                          reps=5, stream=None):
+    sc = Schedule()
+    us = ctypes.c_double(0)
+    _check(load_library().spmspv_autotune_batch(handle, semiring, flags, int(nbatch), _ptr(x_off), _ptr(x_idx),
+                                                _ptr(x_val), _ptr(y_off), _ptr(y_idx), _ptr(y_val), int(y_capacity),
+                                                int(reps), ctypes.byref(sc), ctypes.byref(us), _stream(stream)))
+    return sc, us.value
+
+
+def pagerank_scratch_size(handle) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().pagerank_scratch_size(handle, ctypes.byref(out)))
+    return out.value
+
+
+def pagerank_run(handle, damping, tol, max_iter, flags, rank, scratch, scratch_bytes, stream=None) -> int:
+    it = ctypes.c_int32(0)
+    _check(load_library().pagerank_run(handle, float(damping), float(tol), int(max_iter), int(flags), _ptr(rank),
+                                       _ptr(scratch), int(scratch_bytes), ctypes.byref(it), _stream(stream)))
+    return it.value
 
 
 def bfs_run(handle, semiring, root, flags, level, parent=None, stream=None) -> int:
@@ -391,6 +447,27 @@ class Matrix:
             if (parents and semiring == MIN_SELECT2ND_I32) else None
         nl = msbfs_run(self.handle, semiring, roots, flags, level, parent)
         return level, parent, nl
+
+    def autotune(self, semiring: int = PLUS_TIMES_F32, densities=(1e-4, 1e-3, 1e-2, 1e-1), reps: int = 8):
+        """Run the autotuner (device scratch allocated here); returns the per-band table."""
+        import torch
+        dev = self.colptr.device
+        xi = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+        xv = torch.empty(max(self.n, 1), dtype=torch.float32, device=dev) if semiring == PLUS_TIMES_F32 else None
+        yi = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
+        yv = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
+        return spmspv_autotune(self.handle, semiring, densities, reps, xi, xv, yi, yv)
+
+    def pagerank(self, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 100, flags: int = 0):
+        """Data-driven PageRank on a pattern handle; returns (rank float32 tensor, multiplies)."""
+        import torch
+        dev = self.colptr.device
+        nbytes = pagerank_scratch_size(self.handle)
+        if getattr(self, "_pr_scratch", None) is None or self._pr_scratch.numel() < nbytes:
+            self._pr_scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        rank = torch.empty(self.n, dtype=torch.float32, device=dev)
+        it = pagerank_run(self.handle, damping, tol, max_iter, flags, rank, self._pr_scratch, nbytes)
+        return rank, it
 
     def load_selector(self, params, mean, std):
         spmspv_selector_load(self.handle, params, mean, std)

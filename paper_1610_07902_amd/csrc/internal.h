@@ -50,7 +50,8 @@ struct alignas(256) Ctrl {
     int32_t bfs_mode;       // the selector runs inside a BFS
     int32_t cls;            // class chosen by the selector for the current multiply
     float features[6];      // standardised selector features of the current multiply
-    uint32_t pad[30];
+    int32_t gen_count;      // entries drawn by the tuning-input generator
+    uint32_t pad[29];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -223,6 +224,12 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s);
 hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
+hipError_t launch_pr_init(int32_t n, const int32_t* colptr, float d, float* rank, int32_t* x_idx, float* x_val,
+                          Ctrl* ctrl, hipStream_t s);
+hipError_t launch_pr_update(int32_t n, const int32_t* colptr, float d, float tol, float* rank, const int32_t* y_idx,
+                            const float* y_val, int32_t* x_idx, float* x_val, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_gen_x(int32_t n, double density, uint64_t seed, int32_t* x_idx, float* x_val, Ctrl* ctrl,
+                        hipStream_t s);
 
 // Schedule-selector MLP (6 -> 64 -> 64 -> 10).
 constexpr int kMlpIn = 6, kMlpH1 = 64, kMlpH2 = 64, kMlpOut = 10;

@@ -159,6 +159,35 @@ __global__ void k_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t*
     }
 }
 
+// Tuning input: column j is drawn with probability `thresh / 2^32`, with a
+// value in (0, 1] on a 2^-24 grid, both from the SplitMix64 finaliser of
+// (seed, j).  Entries are appended in any order, one counter update per wave.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_gen_x(int32_t n, uint64_t thresh, uint64_t seed, int32_t* x_idx, float* x_val, Ctrl* ctrl) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t j = base + threadIdx.x;
+        const uint64_t h = j < n ? mix64(seed * 0x2545f4914f6cdd1dull + (uint64_t)j) : 0ull;
+        const bool take = j < n && (h >> 32) < thresh;
+        const uint64_t vote = __ballot(take);
+        int32_t first = 0;
+        if (lane == 0 && vote) first = atomicAdd(&ctrl->gen_count, (int32_t)__popcll(vote));
+        first = __shfl(first, 0, 64);
+        if (take) {
+            const int p = first + (int)__popcll(vote & ((1ull << lane) - 1ull));
+            x_idx[p] = (int32_t)j;
+            if (x_val) x_val[p] = (float)((h & 0xffffffull) + 1ull) * (1.0f / 16777216.0f);
+        }
+    }
+}
+
 // heavy bit of row r = (rcp[r+1] - rcp[r] >= thresh); one thread per 32-row word.
 __global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy) {
     const int64_t nw = ((int64_t)m + 31) >> 5;
@@ -259,6 +288,18 @@ hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t*
     const int64_t total = (int64_t)nsrc * n;
     hipLaunchKernelGGL(k_msbfs_init, dim3(grid_for(total, kSetupBlock)), dim3(kSetupBlock), 0, s, n, nsrc, roots,
                        level, parent, visited, mask_words, frontier, xoff, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_x(int32_t n, double density, uint64_t seed, int32_t* x_idx, float* x_val, Ctrl* ctrl,
+                        hipStream_t s) {
+    double t = density * 4294967296.0;
+    if (t < 0) t = 0;
+    if (t > 4294967296.0) t = 4294967296.0;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(&ctrl->gen_count), 0u,
+                       (int64_t)1);
+    hipLaunchKernelGGL(k_gen_x, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, n, (uint64_t)t, seed, x_idx,
+                       x_val, ctrl);
     return hipGetLastError();
 }
 

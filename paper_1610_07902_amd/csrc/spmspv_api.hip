@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <string>
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "spmspv.h"
@@ -218,6 +220,7 @@ struct spmspv_matrix {
     std::vector<int> level_classes;     // classes the selector chose in the last BFS
     BatchCtx batch;                     // second workspace for batched calls
     spmspv_schedule batch_sched{};      // batched-call schedule (tile_log2 0 = derive)
+    std::vector<spmspv_tune_entry> tuned;   // autotuned schedule per density band
 };
 
 namespace {
@@ -590,6 +593,46 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     return SPMSPV_OK;
 }
 
+// Schedule of the autotuned band nearest (in log density) to f / n.
+const spmspv_schedule* tuned_for(const spmspv_matrix* A, int64_t f) {
+    if (A->tuned.empty()) return nullptr;
+    const double d = std::log(std::max(1.0, (double)f) / (double)A->n);
+    const spmspv_tune_entry* best = &A->tuned[0];
+    for (const auto& e : A->tuned)
+        if (std::fabs(std::log(e.density) - d) < std::fabs(std::log(best->density) - d)) best = &e;
+    return &best->sched;
+}
+
+// Average device time of `reps` calls under schedule `sc` (two untimed
+// calls first), on stream s.
+int time_schedule(spmspv_matrix* A, const spmspv_schedule& sc, int semiring, int xmode, int64_t f,
+                  const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int reps, hipStream_t s,
+                  double* us) {
+    const spmspv_schedule keep = A->sched;
+    A->sched = sc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SPMSPV_OK;
+    auto once = [&]() {
+        return sc.direction == 1 ? enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, A->m,
+                                                nullptr, false, nullptr, false, false, s, nullptr)
+                                 : enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, A->m, nullptr,
+                                           false, nullptr, s, nullptr);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(SPMSPV_EHIP, "event");
+    for (int k = 0; k < 2 && !rc; ++k) rc = once();
+    if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(SPMSPV_EHIP, "event record");
+    for (int k = 0; k < reps && !rc; ++k) rc = once();
+    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(SPMSPV_EHIP, "event record");
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(SPMSPV_EHIP, "event sync");
+    float ms = 0.f;
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SPMSPV_EHIP, "event time");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    A->sched = keep;
+    if (!rc) *us = 1e3 * ms / reps;
+    return rc;
+}
+
 hipEvent_t* profile_slot(spmspv_matrix* A) {
     if (A->prof_ev.empty()) {
         A->prof_ev.resize(size_t(kProfileSlots) * 4);
@@ -820,12 +863,17 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 0u, 1, s));
         rc = run_selected(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
                           mask, s, &cls, nullptr);
-    } else if (A->sched.direction == 1) {
-        rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
-                          mask, false, false, s, ev);
     } else {
-        rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask, s,
-                     ev);
+        const spmspv_schedule keep = A->sched;
+        const spmspv_schedule* tuned = (flags & SPMSPV_AUTO_SCHEDULE) ? tuned_for(A, f) : nullptr;
+        if (tuned) A->sched = *tuned;
+        if (A->sched.direction == 1)
+            rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
+                              mask, false, false, s, ev);
+        else
+            rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask,
+                         s, ev);
+        A->sched = keep;
     }
     if (rc) return rc;
     if (h_nnz_y) {
@@ -1178,6 +1226,250 @@ int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, i
         return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
     }
     if (h_num_levels) *h_num_levels = h.level;
+    return SPMSPV_OK;
+}
+
+int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, int ndens, int reps, int32_t* x_idx,
+                    void* x_val, int32_t* y_idx, void* y_val, spmspv_tune_entry* h_out, void* stream) {
+    if (!A || !h_densities || ndens < 1 || ndens > 64 || reps < 1 || !x_idx || !y_idx || !y_val)
+        return fail(SPMSPV_EINVAL, "bad argument");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (semiring == SR_PLUS_TIMES && !x_val) return fail(SPMSPV_EINVAL, "plus-times tuning needs x_val");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int xmode = semiring == SR_PLUS_TIMES ? XV_BITS32 : (semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE);
+    spmspv_schedule dflt{};
+    default_schedule(A, &dflt);
+    std::vector<spmspv_tune_entry> table;
+    for (int d = 0; d < ndens; ++d) {
+        const double dens = h_densities[d];
+        if (!(dens > 0.0 && dens <= 1.0)) return fail(SPMSPV_EINVAL, "densities must be in (0, 1]");
+        HIP_TRY(launch_gen_x((int32_t)A->n, dens, 0x5eed0000ull + (uint64_t)d, x_idx,
+                             semiring == SR_PLUS_TIMES ? static_cast<float*>(x_val) : nullptr, A->ctrl, s));
+        Ctrl h{};
+        int rc = read_ctrl(A, &h, s);
+        if (rc) return rc;
+        const int64_t f = h.gen_count;
+        const void* xv = semiring == SR_PLUS_TIMES ? x_val : nullptr;
+        auto cost = [&](const spmspv_schedule& sc, double* us) {
+            return time_schedule(A, sc, semiring, xmode, f, x_idx, xv, y_idx, y_val, reps, s, us);
+        };
+        spmspv_tune_entry e{};
+        e.density = dens;
+        e.f = f;
+        rc = cost(dflt, &e.default_us);
+        if (rc) return rc;
+        spmspv_schedule best = dflt;
+        double best_us = e.default_us;
+        auto consider = [&](spmspv_schedule c) -> int {
+            if (check_schedule(A, &c) != SPMSPV_OK) {
+                g_last_error.clear();
+                return SPMSPV_OK;
+            }
+            double us = 0;
+            const int r = cost(c, &us);
+            if (r) return r;
+            if (us < best_us) {
+                best_us = us;
+                best = c;
+            }
+            return SPMSPV_OK;
+        };
+        // Coordinate descent over the push schedule, twice, then the pull direction.
+        const int shapes[7][2] = {{256, 4}, {256, 8}, {256, 16}, {512, 4}, {512, 8}, {1024, 4}, {1024, 8}};
+        const int merges[3] = {256, 512, 1024};
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int tl = kTileLog2Min; tl <= kTileLog2Max; ++tl) {
+                spmspv_schedule c = best;
+                c.direction = 0;
+                c.tile_log2 = tl;
+                if ((rc = consider(c))) return rc;
+            }
+            for (const auto& sh : shapes) {
+                spmspv_schedule c = best;
+                c.direction = 0;
+                c.scatter_block = sh[0];
+                c.scatter_items = sh[1];
+                if ((rc = consider(c))) return rc;
+            }
+            for (int mb : merges) {
+                spmspv_schedule c = best;
+                c.direction = 0;
+                c.merge_block = mb;
+                if ((rc = consider(c))) return rc;
+            }
+        }
+        if (A->pull) {
+            spmspv_schedule c = best;
+            c.direction = 1;
+            if ((rc = consider(c))) return rc;
+        }
+        e.sched = best;
+        e.us = best_us;
+        table.push_back(e);
+        if (h_out) h_out[d] = e;
+    }
+    A->tuned = table;
+    return SPMSPV_OK;
+}
+
+int spmspv_tuned_schedule(spmspv_handle A, int64_t f, spmspv_schedule* h_sched) {
+    if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    const spmspv_schedule* t = tuned_for(A, f);
+    if (!t) return fail(SPMSPV_EINVAL, "the handle has not been autotuned");
+    *h_sched = *t;
+    return SPMSPV_OK;
+}
+
+int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, const int64_t* x_off,
+                          const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,
+                          int64_t y_capacity, int reps, spmspv_schedule* h_best, double* h_us, void* stream) {
+    if (!A || reps < 1) return fail(SPMSPV_EINVAL, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // A checked call first: rejects bad arguments and sizes the outputs.
+    int64_t total = 0;
+    int rc = spmspv_run_batch(A, semiring, flags & ~SPMSPV_VALIDATE, nbatch, x_off, x_idx, x_val, y_off, y_idx,
+                              y_val, y_capacity, &total, stream);
+    if (rc) return rc;
+    const spmspv_schedule keep = A->batch_sched;
+    auto cost = [&](const spmspv_schedule& c, double* us) -> int {
+        A->batch_sched = c;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int r = SPMSPV_OK;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = fail(SPMSPV_EHIP, "event");
+        for (int k = 0; k < reps + 1 && !r; ++k) {
+            if (k == 1 && hipEventRecord(e0, s) != hipSuccess) r = fail(SPMSPV_EHIP, "event record");
+            if (!r) r = spmspv_run_batch(A, semiring, flags & ~SPMSPV_VALIDATE, nbatch, x_off, x_idx, x_val, y_off,
+                                         y_idx, y_val, y_capacity, nullptr, stream);
+        }
+        float ms = 0.f;
+        if (!r && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                   hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = fail(SPMSPV_EHIP, "event timing");
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (!r) *us = 1e3 * ms / reps;
+        return r;
+    };
+    spmspv_schedule best{};
+    rc = batch_shape(A, nbatch, &best);
+    if (rc) {
+        A->batch_sched = keep;
+        return rc;
+    }
+    double best_us = 0;
+    if ((rc = cost(best, &best_us))) {
+        A->batch_sched = keep;
+        return rc;
+    }
+    auto consider = [&](spmspv_schedule c) -> int {
+        spmspv_schedule eff{};
+        A->batch_sched = c;
+        if (batch_shape(A, nbatch, &eff) != SPMSPV_OK || eff.tile_log2 != c.tile_log2 ||
+            eff.scatter_block != c.scatter_block || eff.scatter_items != c.scatter_items) {
+            g_last_error.clear();
+            return SPMSPV_OK;   // infeasible for this batch
+        }
+        double us = 0;
+        const int r = cost(c, &us);
+        if (r) return r;
+        if (us < best_us) {
+            best_us = us;
+            best = c;
+        }
+        return SPMSPV_OK;
+    };
+    const int shapes[7][2] = {{256, 4}, {256, 8}, {256, 16}, {512, 4}, {512, 8}, {1024, 4}, {1024, 8}};
+    const int merges[3] = {256, 512, 1024};
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+        for (int tl = kTileLog2Min; tl <= kTileLog2Max && !rc; ++tl) {
+            spmspv_schedule c = best;
+            c.tile_log2 = tl;
+            rc = consider(c);
+        }
+        for (int k = 0; k < 7 && !rc; ++k) {
+            spmspv_schedule c = best;
+            c.scatter_block = shapes[k][0];
+            c.scatter_items = shapes[k][1];
+            rc = consider(c);
+        }
+        for (int k = 0; k < 3 && !rc; ++k) {
+            spmspv_schedule c = best;
+            c.merge_block = merges[k];
+            rc = consider(c);
+        }
+    }
+    if (rc) {
+        A->batch_sched = keep;
+        return rc;
+    }
+    A->batch_sched = best;
+    if (h_best) *h_best = best;
+    if (h_us) *h_us = best_us;
+    return SPMSPV_OK;
+}
+
+int pagerank_scratch_size(spmspv_handle A, size_t* h_bytes) {
+    if (!A || !h_bytes) return fail(SPMSPV_EINVAL, "NULL argument");
+    *h_bytes = size_t(A->n) * 16 + 256;
+    return SPMSPV_OK;
+}
+
+int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int flags, float* rank, void* scratch,
+                 size_t scratch_bytes, int32_t* h_iters, void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (A->m != A->n) return fail(SPMSPV_EINVAL, "PageRank needs a square matrix");
+    if (A->values) return fail(SPMSPV_EINVAL, "PageRank needs a pattern handle (values NULL)");
+    if (!(damping > 0.f && damping < 1.f) || !(tol >= 0.f) || max_iter < 0)
+        return fail(SPMSPV_EINVAL, "need 0 < damping < 1, tol >= 0, max_iter >= 0");
+    if (!rank || !scratch) return fail(SPMSPV_EINVAL, "NULL argument");
+    size_t need = 0;
+    pagerank_scratch_size(A, &need);
+    if (scratch_bytes < need) return fail(SPMSPV_ENOMEM, "scratch needs " + std::to_string(need) + " bytes");
+    const bool selector = (flags & SPMSPV_USE_SELECTOR) != 0;
+    if (selector && !A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    char* w = static_cast<char*>(scratch);
+    int32_t* x_idx = reinterpret_cast<int32_t*>(w);
+    float* x_val = reinterpret_cast<float*>(w + 4 * n);
+    int32_t* y_idx = reinterpret_cast<int32_t*>(w + 8 * n);
+    float* y_val = reinterpret_cast<float*>(w + 12 * n);
+    HIP_TRY(launch_pr_init((int32_t)n, A->colptr, damping, rank, x_idx, x_val, A->ctrl, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 0u, 1, s));
+    A->level_classes.clear();
+    int32_t hf = 1;
+    int done = 0;
+    while (hf > 0 && done < max_iter) {
+        // kGraphLevels steps per host check; steps after x empties are no-ops
+        const int steps = selector ? 1 : std::min(kGraphLevels, max_iter - done);
+        for (int k = 0; k < steps; ++k) {
+            int rc;
+            if (selector) {
+                int cls = 0;
+                int32_t fnow = 0;
+                rc = run_selected(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n,
+                                  nullptr, false, nullptr, s, &cls, &fnow);
+                if (!rc && fnow > 0) A->level_classes.push_back(cls);
+            } else {
+                rc = enqueue(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n, nullptr,
+                             false, nullptr, s, nullptr);
+            }
+            if (rc) return rc;
+            HIP_TRY(launch_pr_update((int32_t)n, A->colptr, damping, tol, rank, y_idx, y_val, x_idx, x_val, A->ctrl,
+                                     s));
+        }
+        done += steps;
+        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    Ctrl h{};
+    int rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    if (h.err) {
+        clear_err(A, s);
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (h_iters) *h_iters = h.level;
     return SPMSPV_OK;
 }
 

@@ -1,0 +1,101 @@
+"""GPU tests of the autotuner: tuned schedules never change results, the
+table is consistent, and the batched tuner keeps a feasible schedule."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_07902_amd as spv
+    spv.load_library()
+    oracle.build(force=False)
+    synth.build(force=False)
+    return spv
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def rmat15():
+    return synth.rmat(15, 16, seed=41, symmetrize=True)
+
+
+@pytest.mark.parametrize("semiring", [0, 1])
+def test_autotune_table_and_parity(spv, rmat15, semiring):
+    A = rmat15
+    M = spv.Matrix.from_csc(A, flags=spv.WITH_TRANSPOSE)
+    with pytest.raises(spv.SpmspvError):
+        spv.spmspv_tuned_schedule(M.handle, 100)          # not tuned yet
+    dens = (1e-3, 1e-2, 1e-1)
+    table = M.autotune(semiring, dens, reps=3)
+    assert [e["density"] for e in table] == list(dens)
+    for e in table:
+        # the draw is Bernoulli(density) per column: within 6 sigma of n * density
+        mu = A.n * e["density"]
+        assert abs(e["f"] - mu) <= 6 * np.sqrt(mu) + 2
+        assert e["us"] <= e["default_us"] + 1e-9
+        sc = e["sched"]
+        assert 8 <= sc["tile_log2"] <= 15 and sc["direction"] in (0, 1)
+    for k, d in enumerate(dens):
+        f = synth.density_f(A.n, d)
+        got = spv.spmspv_tuned_schedule(M.handle, f)
+        assert got.as_dict() == table[k]["sched"]
+        S, xv = synth.sparse_x(A.n, f, seed=60 + k)
+        if semiring == 0:
+            gi, gv, _ = M.spmspv(dev(S), dev(xv), semiring=0, sorted_output=True, flags=spv.AUTO_SCHEDULE)
+            oi, ov, _ = oracle.spmspv(A, S, xv, 0, sorted_output=True)
+        else:
+            gi, gv, _ = M.spmspv(dev(S), None, semiring=1, sorted_output=True,
+                                 flags=spv.AUTO_SCHEDULE | spv.X_VAL_IS_INDEX)
+            oi, ov, _ = oracle.spmspv(A, S, S.astype(np.int32), 1, sorted_output=True)
+        compare(semiring, gi, gv, oi, ov, sorted_output=True)
+    # the handle's own schedule is untouched by tuning and by auto calls
+    assert M.schedule.direction == 0
+
+
+def test_autotune_bad_arguments(spv, rmat15):
+    M = spv.Matrix.from_csc(rmat15)
+    with pytest.raises(spv.SpmspvError):
+        M.autotune(0, (0.0,), reps=1)
+    with pytest.raises(spv.SpmspvError):
+        M.autotune(0, (1.5,), reps=1)
+
+
+def test_autotune_batch(spv, rmat15):
+    A = rmat15
+    M = spv.Matrix.from_csc(A)
+    sizes = synth.log_uniform_sizes(16, A.n / 4, seed=3)
+    xs = [synth.sparse_x(A.n, int(f), seed=90 + k) for k, f in enumerate(sizes)]
+    off = np.zeros(17, np.int64)
+    off[1:] = np.cumsum(sizes)
+    idx = np.concatenate([x[0] for x in xs])
+    val = np.concatenate([x[1] for x in xs])
+    W = int(sum(A.degrees()[x[0]].sum() for x in xs))
+    M.attach_batch(16, max_f=int(off[-1]), max_products=W)
+    cap = 16 * A.m
+    y_off = torch.empty(17, dtype=torch.int64, device="cuda")
+    y_idx = torch.empty(cap, dtype=torch.int32, device="cuda")
+    y_val = torch.empty(cap, dtype=torch.float32, device="cuda")
+    best, us = spv.spmspv_autotune_batch(M.handle, 0, 0, 16, dev(off), dev(idx), dev(val), y_off, y_idx, y_val, cap,
+                                         reps=2)
+    assert us > 0
+    eff = spv.spmspv_get_batch_schedule(M.handle, 16)
+    assert eff.as_dict() == best.as_dict()
+    total = spv.spmspv_run_batch(M.handle, 0, 0, 16, dev(off), dev(idx), dev(val), y_off, y_idx, y_val, cap)
+    yo = to_np(y_off)
+    assert yo[-1] == total
+    for b in range(16):
+        oi, ov, _ = oracle.spmspv(A, xs[b][0], xs[b][1], 0, sorted_output=True)
+        compare(0, y_idx[yo[b]:yo[b + 1]], y_val[yo[b]:yo[b + 1]], oi, ov, sorted_output=True)
