@@ -88,6 +88,11 @@ enum spmspv_flags {
                                   (Beamer's frontier-edge heuristic); needs a
                                   handle created with one of the two flags
                                   above                                       */
+    SPMSPV_PULL_ROWWISE = 4096,/* spmspv_run with the pull direction, min-
+                                  select2nd or or-and: one thread per row
+                                  not masked, stopping at the first x hit (the
+                                  bottom-up BFS step) instead of the
+                                  merge-path row kernel                       */
     SPMSPV_AUTO_SCHEDULE = 2048,/* spmspv_run: use the schedule spmspv_autotune
                                   found for the density band nearest f / n  */
     SPMSPV_MSBFS = 1024,       /* spmspv_batch_workspace_size / _attach: also
@@ -335,6 +340,10 @@ int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_
 /* Classes chosen per step by the most recent bfs_run or pagerank_run with
  * SPMSPV_USE_SELECTOR: writes min(cap, count) entries, *h_count = count.  */
 int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count);
+
+/* Standardised features of the most recent selector decision (h_out[6],
+ * in the order above; synchronous).                                      */
+int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream);
 
 /* tile_log2 that class `cls` (0..8) runs with on this handle; -1 for 9.   */
 int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2);

@@ -31,6 +31,7 @@ DIRECTION_OPT = 256
 USE_SELECTOR = 512
 MSBFS = 1024
 AUTO_SCHEDULE = 2048
+PULL_ROWWISE = 4096
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10
@@ -45,6 +46,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
+    "spmspv_selector_features",
 )
 
 
@@ -81,6 +83,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    # PyTorch provides the device memory and streams: load its HIP runtime
+    # first so the library binds to the same runtime instance.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     i64, vp, ci, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     lib.spmspv_workspace_size.argtypes = [i64, i64, i64, ci, ctypes.POINTER(sz)]
@@ -112,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_tuned_schedule.argtypes = [vp, i64, ctypes.POINTER(Schedule)]
     lib.spmspv_autotune_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ci, ctypes.POINTER(Schedule),
                                           ctypes.POINTER(ctypes.c_double), vp]
+    lib.spmspv_selector_features.argtypes = [vp, ctypes.POINTER(ctypes.c_float), vp]
     lib.pagerank_scratch_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.pagerank_run.argtypes = [vp, ctypes.c_float, ctypes.c_float, ci, ci, vp, vp, sz,
                                  ctypes.POINTER(ctypes.c_int32), vp]
@@ -197,6 +203,12 @@ def spmspv_selector_classes(handle) -> list:
     buf = (ctypes.c_int32 * max(cnt.value, 1))()
     _check(load_library().spmspv_selector_classes(handle, buf, cnt.value, ctypes.byref(cnt)))
     return list(buf[:cnt.value])
+
+
+def spmspv_selector_features(handle, stream=None) -> list:
+    out = (ctypes.c_float * 6)()
+    _check(load_library().spmspv_selector_features(handle, out, _stream(stream)))
+    return list(out)
 
 
 def spmspv_class_tile(handle, cls: int) -> int:

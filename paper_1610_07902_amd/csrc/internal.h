@@ -185,7 +185,10 @@ constexpr int kPullBlock = 256;
 constexpr int kPullItems = 8;
 constexpr int kPullChunk = kPullBlock * kPullItems;
 
-hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, hipStream_t s);
+// rowwise: one thread per unmasked row with first-hit exit (the bottom-up BFS
+// step; min-select2nd and or-and only) instead of the merge-path kernel.
+hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, bool rowwise,
+                       hipStream_t s);
 hipError_t launch_pull_setup(const int32_t* colptr, const int32_t* rowids, const float* values, int32_t m,
                              int32_t n, int64_t nnz, const int32_t* rowptr, int32_t* cursor, int32_t* colids,
                              float* tvalues, int32_t* part, uint32_t* unsorted, hipStream_t s);

@@ -432,7 +432,9 @@ __global__ void k_check_sorted(const int32_t* colptr, const int32_t* rowids, int
 
 }  // namespace
 
-hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, hipStream_t s) {
+hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, bool early, bool rowwise,
+                       hipStream_t s) {
+    if (rowwise && semiring == SR_PLUS_TIMES) return hipErrorInvalidValue;
     int64_t fg = (a.f_host + 255) / 256 + 1;
     if (a.f_dev || fg > 1024) fg = 1024;
     const int f_grid = (int)fg;
@@ -443,7 +445,7 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
         case XV_U8: hipLaunchKernelGGL(k_pull_prep<XV_U8>, dim3(f_grid), dim3(256), 0, s, a); break;
         default: hipLaunchKernelGGL(k_pull_prep<XV_TRUE>, dim3(f_grid), dim3(256), 0, s, a); break;
     }
-    if (bfs) {
+    if (rowwise) {
         // bottom-up step: one thread per row, first-hit exit
         const dim3 gb((a.m + 255) / 256 < 8192 ? (a.m + 255) / 256 : 8192), bb(256);
         if (semiring == SR_MIN_SELECT2ND) {

@@ -372,7 +372,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
 int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
                  const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
                  int64_t* d_nnz_y, bool bfs, const uint32_t* mask, bool bump, bool gate, hipStream_t s,
-                 hipEvent_t* ev) {
+                 hipEvent_t* ev, bool rowwise = false) {
     const uint32_t ident = semiring == SR_MIN_SELECT2ND ? 0x7fffffffu : 0u;
     if (A->ydense_ident != ident) {
         HIP_TRY(launch_fill_ident(A->p_ydense, ident, A->m, s));
@@ -409,7 +409,7 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     pa.gate = gate ? 1 : 0;
     const bool early = semiring == SR_OR_AND || (semiring == SR_MIN_SELECT2ND && xmode == XV_INDEX && A->rows_sorted);
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_pull(pa, semiring, xmode, bfs, early, s));
+    HIP_TRY(launch_pull(pa, semiring, xmode, bfs, early, bfs || rowwise, s));
     if (ev) {
         HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(hipEventRecord(ev[2], s));
@@ -841,6 +841,8 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
     if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
     else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
     if (f > 0 && !x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    if ((flags & SPMSPV_PULL_ROWWISE) && semiring == SR_PLUS_TIMES)
+        return fail(SPMSPV_EINVAL, "SPMSPV_PULL_ROWWISE is for min-select2nd and or-and");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     if (flags & SPMSPV_VALIDATE) {
@@ -869,7 +871,7 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
         if (tuned) A->sched = *tuned;
         if (A->sched.direction == 1)
             rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
-                              mask, false, false, s, ev);
+                              mask, false, false, s, ev, (flags & SPMSPV_PULL_ROWWISE) != 0);
         else
             rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask,
                          s, ev);
@@ -1050,6 +1052,15 @@ int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_
     if (!A || !h_count) return fail(SPMSPV_EINVAL, "NULL argument");
     *h_count = (int32_t)A->level_classes.size();
     for (int32_t k = 0; k < cap && k < *h_count; ++k) h_out[k] = A->level_classes[(size_t)k];
+    return SPMSPV_OK;
+}
+
+int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream) {
+    if (!A || !h_out) return fail(SPMSPV_EINVAL, "NULL argument");
+    Ctrl h{};
+    const int rc = read_ctrl(A, &h, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    for (int c = 0; c < kMlpIn; ++c) h_out[c] = h.features[c];
     return SPMSPV_OK;
 }
 

@@ -212,6 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         for (int i = blockIdx.x * BLOCK + tid; i <= a.nb; i += gridDim.x * BLOCK) a.kcount[i] = 0;
     if (blockIdx.x == 0 && tid == 0) {
         st_ctrl_u(&a.ctrl->ticket_merge, 0u);
+        if (!BATCH && !a.f_dev) st_ctrl(&a.ctrl->f, f);   // the selector reads f from here
         if (a.bump_level && f > 0) st_ctrl(&a.ctrl->level, ld_ctrl(&a.ctrl->level) + 1);
         if (f <= 0) {
             st_ctrl(&a.ctrl->W, 0);

@@ -258,3 +258,31 @@ def test_selector_load_rejects_bad_weights(spv, rmat14):
     S = dev(np.arange(10, dtype=np.int32))
     with pytest.raises(spv.SpmspvError):
         M.spmspv(S, dev(np.ones(10, np.float32)), flags=spv.USE_SELECTOR)   # selector disabled
+
+
+def test_device_features_match_host(spv, rmat14):
+    """The features the device computes for its decision equal the host's
+    computation from the same call's statistics (what training uses)."""
+    from paper_1610_07902_amd import selector
+    A = rmat14
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
+    rng = np.random.default_rng(8)
+    mean = rng.normal(5, 2, 6).astype(np.float32)
+    std = rng.uniform(0.5, 3, 6).astype(np.float32)
+    p = np.zeros(spv.MLP_PARAMS, np.float32)
+    p[-10 + 4] = 1.0
+    M.load_selector(p, mean, std)
+    for f in (1, 37, 2000):
+        S, _ = synth.sparse_x(A.n, f, seed=f)
+        M.spmspv(dev(S), None, semiring=1, flags=spv.USE_SELECTOR | spv.X_VAL_IS_INDEX)
+        st = M.last_stats()
+        dev_feat = np.array(spv.spmspv_selector_features(M.handle))
+        raw = selector.raw_features(f, st["W"], st["maxlen"], A.n, A.nnz, A.n)
+        host = (selector.encode(raw) - mean) / std
+        assert np.allclose(dev_feat, host, rtol=1e-5, atol=1e-5), (dev_feat, host)
+    # inside a BFS the last feature counts the vertices not yet reached
+    root = int(np.argmax(A.degrees()))
+    lev, _, nl = M.bfs(root, semiring=1, flags=spv.USE_SELECTOR)
+    dev_feat = np.array(spv.spmspv_selector_features(M.handle))
+    reached = int((to_np(lev) >= 0).sum())
+    assert np.isclose(dev_feat[5] * std[5] + mean[5], np.log2(1 + A.n - reached), atol=1e-4)

@@ -1,0 +1,66 @@
+"""What the trained selector gains over the method without it.
+
+The network is trained on the GPU (the library's own forward / backward /
+Adam kernels) from timings of the library's own calls on small training
+graphs, then judged on a held-out graph it never saw: on each held-out
+input every class is timed, and the selector's choice is scored against
+the fastest class (regret = summed time of the choices / summed best time).
+Without the selector the library runs its default schedule (push with 256
+buckets, class 4) everywhere; the test requires the learned choices to cost
+less than that, and reports the best single fixed class as well."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def spv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_07902_amd as spv
+    spv.load_library()
+    synth.build(force=False)
+    return spv
+
+
+DEFAULT_CLASS = 4
+
+
+def collect(spv, A, name, roots, seed):
+    from paper_1610_07902_amd import selector
+    P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
+    s = selector.bfs_samples(P, A.nnz, synth.roots(A, roots, seed=seed), reps=2, tag=name)
+    s.extend(selector.random_samples(P, A.nnz, (1e-4, 1e-3, 1e-2, 1e-1, 3e-1), spv.MIN_SELECT2ND_I32, reps=2,
+                                     seed=seed, tag=name))
+    P.close()
+    return s
+
+
+def test_trained_selector_beats_default_schedule_on_held_out_graph(spv, capsys):
+    from paper_1610_07902_amd import selector
+    train = selector.Samples()
+    for name, A in (("rmat13", synth.rmat(13, 16, seed=201, symmetrize=True)),
+                    ("rmat15", synth.rmat(15, 16, seed=202, symmetrize=True)),
+                    ("grid2d", synth.grid(128, 128, 1)),
+                    ("grid3d", synth.grid(24, 24, 24))):
+        train.extend(collect(spv, A, name, 3, 11))
+    params, mean, std, hist = selector.train(train, epochs=150, lr=2e-3)
+    assert hist[-1] < hist[0]
+    held = selector.Samples()
+    held.extend(collect(spv, synth.rmat(16, 16, seed=203, symmetrize=True), "rmat16", 3, 12))
+    held.extend(collect(spv, synth.grid(40, 40, 20), "grid3d-40", 2, 13))
+    T = held.T
+    pred = selector.predict(params, mean, std, held.X)
+    learned = selector.regret(T, pred)
+    default = selector.regret(T, np.full(len(pred), DEFAULT_CLASS))
+    single = min(selector.regret(T, np.full(len(pred), c)) for c in range(10) if np.isfinite(T[:, c]).all())
+    with capsys.disabled():
+        print(f"\n[selector gain] held-out samples {len(pred)}: regret learned {learned:.3f}, "
+              f"default class {default:.3f}, best single class in hindsight {single:.3f}")
+    assert learned < default, (learned, default)
+    assert learned < 1.5
