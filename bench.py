@@ -65,6 +65,9 @@ def main():
                     help="only run plain 256 MiB device copies (HBM counter calibration)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched workload (R-MAT scale 20)")
     ap.add_argument("--no-msbfs", action="store_true", help="skip the 64-source BFS of the batched workload")
+    ap.add_argument("--selector-only", action="store_true", help="only the learned-selector evaluation")
+    ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
+    ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -84,6 +87,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batch_only:
         print(json.dumps(batch_bench(spv, dev, msbfs=not args.no_msbfs)))
+        return
+    if args.selector_only:
+        print(json.dumps(selector_eval(spv, dev, args.selector_scale)))
         return
 
     t0 = time.time()
@@ -199,6 +205,9 @@ def main():
         del M, xi_d, xv_d
         torch.cuda.empty_cache()
         result["batched"] = batch_bench(spv, dev, msbfs=not args.no_msbfs)
+        torch.cuda.empty_cache()
+        if not args.no_selector_eval:
+            result["learned_selector"] = selector_eval(spv, dev, args.selector_scale)
     print(json.dumps(result))
 
 
@@ -440,6 +449,77 @@ def batch_bench(spv, dev, msbfs=True, reps=5):
         log(f"64-source BFS: {out['msbfs64']}")
         P.close()
     M.close()
+    return out
+
+
+def selector_eval(spv, dev, scale=24, nroots=16, reps=2):
+    """Held-out evaluation of the trained selector: R-MAT scale 24 (ef16,
+    symmetrised; never seen in training).  BFS from 16 roots with the fixed
+    default schedule (push), the frontier-edge direction heuristic, and the
+    learned selector, against the best schedule in hindsight (every level
+    timed under all ten classes; strict = per-level minimum, single = best
+    one class for all levels).  Then data-driven PageRank (d 0.85, tol 1e-6)
+    with the default schedule and with the selector."""
+    import torch
+    import synth
+    from paper_1610_07902_amd import selector
+    t0 = time.time()
+    A = synth.rmat(scale, 16, seed=24, symmetrize=True, with_values=False)
+    log(f"selector eval: generated R-MAT s{scale} n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True, device=dev)
+    params, mean, std, meta = selector.load_weights()
+    P.load_selector(params, mean, std)
+    roots = synth.roots(A, nroots, seed=2000)
+    del A
+    out = {"graph": f"R-MAT scale {scale} ef16 symmetrised (held out)", "n": P.n, "nnz": P.nnz, "roots": nroots,
+           "training": meta}
+
+    def run_bfs(flags):
+        P.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, parents=True, flags=flags)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        classes = []
+        for r in roots:
+            P.bfs(int(r), spv.MIN_SELECT2ND_I32, parents=True, flags=flags)
+            if flags & spv.USE_SELECTOR:
+                classes.append(P.selector_classes())
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, classes
+
+    for name, fl in (("default_push", spv.USE_GRAPH), ("direction_heuristic", spv.USE_GRAPH | spv.DIRECTION_OPT),
+                     ("learned", spv.USE_SELECTOR), ("learned_in_graph", spv.USE_SELECTOR | spv.USE_GRAPH)):
+        ms, cls = run_bfs(fl)
+        out[name + "_ms"] = round(ms, 2)
+        if cls:
+            out["learned_classes_root0"] = cls[0]
+        log(f"selector eval BFS {name}: {ms:.2f} ms")
+    samples = selector.bfs_samples(P, P.nnz, roots, reps=reps, tag=f"rmat{scale}")
+    T = samples.T
+    out["hindsight_strict_ms"] = round(float(T.min(1).sum()) * 1e-3, 2)
+    single = [float(T[:, c].sum()) * 1e-3 for c in range(10)]
+    out["hindsight_single_class"] = int(np.argmin(single))
+    out["hindsight_single_ms"] = round(min(single), 2)
+    pred = selector.predict(params, mean, std, samples.X)
+    out["learned_choice_regret"] = round(selector.regret(T, pred), 4)
+    out["learned_over_hindsight"] = round(out["learned_ms"] / out["hindsight_strict_ms"], 3)
+    out["learned_in_graph_over_hindsight"] = round(out["learned_in_graph_ms"] / out["hindsight_strict_ms"], 3)
+    out["default_over_hindsight"] = round(out["default_push_ms"] / out["hindsight_strict_ms"], 3)
+    log(f"selector eval hindsight strict {out['hindsight_strict_ms']} ms, single class "
+        f"{out['hindsight_single_class']} {out['hindsight_single_ms']} ms, choice regret {out['learned_choice_regret']}")
+    for name, fl in (("pagerank_default", 0), ("pagerank_learned", spv.USE_SELECTOR)):
+        P.pagerank(0.85, 1e-6, 100, flags=fl)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, it = P.pagerank(0.85, 1e-6, 100, flags=fl)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round((time.perf_counter() - t) * 1e3, 2)
+        out[name + "_iters"] = it
+        log(f"selector eval {name}: {out[name + '_ms']} ms, {it} multiplies")
+    out["note"] = ("hindsight times are sums of per-level event-timed calls of each class (masked SpMSpV steps); "
+                   "learned and fixed BFS times are end-to-end host-timed runs; 'learned' reads each decision on the "
+                   "host (bucket count and direction), 'learned_in_graph' consumes it on the device inside the "
+                   "captured level graph (direction only)")
+    P.close()
     return out
 
 

@@ -98,12 +98,16 @@ enum spmspv_flags {
     SPMSPV_MSBFS = 1024,       /* spmspv_batch_workspace_size / _attach: also
                                   hold per-source frontiers and visited
                                   bitmaps for msbfs_run                       */
-    SPMSPV_USE_SELECTOR = 512  /* spmspv_run / bfs_run: a small MLP loaded with
-                                  spmspv_selector_load picks the bucket count
-                                  (or the pull direction) per call from
-                                  features the scan computes on the device;
-                                  one extra host synchronisation per call or
-                                  BFS level                                   */
+    SPMSPV_USE_SELECTOR = 512  /* spmspv_run / bfs_run / pagerank_run: a small
+                                  MLP loaded with spmspv_selector_load picks
+                                  the bucket count (or the pull direction)
+                                  per call from features the scan computes on
+                                  the device; one extra host synchronisation
+                                  per call or step.  bfs_run with
+                                  SPMSPV_USE_GRAPH on a handle with a row
+                                  form instead consumes the decision on the
+                                  device (direction only, inside the captured
+                                  level graph, no host synchronisation)       */
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any

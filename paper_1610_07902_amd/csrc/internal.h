@@ -241,7 +241,10 @@ constexpr int kMlpBatchMax = 128;
 hipError_t launch_mlp_forward(const float* p, const float* X, int B, float* logits, hipStream_t s);
 hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float lr, const float* X,
                                  const int32_t* labels, int B, float* grad_out, float* loss_out, hipStream_t s);
-hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, hipStream_t s);
+// set_dir: also write the level's direction (1 = pull when the class is pull
+// and the handle has a row form) for gated BFS kernels.
+hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
+                         hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
                            int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
 

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(TB) void k_mlp_train_step(float* p, float* am, floa
 //   mean column length nnz / n, vertices not yet reached.
 // The maximum column length is handed to maxlen_last here only when the
 // pull direction will run (the scatter does it on the push path).
-__global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull) {
+__global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir) {
     __shared__ float feat[MI], h1[MH1], h2[MH2], z[MO];
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -225,6 +225,9 @@ __global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, i
             if (z[k] > z[best]) best = k;
         for (int c = 0; c < MI; ++c) ctrl->features[c] = feat[c];
         const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (set_dir)
+            __hip_atomic_store(&ctrl->dir, (best == MO - 1 && has_pull && f > 0) ? 1 : 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         if (best == MO - 1 && has_pull && f > 0) {
             __hip_atomic_store(&ctrl->maxlen_last, atomicExch(&ctrl->maxlen, 0), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -253,8 +256,9 @@ hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float
     return hipGetLastError();
 }
 
-hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, ctrl, sel, n, nnz, has_pull);
+hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, ctrl, sel, n, nnz, has_pull, set_dir);
     return hipGetLastError();
 }
 

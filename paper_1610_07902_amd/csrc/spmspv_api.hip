@@ -269,7 +269,7 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
 int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev, const int32_t* x_idx,
             const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
             const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
-            int phases = 3, int clear_nb = 0) {
+            int phases = 3, int clear_nb = 0, bool learned_gate = false) {
     spmspv_schedule sc = A->sched;
     if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
     const int nb = (int)((A->m + (int64_t(1) << sc.tile_log2) - 1) >> sc.tile_log2);
@@ -356,7 +356,10 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     if (phases & 1) {
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(launch_scan(sa, (int)g1, s));
-        if (diropt) HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
+        if (diropt && learned_gate)   // the selector picks the direction on the device
+            HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 1, s));
+        else if (diropt)
+            HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     }
     if (phases & 2) {
@@ -444,7 +447,7 @@ int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     int rc = enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
                      nullptr, false, -1, 1, clear_nb);
     if (rc) return rc;
-    HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, s));
+    HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 0, s));
     Ctrl h{};
     rc = read_ctrl(A, &h, s);
     if (rc) return rc;
@@ -904,8 +907,12 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     if (root < 0 || root >= A->n) return fail(SPMSPV_EINVAL, "root out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
-    const bool diropt = (flags & SPMSPV_DIRECTION_OPT) != 0;
     const bool selector = (flags & SPMSPV_USE_SELECTOR) != 0;
+    // With a captured level graph and a row form, the selector's decision is
+    // consumed on the device: it sets the level's direction and the gated
+    // push / pull kernels follow it (the push tile stays the handle's).
+    const bool learned_gate = selector && (flags & SPMSPV_USE_GRAPH) && A->pull;
+    const bool diropt = (flags & SPMSPV_DIRECTION_OPT) != 0 || learned_gate;
     if (selector && !A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
     if (diropt && !A->pull)
         return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DIRECTION_OPT needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
@@ -916,7 +923,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
             int32_t* x = A->front[l & 1];
             int32_t* y = A->front[(l + 1) & 1];
             int rc = enqueue(A, semiring, xmode, 0, &A->ctrl->f, x, nullptr, y, nullptr, A->m, nullptr, true,
-                             A->visited, st, nullptr, diropt);
+                             A->visited, st, nullptr, diropt, -1, 3, 0, learned_gate);
             if (rc) return rc;
             if (diropt) {
                 // pull kernels for the same level; they run only when k_decide chose pull
@@ -928,7 +935,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         return SPMSPV_OK;
     };
 
-    if (selector) {
+    if (selector && !learned_gate) {
         // One host read per level: scan, device-side inference, chosen path.
         HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz, 0, s));
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
@@ -956,7 +963,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         return SPMSPV_OK;
     }
     const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
-    const int key = semiring + 1 + (diropt ? 8 : 0);
+    const int key = semiring + 1 + (diropt ? 8 : 0) + (learned_gate ? 16 : 0);
     if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
         if (A->graph) {
             (void)hipGraphExecDestroy(A->graph);
@@ -984,6 +991,10 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     }
     HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz,
                             diropt ? 1 : 0, s));
+    if (learned_gate) {
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->seen), 0u, 2, s));
+    }
     // Level loop: kGraphLevels levels per batch, then one host check of the
     // frontier length.  Levels after the frontier empties are no-ops.
     int32_t hf = 1;

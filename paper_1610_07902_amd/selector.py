@@ -184,13 +184,24 @@ def init_params(rng) -> np.ndarray:
     return p
 
 
+def labels(T: np.ndarray, tie: float = 0.03) -> np.ndarray:
+    """Fastest class per sample; classes within `tie` of the fastest count as
+    tied and the tie goes to the class that is fastest most often overall, so
+    near-equal timings give consistent labels."""
+    best = T.min(1, keepdims=True)
+    prior = np.bincount(T.argmin(1), minlength=OUT).astype(np.float64)
+    ok = T <= best * (1 + tie)
+    score = np.where(ok, prior[None, :] + 1e-9 * (OUT - np.arange(OUT))[None, :], -1.0)
+    return score.argmax(1).astype(np.int32)
+
+
 def train(samples: Samples, epochs: int = 300, lr: float = 1e-3, batch: int = 128, seed: int = 0):
     """Adam on softmax cross-entropy towards the fastest class, on the GPU.
     Returns (params, mean, std, loss history)."""
     import torch
     X = encode(samples.X)
     T = samples.T
-    y = np.argmin(T, axis=1).astype(np.int32)
+    y = labels(T)
     mean = X.mean(0)
     std = X.std(0)
     std[std < 1e-3] = 1.0

@@ -286,3 +286,24 @@ def test_device_features_match_host(spv, rmat14):
     dev_feat = np.array(spv.spmspv_selector_features(M.handle))
     reached = int((to_np(lev) >= 0).sum())
     assert np.isclose(dev_feat[5] * std[5] + mean[5], np.log2(1 + A.n - reached), atol=1e-4)
+
+
+@pytest.mark.parametrize("cls", [4, 9, -1])
+@pytest.mark.parametrize("semiring", [1, 2])
+def test_selector_bfs_device_gated(spv, rmat14, cls, semiring):
+    """Selector inside the captured level graph: the decision stays on the
+    device (direction only); results equal the oracle's for every class."""
+    A = rmat14
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
+    if cls >= 0:
+        M.load_selector(*constant_selector(cls))
+    else:
+        rng = np.random.default_rng(5)
+        M.load_selector(init_params(rng, scale=3.0), np.full(6, 8.0, np.float32), np.full(6, 4.0, np.float32))
+    for root in synth.roots(A, 3, seed=9):
+        lev, par, nl = M.bfs(int(root), semiring=semiring, flags=spv.USE_SELECTOR | spv.USE_GRAPH)
+        olev, opar, onl = oracle.bfs(A, int(root))
+        assert nl == onl
+        assert np.array_equal(to_np(lev), olev)
+        if semiring == 1:
+            assert np.array_equal(to_np(par), opar)

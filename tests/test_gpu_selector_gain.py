@@ -46,10 +46,13 @@ def test_trained_selector_beats_default_schedule_on_held_out_graph(spv, capsys):
     train = selector.Samples()
     for name, A in (("rmat13", synth.rmat(13, 16, seed=201, symmetrize=True)),
                     ("rmat15", synth.rmat(15, 16, seed=202, symmetrize=True)),
-                    ("grid2d", synth.grid(128, 128, 1)),
-                    ("grid3d", synth.grid(24, 24, 24))):
+                    ("rmat17", synth.rmat(17, 16, seed=204, symmetrize=True)),
+                    ("grid2d-128", synth.grid(128, 128, 1)),
+                    ("grid2d-512", synth.grid(512, 512, 1)),
+                    ("grid3d-24", synth.grid(24, 24, 24)),
+                    ("grid3d-64", synth.grid(64, 64, 64))):
         train.extend(collect(spv, A, name, 3, 11))
-    params, mean, std, hist = selector.train(train, epochs=150, lr=2e-3)
+    params, mean, std, hist = selector.train(train, epochs=200, lr=2e-3)
     assert hist[-1] < hist[0]
     held = selector.Samples()
     held.extend(collect(spv, synth.rmat(16, 16, seed=203, symmetrize=True), "rmat16", 3, 12))
@@ -62,5 +65,10 @@ def test_trained_selector_beats_default_schedule_on_held_out_graph(spv, capsys):
     with capsys.disabled():
         print(f"\n[selector gain] held-out samples {len(pred)}: regret learned {learned:.3f}, "
               f"default class {default:.3f}, best single class in hindsight {single:.3f}")
+        print("[selector gain] best classes", np.bincount(T.argmin(1), minlength=10).tolist(),
+              "chosen", np.bincount(pred, minlength=10).tolist())
+        worst = np.argsort(-(T[np.arange(len(pred)), pred] - T.min(1)))[:5]
+        for k in worst:
+            print("  ", held.tags[k], "chose", pred[k], "best", T[k].argmin(), "us", np.round(T[k], 1).tolist())
     assert learned < default, (learned, default)
     assert learned < 1.5
