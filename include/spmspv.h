@@ -268,7 +268,7 @@ int pagerank_scratch_size(spmspv_handle A, size_t* h_bytes);
  * 1 / outdeg.  rank [n] (device float) receives the result.  Flags:
  * SPMSPV_USE_SELECTOR picks each multiply's schedule with the loaded
  * selector (one host synchronisation per step; without it the host checks
- * every 16 steps).  *h_iters = multiplies performed.  Synchronous.       */
+ * every 8 steps).  *h_iters = multiplies performed.  Synchronous.        */
 int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int flags, float* rank, void* scratch,
                  size_t scratch_bytes, int32_t* h_iters, void* stream);
 

@@ -213,8 +213,9 @@ hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int ite
 hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 2;
-constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kScanItems = 2;         // host-known f: one tile per workgroup
+constexpr int kScanItemsWide = 8;     // device-known f or batched: looping grid
+constexpr int kScanTile = kScanBlock * kScanItems;   // smallest tile (sizes look-back arrays)
 constexpr int kMergeItems = 8;
 constexpr int kHeavyRow = 2048;    // rows with this many stored entries may be collapsed per wave
 constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk

@@ -63,19 +63,33 @@ __global__ __launch_bounds__(256) void k_pull_prep(PullArgs a) {
     if (a.gate && ldc(&a.ctrl->dir) != 1) return;   // this BFS level runs push
     const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.bump_level && f > 0) stc(&a.ctrl->level, ldc(&a.ctrl->level) + 1);
-    for (int p = blockIdx.x * 256 + threadIdx.x; p < f; p += gridDim.x * 256) {
-        const int32_t j = a.x_idx[p];
-        if (j < 0 || j >= a.n) {
-            atomicOr(&a.ctrl->err, ERR_X_RANGE);
-            continue;
+    // Bitmap words are ORed once per run of lanes sharing a word (a sorted
+    // frontier puts up to 32 consecutive lanes on one word, whose atomics
+    // would otherwise serialise on one address).
+    const int lane = threadIdx.x & 63;
+    for (int base = blockIdx.x * 256; base < f; base += gridDim.x * 256) {
+        const int p = base + threadIdx.x;
+        const int32_t j = p < f ? a.x_idx[p] : -1;
+        const bool inr = j >= 0 && j < a.n;
+        if (p < f && !inr) atomicOr(&a.ctrl->err, ERR_X_RANGE);
+        if (inr) {
+            uint32_t v;
+            if constexpr (XMODE == XV_BITS32) v = reinterpret_cast<const uint32_t*>(a.x_val)[p];
+            else if constexpr (XMODE == XV_INDEX) v = (uint32_t)j;
+            else if constexpr (XMODE == XV_U8) v = reinterpret_cast<const uint8_t*>(a.x_val)[p] ? 1u : 0u;
+            else v = 1u;
+            a.xdense[j] = v;
         }
-        uint32_t v;
-        if constexpr (XMODE == XV_BITS32) v = reinterpret_cast<const uint32_t*>(a.x_val)[p];
-        else if constexpr (XMODE == XV_INDEX) v = (uint32_t)j;
-        else if constexpr (XMODE == XV_U8) v = reinterpret_cast<const uint8_t*>(a.x_val)[p] ? 1u : 0u;
-        else v = 1u;
-        a.xdense[j] = v;
-        atomicOr(&a.xbits[j >> 5], 1u << (j & 31));
+        const uint32_t word = inr ? (uint32_t)j >> 5 : 0xffffffffu;
+        uint32_t bits = inr ? 1u << (j & 31) : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ow = (uint32_t)__shfl_down((int)word, d, 64);
+            const uint32_t ob = (uint32_t)__shfl_down((int)bits, d, 64);
+            if (lane + d < 64 && ow == word) bits |= ob;
+        }
+        const uint32_t prev = (uint32_t)__shfl_up((int)word, 1, 64);
+        if (inr && (lane == 0 || prev != word)) atomicOr(&a.xbits[word], bits);
     }
 }
 
@@ -291,6 +305,7 @@ __device__ uint64_t lookback_p(uint64_t* st, int tile, uint64_t agg, uint32_t* e
 template <int SR, bool BFS>
 __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
     __shared__ int s_tmp[kEmitBlock / 64 + 1];
+    __shared__ uint16_t s_list[kEmitWords * 32];
     __shared__ int64_t s_excl;
     const int tid = threadIdx.x;
     if (a.gate && ldc(&a.ctrl->dir) != 1) return;
@@ -350,33 +365,40 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
     const int lvl = BFS ? ldc(&a.ctrl->level) : 0;
     int32_t* const level = BFS ? ldc_ptr(&a.ctrl->bfs_level) : nullptr;
     int32_t* const parent = BFS ? ldc_ptr(&a.ctrl->bfs_parent) : nullptr;
-    int64_t o = excl + pos;
+    // Rows of this workgroup's words go to an LDS list in order, then every
+    // thread writes list entries t, t + block, ...: consecutive lanes write
+    // consecutive y slots (coalesced) and increasing rows.
+    int c = pos;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int w = w0 + tid * PER + k;
+        const int wl = tid * PER + k;
         uint32_t b = bits[k];
         if (b) {
-            a.ybits[w] = 0u;
-            if (BFS) a.visited[w] |= b;
+            a.ybits[w0 + wl] = 0u;
+            if (BFS) a.visited[w0 + wl] |= b;
         }
         while (b) {
             const int bit = __ffs(b) - 1;
             b &= b - 1u;
-            const int r = (w << 5) + bit;
-            const uint32_t v = a.ydense[r];
-            a.ydense[r] = ident<SR>();
-            if (o < a.y_cap) {
-                a.y_idx[o] = r;
-                if (a.y_val) {
-                    if (SR == SR_OR_AND) reinterpret_cast<uint8_t*>(a.y_val)[o] = (uint8_t)(v != 0u);
-                    else reinterpret_cast<uint32_t*>(a.y_val)[o] = v;
-                }
+            s_list[c++] = (uint16_t)((wl << 5) + bit);
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < tot; t += kEmitBlock) {
+        const int r = (w0 << 5) + s_list[t];
+        const uint32_t v = a.ydense[r];
+        a.ydense[r] = ident<SR>();
+        const int64_t o = excl + t;
+        if (o < a.y_cap) {
+            a.y_idx[o] = r;
+            if (a.y_val) {
+                if (SR == SR_OR_AND) reinterpret_cast<uint8_t*>(a.y_val)[o] = (uint8_t)(v != 0u);
+                else reinterpret_cast<uint32_t*>(a.y_val)[o] = v;
             }
-            if (BFS) {
-                level[r] = lvl;
-                if (parent) parent[r] = (int32_t)v;
-            }
-            ++o;
+        }
+        if (BFS) {
+            level[r] = lvl;
+            if (parent) parent[r] = (int32_t)v;
         }
     }
     // the look-back words of this call are cleared by the next k_pull_prep
@@ -436,7 +458,7 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
                        hipStream_t s) {
     if (rowwise && semiring == SR_PLUS_TIMES) return hipErrorInvalidValue;
     int64_t fg = (a.f_host + 255) / 256 + 1;
-    if (a.f_dev || fg > 1024) fg = 1024;
+    if (a.f_dev || fg > 512) fg = 512;
     const int f_grid = (int)fg;
     hipLaunchKernelGGL(k_lbp_clear, dim3(64), dim3(256), 0, s, a.lbp, a.emit_blocks);
     switch (xmode) {
@@ -447,7 +469,7 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
     }
     if (rowwise) {
         // bottom-up step: one thread per row, first-hit exit
-        const dim3 gb((a.m + 255) / 256 < 8192 ? (a.m + 255) / 256 : 8192), bb(256);
+        const dim3 gb((a.m + 255) / 256 < 2048 ? (a.m + 255) / 256 : 2048), bb(256);
         if (semiring == SR_MIN_SELECT2ND) {
             if (early) hipLaunchKernelGGL((k_pull_bfs<SR_MIN_SELECT2ND, true>), gb, bb, 0, s, a);
             else hipLaunchKernelGGL((k_pull_bfs<SR_MIN_SELECT2ND, false>), gb, bb, 0, s, a);

@@ -40,7 +40,7 @@ constexpr int kTileLog2Max = 15;
 constexpr int kChunkMin = 256;
 constexpr size_t kAlign = 256;
 constexpr int kProfileSlots = 1024;
-constexpr int kGraphLevels = 16;
+constexpr int kGraphLevels = 8;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

@@ -848,24 +848,20 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                                (int)bytes);
 }
 
-template <bool BATCH>
+template <int ITEMS, bool BATCH>
 static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s) {
     switch (a.xmode) {
         case XV_BITS32:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_BITS32, BATCH>), dim3(grid), dim3(kScanBlock), 0,
-                               s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_BITS32, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
             break;
         case XV_INDEX:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_INDEX, BATCH>), dim3(grid), dim3(kScanBlock), 0,
-                               s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_INDEX, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
             break;
         case XV_U8:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_U8, BATCH>), dim3(grid), dim3(kScanBlock), 0, s,
-                               a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_U8, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
             break;
         case XV_TRUE:
-            hipLaunchKernelGGL((k_scan<kScanBlock, kScanItems, XV_TRUE, BATCH>), dim3(grid), dim3(kScanBlock), 0,
-                               s, a);
+            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_TRUE, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
             break;
         default:
             return hipErrorInvalidValue;
@@ -873,12 +869,16 @@ static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Frontier lengths known only on the device (BFS, PageRank) and batched
+// calls use a fixed grid that loops over tiles; their tiles are 4x wider so
+// a large frontier needs fewer look-back rounds per workgroup.
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
     if (a.xoff) {
         if (a.nbatch < 1 || a.nbatch > kMaxBatch || !a.cxid || !a.kcount) return hipErrorInvalidValue;
-        return scan_mode<true>(a, grid, s);
+        return scan_mode<kScanItemsWide, true>(a, grid, s);
     }
-    return scan_mode<false>(a, grid, s);
+    if (a.f_dev) return scan_mode<kScanItemsWide, false>(a, grid, s);
+    return scan_mode<kScanItems, false>(a, grid, s);
 }
 
 template <int BLOCK, int ITEMS, int SR, int MODE>
