@@ -345,6 +345,13 @@ int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_
  * SPMSPV_USE_SELECTOR: writes min(cap, count) entries, *h_count = count.  */
 int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count);
 
+/* Replay a class sequence: while set (count > 0), bfs_run with
+ * SPMSPV_USE_SELECTOR runs step k with class h_classes[k] (0..9) instead of
+ * the network's choice, in the same host-driven loop (steps past the end
+ * use the network).  count = 0 clears it.  Used to time a schedule found in
+ * hindsight under exactly the loop the selector runs in.                 */
+int spmspv_force_classes(spmspv_handle A, const int32_t* h_classes, int32_t count);
+
 /* Standardised features of the most recent selector decision (h_out[6],
  * in the order above; synchronous).                                      */
 int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream);

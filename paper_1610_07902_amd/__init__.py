@@ -46,7 +46,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
-    "spmspv_selector_features",
+    "spmspv_selector_features", "spmspv_force_classes",
 )
 
 
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_autotune_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ci, ctypes.POINTER(Schedule),
                                           ctypes.POINTER(ctypes.c_double), vp]
     lib.spmspv_selector_features.argtypes = [vp, ctypes.POINTER(ctypes.c_float), vp]
+    lib.spmspv_force_classes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.pagerank_scratch_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.pagerank_run.argtypes = [vp, ctypes.c_float, ctypes.c_float, ci, ci, vp, vp, sz,
                                  ctypes.POINTER(ctypes.c_int32), vp]
@@ -209,6 +210,11 @@ def spmspv_selector_features(handle, stream=None) -> list:
     out = (ctypes.c_float * 6)()
     _check(load_library().spmspv_selector_features(handle, out, _stream(stream)))
     return list(out)
+
+
+def spmspv_force_classes(handle, classes=()):
+    arr = (ctypes.c_int32 * max(len(classes), 1))(*[int(c) for c in classes])
+    _check(load_library().spmspv_force_classes(handle, arr, len(classes)))
 
 
 def spmspv_class_tile(handle, cls: int) -> int:

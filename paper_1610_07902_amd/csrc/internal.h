@@ -245,7 +245,7 @@ hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float
 // set_dir: also write the level's direction (1 = pull when the class is pull
 // and the handle has a row form) for gated BFS kernels.
 hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
-                         hipStream_t s);
+                         int forced, hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
                            int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
 

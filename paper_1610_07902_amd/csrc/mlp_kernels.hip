@@ -185,7 +185,9 @@ __global__ __launch_bounds__(TB) void k_mlp_train_step(float* p, float* am, floa
 //   mean column length nnz / n, vertices not yet reached.
 // The maximum column length is handed to maxlen_last here only when the
 // pull direction will run (the scatter does it on the push path).
-__global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir) {
+// forced >= 0 replaces the network's decision (a given class sequence).
+__global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
+                         int forced) {
     __shared__ float feat[MI], h1[MH1], h2[MH2], z[MO];
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -223,6 +225,7 @@ __global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, i
         int best = 0;
         for (int k = 1; k < MO; ++k)
             if (z[k] > z[best]) best = k;
+        if (forced >= 0 && forced < MO) best = forced;
         for (int c = 0; c < MI; ++c) ctrl->features[c] = feat[c];
         const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (set_dir)
@@ -257,8 +260,8 @@ hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float
 }
 
 hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, ctrl, sel, n, nnz, has_pull, set_dir);
+                         int forced, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, ctrl, sel, n, nnz, has_pull, set_dir, forced);
     return hipGetLastError();
 }
 

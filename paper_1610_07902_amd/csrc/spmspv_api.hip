@@ -221,6 +221,7 @@ struct spmspv_matrix {
     BatchCtx batch;                     // second workspace for batched calls
     spmspv_schedule batch_sched{};      // batched-call schedule (tile_log2 0 = derive)
     std::vector<spmspv_tune_entry> tuned;   // autotuned schedule per density band
+    std::vector<int32_t> forced_classes;    // per-step classes replacing the selector (replay)
 };
 
 namespace {
@@ -357,7 +358,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(launch_scan(sa, (int)g1, s));
         if (diropt && learned_gate)   // the selector picks the direction on the device
-            HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 1, s));
+            HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 1, -1, s));
         else if (diropt)
             HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
@@ -442,12 +443,13 @@ int class_tile(const spmspv_matrix* A, int c) {
 // push tile or the pull direction.  Returns the class in *cls.
 int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
                  const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
-                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, hipStream_t s, int* cls, int32_t* f_now) {
+                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, hipStream_t s, int* cls, int32_t* f_now,
+                 int forced = -1) {
     const int clear_nb = (int)((A->m + (int64_t(1) << kTileLog2Min) - 1) >> kTileLog2Min);
     int rc = enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
                      nullptr, false, -1, 1, clear_nb);
     if (rc) return rc;
-    HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 0, s));
+    HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 0, forced, s));
     Ctrl h{};
     rc = read_ctrl(A, &h, s);
     if (rc) return rc;
@@ -911,9 +913,10 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     // With a captured level graph and a row form, the selector's decision is
     // consumed on the device: it sets the level's direction and the gated
     // push / pull kernels follow it (the push tile stays the handle's).
-    const bool learned_gate = selector && (flags & SPMSPV_USE_GRAPH) && A->pull;
+    const bool learned_gate = selector && (flags & SPMSPV_USE_GRAPH) && A->pull && A->forced_classes.empty();
     const bool diropt = (flags & SPMSPV_DIRECTION_OPT) != 0 || learned_gate;
-    if (selector && !A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
+    if (selector && !A->selector_loaded && A->forced_classes.empty())
+        return fail(SPMSPV_EINVAL, "no selector weights loaded");
     if (diropt && !A->pull)
         return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DIRECTION_OPT needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
 
@@ -945,9 +948,10 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
             if (l > A->n + 1) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
             int cls = 0;
             int32_t fnow = 0;
+            const int forced = l < (int64_t)A->forced_classes.size() ? A->forced_classes[(size_t)l] : -1;
             const int rc = run_selected(A, semiring, xmode, 0, &A->ctrl->f, A->front[l & 1], nullptr,
                                         A->front[(l + 1) & 1], nullptr, A->m, nullptr, true, A->visited, s, &cls,
-                                        &fnow);
+                                        &fnow, forced);
             if (rc) return rc;
             if (fnow == 0) break;
             A->level_classes.push_back(cls);
@@ -1063,6 +1067,14 @@ int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_
     if (!A || !h_count) return fail(SPMSPV_EINVAL, "NULL argument");
     *h_count = (int32_t)A->level_classes.size();
     for (int32_t k = 0; k < cap && k < *h_count; ++k) h_out[k] = A->level_classes[(size_t)k];
+    return SPMSPV_OK;
+}
+
+int spmspv_force_classes(spmspv_handle A, const int32_t* h_classes, int32_t count) {
+    if (!A || count < 0 || (count > 0 && !h_classes)) return fail(SPMSPV_EINVAL, "bad argument");
+    for (int32_t k = 0; k < count; ++k)
+        if (h_classes[k] < 0 || h_classes[k] > 9) return fail(SPMSPV_EINVAL, "classes must be in [0, 9]");
+    A->forced_classes.assign(h_classes, h_classes + count);
     return SPMSPV_OK;
 }
 

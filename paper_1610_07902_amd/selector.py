@@ -205,6 +205,11 @@ def train(samples: Samples, epochs: int = 300, lr: float = 1e-3, batch: int = 12
     mean = X.mean(0)
     std = X.std(0)
     std[std < 1e-3] = 1.0
+    # Cost-sensitive: a sample is repeated in proportion to its best time (in
+    # 100 us units, 1..16 copies), so mistakes on expensive steps weigh more.
+    reps = np.clip(np.ceil(T.min(1) / 100.0), 1, 16).astype(int)
+    keep = np.repeat(np.arange(T.shape[0]), reps)
+    X, y = X[keep], y[keep]
     Z = ((X - mean) / std).astype(np.float32)
     rng = np.random.default_rng(seed)
     p = torch.as_tensor(init_params(rng)).cuda()

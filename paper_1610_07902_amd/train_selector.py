@@ -53,7 +53,8 @@ def collect(quick: bool = False, roots_per_graph: int = 4, reps: int = 3, log=pr
         t0 = time.time()
         # pattern handle (BFS and min-select2nd) and a valued one (plus-times)
         P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
-        roots = synth.roots(A, roots_per_graph, seed=7)
+        # low-diameter graphs give few levels per root: take more roots
+        roots = synth.roots(A, roots_per_graph * (3 if name.startswith("rmat") else 1), seed=7)
         s = selector.bfs_samples(P, A.nnz, roots, reps=reps, tag=name)
         s.extend(selector.random_samples(P, A.nnz, DENSITIES, spv.MIN_SELECT2ND_I32, reps=reps, seed=1,
                                          tag=name + "/min"))

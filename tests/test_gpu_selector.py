@@ -307,3 +307,22 @@ def test_selector_bfs_device_gated(spv, rmat14, cls, semiring):
         assert np.array_equal(to_np(lev), olev)
         if semiring == 1:
             assert np.array_equal(to_np(par), opar)
+
+
+def test_forced_class_sequence_replay(spv, rmat14):
+    """A given class sequence replaces the network step by step; results stay
+    the oracle's and the recorded classes are the forced ones."""
+    A = rmat14
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
+    root = int(np.argmax(A.degrees()))
+    olev, opar, onl = oracle.bfs(A, root)
+    seq = [9, 3, 9, 0, 8, 9, 2, 9, 5, 1][:onl]
+    spv.spmspv_force_classes(M.handle, seq)
+    lev, par, nl = M.bfs(root, semiring=1, flags=spv.USE_SELECTOR)   # no weights needed while forced
+    assert nl == onl and np.array_equal(to_np(lev), olev) and np.array_equal(to_np(par), opar)
+    assert M.selector_classes() == seq
+    spv.spmspv_force_classes(M.handle, [])
+    with pytest.raises(spv.SpmspvError):
+        M.bfs(root, semiring=1, flags=spv.USE_SELECTOR)                # no weights, nothing forced
+    with pytest.raises(spv.SpmspvError):
+        spv.spmspv_force_classes(M.handle, [10])
