@@ -218,7 +218,12 @@ constexpr int kScanItemsWide = 8;     // device-known f or batched: looping grid
 constexpr int kScanTile = kScanBlock * kScanItems;   // smallest tile (sizes look-back arrays)
 constexpr int kMergeItems = 8;
 constexpr int kHeavyRow = 2048;    // rows with this many stored entries may be collapsed per wave
-constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk
+constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk (largest tiles)
+constexpr int kTileLog2Cap = 15;   // widest merge tile (2^15 rows) the LDS holds
+// Rows the merge's LDS list holds: the whole tile up to 2^14 rows.
+__host__ __device__ inline int merge_list_cap(int tile_log2) {
+    return tile_log2 <= 14 ? (1 << tile_log2) : kMergeList;
+}
 
 // Set-up kernels (spmspv_create, bfs_run).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);

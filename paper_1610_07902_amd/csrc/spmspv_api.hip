@@ -263,6 +263,18 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
 }
 
 
+// Bucketing workgroups one compute unit holds at once (LDS and 2048
+// threads per CU): the scatter grid is at most this many per CU, so every
+// workgroup of the grid is resident and short chunks overlap their memory
+// round trips across workgroups.
+int64_t scatter_occupancy(const spmspv_matrix* A, int nb, int block, int chunk, bool batch) {
+    const size_t lds = scatter_lds_bytes(nb, chunk, batch) + 1024;
+    int64_t by_lds = (int64_t)(A->lds_max / (lds ? lds : 1));
+    int64_t by_threads = 2048 / block;
+    int64_t occ = by_lds < by_threads ? by_lds : by_threads;
+    return occ < 1 ? 1 : occ;
+}
+
 // Enqueue the three phases of one y <- A x.
 // phases: 1 = scan only, 2 = scatter + merge only, 3 = all.  tile_log2 < 0
 // uses the handle's schedule.  clear_nb > 0 makes the scan clear that many
@@ -334,7 +346,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     if (wbound > A->nnz) wbound = A->nnz;
     int64_t g2 = (wbound + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
-    if (g2 > A->num_cu) g2 = A->num_cu;
+    const int64_t g2max = int64_t(A->num_cu) * scatter_occupancy(A, nb, sc.scatter_block, chunk, false);
+    if (g2 > g2max) g2 = g2max;
 
     MergeArgs ma{};
     ma.ctrl = A->ctrl;
@@ -565,7 +578,8 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     ca.mask_words = L.mask_words;
     int64_t g2 = (L.max_products + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
-    if (g2 > 2 * A->num_cu) g2 = 2 * A->num_cu;
+    const int64_t g2max = int64_t(A->num_cu) * scatter_occupancy(A, K, sc.scatter_block, chunk, true);
+    if (g2 > g2max) g2 = g2max;
 
     MergeArgs ma{};
     ma.ctrl = A->ctrl;

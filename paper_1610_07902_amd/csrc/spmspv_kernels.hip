@@ -549,11 +549,11 @@ __device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) 
 // 32-bit word sustains about 2.4 lanes per cycle on distinct addresses.
 // So plus-times adds through compare-and-swap, with untouched cells holding
 // kUntouched (a signalling NaN: products and sums of real values are never
-// signalling NaNs, so the cell itself records the first touch and no bitmap
-// atomic is needed).  Rows flagged heavy (hubs; many lanes of one wave may
-// hit the same one, where retries would pile up) start at +0.0 and take the
-// native float atomic plus a bitmap bit.  min and or use their native
-// integer atomics and the bitmap.
+// signalling NaNs, so the swap that replaces it is the row's first touch and
+// only that lane sets the row's bitmap bit).  Rows flagged heavy (hubs; many
+// lanes of one wave may hit the same one, where retries would pile up) start
+// at +0.0 and take the native float atomic plus a bitmap bit.  min and or
+// use their native integer atomics and the bitmap.
 constexpr uint32_t kUntouched = 0x7fa5a5a5u;
 
 // Applies K entries held by one thread.  For plus-times the K reads and
@@ -595,6 +595,10 @@ __device__ __forceinline__ void add_rows(const uint32_t (&r)[K], const uint32_t 
                 got[u] = atomicCAS(&spa[r[u]], old[u], nv);
             }
         }
+        // the lane whose swap replaced kUntouched made the first touch
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (light[u] && old[u] == kUntouched) atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
     } else {
 #pragma unroll
         for (int u = 0; u < K; ++u) {
@@ -629,7 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     uint32_t* spa = lds_merge;                                       // [T]
     uint32_t* bm = spa + T;                                          // [T/32]
     uint32_t* hb = bm + (T >> 5);                                    // [T/32] heavy rows
-    uint16_t* list = reinterpret_cast<uint16_t*>(hb + (T >> 5));     // [kMergeList]
+    uint16_t* list = reinterpret_cast<uint16_t*>(hb + (T >> 5));     // [merge_list_cap(tl)]
     __shared__ int64_t s_excl;
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
@@ -638,13 +642,24 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     // workgroups dispatched no later than its own (the wait is bounded).
     if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
     const int b = blockIdx.x;
-    const int W = ld_ctrl(&a.ctrl->W);
     int xb = 0, bt = b;   // vector and bucket within it
     if constexpr (BATCH) {
         xb = b / a.nbx;
         bt = b - xb * a.nbx;
     }
     const int row0 = bt << tl;
+    // heavy-row words of this tile, fetched before the control reads
+    constexpr int kHw = (1 << kTileLog2Cap) / 32 / BLOCK;
+    uint32_t hw[kHw];
+    {
+        const int nwt = (min(T, a.m - row0) + 31) >> 5;
+#pragma unroll
+        for (int k = 0; k < kHw; ++k) {
+            const int w = tid + k * BLOCK;
+            hw[k] = w < nwt ? a.heavy[(row0 >> 5) + w] : 0u;
+        }
+    }
+    const int W = ld_ctrl(&a.ctrl->W);
     const int cnt_raw = ld_ctrl(&a.cursor[b]);
     int base, cap;
     if constexpr (BATCH) {
@@ -687,9 +702,13 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
             vv[i] = ent.y;
         }
     }
-    for (int w = tid; w < nw; w += BLOCK) {
-        bm[w] = 0u;
-        hb[w] = a.heavy[(row0 >> 5) + w];
+#pragma unroll
+    for (int k = 0; k < kHw; ++k) {
+        const int w = tid + k * BLOCK;
+        if (w < nw) {
+            bm[w] = 0u;
+            hb[w] = hw[k];
+        }
     }
     if constexpr (SR == SR_PLUS_TIMES) __syncthreads();   // the cell init below reads hb
     {
@@ -750,18 +769,6 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     }
     if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
     __syncthreads();
-    if constexpr (SR == SR_PLUS_TIMES) {   // touched light rows are the cells that left kUntouched
-        // one wave-wide vote per 64 consecutive cells (conflict-free reads)
-        const int lane = tid & (kWave - 1);
-        for (int c0 = (tid - lane); c0 < nw * 32; c0 += BLOCK) {
-            const uint64_t v = __ballot(spa[c0 + lane] != kUntouched);
-            if (lane < 2) {
-                const int w = (c0 >> 5) + lane;
-                if (w < nw) bm[w] |= (uint32_t)(v >> (32 * lane)) & ~hb[w];
-            }
-        }
-        __syncthreads();
-    }
     int pc = 0;
     for (int w = tid; w < nw; w += BLOCK) pc += __popc(bm[w]);
     int ucnt;
@@ -792,12 +799,13 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         visited += (int64_t)xb * a.mask_words;
     }
 
-    // In-order walk of the bitmap, kMergeList / 32 words per round.
-    constexpr int kRoundWords = kMergeList / 32;
+    // In-order walk of the bitmap: one word per thread per round, as many
+    // words as the LDS list holds (the whole tile up to 16K rows).
+    const int round_words = min(BLOCK, merge_list_cap(tl) >> 5);
     int64_t carry = 0;
-    for (int w0 = 0; w0 < nw; w0 += kRoundWords) {
+    for (int w0 = 0; w0 < nw; w0 += round_words) {
         const int w = w0 + tid;
-        const bool mine = tid < kRoundWords && w < nw;
+        const bool mine = tid < round_words && w < nw;
         const uint32_t bits = mine ? bm[w] : 0u;
         int tot;
         const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
@@ -833,7 +841,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
 
 size_t merge_lds_bytes(int tile_log2) {
     const size_t T = size_t(1) << tile_log2;
-    return T * 4 + (T / 32) * 8 + size_t(kMergeList) * 2;
+    return T * 4 + (T / 32) * 8 + size_t(merge_list_cap(tile_log2)) * 2;
 }
 
 size_t scatter_lds_bytes(int nb, int chunk, bool batch) {
