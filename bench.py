@@ -415,6 +415,13 @@ def batch_bench(spv, dev, msbfs=True, reps=5):
 
     out = {"workload": "64 x, f_i log-uniform in [1, n/4], plus-times fp32, R-MAT scale 20 ef16 symmetrised",
            "n": A.n, "nnz": A.nnz, "sum_f": int(off[-1]), "products": Wt}
+    med, mn = timed(batched, False)
+    out["batched_untuned"] = {"ms": round(med * 1e3, 3), "GTEPS": round(Wt / med / 1e9, 3),
+                              "schedule": spv.spmspv_get_batch_schedule(M.handle, 64).as_dict()}
+    # the autotuner picks the batch's bucket count, workgroup shape and merge block on this batch
+    tuned, tuned_us = spv.spmspv_autotune_batch(M.handle, 0, 0, 64, off_d, cat_i, cat_v, by_off, by_idx, by_val, cap,
+                                                reps=3, stream=stream)
+    log(f"batched workload: untuned {out['batched_untuned']}; tuned {tuned.as_dict()} {tuned_us:.1f} us")
     for name, fn, arg in (("plain_sync", plain, True), ("plain_nosync", plain, False),
                           ("batched", batched, False), ("batched_sync", batched, True)):
         med, mn = timed(fn, arg)
