@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched workload (R-MAT scale 20)")
     ap.add_argument("--no-msbfs", action="store_true", help="skip the 64-source BFS of the batched workload")
     ap.add_argument("--selector-only", action="store_true", help="only the learned-selector evaluation")
+    ap.add_argument("--grid-only", action="store_true", help="only the 3-D grid BFS (256^3)")
     ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
     ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
     args = ap.parse_args()
@@ -90,6 +91,9 @@ def main():
         return
     if args.selector_only:
         print(json.dumps(selector_eval(spv, dev, args.selector_scale)))
+        return
+    if args.grid_only:
+        print(json.dumps(grid_bfs_bench(spv, dev)))
         return
 
     t0 = time.time()
@@ -205,6 +209,8 @@ def main():
         del M, xi_d, xv_d
         torch.cuda.empty_cache()
         result["batched"] = batch_bench(spv, dev, msbfs=not args.no_msbfs)
+        torch.cuda.empty_cache()
+        result["grid_bfs"] = grid_bfs_bench(spv, dev)
         torch.cuda.empty_cache()
         if not args.no_selector_eval:
             result["learned_selector"] = selector_eval(spv, dev, args.selector_scale)
@@ -456,6 +462,47 @@ def batch_bench(spv, dev, msbfs=True, reps=5):
         log(f"64-source BFS: {out['msbfs64']}")
         P.close()
     M.close()
+    return out
+
+
+def grid_bfs_bench(spv, dev, side=256):
+    """High-diameter BFS: 3-D 7-point grid side^3 with the diagonal, pattern,
+    or-and, from the corner vertex 0 (3*(side-1)+1 levels of small
+    frontiers): per-level launches versus the captured level graph, and the
+    direction-optimising and learned variants."""
+    import torch
+    import synth
+    t0 = time.time()
+    G = synth.grid(side, side, side)
+    P = spv.Matrix.from_csc(G, flags=spv.SYMMETRIC, pattern=True, device=dev)
+    nnz = G.nnz
+    del G
+    log(f"grid BFS: {side}^3 n={P.n} nnz={nnz} set-up {time.time() - t0:.1f}s")
+    out = {"graph": f"3-D 7-point grid {side}^3 with diagonal", "n": P.n, "nnz": nnz}
+    try:
+        from paper_1610_07902_amd import selector
+        params, mean, std, _ = selector.load_weights()
+        P.load_selector(params, mean, std)
+        variants = (("per_level_launch", 0), ("graph", spv.USE_GRAPH),
+                    ("persistent", spv.USE_GRAPH | spv.PERSISTENT),
+                    ("graph_direction_heuristic", spv.USE_GRAPH | spv.DIRECTION_OPT),
+                    ("graph_learned", spv.USE_GRAPH | spv.USE_SELECTOR))
+    except OSError:
+        variants = (("per_level_launch", 0), ("graph", spv.USE_GRAPH),
+                    ("persistent", spv.USE_GRAPH | spv.PERSISTENT),
+                    ("graph_direction_heuristic", spv.USE_GRAPH | spv.DIRECTION_OPT))
+    for name, fl in variants:
+        P.bfs(0, spv.OR_AND_BOOL, parents=False, flags=fl)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lev, _, nl = P.bfs(0, spv.OR_AND_BOOL, parents=False, flags=fl)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        out[name] = {"ms": round(ms, 2), "levels": nl, "us_per_level": round(ms * 1e3 / nl, 2),
+                     "GTEPS": round(nnz / (ms * 1e-3) / 1e9, 3)}
+        log(f"grid BFS {name}: {out[name]}")
+    out["note"] = "GTEPS = stored entries (every column is expanded once) / time"
+    P.close()
     return out
 
 

@@ -88,6 +88,14 @@ enum spmspv_flags {
                                   (Beamer's frontier-edge heuristic); needs a
                                   handle created with one of the two flags
                                   above                                       */
+    SPMSPV_PERSISTENT = 8192,  /* bfs_run (push, no direction switching) on a
+                                  graph whose longest column has at most 64
+                                  entries: levels with at most 65536 frontier
+                                  vertices run in one cooperative persistent
+                                  kernel (two grid barriers per level, direct
+                                  atomic discovery, same levels and minimum
+                                  parents); larger frontiers take the
+                                  bucketing levels.  Ignored otherwise        */
     SPMSPV_PULL_ROWWISE = 4096,/* spmspv_run with the pull direction, min-
                                   select2nd or or-and: one thread per row
                                   not masked, stopping at the first x hit (the

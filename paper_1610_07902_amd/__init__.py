@@ -32,6 +32,7 @@ USE_SELECTOR = 512
 MSBFS = 1024
 AUTO_SCHEDULE = 2048
 PULL_ROWWISE = 4096
+PERSISTENT = 8192
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10

@@ -225,6 +225,23 @@ __host__ __device__ inline int merge_list_cap(int tile_log2) {
     return tile_log2 <= 14 ? (1 << tile_log2) : kMergeList;
 }
 
+// Persistent BFS levels for small frontiers on low-degree graphs.
+constexpr int kTinyFrontier = 65536;   // vertices per frontier handled by the persistent kernel
+constexpr int kPersistMaxDeg = 64;     // largest column length it accepts (lanes walk lists together)
+struct PersistArgs {
+    Ctrl* ctrl;
+    const int32_t* colptr;
+    const int32_t* rowids;
+    int32_t* front0;
+    int32_t* front1;
+    uint32_t* visited;
+    uint32_t* disc;          // [m/32] discovered-this-level bitmap, zero between levels
+    int32_t* pmin;           // [m] smallest frontier in-neighbour, INT32_MAX between levels
+    uint32_t* bar;           // [2] grid barrier: arrivals, generation
+};
+int persistent_grid(int num_cu);
+hipError_t launch_bfs_persistent(const PersistArgs& a, bool min_semiring, int grid, hipStream_t s);
+
 // Set-up kernels (spmspv_create, bfs_run).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl,

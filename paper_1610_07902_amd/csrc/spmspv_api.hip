@@ -53,7 +53,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
-        heavy, total;
+        heavy, disc, pmin, bar, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values, selector;
     bool pull, transpose;
@@ -86,6 +86,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
     L.heavy = take(size_t((m + 31) / 32) * 4);
+    L.disc = take(size_t((m + 31) / 32) * 4);
+    L.pmin = take(size_t(m) * 4);
+    L.bar = take(16);
     L.selector = take(size_t(kMlpParams + 2 * kMlpIn) * 4);
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
@@ -188,6 +191,10 @@ struct spmspv_matrix {
     uint2* buckets = nullptr;
     uint32_t* visited = nullptr;
     uint32_t* heavy = nullptr;
+    uint32_t* disc = nullptr;           // persistent BFS: discovered bitmap
+    int32_t* pmin = nullptr;            // persistent BFS: smallest frontier in-neighbour
+    uint32_t* bar = nullptr;            // persistent BFS: grid barrier words
+    int persist_grid = -1;              // co-resident workgroups of the persistent kernel (0 = unavailable)
     int32_t* front[2] = {nullptr, nullptr};
     int32_t maxdeg = 0;
     int device = 0;
@@ -741,6 +748,9 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
     A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
     A->heavy = reinterpret_cast<uint32_t*>(A->ws + L.heavy);
+    A->disc = reinterpret_cast<uint32_t*>(A->ws + L.disc);
+    A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
+    A->bar = reinterpret_cast<uint32_t*>(A->ws + L.bar);
     A->selector = reinterpret_cast<float*>(A->ws + L.selector);
 
     auto bail = [&](int status) {
@@ -768,6 +778,10 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         return bail(hip_fail(e, "row count scan"));
     if ((e = launch_heavy_rows(A->rcp, (int32_t)m, kHeavyRow, A->heavy, s)) != hipSuccess)
         return bail(hip_fail(e, "heavy rows"));
+    if ((e = launch_fill_u32(A->disc, 0u, (m + 31) / 32, s)) != hipSuccess ||
+        (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->pmin), 0x7fffffffu, m, s)) != hipSuccess ||
+        (e = launch_fill_u32(A->bar, 0u, 4, s)) != hipSuccess)
+        return bail(hip_fail(e, "persistent BFS state"));
     if (L.pull) {
         A->pull = true;
         A->p_xbits = reinterpret_cast<uint32_t*>(A->ws + L.p_xbits);
@@ -1009,6 +1023,24 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     }
     HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz,
                             diropt ? 1 : 0, s));
+    // Small frontiers of a low-degree graph run in the persistent kernel;
+    // larger ones in batches of the bucketing levels below.
+    bool persist = (flags & SPMSPV_PERSISTENT) && !diropt && A->maxdeg <= kPersistMaxDeg;
+    if (persist && A->persist_grid < 0) A->persist_grid = persistent_grid(A->num_cu);
+    persist = persist && A->persist_grid > 0;
+    PersistArgs pa{};
+    if (persist) {
+        pa.ctrl = A->ctrl;
+        pa.colptr = A->colptr;
+        pa.rowids = A->rowids;
+        pa.front0 = A->front[0];
+        pa.front1 = A->front[1];
+        pa.visited = A->visited;
+        pa.disc = A->disc;
+        pa.pmin = A->pmin;
+        pa.bar = A->bar;
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->gen_count), 0u, 1, s));
+    }
     if (learned_gate) {
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->seen), 0u, 2, s));
@@ -1018,6 +1050,13 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     int32_t hf = 1;
     for (int64_t batch = 0; hf > 0; ++batch) {
         if (batch * kGraphLevels > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+        if (persist) {
+            HIP_TRY(launch_fill_u32(A->bar, 0u, 1, s));   // arrival counter (a timed-out wait may leave it set)
+            HIP_TRY(launch_bfs_persistent(pa, semiring == SR_MIN_SELECT2ND, A->persist_grid, s));
+            HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hf == 0) break;
+        }
         if (use_graph) HIP_TRY(hipGraphLaunch(A->graph, s));
         else {
             const int rc = enqueue_levels(kGraphLevels, s);
