@@ -50,8 +50,9 @@ struct alignas(256) Ctrl {
     int32_t bfs_mode;       // the selector runs inside a BFS
     int32_t cls;            // class chosen by the selector for the current multiply
     float features[6];      // standardised selector features of the current multiply
-    int32_t gen_count;      // entries drawn by the tuning-input generator
-    uint32_t pad[29];
+    int32_t gen_count;      // entries drawn by the tuning-input generator / appended by a BFS step
+    int32_t gen_count2;     // second append counter (persistent BFS alternates the two per level)
+    uint32_t pad[28];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 

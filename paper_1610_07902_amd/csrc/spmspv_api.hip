@@ -1039,7 +1039,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         pa.disc = A->disc;
         pa.pmin = A->pmin;
         pa.bar = A->bar;
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->gen_count), 0u, 1, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->gen_count), 0u, 2, s));   // both counters
     }
     if (learned_gate) {
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
