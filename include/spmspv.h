@@ -299,9 +299,12 @@ int spmspv_batch_workspace_size(spmspv_handle A, int max_batch, int64_t max_f, i
                                 size_t* h_bytes);
 
 /* Bind a batch workspace of ws_bytes device bytes (owned by the caller,
- * borrowed until the handle is destroyed or another is attached). */
+ * borrowed until the handle is destroyed or another is attached).  The
+ * scan's look-back words inside it are cleared on `stream` (a hipStream_t,
+ * NULL = default stream); batched calls on other streams must be ordered
+ * after that clear by the caller. */
 int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
-                        void* workspace, size_t ws_bytes);
+                        void* workspace, size_t ws_bytes, void* stream);
 
 /* y_b <- A x_b for b < nbatch, one scan, two bucketing passes and one merge
  * launch for the whole batch.  Flags: SPMSPV_X_VAL_IS_INDEX, X_ALL_TRUE

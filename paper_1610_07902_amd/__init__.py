@@ -108,7 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_mlp_forward.argtypes = [vp, vp, ci, vp, vp]
     lib.spmspv_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp, vp, ci, vp, vp, vp]
     lib.spmspv_batch_workspace_size.argtypes = [vp, ci, i64, i64, ci, ctypes.POINTER(sz)]
-    lib.spmspv_batch_attach.argtypes = [vp, ci, i64, i64, ci, vp, sz]
+    lib.spmspv_batch_attach.argtypes = [vp, ci, i64, i64, ci, vp, sz, vp]
     lib.spmspv_run_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.spmspv_set_batch_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.spmspv_get_batch_schedule.argtypes = [vp, ci, ctypes.POINTER(Schedule)]
@@ -247,9 +247,9 @@ def spmspv_batch_workspace_size(handle, max_batch, max_f=0, max_products=0, flag
     return out.value
 
 
-def spmspv_batch_attach(handle, max_batch, max_f, max_products, flags, workspace, ws_bytes):
+def spmspv_batch_attach(handle, max_batch, max_f, max_products, flags, workspace, ws_bytes, stream=None):
     _check(load_library().spmspv_batch_attach(handle, int(max_batch), int(max_f), int(max_products), int(flags),
-                                              _ptr(workspace), int(ws_bytes)))
+                                              _ptr(workspace), int(ws_bytes), _stream(stream)))
 
 
 def spmspv_run_batch(handle, semiring, flags, nbatch, x_off, x_idx, x_val, y_off, y_idx, y_val, y_capacity,

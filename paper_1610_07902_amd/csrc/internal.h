@@ -114,6 +114,8 @@ struct ScatterArgs {
     const int32_t* kbase;    // [nb+1] bucket bases of the batched scatter
     int32_t nbx;             // buckets per vector
     int32_t mask_words;      // words per vector in a batched mask
+    int64_t xstride;         // > 0: fixed bases, key (x, b) owns slots x * xstride + [rcp[bT], rcp[(b+1)T])
+                             // (no counting pass; needs bucket storage of nbatch * nnz)
     uint2* buckets;          // [nnz] (row, value bits)
     const uint32_t* mask;    // nullable visited bitmap: drop rows whose bit is set
     uint64_t* lb1;           // scan look-back words to clear (two halves of lb1_n)
@@ -143,7 +145,8 @@ struct MergeArgs {
     int set_f;               // BFS: publish nnz(y) as the next frontier length
     int gate;                // 1: skip when ctrl->dir selects pull
     // Batched calls (key = vector * nbx + bucket)
-    const int32_t* kbase;    // [nb+1]
+    const int32_t* kbase;    // [nb+1] (counted bases), unused when xstride > 0
+    int64_t xstride;         // > 0: fixed bases as in ScatterArgs
     int32_t nbx;
     int32_t nbatch;
     int64_t* yoff;           // [nbatch+1] out: start of each vector's y

@@ -611,9 +611,21 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     ma.n_stride = A->n;
     ma.mask_words = L.mask_words;
 
+    // Multi-source BFS frontiers are sets (no repeated index inside one
+    // vector), so with storage for nnz entries per vector (the default size
+    // of its workspace) key (x, b) owns the fixed slice x * nnz + [rcp[bT],
+    // rcp[(b+1)T]) and the counting pass is not needed.
+    const bool fixed = bfs && L.max_products >= (int64_t)nbatch * A->nnz && A->nnz > 0;
+    if (fixed) {
+        ca.xstride = A->nnz;
+        ma.xstride = A->nnz;
+        ca.lb1_clear = (int32_t)L.lb1_n;   // the counting pass normally clears these
+    }
     HIP_TRY(launch_scan(sa, (int)g1, s));
-    HIP_TRY(launch_scatter_batch(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, true, s));
-    HIP_TRY(launch_exclusive_scan_i32(kcount, K + 1, i32(L.partials), s));
+    if (!fixed) {
+        HIP_TRY(launch_scatter_batch(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, true, s));
+        HIP_TRY(launch_exclusive_scan_i32(kcount, K + 1, i32(L.partials), s));
+    }
     HIP_TRY(launch_scatter_batch(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, false, s));
     HIP_TRY(launch_merge_batch(ma, semiring, sc.merge_block, bfs, s));
     return SPMSPV_OK;
@@ -1161,7 +1173,7 @@ int spmspv_batch_workspace_size(spmspv_handle A, int max_batch, int64_t max_f, i
 }
 
 int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
-                        void* workspace, size_t ws_bytes) {
+                        void* workspace, size_t ws_bytes, void* stream) {
     size_t need = 0;
     const int rc = spmspv_batch_workspace_size(A, max_batch, max_f, max_products, flags, &need);
     if (rc) return rc;
@@ -1173,6 +1185,15 @@ int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t m
     A->batch.max_batch = max_batch;
     A->batch.L = make_batch_layout(A->m, A->n, A->nnz, max_batch, max_f, max_products, bfs);
     A->batch.ws = static_cast<char*>(workspace);
+    // The first scan looks back over these words; later calls clear them in
+    // their first bucketing pass.  (The counters and merge look-back words
+    // are cleared by every scan.)
+    const hipError_t e = launch_clear_u64(reinterpret_cast<uint64_t*>(A->batch.ws + A->batch.L.lb1),
+                                          (int)A->batch.L.lb1_n * 2, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        A->batch.bound = false;
+        return hip_fail(e, "clear batch look-back words");
+    }
     return SPMSPV_OK;
 }
 

@@ -277,9 +277,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         __syncthreads();
         uint64_t off = s_excl_sum + tex_sum;
         uint64_t c = s_excl_cnt + tex_cnt;
+        // A consistent prefix keeps every column slot below f (the tables'
+        // size); an inconsistent look-back state must not store past them.
+        bool lost = false;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if (ln[i] > 0) {
+            if (ln[i] > 0 && c >= (uint64_t)f) lost = true;
+            if (ln[i] > 0 && c < (uint64_t)f) {
                 a.cstart[c] = st[i];
                 a.coff[c] = (int32_t)off;   // exact whenever the total is valid (<= nnz)
                 a.cxv[c] = xv[i];
@@ -296,12 +300,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
                 for (int64_t k = ((int64_t)off + chunk - 1) >> a.chunk_log2;
                      (k << a.chunk_log2) < (int64_t)off + ln[i] && k < a.chunk_n; ++k)
                     a.chunk_col[k] = (int32_t)c;
+            }
+            if (ln[i] > 0) {
                 off += (uint64_t)ln[i];
                 c += 1;
             }
         }
+        if (lost) atomicOr(&a.ctrl->err, ERR_SPIN);
         if (tile == ntiles - 1 && tid == BLOCK - 1) {
-            if (off > (uint64_t)a.nnz) {
+            if (off > (uint64_t)a.nnz || c > (uint64_t)f) {
                 // Single vector: more products than stored entries means x
                 // has duplicate indices.  Batched: more products than the
                 // bucket storage holds.
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
 
-    if (MODE != SC_BATCH) {   // the first pass over the products of this call
+    if (MODE != SC_BATCH || a.xstride) {   // the first pass over the products of this call
         if (blockIdx.x == 0 && tid == 0) {
             st_ctrl_u(&a.ctrl->ticket_scan, 0u);
             st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
@@ -385,6 +392,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     }
 
     if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
+    // A failed look-back leaves the column tables inconsistent: scatter
+    // nothing (the error is reported with the call's status).
+    if (ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err)) & (int32_t)ERR_SPIN) return;
     const int W = ld_ctrl(&a.ctrl->W);
     const int fnz = ld_ctrl(&a.ctrl->fnz);
     const int nchunks = (int)(((int64_t)W + C - 1) / C);
@@ -477,9 +487,13 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
                 loff[b] = carry + e;
                 if (n > 0) {
                     int base, cap;
-                    if constexpr (MODE == SC_BATCH) {
+                    if (MODE == SC_BATCH && a.xstride == 0) {
                         base = a.kbase[b];
                         cap = a.kbase[b + 1] - base;
+                    } else if (MODE == SC_BATCH) {   // fixed bases: row-count prefix inside the vector's slice
+                        const int r0 = (b - (b / a.nbx) * a.nbx) << tl;
+                        base = a.rcp[r0];
+                        cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
                     } else {
                         const int r0 = b << tl;
                         base = a.rcp[r0];
@@ -511,7 +525,8 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             const uint2 e = stage[t];
             const int b = MODE == SC_BATCH ? skey[t] : (int)e.x >> tl;
             const int gb = hist[b];
-            if (gb >= 0) a.buckets[gb + (t - loff[b])] = e;
+            const int64_t slice = (MODE == SC_BATCH && a.xstride) ? (int64_t)(b / a.nbx) * a.xstride : 0;
+            if (gb >= 0) a.buckets[slice + gb + (t - loff[b])] = e;
         }
         __syncthreads();
 #pragma unroll
@@ -661,13 +676,14 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     }
     const int W = ld_ctrl(&a.ctrl->W);
     const int cnt_raw = ld_ctrl(&a.cursor[b]);
-    int base, cap;
-    if constexpr (BATCH) {
+    int64_t base;
+    int cap;
+    if (BATCH && a.xstride == 0) {
         base = a.kbase[b];
-        cap = a.kbase[b + 1] - base;
+        cap = a.kbase[b + 1] - a.kbase[b];
     } else {
-        base = a.rcp[row0];
-        cap = a.rcp[min(row0 + T, a.m)] - base;
+        base = (BATCH ? (int64_t)xb * a.xstride : 0) + a.rcp[row0];
+        cap = a.rcp[min(row0 + T, a.m)] - a.rcp[row0];
     }
     __syncthreads();
     if (W == 0) {
@@ -936,7 +952,8 @@ hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int ite
 
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
                                 hipStream_t s) {
-    if (!a.cxid || a.nbx < 1 || (count && !a.kcount) || (!count && !a.kbase)) return hipErrorInvalidValue;
+    if (!a.cxid || a.nbx < 1 || (count && !a.kcount) || (!count && !a.kbase && a.xstride == 0))
+        return hipErrorInvalidValue;
     return count ? scatter_shape<SC_COUNT>(a, semiring, block, items, grid, s)
                  : scatter_shape<SC_BATCH>(a, semiring, block, items, grid, s);
 }
@@ -979,7 +996,7 @@ hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, h
 }
 
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
-    if (!a.kbase || !a.yoff || a.nbx < 1 || a.nbatch < 1 || (int64_t)a.nbx * a.nbatch != a.nb)
+    if ((!a.kbase && a.xstride == 0) || !a.yoff || a.nbx < 1 || a.nbatch < 1 || (int64_t)a.nbx * a.nbatch != a.nb)
         return hipErrorInvalidValue;
     return merge_dispatch<true>(a, semiring, block, bfs, s);
 }

@@ -144,6 +144,32 @@ def test_batch_errors(spv, rmat14):
     assert e.value.status == spv.ECAPACITY
 
 
+def test_batch_attach_over_stale_memory(spv, rmat14):
+    """A batch workspace is used as handed over, whatever it held: every
+    word the first call depends on is initialised by the attach or the call
+    itself.  0x80 bytes make every 64-bit look-back word read as a complete
+    prefix with a huge value."""
+    A = rmat14
+    M = spv.Matrix.from_csc(A)
+    xs, off, idx, val = make_batch(A, [3000, 0, 5000, 200], 13)
+    nbytes = spv.spmspv_batch_workspace_size(M.handle, 8, int(off[-1]), A.nnz * 2, 0)
+    ws = torch.full((nbytes,), 0x80, dtype=torch.uint8, device="cuda")
+    spv.spmspv_batch_attach(M.handle, 8, int(off[-1]), A.nnz * 2, 0, ws, nbytes)
+    M.batch_ws = ws
+    check_batch(spv, M, A, xs, off, idx, val, 0)
+    check_batch(spv, M, A, xs, off, idx, val, 1)
+    P = spv.Matrix.from_csc(A, pattern=True)
+    nbytes = spv.spmspv_batch_workspace_size(P.handle, 4, 0, 0, spv.MSBFS)
+    ws = torch.full((nbytes,), 0x80, dtype=torch.uint8, device="cuda")
+    spv.spmspv_batch_attach(P.handle, 4, 0, 0, spv.MSBFS, ws, nbytes)
+    P.batch_ws = ws
+    roots = [int(r) for r in synth.roots(A, 4, seed=17)]
+    lev, _, _ = P.msbfs(roots, semiring=2, parents=False)
+    lev = to_np(lev)
+    for k, r in enumerate(roots):
+        assert np.array_equal(lev[k], oracle.bfs(A, r)[0]), f"source {k} root {r}"
+
+
 def test_batch_then_single_calls_agree(spv, rmat14):
     """Batched and single calls share the handle's control block."""
     A = rmat14
