@@ -10,8 +10,8 @@ All inputs are resident in HBM before timing starts.
 
 Printed: one JSON line with the headline metric (GTEPS = products / s, the
 products being the sum of the selected column lengths), the dominant
-kernel's achieved HBM bandwidth against the 8 TB/s peak (HIP events around
-each kernel on the launch stream), the CPU oracle's rate on a bounded sample
+kernel's achieved HBM bandwidth against the 8 TB/s peak (each kernel's own
+start and end timestamps in HIP events on the launch stream), the CPU oracle's rate on a bounded sample
 of the same workload, and side measurements (density sweep, min-select2nd,
 BFS from 16 roots).
 """

@@ -77,7 +77,8 @@ enum spmspv_flags {
                                   NULL                                         */
     SPMSPV_USE_GRAPH = 16,     /* bfs_run: replay the level loop as a captured
                                   hipGraph                                     */
-    SPMSPV_PROFILE = 32,       /* record HIP events around each kernel (see
+    SPMSPV_PROFILE = 32,       /* record each kernel's own start and end
+                                  timestamps in HIP events (see
                                   spmspv_profile_read)                        */
     SPMSPV_WITH_TRANSPOSE = 64,/* create: also build the CSR form of A so the
                                   pull direction is available                 */

@@ -212,9 +212,16 @@ hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t*
                              hipStream_t s);
 bool scatter_shape_supported(int block, int items);
 
-hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s);
-hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s);
-hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
+// Optional timing of one launch: the events take the kernel's own start and
+// end timestamps (no marker packets around it).
+struct LaunchEvents {
+    hipEvent_t start, stop;
+};
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s, const LaunchEvents* ev = nullptr);
+hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s,
+                          const LaunchEvents* ev = nullptr);
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s,
+                        const LaunchEvents* ev = nullptr);
 
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 2;         // host-known f: one tile per workgroup

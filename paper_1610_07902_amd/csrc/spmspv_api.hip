@@ -374,20 +374,21 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ma.set_f = bfs ? 1 : 0;
     ma.gate = diropt ? 1 : 0;
 
+    // With profiling, each kernel's own start and end timestamps go to a pair
+    // of events (scan, scatter, merge).
+    const LaunchEvents le[3] = {{ev ? ev[0] : nullptr, ev ? ev[1] : nullptr},
+                                {ev ? ev[2] : nullptr, ev ? ev[3] : nullptr},
+                                {ev ? ev[4] : nullptr, ev ? ev[5] : nullptr}};
     if (phases & 1) {
-        if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(launch_scan(sa, (int)g1, s));
+        HIP_TRY(launch_scan(sa, (int)g1, s, ev ? &le[0] : nullptr));
         if (diropt && learned_gate)   // the selector picks the direction on the device
             HIP_TRY(launch_select(A->ctrl, A->selector, (int32_t)A->n, A->nnz, A->pull ? 1 : 0, 1, -1, s));
         else if (diropt)
             HIP_TRY(launch_decide(A->ctrl, (int32_t)A->n, A->nnz, s));
-        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     }
     if (phases & 2) {
-        HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s));
-        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s));
-        if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+        HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s, ev ? &le[1] : nullptr));
+        HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s, ev ? &le[2] : nullptr));
     }
     return SPMSPV_OK;
 }
@@ -434,10 +435,8 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     const bool early = semiring == SR_OR_AND || (semiring == SR_MIN_SELECT2ND && xmode == XV_INDEX && A->rows_sorted);
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_pull(pa, semiring, xmode, bfs, early, bfs || rowwise, s));
-    if (ev) {
-        HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(hipEventRecord(ev[3], s));
+    if (ev) {   // the pull launches count as the first phase
+        for (int k = 1; k < 6; ++k) HIP_TRY(hipEventRecord(ev[k], s));
     }
     return SPMSPV_OK;
 }
@@ -673,12 +672,12 @@ int time_schedule(spmspv_matrix* A, const spmspv_schedule& sc, int semiring, int
 
 hipEvent_t* profile_slot(spmspv_matrix* A) {
     if (A->prof_ev.empty()) {
-        A->prof_ev.resize(size_t(kProfileSlots) * 4);
+        A->prof_ev.resize(size_t(kProfileSlots) * 6);
         for (auto& e : A->prof_ev)
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
     }
     if (A->prof_used >= kProfileSlots) return nullptr;
-    return &A->prof_ev[size_t(A->prof_used++) * 4];
+    return &A->prof_ev[size_t(A->prof_used++) * 6];
 }
 
 int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s) {
@@ -1603,11 +1602,11 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls) {
     if (!A || !h_ms || !h_calls) return fail(SPMSPV_EINVAL, "NULL argument");
     h_ms[0] = h_ms[1] = h_ms[2] = 0.0;
     for (int c = 0; c < A->prof_used; ++c) {
-        hipEvent_t* ev = &A->prof_ev[size_t(c) * 4];
-        HIP_TRY(hipEventSynchronize(ev[3]));
+        hipEvent_t* ev = &A->prof_ev[size_t(c) * 6];
+        HIP_TRY(hipEventSynchronize(ev[5]));
         for (int k = 0; k < 3; ++k) {
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
             h_ms[k] += ms;
         }
     }

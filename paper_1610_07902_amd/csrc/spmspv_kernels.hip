@@ -32,6 +32,8 @@
 // never receives more entries than its rows hold: total bucket space is
 // nnz(A), the bound of "Performance optimizations / Memory allocation".
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace spv {
@@ -872,20 +874,27 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                                (int)bytes);
 }
 
+template <typename K, typename... Args>
+static void launch_k(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LaunchEvents* ev,
+                     Args... args) {
+    if (ev) hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, s, ev->start, ev->stop, 0, args...);
+    else hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+}
+
 template <int ITEMS, bool BATCH>
-static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s) {
+static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s, const LaunchEvents* ev) {
     switch (a.xmode) {
         case XV_BITS32:
-            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_BITS32, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_BITS32, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_INDEX:
-            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_INDEX, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_INDEX, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_U8:
-            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_U8, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_U8, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_TRUE:
-            hipLaunchKernelGGL((k_scan<kScanBlock, ITEMS, XV_TRUE, BATCH>), dim3(grid), dim3(kScanBlock), 0, s, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_TRUE, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         default:
             return hipErrorInvalidValue;
@@ -896,32 +905,32 @@ static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s) {
 // Frontier lengths known only on the device (BFS, PageRank) and batched
 // calls use a fixed grid that loops over tiles; their tiles are 4x wider so
 // a large frontier needs fewer look-back rounds per workgroup.
-hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s) {
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s, const LaunchEvents* ev) {
     if (a.xoff) {
         if (a.nbatch < 1 || a.nbatch > kMaxBatch || !a.cxid || !a.kcount) return hipErrorInvalidValue;
-        return scan_mode<kScanItemsWide, true>(a, grid, s);
+        return scan_mode<kScanItemsWide, true>(a, grid, s, ev);
     }
-    if (a.f_dev) return scan_mode<kScanItemsWide, false>(a, grid, s);
-    return scan_mode<kScanItems, false>(a, grid, s);
+    if (a.f_dev) return scan_mode<kScanItemsWide, false>(a, grid, s, ev);
+    return scan_mode<kScanItems, false>(a, grid, s, ev);
 }
 
 template <int BLOCK, int ITEMS, int SR, int MODE>
-static hipError_t scatter_one(const ScatterArgs& a, int grid, hipStream_t s) {
+static hipError_t scatter_one(const ScatterArgs& a, int grid, hipStream_t s, const LaunchEvents* ev) {
     const size_t lds = scatter_lds_bytes(a.nb, BLOCK * ITEMS, MODE != SC_SINGLE);
     auto kern = k_scatter<BLOCK, ITEMS, SR, MODE>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    launch_k(kern, dim3(grid), dim3(BLOCK), lds, s, ev, a);
     return hipGetLastError();
 }
 
 template <int BLOCK, int ITEMS, int MODE>
-static hipError_t scatter_sr(const ScatterArgs& a, int semiring, int grid, hipStream_t s) {
-    if constexpr (MODE == SC_COUNT) return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s);
+static hipError_t scatter_sr(const ScatterArgs& a, int semiring, int grid, hipStream_t s, const LaunchEvents* ev) {
+    if constexpr (MODE == SC_COUNT) return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s, ev);
     switch (semiring) {
-        case SR_PLUS_TIMES: return scatter_one<BLOCK, ITEMS, SR_PLUS_TIMES, MODE>(a, grid, s);
-        case SR_MIN_SELECT2ND: return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s);
-        default: return scatter_one<BLOCK, ITEMS, SR_OR_AND, MODE>(a, grid, s);
+        case SR_PLUS_TIMES: return scatter_one<BLOCK, ITEMS, SR_PLUS_TIMES, MODE>(a, grid, s, ev);
+        case SR_MIN_SELECT2ND: return scatter_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(a, grid, s, ev);
+        default: return scatter_one<BLOCK, ITEMS, SR_OR_AND, MODE>(a, grid, s, ev);
     }
 }
 
@@ -931,23 +940,25 @@ bool scatter_shape_supported(int block, int items) {
 }
 
 template <int MODE>
-static hipError_t scatter_shape(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
+static hipError_t scatter_shape(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s,
+                                const LaunchEvents* ev = nullptr) {
     if (block == 256) {
-        if (items == 4) return scatter_sr<256, 4, MODE>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<256, 8, MODE>(a, semiring, grid, s);
-        if (items == 16) return scatter_sr<256, 16, MODE>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<256, 4, MODE>(a, semiring, grid, s, ev);
+        if (items == 8) return scatter_sr<256, 8, MODE>(a, semiring, grid, s, ev);
+        if (items == 16) return scatter_sr<256, 16, MODE>(a, semiring, grid, s, ev);
     } else if (block == 512) {
-        if (items == 4) return scatter_sr<512, 4, MODE>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<512, 8, MODE>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<512, 4, MODE>(a, semiring, grid, s, ev);
+        if (items == 8) return scatter_sr<512, 8, MODE>(a, semiring, grid, s, ev);
     } else if (block == 1024) {
-        if (items == 4) return scatter_sr<1024, 4, MODE>(a, semiring, grid, s);
-        if (items == 8) return scatter_sr<1024, 8, MODE>(a, semiring, grid, s);
+        if (items == 4) return scatter_sr<1024, 4, MODE>(a, semiring, grid, s, ev);
+        if (items == 8) return scatter_sr<1024, 8, MODE>(a, semiring, grid, s, ev);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s) {
-    return scatter_shape<SC_SINGLE>(a, semiring, block, items, grid, s);
+hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s,
+                          const LaunchEvents* ev) {
+    return scatter_shape<SC_SINGLE>(a, semiring, block, items, grid, s, ev);
 }
 
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
@@ -959,40 +970,42 @@ hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, i
 }
 
 template <int BLOCK, int SR, bool BFS, bool BATCH>
-static hipError_t merge_one(const MergeArgs& a, hipStream_t s) {
+static hipError_t merge_one(const MergeArgs& a, hipStream_t s, const LaunchEvents* ev) {
     const size_t lds = merge_lds_bytes(a.tile_log2);
     auto kern = k_merge<BLOCK, kMergeItems, SR, BFS, BATCH>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(a.nb), dim3(BLOCK), lds, s, a);
+    launch_k(kern, dim3(a.nb), dim3(BLOCK), lds, s, ev, a);
     return hipGetLastError();
 }
 
 template <int BLOCK, bool BATCH>
-static hipError_t merge_block(const MergeArgs& a, int semiring, bool bfs, hipStream_t s) {
+static hipError_t merge_block(const MergeArgs& a, int semiring, bool bfs, hipStream_t s, const LaunchEvents* ev) {
     switch (semiring) {
         case SR_PLUS_TIMES:
             if (bfs) return hipErrorInvalidValue;
-            return merge_one<BLOCK, SR_PLUS_TIMES, false, BATCH>(a, s);
+            return merge_one<BLOCK, SR_PLUS_TIMES, false, BATCH>(a, s, ev);
         case SR_MIN_SELECT2ND:
-            return bfs ? merge_one<BLOCK, SR_MIN_SELECT2ND, true, BATCH>(a, s)
-                       : merge_one<BLOCK, SR_MIN_SELECT2ND, false, BATCH>(a, s);
+            return bfs ? merge_one<BLOCK, SR_MIN_SELECT2ND, true, BATCH>(a, s, ev)
+                       : merge_one<BLOCK, SR_MIN_SELECT2ND, false, BATCH>(a, s, ev);
         default:
-            return bfs ? merge_one<BLOCK, SR_OR_AND, true, BATCH>(a, s)
-                       : merge_one<BLOCK, SR_OR_AND, false, BATCH>(a, s);
+            return bfs ? merge_one<BLOCK, SR_OR_AND, true, BATCH>(a, s, ev)
+                       : merge_one<BLOCK, SR_OR_AND, false, BATCH>(a, s, ev);
     }
 }
 
 template <bool BATCH>
-static hipError_t merge_dispatch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
-    if (block == 256) return merge_block<256, BATCH>(a, semiring, bfs, s);
-    if (block == 512) return merge_block<512, BATCH>(a, semiring, bfs, s);
-    if (block == 1024) return merge_block<1024, BATCH>(a, semiring, bfs, s);
+static hipError_t merge_dispatch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s,
+                                 const LaunchEvents* ev = nullptr) {
+    if (block == 256) return merge_block<256, BATCH>(a, semiring, bfs, s, ev);
+    if (block == 512) return merge_block<512, BATCH>(a, semiring, bfs, s, ev);
+    if (block == 1024) return merge_block<1024, BATCH>(a, semiring, bfs, s, ev);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
-    return merge_dispatch<false>(a, semiring, block, bfs, s);
+hipError_t launch_merge(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s,
+                        const LaunchEvents* ev) {
+    return merge_dispatch<false>(a, semiring, block, bfs, s, ev);
 }
 
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s) {
