@@ -96,15 +96,68 @@ __global__ __launch_bounds__(256) void k_pull_prep(PullArgs a) {
 // ------------------------------------------------------------- row walk
 // Workgroup c covers merge-path diagonals [c*C, (c+1)*C) of the sequence
 // "stored entries of row 0, end of row 0, entries of row 1, ...".  part[c] =
-// rows ended before diagonal c*C (computed once per matrix).  Each thread
-// walks ITEMS consecutive diagonals; a row wholly inside one thread is
-// written directly, a row split across threads or workgroups is combined
-// with one global atomic per piece.
+// rows ended before diagonal c*C (computed once per matrix), so the
+// workgroup's stored entries are the contiguous range [q0, q1).
+//   A: the entries are read coalesced (lane k of a pass takes entry q0 + k),
+//      probed against the x bitmap and multiplied; products and hit bits go
+//      to LDS.
+//   B: each thread walks ITEMS consecutive diagonals, folding the products
+//      of its rows from LDS; a row that starts and ends inside the thread is
+//      final.
+//   C: a block-wide segmented scan carries the open row of each thread into
+//      the next, so a row split across threads is combined in registers; only
+//      rows that cross a workgroup boundary take a global atomic.
+//   D: result bits are ORed once per run of lanes sharing a bitmap word.
+template <int SR>
+struct Seg {   // open-segment state of the carry scan
+    uint32_t v;
+    bool hit, end;
+};
+
+template <int SR>
+__device__ __forceinline__ Seg<SR> seg_comb(const Seg<SR>& l, const Seg<SR>& r) {
+    if (r.end) return r;
+    Seg<SR> o;
+    o.end = l.end;
+    o.hit = l.hit || r.hit;
+    o.v = l.hit ? (r.hit ? comb<SR>(l.v, r.v) : l.v) : r.v;
+    return o;
+}
+
+template <int SR>
+__device__ __forceinline__ Seg<SR> seg_shfl_up(const Seg<SR>& s, int d) {
+    Seg<SR> o;
+    o.v = (uint32_t)__shfl_up((int)s.v, d, 64);
+    const int fl = __shfl_up((int)s.hit | ((int)s.end << 1), d, 64);
+    o.hit = fl & 1;
+    o.end = (fl >> 1) & 1;
+    return o;
+}
+
+// OR `bits` into ybits[word] once per run of lanes holding the same word
+// (words are non-decreasing across lanes; 0xffffffff = nothing).
+__device__ __forceinline__ void or_bits_wave(uint32_t* ybits, uint32_t word, uint32_t bits) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t ow = (uint32_t)__shfl_down((int)word, d, 64);
+        const uint32_t ob = (uint32_t)__shfl_down((int)bits, d, 64);
+        if (lane + d < 64 && ow == word) bits |= ob;
+    }
+    const uint32_t prev = (uint32_t)__shfl_up((int)word, 1, 64);
+    if (word != 0xffffffffu && bits && (lane == 0 || prev != word)) atomicOr(&ybits[word], bits);
+}
+
 template <int BLOCK, int ITEMS, int SR, bool EARLY>
 __global__ __launch_bounds__(BLOCK) void k_pull(PullArgs a) {
     constexpr int C = BLOCK * ITEMS;
-    __shared__ int32_t s_re[C + 2];   // diagonal index of each row end touched by this workgroup
-    const int tid = threadIdx.x;
+    constexpr int NW = BLOCK / 64;
+    __shared__ int32_t s_re[C + 2];       // diagonal index of each row end touched by this workgroup
+    __shared__ uint32_t s_prod[C];        // product of entry q0 + k (where its hit bit is set)
+    __shared__ uint32_t s_hit[C / 32];
+    __shared__ uint32_t s_wv[NW];
+    __shared__ int s_wf[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (a.gate && ldc(&a.ctrl->dir) != 1) return;
     const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
     if (f <= 0) return;
@@ -116,101 +169,165 @@ __global__ __launch_bounds__(BLOCK) void k_pull(PullArgs a) {
     const int r1 = a.part[blockIdx.x + 1];
     const int rlast = min(r1, a.m - 1);
     for (int k = tid; k <= rlast - r0; k += BLOCK) s_re[k] = (r0 + k) + a.rowptr[r0 + k + 1];
+
+    // A: products of the workgroup's entries
+    const int64_t q0 = d0 - r0;
+    const int ne = (int)((d1 - r1) - q0);
+    {
+        uint32_t cj[ITEMS];
+        bool hv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int k = i * BLOCK + tid;
+            cj[i] = k < ne ? a.colids[q0 + k] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int k = i * BLOCK + tid;
+            hv[i] = k < ne && ((a.xbits[cj[i] >> 5] >> (cj[i] & 31)) & 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int k = i * BLOCK + tid;
+            uint32_t pv = 0u;
+            if (hv[i]) {
+                if constexpr (SR == SR_PLUS_TIMES) {
+                    const float av = a.values ? a.values[q0 + k] : 1.0f;
+                    pv = __float_as_uint(__fmul_rn(av, __uint_as_float(a.xdense[cj[i]])));
+                } else if constexpr (SR == SR_MIN_SELECT2ND) {
+                    pv = a.xdense[cj[i]];
+                } else {
+                    const uint32_t av = a.values ? (a.values[q0 + k] != 0.0f ? 1u : 0u) : 1u;
+                    pv = av & a.xdense[cj[i]];
+                }
+            }
+            s_prod[k] = pv;
+            const uint64_t bal = __ballot(hv[i]);
+            if (lane == 0) s_hit[k >> 5] = (uint32_t)bal;
+            else if (lane == 32) s_hit[k >> 5] = (uint32_t)(bal >> 32);
+        }
+    }
     __syncthreads();
 
-    int64_t dt = d0 + (int64_t)tid * ITEMS;
-    const int64_t dend = min(dt + ITEMS, d1);
-    if (dt >= dend) return;
-    // rows ended before dt: count of s_re[k] < dt among rows r0..rlast
-    int lo = 0, hi = rlast - r0 + 1;
+    // B: this thread's diagonals [dt, dend)
+    const int64_t dt = d0 + (int64_t)tid * ITEMS;
+    const int nsteps = dt < d1 ? (int)(min(dt + ITEMS, d1) - dt) : 0;
+    int lo = 0, hi = rlast - r0 + 1;   // rows ended before dt
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if ((int64_t)s_re[mid] < dt) lo = mid + 1; else hi = mid;
     }
-    // Phase 1 (LDS only): classify each of the thread's steps as a stored
-    // entry or the end of a row.  Phases 2-4 issue every column-id load, then
-    // every x-bitmap probe, then the value loads, so a thread keeps all its
-    // memory traffic in flight at once; phase 5 folds in order.
-    const int nsteps = (int)(dend - dt);
-    const uint32_t* __restrict__ colids = a.colids;
     int r = r0 + lo;
     int64_t q = dt - r;
-    const bool whole0 = r < a.m && q == a.rowptr[r];   // the thread holds its first row from the start
-    int32_t qs[ITEMS], rs[ITEMS];
-    uint8_t kind[ITEMS];   // 0 none, 1 stored entry, 2 end of row rs[i]
+    // the thread's first row began before the thread (false when it has no steps)
+    const bool open0 = nsteps > 0 && r < a.m && q != a.rowptr[r];
+    Seg<SR> own;             // the thread's trailing open segment (end = it saw a row end)
+    own.v = ident<SR>();
+    own.hit = false;
+    own.end = false;
+    int rowA = -1;           // first row ending here when it began before the thread
+    uint32_t headv = ident<SR>();
+    bool headhit = false;
+    uint32_t wA = 0xffffffffu, bA = 0u, wB = 0xffffffffu, bB = 0u;   // result bits, at most two words
+    auto mark = [&](int row) {
+        const uint32_t w = (uint32_t)row >> 5, bit = 1u << (row & 31);
+        if (wA == 0xffffffffu || wA == w) {
+            wA = w;
+            bA |= bit;
+        } else {
+            wB = w;
+            bB |= bit;
+        }
+    };
+    bool masked = r < a.m && a.mask && ((a.mask[r >> 5] >> (r & 31)) & 1u);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        qs[i] = 0;
-        rs[i] = r;
-        kind[i] = 0;
         if (i < nsteps && r < a.m) {
             const int64_t rend = (int64_t)s_re[r - r0] - r;   // rowptr[r + 1]
             if (q < rend) {
-                kind[i] = 1;
-                qs[i] = (int32_t)q;
+                const int k = (int)(q - q0);
+                if (!masked && ((s_hit[k >> 5] >> (k & 31)) & 1u)) {
+                    const uint32_t p = s_prod[k];
+                    own.v = own.hit ? comb<SR>(own.v, p) : p;
+                    own.hit = true;
+                }
                 ++q;
-            } else {
-                kind[i] = 2;
+            } else {   // end of row r
+                if (!own.end && open0) {
+                    rowA = r;
+                    headv = own.v;
+                    headhit = own.hit;
+                } else if (own.hit) {   // the row began and ended in this thread
+                    a.ydense[r] = own.v;
+                    mark(r);
+                }
+                own.end = true;
+                own.v = ident<SR>();
+                own.hit = false;
                 ++r;
+                masked = r < a.m && a.mask && ((a.mask[r >> 5] >> (r & 31)) & 1u);
             }
         }
     }
-    // Phase 2: entries of masked (visited) rows are skipped; column ids.
-    bool use[ITEMS];
-    uint32_t cj[ITEMS];
+
+    // C: exclusive segmented scan of the threads' open segments
+    Seg<SR> inc = own;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        use[i] = kind[i] == 1;
-        if (use[i] && a.mask) use[i] = ((a.mask[rs[i] >> 5] >> (rs[i] & 31)) & 1u) == 0u;
-        cj[i] = use[i] ? colids[qs[i]] : 0u;
+    for (int d = 1; d < 64; d <<= 1) {
+        const Seg<SR> o = seg_shfl_up<SR>(inc, d);
+        if (lane >= d) inc = seg_comb<SR>(o, inc);
     }
-    // Phase 3: probe x.
-    bool hitv[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) hitv[i] = use[i] && ((a.xbits[cj[i] >> 5] >> (cj[i] & 31)) & 1u);
-    // Phase 4: Mult for the hits.
-    uint32_t tv[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        tv[i] = 0u;
-        if (hitv[i]) {
-            if constexpr (SR == SR_PLUS_TIMES) {
-                const float av = a.values ? a.values[qs[i]] : 1.0f;
-                tv[i] = __float_as_uint(__fmul_rn(av, __uint_as_float(a.xdense[cj[i]])));
-            } else if constexpr (SR == SR_MIN_SELECT2ND) {
-                tv[i] = a.xdense[cj[i]];
-            } else {
-                const uint32_t av = a.values ? (a.values[qs[i]] != 0.0f ? 1u : 0u) : 1u;
-                tv[i] = av & a.xdense[cj[i]];
-            }
+    if (lane == 63) {
+        s_wv[wid] = inc.v;
+        s_wf[wid] = (int)inc.hit | ((int)inc.end << 1);
+    }
+    __syncthreads();
+    Seg<SR> carry;   // open segment arriving from the threads before this one
+    carry.v = ident<SR>();
+    carry.hit = false;
+    carry.end = false;
+    for (int w = 0; w < wid; ++w) {
+        Seg<SR> ws;
+        ws.v = s_wv[w];
+        ws.hit = s_wf[w] & 1;
+        ws.end = (s_wf[w] >> 1) & 1;
+        carry = seg_comb<SR>(carry, ws);
+    }
+    {
+        Seg<SR> prev = seg_shfl_up<SR>(inc, 1);
+        if (lane > 0) carry = seg_comb<SR>(carry, prev);
+    }
+    // A row that began before the workgroup gets contributions from another
+    // workgroup too: combine it atomically.  Only the workgroup's first row
+    // can have begun before it.
+    const bool first_mid = q0 > (int64_t)a.rowptr[r0];
+    if (rowA >= 0) {
+        const bool hit = carry.hit || headhit;
+        if (hit) {
+            const uint32_t v = carry.hit ? (headhit ? comb<SR>(carry.v, headv) : carry.v) : headv;
+            if (rowA == r0 && first_mid) comb_global<SR>(&a.ydense[rowA], v);
+            else a.ydense[rowA] = v;
+            mark(rowA);
         }
     }
-    // Phase 5: fold per row; a row wholly inside this thread is written
-    // directly, a piece of a longer row is combined with a global atomic.
-    bool whole = whole0, hit = false;
-    uint32_t acc = ident<SR>();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (kind[i] == 1) {
-            if (hitv[i]) {
-                acc = hit ? comb<SR>(acc, tv[i]) : tv[i];
-                hit = true;
-            }
-        } else if (kind[i] == 2) {
-            if (hit) {
-                if (whole) a.ydense[rs[i]] = acc;
-                else comb_global<SR>(&a.ydense[rs[i]], acc);
-                atomicOr(&a.ybits[rs[i] >> 5], 1u << (rs[i] & 31));
-            }
-            hit = false;
-            whole = true;
-            acc = ident<SR>();
+    // the open row at the workgroup's end continues in the next workgroup
+    if (nsteps > 0 && dt + nsteps == d1 && r < a.m) {
+        const Seg<SR> tail = own.end ? own : seg_comb<SR>(carry, own);
+        if (tail.hit) {
+            comb_global<SR>(&a.ydense[r], tail.v);
+            mark(r);
         }
     }
-    if (hit && r < a.m) {   // row r continues past this thread
-        comb_global<SR>(&a.ydense[r], acc);
-        atomicOr(&a.ybits[r >> 5], 1u << (r & 31));
+    // D
+    if (wA != 0xffffffffu && wB != 0xffffffffu && wB < wA) {   // keep the pair ordered
+        const uint32_t tw = wA, tb = bA;
+        wA = wB;
+        bA = bB;
+        wB = tw;
+        bB = tb;
     }
+    or_bits_wave(a.ybits, wA, bA);
+    or_bits_wave(a.ybits, wB, bB);
 }
 
 // Bottom-up BFS step: one thread per row, unvisited rows only, stopping at
