@@ -172,7 +172,8 @@ def main():
         "config": {"workload": f"SpMSpV plus-times fp32, R-MAT scale {args.scale} ef16 symmetrised (n={A.n}, "
                                f"nnz={A.nnz}), x density {args.density:g} (f={f}), {args.nx} rotating x",
                    "scale": args.scale, "nnz": A.nnz, "f": f, "mean_products": float(W.mean()),
-                   "mean_nnz_y": float(nnz_y.mean()), "schedule": M.schedule.as_dict()},
+                   "mean_nnz_y": float(nnz_y.mean()),
+                   "schedule": spv.spmspv_effective_schedule(M.handle, f).as_dict()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(dom, args),

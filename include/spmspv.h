@@ -237,9 +237,15 @@ int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, 
                           const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,
                           int64_t y_capacity, int reps, spmspv_schedule* h_best, double* h_us, void* stream);
 
-/* Read / replace the launch schedule (NULL restores the default). */
+/* Read / replace the launch schedule (NULL restores the default).  While
+ * the default is in place, spmspv_run sizes the scatter chunk per call from
+ * the expected product count f * nnz / n: the largest chunk that still gives
+ * every compute unit one (see spmspv_effective_schedule).                 */
 int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched);
 int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
+
+/* The schedule spmspv_run(A, ..., flags, f, ...) would launch with.      */
+int spmspv_effective_schedule(spmspv_handle A, int64_t f, int flags, spmspv_schedule* h_sched);
 
 /* Statistics of the most recent spmspv_run / BFS level (synchronous):
  * h_out[0] = products W (sum of selected column lengths, the work bound of

@@ -47,7 +47,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
-    "spmspv_selector_features", "spmspv_force_classes",
+    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule",
 )
 
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.bfs_run.argtypes = [vp, ci, ctypes.c_int32, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.spmspv_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.spmspv_effective_schedule.argtypes = [vp, i64, ci, ctypes.POINTER(Schedule)]
     lib.spmspv_last_stats.argtypes = [vp, ctypes.POINTER(i64), vp]
     lib.spmspv_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.spmspv_destroy.argtypes = [vp]
@@ -287,6 +288,12 @@ def spmspv_autotune(handle, semiring, densities, reps, x_idx, x_val, y_idx, y_va
     _check(load_library().spmspv_autotune(handle, semiring, d, len(densities), int(reps), _ptr(x_idx), _ptr(x_val),
                                           _ptr(y_idx), _ptr(y_val), out, _stream(stream)))
     return [e.as_dict() for e in out]
+
+
+def spmspv_effective_schedule(handle, f, flags=0) -> Schedule:
+    sc = Schedule()
+    _check(load_library().spmspv_effective_schedule(handle, int(f), int(flags), ctypes.byref(sc)))
+    return sc
 
 
 def spmspv_tuned_schedule(handle, f) -> Schedule:

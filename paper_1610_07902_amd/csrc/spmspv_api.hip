@@ -204,6 +204,7 @@ struct spmspv_matrix {
     // profiling ring
     std::vector<hipEvent_t> prof_ev;
     int prof_used = 0;
+    bool sched_default = true;          // no schedule set by the caller: size the scatter chunk per call
     // BFS graph cache
     hipGraphExec_t graph = nullptr;
     int graph_key = -1;
@@ -249,6 +250,26 @@ int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
     const int64_t nb = (A->m + (int64_t(1) << tl) - 1) >> tl;
     if (scatter_lds_bytes((int)nb, 8192) + 1024 > A->lds_max) s->scatter_items = 4;
     return SPMSPV_OK;
+}
+
+// Default schedule for one standalone call with f x entries: the scatter
+// takes chunks of exactly block x items products, one workgroup per chunk
+// at a time, so with few products a large chunk leaves compute units idle.
+// Take the largest chunk for which the expected product count f * nnz / n
+// still gives every compute unit one.
+spmspv_schedule sized_for_call(const spmspv_matrix* A, int64_t f) {
+    spmspv_schedule s = A->sched;
+    const double w_est = A->n > 0 ? (double)f * (double)A->nnz / (double)A->n : 0.0;
+    const int64_t nb = (A->m + (int64_t(1) << s.tile_log2) - 1) >> s.tile_log2;
+    const int shapes[4][2] = {{1024, 8}, {512, 8}, {256, 8}, {256, 4}};
+    for (const auto& sh : shapes) {
+        const int chunk = sh[0] * sh[1];
+        if (scatter_lds_bytes((int)nb, chunk) + 1024 > A->lds_max) continue;
+        s.scatter_block = sh[0];
+        s.scatter_items = sh[1];
+        if (w_est >= (double)chunk * A->num_cu) break;
+    }
+    return s;
 }
 
 int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
@@ -851,6 +872,16 @@ int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched) {
     return SPMSPV_OK;
 }
 
+int spmspv_effective_schedule(spmspv_handle A, int64_t f, int flags, spmspv_schedule* h_sched) {
+    if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    const spmspv_schedule* tuned = (flags & SPMSPV_AUTO_SCHEDULE) ? tuned_for(A, f) : nullptr;
+    if (tuned) *h_sched = *tuned;
+    else if (A->sched_default) *h_sched = sized_for_call(A, f);
+    else *h_sched = A->sched;
+    return SPMSPV_OK;
+}
+
 int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     spmspv_schedule s{};
@@ -859,6 +890,7 @@ int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
     const int rc = check_schedule(A, &s);
     if (rc) return rc;
     A->sched = s;
+    A->sched_default = h_sched == nullptr;
     if (A->graph) {
         (void)hipGraphExecDestroy(A->graph);
         A->graph = nullptr;
@@ -913,6 +945,7 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
         const spmspv_schedule keep = A->sched;
         const spmspv_schedule* tuned = (flags & SPMSPV_AUTO_SCHEDULE) ? tuned_for(A, f) : nullptr;
         if (tuned) A->sched = *tuned;
+        else if (A->sched_default) A->sched = sized_for_call(A, f);
         if (A->sched.direction == 1)
             rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
                               mask, false, false, s, ev, (flags & SPMSPV_PULL_ROWWISE) != 0);

@@ -99,3 +99,33 @@ def test_autotune_batch(spv, rmat15):
     for b in range(16):
         oi, ov, _ = oracle.spmspv(A, xs[b][0], xs[b][1], 0, sorted_output=True)
         compare(0, y_idx[yo[b]:yo[b + 1]], y_val[yo[b]:yo[b + 1]], oi, ov, sorted_output=True)
+
+
+def test_default_schedule_sizes_the_scatter_chunk(spv, rmat15):
+    """With no schedule set, each call takes the largest scatter chunk that
+    the expected product count f * nnz / n spreads over every compute unit;
+    an explicit schedule is used as given.  Results match the oracle either
+    way."""
+    A = rmat15
+    M = spv.Matrix.from_csc(A)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    chunks = [(1024, 8), (512, 8), (256, 8), (256, 4)]
+    for f in (10, 300, 3000, A.n):
+        eff = spv.spmspv_effective_schedule(M.handle, f)
+        w_est = f * A.nnz / A.n
+        fits = [c for c in chunks if w_est >= c[0] * c[1] * cus]
+        want = fits[0] if fits else chunks[-1]
+        assert (eff.scatter_block, eff.scatter_items) == want, (f, eff.as_dict())
+        assert eff.tile_log2 == M.schedule.tile_log2
+        S, xv = synth.sparse_x(A.n, f, seed=70 + f)
+        gi, gv, _ = M.spmspv(dev(S), dev(xv), semiring=0, sorted_output=True)
+        oi, ov, _ = oracle.spmspv(A, S, xv, 0, sorted_output=True)
+        compare(0, gi, gv, oi, ov, sorted_output=True)
+    s = M.schedule
+    s.scatter_block, s.scatter_items = 1024, 4
+    M.schedule = s
+    eff = spv.spmspv_effective_schedule(M.handle, 10)
+    assert (eff.scatter_block, eff.scatter_items) == (1024, 4)
+    M.schedule = None
+    eff = spv.spmspv_effective_schedule(M.handle, 10)
+    assert (eff.scatter_block, eff.scatter_items) == (256, 4)
