@@ -81,7 +81,7 @@ struct ScanArgs {
     uint64_t* lb3;           // merge look-back words, cleared here
     int32_t nb;              // buckets of the current schedule
     int bump_level;          // BFS: advance ctrl->level when f > 0
-    int single_tile;         // each workgroup processes exactly one tile
+    int wide;                // 1: tiles of kScanItemsWide items per thread (large or device-known f)
     // Batched calls: x is the concatenation of nbatch vectors, vector b at
     // positions [xoff[b], xoff[b+1]); xoff[nbatch] (read on the device) is the
     // total length and must not exceed f_cap.

@@ -340,11 +340,13 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     sa.lb3 = A->lb3;
     sa.nb = clear_nb > nb ? clear_nb : nb;
     sa.bump_level = bfs ? 1 : 0;
-    int64_t g1 = (f_bound + kScanTile - 1) / kScanTile;
+    // f known on the host: one workgroup per tile, narrow tiles unless that
+    // would take more than two workgroups per compute unit.  f on the device
+    // (BFS): a fixed grid of wide tiles loops over the frontier.
+    sa.wide = (f_dev || f_bound > (int64_t)kScanTile * 2 * A->num_cu) ? 1 : 0;
+    const int64_t scan_tile = sa.wide ? (int64_t)kScanBlock * kScanItemsWide : kScanTile;
+    int64_t g1 = (f_bound + scan_tile - 1) / scan_tile;
     if (g1 < 1) g1 = 1;
-    // f known on the host: one workgroup per tile, one ticket each.  f on
-    // the device (BFS): a fixed grid loops over tickets.
-    sa.single_tile = f_dev ? 0 : 1;
     if (f_dev && g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;
 
     ScatterArgs ca{};

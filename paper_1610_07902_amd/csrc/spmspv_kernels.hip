@@ -903,14 +903,15 @@ static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s, const La
 }
 
 // Frontier lengths known only on the device (BFS, PageRank) and batched
-// calls use a fixed grid that loops over tiles; their tiles are 4x wider so
-// a large frontier needs fewer look-back rounds per workgroup.
+// calls use a fixed grid that loops over tiles; their tiles, and those of a
+// host-known f too large for one narrow tile per workgroup, are 4x wider so
+// a large frontier needs fewer look-back rounds.
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s, const LaunchEvents* ev) {
     if (a.xoff) {
         if (a.nbatch < 1 || a.nbatch > kMaxBatch || !a.cxid || !a.kcount) return hipErrorInvalidValue;
         return scan_mode<kScanItemsWide, true>(a, grid, s, ev);
     }
-    if (a.f_dev) return scan_mode<kScanItemsWide, false>(a, grid, s, ev);
+    if (a.f_dev || a.wide) return scan_mode<kScanItemsWide, false>(a, grid, s, ev);
     return scan_mode<kScanItems, false>(a, grid, s, ev);
 }
 
