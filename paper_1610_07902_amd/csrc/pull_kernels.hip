@@ -148,7 +148,7 @@ __device__ __forceinline__ void or_bits_wave(uint32_t* ybits, uint32_t word, uin
     if (word != 0xffffffffu && bits && (lane == 0 || prev != word)) atomicOr(&ybits[word], bits);
 }
 
-template <int BLOCK, int ITEMS, int SR, bool EARLY>
+template <int BLOCK, int ITEMS, int SR>
 __global__ __launch_bounds__(BLOCK) void k_pull(PullArgs a) {
     constexpr int C = BLOCK * ITEMS;
     constexpr int NW = BLOCK / 64;
@@ -593,19 +593,15 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
         } else {
             hipLaunchKernelGGL((k_pull_bfs<SR_OR_AND, true>), gb, bb, 0, s, a);
         }
-    } else {
-    const dim3 g(a.pull_blocks), b(kPullBlock);
-    switch (semiring) {
-        case SR_PLUS_TIMES: hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_PLUS_TIMES, false>), g, b, 0, s, a); break;
-        case SR_MIN_SELECT2ND:
-            if (early) hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_MIN_SELECT2ND, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_MIN_SELECT2ND, false>), g, b, 0, s, a);
-            break;
-        default:
-            if (early) hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND, false>), g, b, 0, s, a);
-            break;
-    }
+    } else {   // merge-path walk over every row (no early exit: each row's full fold)
+        const dim3 g(a.pull_blocks), b(kPullBlock);
+        switch (semiring) {
+            case SR_PLUS_TIMES: hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_PLUS_TIMES>), g, b, 0, s, a); break;
+            case SR_MIN_SELECT2ND:
+                hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_MIN_SELECT2ND>), g, b, 0, s, a);
+                break;
+            default: hipLaunchKernelGGL((k_pull<kPullBlock, kPullItems, SR_OR_AND>), g, b, 0, s, a); break;
+        }
     }
     const dim3 ge(a.emit_blocks), be(kEmitBlock);
     switch (semiring) {
