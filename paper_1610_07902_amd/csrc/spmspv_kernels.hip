@@ -375,6 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     int32_t* s_start = s_off + (C + 1);
     uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));
     int32_t* s_xid = reinterpret_cast<int32_t*>(s_xv + (C + 1)); // batched: vector of each column
+    uint16_t* col_of = reinterpret_cast<uint16_t*>(s_xv + (MODE != SC_SINGLE ? 2 : 1) * (C + 1));   // [C] (phase 1)
     uint2* stage = reinterpret_cast<uint2*>(region);            // [C] sort buffer (phase 3)
     int32_t* skey = reinterpret_cast<int32_t*>(stage + C);      // batched: [C] key of each staged entry
     __shared__ int s_tmp[BLOCK / kWave + 1];
@@ -420,10 +421,14 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         }
         __syncthreads();
 
-        // (1) gather + rank.  Each thread owns ITEMS consecutive products:
-        // one binary search finds the column of the first, the rest walk
-        // forward.  All row-id / value / mask loads are then issued together
-        // (indices clamped into range), and ranks are taken in LDS.
+        // (1) gather + rank.  Column map: each thread finds the column of
+        // its ITEMS consecutive products (one binary search, then a forward
+        // walk) and records it in LDS.  Products are then taken strided
+        // (item i of thread t is product i * BLOCK + t), so the lanes of a
+        // wave read consecutive row ids and values: one request per cache
+        // line instead of one per lane.  All row-id / value / mask loads are
+        // issued together (indices clamped into range); ranks are taken in
+        // LDS.
         int32_t row[ITEMS], bk[ITEMS], rank[ITEMS], qq[ITEMS], xid[ITEMS];
         uint32_t xcol[ITEMS];
         {
@@ -441,10 +446,17 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
                     ++lo;
                     next = lo + 1 < ncols ? s_off[lo + 1] : 0x7fffffff;
                 }
-                qq[i] = rq < cnt ? s_start[lo] + (rq - s_off[lo]) : -1;
-                xcol[i] = s_xv[lo];
-                xid[i] = MODE != SC_SINGLE ? s_xid[lo] : 0;
+                if (rq < cnt) col_of[rq] = (uint16_t)lo;
             }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int k = i * BLOCK + tid;
+            const int lo = k < cnt ? col_of[k] : 0;
+            qq[i] = k < cnt ? s_start[lo] + (k - s_off[lo]) : -1;
+            xcol[i] = s_xv[lo];
+            xid[i] = MODE != SC_SINGLE ? s_xid[lo] : 0;
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) row[i] = a.rowids[qq[i] >= 0 ? qq[i] : 0];
@@ -863,7 +875,9 @@ size_t merge_lds_bytes(int tile_log2) {
 }
 
 size_t scatter_lds_bytes(int nb, int chunk, bool batch) {
-    const size_t table = size_t(chunk + 1) * (batch ? 16 : 12), sortbuf = size_t(chunk) * (batch ? 12 : 8);
+    // column table (+ the per-product column map) in phase 1, sort buffer in phase 3
+    const size_t table = size_t(chunk + 1) * (batch ? 16 : 12) + size_t(chunk) * 2,
+                 sortbuf = size_t(chunk) * (batch ? 12 : 8);
     return size_t(2 * nb + 2) * 4 + (table > sortbuf ? table : sortbuf);
 }
 
