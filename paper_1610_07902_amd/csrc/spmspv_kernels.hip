@@ -490,50 +490,85 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             }
             continue;   // the loop head synchronises before hist is reused
         }
-        // (2) chunk-local offsets and one slot reservation per touched bucket
-        int carry = 0;
-        for (int b0 = 0; b0 < nb; b0 += BLOCK) {
-            const int b = b0 + tid;
+        // (2) chunk-local offsets and one slot reservation per touched
+        // bucket.  With at most one bucket per thread (the usual case) the
+        // reservation's round trip overlaps the counting sort (3), which
+        // does not need it; its result is stored after the sort.
+        int kept;
+        if (nb <= BLOCK) {
+            const int b = tid;
             const int n = b < nb ? hist[b] : 0;
-            int tot;
-            const int e = block_exclusive_i32<BLOCK>(n, s_tmp, tot);
-            if (b < nb) {
-                loff[b] = carry + e;
-                if (n > 0) {
-                    int base, cap;
-                    if (MODE == SC_BATCH && a.xstride == 0) {
-                        base = a.kbase[b];
-                        cap = a.kbase[b + 1] - base;
-                    } else if (MODE == SC_BATCH) {   // fixed bases: row-count prefix inside the vector's slice
-                        const int r0 = (b - (b / a.nbx) * a.nbx) << tl;
-                        base = a.rcp[r0];
-                        cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
-                    } else {
-                        const int r0 = b << tl;
-                        base = a.rcp[r0];
-                        cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
-                    }
-                    const int g = atomicAdd(&a.cursor[b], n);
-                    if (g + n > cap) {
-                        atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
-                        hist[b] = -1;
-                    } else {
-                        hist[b] = base + g;
-                    }
+            const int e = block_exclusive_i32<BLOCK>(n, s_tmp, kept);
+            int base = 0, top = 0, g = 0;   // the bucket's slots are [base, top)
+            if (b < nb) loff[b] = e;
+            if (n > 0) {
+                g = atomicAdd(&a.cursor[b], n);
+                if (MODE == SC_BATCH && a.xstride == 0) {
+                    base = a.kbase[b];
+                    top = a.kbase[b + 1];
+                } else {
+                    const int r0 = (MODE == SC_BATCH ? b - (b / a.nbx) * a.nbx : b) << tl;
+                    base = a.rcp[r0];
+                    top = a.rcp[min(r0 + (1 << tl), a.m)];
                 }
             }
-            carry += tot;
-        }
-        const int kept = carry;
-        __syncthreads();
-        // (3) counting sort into the LDS buffer
+            __syncthreads();
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (bk[i] >= 0) {
-                stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
-                if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+            for (int i = 0; i < ITEMS; ++i)
+                if (bk[i] >= 0) {
+                    stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+                    if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+                }
+            if (n > 0) {
+                if (base + g + n > top) {
+                    atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                    hist[b] = -1;
+                } else {
+                    hist[b] = base + g;
+                }
             }
-        __syncthreads();
+            __syncthreads();
+        } else {
+            int carry = 0;
+            for (int b0 = 0; b0 < nb; b0 += BLOCK) {
+                const int b = b0 + tid;
+                const int n = b < nb ? hist[b] : 0;
+                int tot;
+                const int e = block_exclusive_i32<BLOCK>(n, s_tmp, tot);
+                if (b < nb) {
+                    loff[b] = carry + e;
+                    if (n > 0) {
+                        int base, cap;
+                        if (MODE == SC_BATCH && a.xstride == 0) {
+                            base = a.kbase[b];
+                            cap = a.kbase[b + 1] - base;
+                        } else {   // row-count prefix (inside the vector's slice for fixed batched bases)
+                            const int r0 = (MODE == SC_BATCH ? b - (b / a.nbx) * a.nbx : b) << tl;
+                            base = a.rcp[r0];
+                            cap = a.rcp[min(r0 + (1 << tl), a.m)] - base;
+                        }
+                        const int g = atomicAdd(&a.cursor[b], n);
+                        if (g + n > cap) {
+                            atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
+                            hist[b] = -1;
+                        } else {
+                            hist[b] = base + g;
+                        }
+                    }
+                }
+                carry += tot;
+            }
+            kept = carry;
+            __syncthreads();
+            // (3) counting sort into the LDS buffer
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (bk[i] >= 0) {
+                    stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+                    if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+                }
+            __syncthreads();
+        }
         // (4) coalesced write-out of the bucket runs
         for (int t = tid; t < kept; t += BLOCK) {
             const uint2 e = stage[t];
