@@ -63,6 +63,8 @@ __global__ __launch_bounds__(256) void k_pull_prep(PullArgs a) {
     if (a.gate && ldc(&a.ctrl->dir) != 1) return;   // this BFS level runs push
     const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.bump_level && f > 0) stc(&a.ctrl->level, ldc(&a.ctrl->level) + 1);
+    // the emit look-back words of this call (the previous emit has finished)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < a.emit_blocks; i += gridDim.x * 256) a.lbp[i] = 0;
     // Bitmap words are ORed once per run of lanes sharing a word (a sorted
     // frontier puts up to 32 consecutive lanes on one word, whose atomics
     // would otherwise serialise on one address).
@@ -577,7 +579,6 @@ hipError_t launch_pull(const PullArgs& a, int semiring, int xmode, bool bfs, boo
     int64_t fg = (a.f_host + 255) / 256 + 1;
     if (a.f_dev || fg > 512) fg = 512;
     const int f_grid = (int)fg;
-    hipLaunchKernelGGL(k_lbp_clear, dim3(64), dim3(256), 0, s, a.lbp, a.emit_blocks);
     switch (xmode) {
         case XV_BITS32: hipLaunchKernelGGL(k_pull_prep<XV_BITS32>, dim3(f_grid), dim3(256), 0, s, a); break;
         case XV_INDEX: hipLaunchKernelGGL(k_pull_prep<XV_INDEX>, dim3(f_grid), dim3(256), 0, s, a); break;

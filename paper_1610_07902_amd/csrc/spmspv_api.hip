@@ -1093,27 +1093,27 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     }
     // Level loop: kGraphLevels levels per batch, then one host check of the
     // frontier length.  Levels after the frontier empties are no-ops.
-    int32_t hf = 1;
-    for (int64_t batch = 0; hf > 0; ++batch) {
+    // Each host check reads the whole control block, so the last one also
+    // gives the level count and error bits.
+    Ctrl h{};
+    h.f = 1;
+    for (int64_t batch = 0; h.f > 0; ++batch) {
         if (batch * kGraphLevels > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
         if (persist) {
             HIP_TRY(launch_fill_u32(A->bar, 0u, 1, s));   // arrival counter (a timed-out wait may leave it set)
             HIP_TRY(launch_bfs_persistent(pa, semiring == SR_MIN_SELECT2ND, A->persist_grid, s));
-            HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (hf == 0) break;
+            const int rc = read_ctrl(A, &h, s);
+            if (rc) return rc;
+            if (h.f == 0) break;
         }
         if (use_graph) HIP_TRY(hipGraphLaunch(A->graph, s));
         else {
             const int rc = enqueue_levels(kGraphLevels, s);
             if (rc) return rc;
         }
-        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        const int rc = read_ctrl(A, &h, s);
+        if (rc) return rc;
     }
-    Ctrl h{};
-    int rc = read_ctrl(A, &h, s);
-    if (rc) return rc;
     if (h.err) {
         clear_err(A, s);
         return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
