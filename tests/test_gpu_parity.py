@@ -107,6 +107,21 @@ def test_schedule_invariance(spv, c1, sched):
         M.schedule = None
 
 
+@pytest.mark.parametrize("sb", [256, 512])
+def test_more_buckets_than_scatter_threads(spv, sb):
+    """512 buckets: with 256 scatter threads each thread reserves slots for
+    two buckets (the looped reservation), with 512 for one (the reservation
+    that overlaps the LDS sort)."""
+    A = synth.rmat(17, seed=17, symmetrize=True)
+    M = spv.Matrix.from_csc(A)
+    M.schedule = spv.Schedule(0, 8, sb, 4, 256, 0)
+    assert (A.m + 255) // 256 == 512
+    for f in (40, 2000, 60000):
+        S, xv = synth.sparse_x(A.n, f, seed=900 + f)
+        run_and_compare(spv, M, A, S, spv.PLUS_TIMES_F32, xv, sorted_output=True)
+        run_and_compare(spv, M, A, S, spv.MIN_SELECT2ND_I32, S.astype(np.int32))
+
+
 def test_empty_x_and_empty_columns(spv, c1):
     A, M = c1
     x = torch.empty(0, dtype=torch.int32, device="cuda")
