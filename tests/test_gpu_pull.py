@@ -67,6 +67,37 @@ def test_pull_with_transpose_all_semirings(spv, shape):
         run_pair(spv, M, A, S, 2, None, flags=spv.X_ALL_TRUE)
 
 
+@pytest.mark.parametrize("flag", ["WITH_TRANSPOSE", "SYMMETRIC"])
+def test_pull_many_columns(spv, flag):
+    """More than 2^20 columns (an x bitmap larger than any LDS slice) and a
+    hub row spanning many merge-path chunks."""
+    rng = np.random.default_rng(11)
+    if flag == "SYMMETRIC":
+        n = m = 1_300_000
+        nt = 3 * n
+        r = rng.integers(0, n, nt)
+        c = rng.integers(0, n, nt)
+        hub = np.arange(0, n, 5)
+        rows = np.concatenate([r, c, np.full(hub.size, 7), hub]).astype(np.int32)
+        cols = np.concatenate([c, r, hub, np.full(hub.size, 7)]).astype(np.int32)
+    else:
+        m, n = 30000, 1_500_000
+        nt = 3_000_000
+        hub = np.arange(0, n, 3)
+        rows = np.concatenate([rng.integers(0, m, nt), np.full(hub.size, 7)]).astype(np.int32)
+        cols = np.concatenate([rng.integers(0, n, nt), hub]).astype(np.int32)
+    colptr, rowids = synth.coo_to_csc(m, n, rows, cols, drop_self=False)
+    # a symmetric handle reads A's columns as its rows: pattern only there
+    A = synth.CSC(m, n, colptr, rowids, None if flag == "SYMMETRIC" else synth.values(rowids.size, 6))
+    M = spv.Matrix.from_csc(A, flags=getattr(spv, flag))
+    pull_schedule(spv, M)
+    for f in (50, 20000, 400000):
+        S, xv = synth.sparse_x(n, f, seed=f + 3)
+        run_pair(spv, M, A, S, 0, xv)
+        run_pair(spv, M, A, S, 1, None, flags=spv.X_VAL_IS_INDEX)
+        run_pair(spv, M, A, S, 2, None, flags=spv.X_ALL_TRUE)
+
+
 def test_pull_symmetric_pattern(spv):
     A = synth.rmat(15, seed=3, symmetrize=True, with_values=False)
     M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC)
