@@ -283,7 +283,11 @@ int pagerank_scratch_size(spmspv_handle A, size_t* h_bytes);
  * 1 / outdeg.  rank [n] (device float) receives the result.  Flags:
  * SPMSPV_USE_SELECTOR picks each multiply's schedule with the loaded
  * selector (one host synchronisation per step; without it the host checks
- * every 8 steps).  *h_iters = multiplies performed.  Synchronous.        */
+ * every 8 steps); with SPMSPV_USE_GRAPH as well (and a row form) the
+ * selector's direction is consumed on the device, gating the push and pull
+ * kernels, and the host checks every 8 steps (bucket count: the handle's
+ * schedule; spmspv_selector_classes then reports nothing).
+ * *h_iters = multiplies performed.  Synchronous.                          */
 int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int flags, float* rank, void* scratch,
                  size_t scratch_bytes, int32_t* h_iters, void* stream);
 
@@ -363,11 +367,12 @@ int spmspv_selector_load(spmspv_handle A, const float* h_params, const float* h_
  * SPMSPV_USE_SELECTOR: writes min(cap, count) entries, *h_count = count.  */
 int spmspv_selector_classes(spmspv_handle A, int32_t* h_out, int32_t cap, int32_t* h_count);
 
-/* Replay a class sequence: while set (count > 0), bfs_run with
- * SPMSPV_USE_SELECTOR runs step k with class h_classes[k] (0..9) instead of
- * the network's choice, in the same host-driven loop (steps past the end
- * use the network).  count = 0 clears it.  Used to time a schedule found in
- * hindsight under exactly the loop the selector runs in.                 */
+/* Replay a class sequence: while set (count > 0), bfs_run and pagerank_run
+ * with SPMSPV_USE_SELECTOR run step k (BFS level / PageRank multiply) with
+ * class h_classes[k] (0..9) instead of the network's choice, in the same
+ * host-driven loop (steps past the end use the network).  count = 0 clears
+ * it.  Used to time a schedule found in hindsight under exactly the loop the
+ * selector runs in.                                                       */
 int spmspv_force_classes(spmspv_handle A, const int32_t* h_classes, int32_t count);
 
 /* Standardised features of the most recent selector decision (h_out[6],

@@ -1568,7 +1568,8 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
     pagerank_scratch_size(A, &need);
     if (scratch_bytes < need) return fail(SPMSPV_ENOMEM, "scratch needs " + std::to_string(need) + " bytes");
     const bool selector = (flags & SPMSPV_USE_SELECTOR) != 0;
-    if (selector && !A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
+    if (selector && !A->selector_loaded && A->forced_classes.empty())
+        return fail(SPMSPV_EINVAL, "no selector weights loaded");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = A->n;
     char* w = static_cast<char*>(scratch);
@@ -1583,14 +1584,28 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
     int done = 0;
     while (hf > 0 && done < max_iter) {
         // kGraphLevels steps per host check; steps after x empties are no-ops
-        const int steps = selector ? 1 : std::min(kGraphLevels, max_iter - done);
+        // With the selector: one host read per multiply (bucket count and
+        // direction), or with SPMSPV_USE_GRAPH the network's direction taken
+        // on the device, gating the push and pull kernels, with a host check
+        // every kGraphLevels multiplies (as for BFS).  A replayed sequence is
+        // always read on the host.
+        const bool gated = selector && A->forced_classes.empty() && A->pull && (flags & SPMSPV_USE_GRAPH);
+        const int steps = selector && !gated ? 1 : std::min(kGraphLevels, max_iter - done);
         for (int k = 0; k < steps; ++k) {
             int rc;
-            if (selector) {
+            if (gated) {
+                rc = enqueue(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n, nullptr,
+                             false, nullptr, s, nullptr, true, -1, 3, 0, true);
+                if (!rc)
+                    rc = enqueue_pull(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n,
+                                      nullptr, false, nullptr, false, true, s, nullptr);
+            } else if (selector) {
                 int cls = 0;
                 int32_t fnow = 0;
+                const int forced = done + k < (int)A->forced_classes.size() ? A->forced_classes[(size_t)(done + k)]
+                                                                              : -1;
                 rc = run_selected(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n,
-                                  nullptr, false, nullptr, s, &cls, &fnow);
+                                  nullptr, false, nullptr, s, &cls, &fnow, forced);
                 if (!rc && fnow > 0) A->level_classes.push_back(cls);
             } else {
                 rc = enqueue(A, SR_PLUS_TIMES, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n, nullptr,

@@ -85,6 +85,19 @@ def test_pagerank_with_selector(spv, cls):
     assert M.selector_classes() == [cls] * it
 
 
+@pytest.mark.parametrize("cls", [2, 9])
+def test_pagerank_with_selector_on_device(spv, cls):
+    """Direction consumed on the device (no host read per multiply): same
+    ranks as the oracle whichever direction the network picks."""
+    A = synth.rmat(13, 16, seed=75, symmetrize=True)
+    M = spv.Matrix.from_csc(A, pattern=True, flags=spv.SYMMETRIC)
+    p = np.zeros(spv.MLP_PARAMS, np.float32)
+    p[-10 + cls] = 5.0
+    M.load_selector(p, np.zeros(6, np.float32), np.ones(6, np.float32))
+    r, it = M.pagerank(0.85, 1e-6, 100, flags=spv.USE_SELECTOR | spv.USE_GRAPH)
+    check(A, r, it, 1e-6, 100)
+
+
 def test_pagerank_bad_arguments(spv):
     A = synth.rmat(10, 8, seed=74, symmetrize=True)
     Mv = spv.Matrix.from_csc(A)                        # has values
