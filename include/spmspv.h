@@ -239,8 +239,9 @@ int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, 
 
 /* Read / replace the launch schedule (NULL restores the default).  While
  * the default is in place, spmspv_run sizes the scatter chunk per call from
- * the expected product count f * nnz / n: the largest chunk that still gives
- * every compute unit one (see spmspv_effective_schedule).                 */
+ * the expected product count f * nnz / n: the largest chunk, up to 4096
+ * products, that still gives every compute unit one (see
+ * spmspv_effective_schedule).                                             */
 int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched);
 int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
 

@@ -255,13 +255,15 @@ int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
 // Default schedule for one standalone call with f x entries: the scatter
 // takes chunks of exactly block x items products, one workgroup per chunk
 // at a time, so with few products a large chunk leaves compute units idle.
-// Take the largest chunk for which the expected product count f * nnz / n
-// still gives every compute unit one.
+// Take the largest chunk (at most 4096 products: two workgroups per compute
+// unit overlap their phases; measured faster than 8192 at every density on
+// R-MAT scale 22) for which the expected product count f * nnz / n still
+// gives every compute unit one.
 spmspv_schedule sized_for_call(const spmspv_matrix* A, int64_t f) {
     spmspv_schedule s = A->sched;
     const double w_est = A->n > 0 ? (double)f * (double)A->nnz / (double)A->n : 0.0;
     const int64_t nb = (A->m + (int64_t(1) << s.tile_log2) - 1) >> s.tile_log2;
-    const int shapes[4][2] = {{1024, 8}, {512, 8}, {256, 8}, {256, 4}};
+    const int shapes[3][2] = {{512, 8}, {256, 8}, {256, 4}};
     for (const auto& sh : shapes) {
         const int chunk = sh[0] * sh[1];
         if (scatter_lds_bytes((int)nb, chunk) + 1024 > A->lds_max) continue;
