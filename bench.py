@@ -323,9 +323,11 @@ def sweep(spv, M, A, deg, dev, stream):
             y_val = torch.empty(A.m, dtype=torch.float32 if sr == 0 else torch.int32, device=dev)
             rec = {"f": f}
             for direction in (0, 1):
-                s = M.schedule
-                s.direction = direction
-                M.schedule = s
+                M.schedule = None   # push: the default, sized per call
+                if direction == 1:
+                    s = M.schedule
+                    s.direction = 1
+                    M.schedule = s
                 ms = time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, A.m, 64, stream)
                 key = "push" if direction == 0 else "pull"
                 rec[key + "_us"] = round(ms * 1e3, 2)
