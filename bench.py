@@ -471,8 +471,9 @@ def batch_bench(spv, dev, msbfs=True, reps=5):
 def grid_bfs_bench(spv, dev, side=256):
     """High-diameter BFS: 3-D 7-point grid side^3 with the diagonal, pattern,
     or-and, from the corner vertex 0 (3*(side-1)+1 levels of small
-    frontiers): per-level launches versus the captured level graph, and the
-    direction-optimising and learned variants."""
+    frontiers): per-level launches versus the captured level graph, the
+    persistent kernel, and the direction-optimising and learned variants;
+    then the persistent kernel with min-select2nd and parents."""
     import torch
     import synth
     t0 = time.time()
@@ -494,11 +495,13 @@ def grid_bfs_bench(spv, dev, side=256):
         variants = (("per_level_launch", 0), ("graph", spv.USE_GRAPH),
                     ("persistent", spv.USE_GRAPH | spv.PERSISTENT),
                     ("graph_direction_heuristic", spv.USE_GRAPH | spv.DIRECTION_OPT))
+    variants += (("persistent_min_parents", spv.USE_GRAPH | spv.PERSISTENT),)
     for name, fl in variants:
-        P.bfs(0, spv.OR_AND_BOOL, parents=False, flags=fl)
+        sr, par = (spv.MIN_SELECT2ND_I32, True) if name.endswith("_parents") else (spv.OR_AND_BOOL, False)
+        P.bfs(0, sr, parents=par, flags=fl)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        lev, _, nl = P.bfs(0, spv.OR_AND_BOOL, parents=False, flags=fl)
+        lev, _, nl = P.bfs(0, sr, parents=par, flags=fl)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3
         out[name] = {"ms": round(ms, 2), "levels": nl, "us_per_level": round(ms * 1e3 / nl, 2),

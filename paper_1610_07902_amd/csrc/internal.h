@@ -50,9 +50,8 @@ struct alignas(256) Ctrl {
     int32_t bfs_mode;       // the selector runs inside a BFS
     int32_t cls;            // class chosen by the selector for the current multiply
     float features[6];      // standardised selector features of the current multiply
-    int32_t gen_count;      // entries drawn by the tuning-input generator / appended by a BFS step
-    int32_t gen_count2;     // second append counter (persistent BFS alternates the two per level)
-    uint32_t pad[28];
+    int32_t gen_count;      // entries drawn by the tuning-input generator / appended by a PageRank step
+    uint32_t pad[29];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -243,12 +242,12 @@ struct PersistArgs {
     Ctrl* ctrl;
     const int32_t* colptr;
     const int32_t* rowids;
-    int32_t* front0;
-    int32_t* front1;
+    int32_t n;               // vertices (square A): the length of every list and bitmap below
+    int32_t* front[3];       // [n] each: frontier lists of three consecutive levels; front[0] on entry and exit
     uint32_t* visited;
-    uint32_t* disc;          // [m/32] discovered-this-level bitmap, zero between levels
-    int32_t* pmin;           // [m] smallest frontier in-neighbour, INT32_MAX between levels
-    uint32_t* bar;           // [2] grid barrier: arrivals, generation
+    uint32_t* disc[3];       // [n/32] each: discovered-at-that-level bitmaps (min-select2nd), zero between launches
+    int32_t* pmin;           // [n] smallest frontier in-neighbour (min-select2nd), INT32_MAX between launches
+    uint32_t* bar;           // [160]: arrivals, three append counters, generation, 32 words apart; zero at launch
 };
 int persistent_grid(int num_cu);
 hipError_t launch_bfs_persistent(const PersistArgs& a, bool min_semiring, int grid, hipStream_t s);

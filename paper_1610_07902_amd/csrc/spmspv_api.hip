@@ -53,7 +53,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
-        heavy, disc, pmin, bar, total;
+        front2, heavy, disc, pmin, bar, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values, selector;
     bool pull, transpose;
@@ -85,10 +85,11 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.visited = take(size_t((m + 31) / 32) * 4);
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
+    L.front2 = take(size_t(m) * 4);
     L.heavy = take(size_t((m + 31) / 32) * 4);
-    L.disc = take(size_t((m + 31) / 32) * 4);
+    L.disc = take(size_t((m + 31) / 32) * 4 * 3);
     L.pmin = take(size_t(m) * 4);
-    L.bar = take(16);
+    L.bar = take(160 * 4);
     L.selector = take(size_t(kMlpParams + 2 * kMlpIn) * 4);
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
@@ -191,11 +192,12 @@ struct spmspv_matrix {
     uint2* buckets = nullptr;
     uint32_t* visited = nullptr;
     uint32_t* heavy = nullptr;
-    uint32_t* disc = nullptr;           // persistent BFS: discovered bitmap
+    uint32_t* disc = nullptr;           // persistent BFS: three discovered-at-level bitmaps of m/32 words
     int32_t* pmin = nullptr;            // persistent BFS: smallest frontier in-neighbour
     uint32_t* bar = nullptr;            // persistent BFS: grid barrier words
     int persist_grid = -1;              // co-resident workgroups of the persistent kernel (0 = unavailable)
     int32_t* front[2] = {nullptr, nullptr};
+    int32_t* front2 = nullptr;          // persistent BFS: third frontier list
     int32_t maxdeg = 0;
     int device = 0;
     int num_cu = 256;
@@ -711,8 +713,18 @@ int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s) {
     return SPMSPV_OK;
 }
 
+// Persistent BFS scratch between launches: bitmaps clear, pmin at INT32_MAX.
+hipError_t reset_persistent_state(spmspv_matrix* A, hipStream_t s) {
+    hipError_t e = launch_fill_u32(A->disc, 0u, 3 * ((A->m + 31) / 32), s);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->pmin), 0x7fffffffu, A->m, s);
+    return e;
+}
+
+// Clears the sticky error bits, and the persistent BFS scratch, which a
+// launch that gave up at a barrier leaves as it was.
 int clear_err(spmspv_matrix* A, hipStream_t s) {
     HIP_TRY(launch_fill_u32(&A->ctrl->err, 0u, 1, s));
+    HIP_TRY(reset_persistent_state(A, s));
     return SPMSPV_OK;
 }
 
@@ -783,6 +795,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->visited = reinterpret_cast<uint32_t*>(A->ws + L.visited);
     A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
     A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
+    A->front2 = reinterpret_cast<int32_t*>(A->ws + L.front2);
     A->heavy = reinterpret_cast<uint32_t*>(A->ws + L.heavy);
     A->disc = reinterpret_cast<uint32_t*>(A->ws + L.disc);
     A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
@@ -814,9 +827,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         return bail(hip_fail(e, "row count scan"));
     if ((e = launch_heavy_rows(A->rcp, (int32_t)m, kHeavyRow, A->heavy, s)) != hipSuccess)
         return bail(hip_fail(e, "heavy rows"));
-    if ((e = launch_fill_u32(A->disc, 0u, (m + 31) / 32, s)) != hipSuccess ||
-        (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->pmin), 0x7fffffffu, m, s)) != hipSuccess ||
-        (e = launch_fill_u32(A->bar, 0u, 4, s)) != hipSuccess)
+    if ((e = reset_persistent_state(A, s)) != hipSuccess || (e = launch_fill_u32(A->bar, 0u, 160, s)) != hipSuccess)
         return bail(hip_fail(e, "persistent BFS state"));
     if (L.pull) {
         A->pull = true;
@@ -1081,13 +1092,14 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         pa.ctrl = A->ctrl;
         pa.colptr = A->colptr;
         pa.rowids = A->rowids;
-        pa.front0 = A->front[0];
-        pa.front1 = A->front[1];
+        pa.n = (int32_t)A->m;
+        pa.front[0] = A->front[0];
+        pa.front[1] = A->front[1];
+        pa.front[2] = A->front2;
         pa.visited = A->visited;
-        pa.disc = A->disc;
+        for (int k = 0; k < 3; ++k) pa.disc[k] = A->disc + k * ((A->m + 31) / 32);
         pa.pmin = A->pmin;
         pa.bar = A->bar;
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->gen_count), 0u, 2, s));   // both counters
     }
     if (learned_gate) {
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
@@ -1102,7 +1114,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
     for (int64_t batch = 0; h.f > 0; ++batch) {
         if (batch * kGraphLevels > A->n + kGraphLevels) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
         if (persist) {
-            HIP_TRY(launch_fill_u32(A->bar, 0u, 1, s));   // arrival counter (a timed-out wait may leave it set)
+            HIP_TRY(launch_fill_u32(A->bar, 0u, 160, s));   // arrivals, append counters, barrier count
             HIP_TRY(launch_bfs_persistent(pa, semiring == SR_MIN_SELECT2ND, A->persist_grid, s));
             const int rc = read_ctrl(A, &h, s);
             if (rc) return rc;

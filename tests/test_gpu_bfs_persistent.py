@@ -79,3 +79,34 @@ def test_persistent_repeated_runs_and_isolated_root(spv):
     for _ in range(2):
         for r in roots:
             check(spv, M, A, r, 1, spv.PERSISTENT)
+
+
+@pytest.mark.parametrize("tail", [0, 1, 2])
+def test_persistent_hand_off_from_every_slot(spv, tail):
+    """The kernel rotates three frontier lists; a frontier that outgrows the
+    persistent range is copied back to the first list unless it already
+    lies there.  A path of `tail` extra vertices in front of an expander
+    shifts the level of the hand-off by one per vertex, so the three cases
+    cover every list the frontier can end in.  The same handle then runs
+    again without the persistent levels and with them, to show the kernel
+    left its scratch state clean."""
+    n0 = 1 << 19
+    rng = np.random.default_rng(11)
+    k = n0 * 8 // 2
+    r = rng.integers(0, n0, k).astype(np.int64)
+    c = rng.integers(0, n0, k).astype(np.int64)
+    # chain n0+tail - ... - n0 - 0 (edges (n0+i, n0+i+1) and (n0, 0))
+    pr = np.concatenate([np.arange(n0, n0 + tail), [n0]]).astype(np.int64)
+    pc = np.concatenate([np.arange(n0 + 1, n0 + tail + 1), [0]]).astype(np.int64)
+    n = n0 + tail + 1
+    rows = np.concatenate([r, c, pr, pc]).astype(np.int32)
+    cols = np.concatenate([c, r, pc, pr]).astype(np.int32)
+    colptr, rowids = synth.coo_to_csc(n, n, rows, cols)
+    A = synth.CSC(n, n, colptr, rowids, None, f"tail{tail}")
+    assert int(np.diff(A.colptr).max()) <= 64
+    M = spv.Matrix.from_csc(A, pattern=True)
+    root = n0 + tail
+    check(spv, M, A, root, 1, spv.PERSISTENT)
+    check(spv, M, A, root, 2, 0)
+    check(spv, M, A, root, 1, spv.PERSISTENT | spv.USE_GRAPH)
+    check(spv, M, A, int(synth.roots(A, 1, seed=tail)[0]), 2, spv.PERSISTENT)
