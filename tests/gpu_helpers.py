@@ -29,7 +29,7 @@ def compare(semiring, g_idx, g_val, o_idx, o_val, sorted_output=False, terms_abs
         ref = ov.astype(np.float64)
         bound = REL_TOL * (np.abs(ref) if terms_abs is None else terms_abs)
         err = np.abs(gv.astype(np.float64) - ref)
-        bad = np.nonzero(err > bound)[0]
+        bad = np.nonzero(~(err <= bound))[0]   # written so that a NaN counts as outside
         assert bad.size == 0, f"{bad.size} values outside tolerance, worst rel {np.max(err / np.maximum(np.abs(ref), 1e-300))}"
     elif semiring == 1:
         bad = np.nonzero(gv.astype(np.int64) != ov.astype(np.int64))[0]
