@@ -420,16 +420,26 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     return SPMSPV_OK;
 }
 
-// Enqueue one pull-direction multiply (three launches).
-int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
-                 const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
-                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, bool bump, bool gate, hipStream_t s,
-                 hipEvent_t* ev, bool rowwise = false) {
+// The pull direction's dense output holds the semiring's identity between
+// calls (every emitted row is reset to it); a change of semiring refills it.
+// Called eagerly before a BFS level graph is captured or replayed too, so a
+// graph never holds the refill: the host's record of the identity would not
+// follow a replay.
+int set_ydense_ident(spmspv_matrix* A, int semiring, hipStream_t s) {
     const uint32_t ident = semiring == SR_MIN_SELECT2ND ? 0x7fffffffu : 0u;
     if (A->ydense_ident != ident) {
         HIP_TRY(launch_fill_ident(A->p_ydense, ident, A->m, s));
         A->ydense_ident = ident;
     }
+    return SPMSPV_OK;
+}
+
+// Enqueue one pull-direction multiply (three launches).
+int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev,
+                 const int32_t* x_idx, const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap,
+                 int64_t* d_nnz_y, bool bfs, const uint32_t* mask, bool bump, bool gate, hipStream_t s,
+                 hipEvent_t* ev, bool rowwise = false) {
+    if (const int rc = set_ydense_ident(A, semiring, s)) return rc;
     PullArgs pa{};
     pa.ctrl = A->ctrl;
     pa.m = (int32_t)A->m;
@@ -1054,6 +1064,10 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         return SPMSPV_OK;
     }
     const bool use_graph = (flags & SPMSPV_USE_GRAPH) != 0;
+    if (use_graph && A->pull) {
+        const int rc = set_ydense_ident(A, semiring, s);
+        if (rc) return rc;
+    }
     const int key = semiring + 1 + (diropt ? 8 : 0) + (learned_gate ? 16 : 0);
     if (use_graph && (A->graph == nullptr || A->graph_key != key)) {
         if (A->graph) {

@@ -151,3 +151,30 @@ def test_direction_optimizing_grid(spv):
     ep = np.where(z > 0, v - nx * nx, np.where(y > 0, v - nx, v - 1))
     ep[0] = 0
     assert np.array_equal(par.cpu().numpy(), ep)
+
+
+def test_pull_identity_kept_across_bfs_graph_replays(spv):
+    """The pull multiply combines rows that straddle two workgroups into a
+    dense buffer that holds the semiring's identity between calls.  Captured
+    BFS level graphs (with min-select2nd pull levels) replayed between
+    plus-times pull calls must leave that buffer as the next call expects."""
+    A = synth.rmat(15, seed=5, symmetrize=True, with_values=False)
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC)
+    roots = synth.roots(A, 2, seed=3)
+    S, xv = synth.sparse_x(A.n, 20000, seed=8)
+
+    def bfs_check(r):
+        lev, par, nl = M.bfs(int(r), spv.MIN_SELECT2ND_I32, flags=spv.USE_GRAPH | spv.DIRECTION_OPT)
+        olev, opar, onl = oracle.bfs(A, int(r))
+        assert nl == onl
+        assert np.array_equal(lev.cpu().numpy(), olev) and np.array_equal(par.cpu().numpy(), opar)
+
+    pull_schedule(spv, M)
+    run_pair(spv, M, A, S, 0, xv)   # plus-times pull: identity 0
+    bfs_check(roots[0])             # captures the level graph
+    run_pair(spv, M, A, S, 0, xv)
+    bfs_check(roots[1])             # replays it
+    run_pair(spv, M, A, S, 0, xv)
+    run_pair(spv, M, A, S, 1, None, flags=spv.X_VAL_IS_INDEX)
+    bfs_check(roots[0])
+    run_pair(spv, M, A, S, 0, xv)
