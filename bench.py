@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--grid-only", action="store_true", help="only the 3-D grid BFS (256^3)")
     ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
     ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
+    ap.add_argument("--bfs-profile", choices=("learned_graph", "learned", "diropt", "push"),
+                    help="only BFS from 4 roots of the held-out graph in one level-loop mode (for rocprofv3)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,6 +96,9 @@ def main():
         return
     if args.grid_only:
         print(json.dumps(grid_bfs_bench(spv, dev)))
+        return
+    if args.bfs_profile:
+        print(json.dumps(bfs_profile(spv, dev, args.bfs_profile, args.selector_scale)))
         return
 
     t0 = time.time()
@@ -508,6 +513,38 @@ def grid_bfs_bench(spv, dev, side=256):
                      "GTEPS": round(nnz / (ms * 1e-3) / 1e9, 3)}
         log(f"grid BFS {name}: {out[name]}")
     out["note"] = "GTEPS = stored entries (every column is expanded once) / time"
+    P.close()
+    return out
+
+
+def bfs_profile(spv, dev, mode, scale=24, nroots=4):
+    """BFS (min-select2nd, parents) on the held-out R-MAT graph of the
+    selector evaluation in one level-loop mode: one untimed run, then
+    `nroots` timed ones.  Small enough to run under a kernel trace."""
+    import torch
+    import synth
+    from paper_1610_07902_amd import selector
+    A = synth.rmat(scale, 16, seed=24, symmetrize=True, with_values=False)
+    P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True, device=dev)
+    params, mean, std, _ = selector.load_weights()
+    P.load_selector(params, mean, std)
+    roots = synth.roots(A, nroots, seed=2000)
+    del A
+    fl = {"learned_graph": spv.USE_SELECTOR | spv.USE_GRAPH, "learned": spv.USE_SELECTOR,
+          "diropt": spv.USE_GRAPH | spv.DIRECTION_OPT, "push": spv.USE_GRAPH}[mode]
+    P.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, flags=fl)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    levels = []
+    for r in roots:
+        _, _, nl = P.bfs(int(r), spv.MIN_SELECT2ND_I32, flags=fl)
+        levels.append(nl)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    out = {"mode": mode, "graph": f"R-MAT scale {scale} ef16 symmetrised", "roots": nroots, "ms": round(ms, 2),
+           "levels": levels}
+    if fl & spv.USE_SELECTOR:
+        out["classes_last_root"] = P.selector_classes()
     P.close()
     return out
 
