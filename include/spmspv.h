@@ -93,7 +93,7 @@ enum spmspv_flags {
                                   graph whose longest column has at most 64
                                   entries: levels with at most 65536 frontier
                                   vertices run in one cooperative persistent
-                                  kernel (two grid barriers per level, direct
+                                  kernel (one grid barrier per level, direct
                                   atomic discovery, same levels and minimum
                                   parents); larger frontiers take the
                                   bucketing levels.  Ignored otherwise        */
