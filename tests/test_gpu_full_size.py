@@ -17,6 +17,8 @@ oracle's dense accumulator takes tens of milliseconds per multiply here.
 * The batched workload (R-MAT scale 20, 64 x with log-uniform sizes) with
   the autotuned batch schedule, every vector against the oracle, and the
   64-source BFS with sampled sources against the queue BFS.
+* BFS on the selector evaluation's held-out R-MAT scale 24 graph through the
+  learned (device-gated and host-read) and heuristic level loops.
 
 The tolerances are those of the other parity tests: bit-exact for int32,
 bool and every index set; fp32 within 1e-5 of the fp64 sum (all inputs are
@@ -217,4 +219,26 @@ def test_full_size_64_source_bfs(spv, s20):
         assert np.array_equal(lev[k], olev)
         assert np.array_equal(par[k], opar)
     assert nl >= onl
+    P.close()
+
+
+def test_full_size_held_out_bfs_learned_and_heuristic(spv):
+    """The selector evaluation's held-out graph (R-MAT scale 24, 16.8M
+    vertices, 521M stored entries): BFS with the trained selector consuming
+    its direction on the device inside the captured level graph, with the
+    host-read selector and with the frontier-edge heuristic, against the
+    queue BFS from one of the evaluation's roots."""
+    from paper_1610_07902_amd import selector
+    A = synth.rmat(24, 16, seed=24, symmetrize=True, with_values=False)
+    assert (A.n, A.nnz) == (16777216, 520757406)
+    P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
+    params, mean, std, _ = selector.load_weights()
+    P.load_selector(params, mean, std)
+    r = int(synth.roots(A, 16, seed=2000)[0])
+    olev, opar, onl = oracle.bfs(A, r)
+    for fl in (spv.USE_SELECTOR | spv.USE_GRAPH, spv.USE_SELECTOR, spv.USE_GRAPH | spv.DIRECTION_OPT):
+        lev, par, nl = P.bfs(r, spv.MIN_SELECT2ND_I32, flags=fl)
+        assert nl == onl
+        assert np.array_equal(to_np(lev), olev)
+        assert np.array_equal(to_np(par), opar)
     P.close()
