@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace spv {
@@ -51,9 +52,20 @@ struct alignas(256) Ctrl {
     int32_t cls;            // class chosen by the selector for the current multiply
     float features[6];      // standardised selector features of the current multiply
     int32_t gen_count;      // entries drawn by the tuning-input generator / appended by a PageRank step
-    uint32_t pad[29];
+    // Direction-switching BFS after a pull level: that level's emit leaves the
+    // next frontier in the pull direction's x bitmap and sums its column
+    // lengths here (chain_ready = 1); the next scan takes the direction
+    // decision itself and publishes chain_word = 2 | direction, which the
+    // decision kernel then consumes instead of deciding again.
+    uint32_t chain_ready;
+    int64_t chain_W;        // stored entries in the columns of that frontier
+    uint32_t chain_word;
+    int32_t chain_max;      // its longest column
+    int32_t chain_fnz;      // its non-empty columns
+    uint32_t pad[23];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
+static_assert(offsetof(Ctrl, chain_W) % 8 == 0, "64-bit atomics need 8-byte alignment");
 
 // Scan phase: gather the selected column ranges, prefix-sum their lengths,
 // compact the non-empty ones and mark where each product chunk starts.
@@ -81,6 +93,14 @@ struct ScanArgs {
     int32_t nb;              // buckets of the current schedule
     int bump_level;          // BFS: advance ctrl->level when f > 0
     int wide;                // 1: tiles of kScanItemsWide items per thread (large or device-known f)
+    // Direction-switching BFS with the pull direction: 1 heuristic, 2
+    // selector (weights in sel), 0 otherwise.  After a pull level the scan
+    // decides the direction itself and builds no tables for a pull level; on
+    // a push level it clears the x bits that pull level left.
+    int chain;
+    const float* sel;
+    int has_pull;
+    uint32_t* xbits;
     // Batched calls: x is the concatenation of nbatch vectors, vector b at
     // positions [xoff[b], xoff[b+1]); xoff[nbatch] (read on the device) is the
     // total length and must not exceed f_cap.
@@ -182,6 +202,12 @@ struct PullArgs {
     int set_f;
     int bump_level;
     int gate;                // 1: skip when ctrl->dir selects push
+    // BFS level of a direction-switching BFS: the emit writes the next
+    // frontier's bitmap over xbits and sums its column lengths (colptr) for
+    // the next decision; prep leaves xbits as the previous emit wrote them.
+    int chain;
+    const int32_t* colptr;
+    int x_index;             // x value = vertex id: read j instead of xdense[j]
 };
 
 constexpr int kPullBlock = 256;
@@ -279,6 +305,6 @@ hipError_t launch_mlp_train_step(float* p, float* am, float* av, int step, float
 hipError_t launch_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
                          int forced, hipStream_t s);
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
+                           uint32_t* xbits, int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s);
 
 }  // namespace spv

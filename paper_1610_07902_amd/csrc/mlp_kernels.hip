@@ -13,16 +13,14 @@
 // thread per sample.  k_select computes the six features of the frontier in
 // the control block and writes the predicted class.
 
-#include "internal.h"
+#include "decide.h"
 
 namespace spv {
 
 namespace {
 
-constexpr int MI = kMlpIn, MH1 = kMlpH1, MH2 = kMlpH2, MO = kMlpOut;
-constexpr int OW1 = 0, OB1 = OW1 + MH1 * MI, OW2 = OB1 + MH1, OB2 = OW2 + MH2 * MH1, OW3 = OB2 + MH2,
-              OB3 = OW3 + MO * MH2;
-static_assert(OB3 + MO == kMlpParams, "parameter layout");
+constexpr int MI = kMI, MH1 = kMH1, MH2 = kMH2, MO = kMO;
+constexpr int OW1 = kOW1, OB1 = kOB1, OW2 = kOW2, OB2 = kOB2, OW3 = kOW3, OB3 = kOB3;
 
 constexpr int TB = 1024;   // threads of the training workgroup
 
@@ -188,60 +186,12 @@ __global__ __launch_bounds__(TB) void k_mlp_train_step(float* p, float* am, floa
 // forced >= 0 replaces the network's decision (a given class sequence).
 __global__ void k_select(Ctrl* ctrl, const float* sel, int32_t n, int64_t nnz, int has_pull, int set_dir,
                          int forced) {
-    __shared__ float feat[MI], h1[MH1], h2[MH2], z[MO];
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t W = __hip_atomic_load(&ctrl->W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t mx = __hip_atomic_load(&ctrl->maxlen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t seen = __hip_atomic_load(&ctrl->seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        seen += ctrl->bfs_mode ? f : 0;
-        __hip_atomic_store(&ctrl->seen, seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double unvisited = ctrl->bfs_mode ? (double)(n - seen) : (double)n;
-        const double raw[MI] = {(double)f, (double)W, (double)mx, (double)n, (double)nnz / (double)n, unvisited};
-        for (int c = 0; c < MI; ++c)
-            feat[c] = ((float)log2(1.0 + raw[c]) - sel[kMlpParams + c]) / sel[kMlpParams + MI + c];
-    }
+    __shared__ int s_done;
+    if (threadIdx.x == 0) s_done = set_dir && ctrl->bfs_mode && consume_chain(ctrl);
     __syncthreads();
-    if (tid < MH1) {
-        float t = sel[OB1 + tid];
-        for (int c = 0; c < MI; ++c) t = fmaf(sel[OW1 + tid * MI + c], feat[c], t);
-        h1[tid] = t > 0.f ? t : 0.f;
-    }
-    __syncthreads();
-    if (tid < MH2) {
-        float t = sel[OB2 + tid];
-        for (int i = 0; i < MH1; ++i) t = fmaf(sel[OW2 + tid * MH1 + i], h1[i], t);
-        h2[tid] = t > 0.f ? t : 0.f;
-    }
-    __syncthreads();
-    if (tid < MO) {
-        float t = sel[OB3 + tid];
-        for (int j = 0; j < MH2; ++j) t = fmaf(sel[OW3 + tid * MH2 + j], h2[j], t);
-        z[tid] = t;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int best = 0;
-        for (int k = 1; k < MO; ++k)
-            if (z[k] > z[best]) best = k;
-        if (forced >= 0 && forced < MO) best = forced;
-        for (int c = 0; c < MI; ++c) ctrl->features[c] = feat[c];
-        const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (set_dir)
-            __hip_atomic_store(&ctrl->dir, (best == MO - 1 && has_pull && f > 0) ? 1 : 0, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        if (best == MO - 1 && has_pull && f > 0) {
-            __hip_atomic_store(&ctrl->maxlen_last, atomicExch(&ctrl->maxlen, 0), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctrl->W_last, __hip_atomic_load(&ctrl->W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctrl->fnz_last,
-                               __hip_atomic_load(&ctrl->fnz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __hip_atomic_store(&ctrl->cls, best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (s_done) return;   // the scan of this BFS level already decided
+    const int32_t f = dc_ld(&ctrl->f), W = dc_ld(&ctrl->W), mx = dc_ld(&ctrl->maxlen), fnz = dc_ld(&ctrl->fnz);
+    select_step(ctrl, sel, n, nnz, has_pull, set_dir, forced, f, W, mx, fnz);
 }
 
 }  // namespace

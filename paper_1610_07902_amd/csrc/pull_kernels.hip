@@ -65,6 +65,9 @@ __global__ __launch_bounds__(256) void k_pull_prep(PullArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.bump_level && f > 0) stc(&a.ctrl->level, ldc(&a.ctrl->level) + 1);
     // the emit look-back words of this call (the previous emit has finished)
     for (int i = blockIdx.x * 256 + threadIdx.x; i < a.emit_blocks; i += gridDim.x * 256) a.lbp[i] = 0;
+    // after a pull level the x bitmap already holds this frontier (its emit
+    // wrote it); the BFS pull reads vertex ids, not xdense
+    if (a.chain && __hip_atomic_load(&a.ctrl->chain_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     // Bitmap words are ORed once per run of lanes sharing a word (a sorted
     // frontier puts up to 32 consecutive lanes on one word, whose atomics
     // would otherwise serialise on one address).
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(256) void k_pull_bfs(PullArgs a) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (in[u] && !stop) {
-                        const uint32_t t = SR == SR_MIN_SELECT2ND ? a.xdense[j[u]] : 1u;
+                        const uint32_t t = SR == SR_MIN_SELECT2ND ? (a.x_index ? j[u] : a.xdense[j[u]]) : 1u;
                         acc = hit ? comb<SR>(acc, t) : t;
                         hit = true;
                         if (FIRST_HIT || SR == SR_OR_AND) stop = true;
@@ -431,10 +434,14 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
     const int f = a.f_dev ? ldc(a.f_dev) : a.f_host;
     const int nw = (a.m + 31) >> 5;
     const int w0 = blockIdx.x * kEmitWords;
-    // clear this call's x bits (every workgroup shares the work)
-    for (int p = blockIdx.x * kEmitBlock + tid; p < f; p += gridDim.x * kEmitBlock) {
-        const int32_t j = a.x_idx[p];
-        if (j >= 0 && j < a.n) a.xbits[j >> 5] = 0u;
+    // Clear this call's x bits (every workgroup shares the work).  In a
+    // direction-switching BFS (chain) every x bitmap word is overwritten with
+    // the next frontier below instead (square A: the same words).
+    if (!a.chain) {
+        for (int p = blockIdx.x * kEmitBlock + tid; p < f; p += gridDim.x * kEmitBlock) {
+            const int32_t j = a.x_idx[p];
+            if (j >= 0 && j < a.n) a.xbits[j >> 5] = 0u;
+        }
     }
     constexpr int PER = kEmitWords / kEmitBlock;
     uint32_t bits[PER];
@@ -444,6 +451,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
         const int w = w0 + tid * PER + k;
         bits[k] = w < nw ? a.ybits[w] : 0u;
         cnt += __popc(bits[k]);
+        if (a.chain && w < nw) a.xbits[w] = bits[k];
     }
     // block exclusive scan of cnt
     const int lane = tid & 63, wid = tid >> 6;
@@ -503,8 +511,16 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
         }
     }
     __syncthreads();
+    int64_t csum = 0;   // chain: column lengths of this workgroup's new frontier vertices
+    int cmax = 0, cnz = 0;
     for (int t = tid; t < tot; t += kEmitBlock) {
         const int r = (w0 << 5) + s_list[t];
+        if (a.chain) {
+            const int d = a.colptr[r + 1] - a.colptr[r];
+            csum += d;
+            cmax = max(cmax, d);
+            cnz += d > 0 ? 1 : 0;
+        }
         const uint32_t v = a.ydense[r];
         a.ydense[r] = ident<SR>();
         const int64_t o = excl + t;
@@ -519,6 +535,21 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
             level[r] = lvl;
             if (parent) parent[r] = (int32_t)v;
         }
+    }
+    if (a.chain) {   // the next level's decision reads these after this kernel
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            csum += __shfl_xor(csum, d, 64);
+            cmax = max(cmax, __shfl_xor(cmax, d, 64));
+            cnz += __shfl_xor(cnz, d, 64);
+        }
+        if (lane == 0 && csum > 0) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl->chain_W), (unsigned long long)csum);
+            atomicMax(&a.ctrl->chain_max, cmax);
+            atomicAdd(&a.ctrl->chain_fnz, cnz);
+        }
+        if (blockIdx.x == 0 && tid == 0)
+            __hip_atomic_store(&a.ctrl->chain_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // the look-back words of this call are cleared by the next k_pull_prep
 }

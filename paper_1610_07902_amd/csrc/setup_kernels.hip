@@ -1,7 +1,7 @@
 // Set-up kernels: run once per matrix (spmspv_create) or once per BFS.
 // Not on the per-multiply path.
 
-#include "internal.h"
+#include "decide.h"
 
 namespace spv {
 
@@ -103,16 +103,23 @@ __global__ __launch_bounds__(kScanBlk) void k_span_apply(int32_t* data, int64_t 
 }
 
 __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy) {
+                           uint32_t* xbits, int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
         level[v] = (v == root) ? 0 : -1;
         if (parent) parent[v] = (v == root) ? root : -1;
     }
     const int64_t nw = ((int64_t)n + 31) >> 5;
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += stride)
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += stride) {
         visited[w] = (w == (root >> 5)) ? (1u << (root & 31)) : 0u;
+        if (xbits) xbits[w] = 0u;   // a BFS that stopped early may have left a pull frontier there
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->chain_ready = 0;
+        ctrl->chain_word = 0;
+        ctrl->chain_W = 0;
+        ctrl->chain_max = 0;
+        ctrl->chain_fnz = 0;
         frontier[0] = root;
         ctrl->f = 1;
         ctrl->level = 0;
@@ -201,26 +208,13 @@ __global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint
     }
 }
 
-// Direction of the next BFS level from the frontier just scanned (Beamer,
-// Asanovic and Patterson's direction-optimizing rule): switch push -> pull
-// when the frontier's stored entries exceed edges_left / 14, pull -> push
-// when the frontier holds fewer than n / 24 vertices.
+// Direction of the next BFS level from the frontier just scanned (the
+// frontier-edge rule of heuristic_step), unless the scan of this level
+// already took the decision.
 __global__ void k_decide(Ctrl* ctrl, int32_t n, int64_t nnz) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int32_t f = __hip_atomic_load(&ctrl->f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t W = __hip_atomic_load(&ctrl->W, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t prev = __hip_atomic_load(&ctrl->dir, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t policy = __hip_atomic_load(&ctrl->policy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int64_t left = __hip_atomic_load(&ctrl->edges_left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int dir = 0;
-    if (policy == 1) {
-        if (prev == 0) dir = ((int64_t)W * 14 > left) ? 1 : 0;
-        else dir = ((int64_t)f * 24 < (int64_t)n) ? 0 : 1;
-    }
-    left -= W;
-    if (left < 0) left = 0;
-    __hip_atomic_store(&ctrl->edges_left, left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ctrl->dir, dir, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (consume_chain(ctrl)) return;
+    heuristic_step(ctrl, n, dc_ld(&ctrl->f), dc_ld(&ctrl->W));
     (void)nnz;
 }
 
@@ -276,9 +270,9 @@ hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s) {
 }
 
 hipError_t launch_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* parent, uint32_t* visited,
-                           int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s) {
+                           uint32_t* xbits, int32_t* frontier, Ctrl* ctrl, int64_t nnz, int policy, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_init, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, n, root, level, parent,
-                       visited, frontier, ctrl, nnz, policy);
+                       visited, xbits, frontier, ctrl, nnz, policy);
     return hipGetLastError();
 }
 

@@ -344,6 +344,14 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     sa.lb3 = A->lb3;
     sa.nb = clear_nb > nb ? clear_nb : nb;
     sa.bump_level = bfs ? 1 : 0;
+    // A direction-switching BFS level: after a pull level the scan takes the
+    // decision itself (see the pull emit's chain mode).
+    if (bfs && diropt && A->pull && f_dev) {
+        sa.chain = learned_gate ? 2 : 1;
+        sa.sel = A->selector;
+        sa.has_pull = 1;
+        sa.xbits = A->p_xbits;
+    }
     // f known on the host: one workgroup per tile, narrow tiles unless that
     // would take more than two workgroups per compute unit.  f on the device
     // (BFS): a fixed grid of wide tiles loops over the frontier.
@@ -469,6 +477,11 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     pa.set_f = bfs ? 1 : 0;
     pa.bump_level = bump ? 1 : 0;
     pa.gate = gate ? 1 : 0;
+    if (bfs && gate) {   // level of a direction-switching BFS (square A)
+        pa.chain = 1;
+        pa.colptr = A->colptr;
+        pa.x_index = xmode == XV_INDEX ? 1 : 0;
+    }
     const bool early = semiring == SR_OR_AND || (semiring == SR_MIN_SELECT2ND && xmode == XV_INDEX && A->rows_sorted);
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_pull(pa, semiring, xmode, bfs, early, bfs || rowwise, s));
@@ -1037,7 +1050,8 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
 
     if (selector && !learned_gate) {
         // One host read per level: scan, device-side inference, chosen path.
-        HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz, 0, s));
+        HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->p_xbits, A->front[0], A->ctrl,
+                                A->nnz, 0, s));
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 1u, 1, s));
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->seen), 0u, 2, s));
         A->level_classes.clear();
@@ -1094,7 +1108,7 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         }
         A->graph_key = key;
     }
-    HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->front[0], A->ctrl, A->nnz,
+    HIP_TRY(launch_bfs_init((int32_t)A->n, root, level, parent, A->visited, A->p_xbits, A->front[0], A->ctrl, A->nnz,
                             diropt ? 1 : 0, s));
     // Small frontiers of a low-degree graph run in the persistent kernel;
     // larger ones in batches of the bucketing levels below.

@@ -34,7 +34,7 @@
 
 #include <hip/hip_ext.h>
 
-#include "internal.h"
+#include "decide.h"
 
 namespace spv {
 
@@ -181,7 +181,7 @@ __device__ __forceinline__ uint32_t x_value(const void* x_val, int p, int32_t j)
     else return 1u;
 }
 
-template <int BLOCK, int ITEMS, int XMODE, bool BATCH>
+template <int BLOCK, int ITEMS, int XMODE, bool BATCH, bool CHAIN>
 __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     constexpr int TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_tmp[BLOCK / kWave + 1];
@@ -223,6 +223,51 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         }
     }
     if (tid == 0) s_max = 0;
+    bool clear_x = false;   // push level after a pull level: clear the x bits that level left
+    if constexpr (CHAIN) {
+        // Direction-switching BFS after a pull level: that level's emit left
+        // this frontier's column sums in the control block, so the decision
+        // is taken here (workgroup 0, published with one word) and a level
+        // that stays pull needs no column tables.
+        if (a.chain && __hip_atomic_load(&a.ctrl->chain_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __shared__ int s_dir;
+            if (blockIdx.x == 0) {
+                const int32_t W = (int32_t)__hip_atomic_load(&a.ctrl->chain_W, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                const int32_t mx = ld_ctrl(&a.ctrl->chain_max), nz = ld_ctrl(&a.ctrl->chain_fnz);
+                int dir;
+                if (a.chain == 2) {
+                    dir = select_step(a.ctrl, a.sel, a.n, a.nnz, a.has_pull, 1, -1, f, W, mx, nz);
+                } else {
+                    if (tid == 0) s_dir = heuristic_step(a.ctrl, a.n, f, W);
+                    __syncthreads();
+                    dir = s_dir;
+                }
+                if (tid == 0) {
+                    st_ctrl(&a.ctrl->W, W);
+                    st_ctrl(&a.ctrl->fnz, nz);
+                    st_ctrl_u(&a.ctrl->chain_word, 2u | (uint32_t)dir);
+                    s_dir = dir;
+                }
+            } else if (tid == 0) {
+                uint32_t w;
+                int spins = 0;
+                while (!((w = __hip_atomic_load(&a.ctrl->chain_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                         2u)) {
+                    if (++spins > kSpinMax) {
+                        atomicOr(&a.ctrl->err, ERR_SPIN);
+                        w = 3u;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                s_dir = (int)(w & 1u);
+            }
+            __syncthreads();
+            if (s_dir) return;
+            clear_x = true;
+        }
+    }
     const int ntiles = (f + TILE - 1) / TILE;
     const int64_t chunk = 1ll << a.chunk_log2;
     int lmax = 0;
@@ -239,6 +284,11 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         // values) so every thread has all its gathers in flight at once.
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) jj[i] = (p0 + i < f) ? a.x_idx[p0 + i] : -1;
+        if (CHAIN && clear_x) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (jj[i] >= 0 && jj[i] < a.n) a.xbits[jj[i] >> 5] = 0u;
+        }
         bool bad = false;
         int32_t b0[ITEMS], b1[ITEMS];
 #pragma unroll
@@ -930,20 +980,20 @@ static void launch_k(K kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, c
     else hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
 }
 
-template <int ITEMS, bool BATCH>
+template <int ITEMS, bool BATCH, bool CHAIN = false>
 static hipError_t scan_mode(const ScanArgs& a, int grid, hipStream_t s, const LaunchEvents* ev) {
     switch (a.xmode) {
         case XV_BITS32:
-            launch_k(k_scan<kScanBlock, ITEMS, XV_BITS32, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_BITS32, BATCH, CHAIN>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_INDEX:
-            launch_k(k_scan<kScanBlock, ITEMS, XV_INDEX, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_INDEX, BATCH, CHAIN>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_U8:
-            launch_k(k_scan<kScanBlock, ITEMS, XV_U8, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_U8, BATCH, CHAIN>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         case XV_TRUE:
-            launch_k(k_scan<kScanBlock, ITEMS, XV_TRUE, BATCH>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
+            launch_k(k_scan<kScanBlock, ITEMS, XV_TRUE, BATCH, CHAIN>, dim3(grid), dim3(kScanBlock), 0, s, ev, a);
             break;
         default:
             return hipErrorInvalidValue;
@@ -959,6 +1009,10 @@ hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t s, const LaunchE
     if (a.xoff) {
         if (a.nbatch < 1 || a.nbatch > kMaxBatch || !a.cxid || !a.kcount) return hipErrorInvalidValue;
         return scan_mode<kScanItemsWide, true>(a, grid, s, ev);
+    }
+    if (a.chain) {
+        if (!a.f_dev || !a.xbits || (a.chain == 2 && !a.sel)) return hipErrorInvalidValue;
+        return scan_mode<kScanItemsWide, false, true>(a, grid, s, ev);
     }
     if (a.f_dev || a.wide) return scan_mode<kScanItemsWide, false>(a, grid, s, ev);
     return scan_mode<kScanItems, false>(a, grid, s, ev);
