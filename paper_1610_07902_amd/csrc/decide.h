@@ -1,7 +1,7 @@
 // Direction (and selector class) of a BFS level, shared by the decision
 // kernels (k_decide, k_select) and by the scan, which takes the decision
-// itself when the previous level ran pull and left the new frontier's
-// figures in the control block.  Not installed.
+// itself when the previous level ran pull and its emit left the new
+// frontier's column sums behind.  Not installed.
 #pragma once
 
 #include "internal.h"
@@ -113,13 +113,9 @@ __device__ inline int select_step(Ctrl* ctrl, const float* sel, int32_t n, int64
 
 // Called first by the decision kernels of a direction-switching BFS level:
 // when the scan already decided (chain_word = 2 | direction), consume that
-// decision (a push level ends the chain) and return true.  The column sums
-// the next pull emit accumulates start from zero either way.
+// decision (a push level ends the chain) and return true.
 __device__ inline bool consume_chain(Ctrl* ctrl) {
     const uint32_t w = __hip_atomic_load(&ctrl->chain_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    dc_st64(&ctrl->chain_W, 0);
-    dc_st(&ctrl->chain_max, 0);
-    dc_st(&ctrl->chain_fnz, 0);
     if (!(w & 2u)) return false;
     if (!(w & 1u)) __hip_atomic_store(&ctrl->chain_ready, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ctrl->chain_word, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -53,19 +53,16 @@ struct alignas(256) Ctrl {
     float features[6];      // standardised selector features of the current multiply
     int32_t gen_count;      // entries drawn by the tuning-input generator / appended by a PageRank step
     // Direction-switching BFS after a pull level: that level's emit leaves the
-    // next frontier in the pull direction's x bitmap and sums its column
-    // lengths here (chain_ready = 1); the next scan takes the direction
-    // decision itself and publishes chain_word = 2 | direction, which the
-    // decision kernel then consumes instead of deciding again.
+    // next frontier in the pull direction's x bitmap and per-workgroup sums
+    // of its column lengths in the pull workspace (chain_ready = 1); the next
+    // scan takes the direction decision itself and publishes chain_word =
+    // 2 | direction, which the decision kernel then consumes instead of
+    // deciding again.
     uint32_t chain_ready;
-    int64_t chain_W;        // stored entries in the columns of that frontier
     uint32_t chain_word;
-    int32_t chain_max;      // its longest column
-    int32_t chain_fnz;      // its non-empty columns
-    uint32_t pad[23];
+    uint32_t pad[27];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
-static_assert(offsetof(Ctrl, chain_W) % 8 == 0, "64-bit atomics need 8-byte alignment");
 
 // Scan phase: gather the selected column ranges, prefix-sum their lengths,
 // compact the non-empty ones and mark where each product chunk starts.
@@ -101,6 +98,8 @@ struct ScanArgs {
     const float* sel;
     int has_pull;
     uint32_t* xbits;
+    const int64_t* chain_part;   // [2 * chain_nparts] the previous emit's per-workgroup column sums
+    int32_t chain_nparts;
     // Batched calls: x is the concatenation of nbatch vectors, vector b at
     // positions [xoff[b], xoff[b+1]); xoff[nbatch] (read on the device) is the
     // total length and must not exceed f_cap.
@@ -207,6 +206,7 @@ struct PullArgs {
     // the next decision; prep leaves xbits as the previous emit wrote them.
     int chain;
     const int32_t* colptr;
+    int64_t* chain_part;     // [2 * emit_blocks]: per workgroup, stored entries and (longest << 32 | non-empty)
     int x_index;             // x value = vertex id: read j instead of xdense[j]
 };
 

@@ -536,20 +536,31 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(PullArgs a) {
             if (parent) parent[r] = (int32_t)v;
         }
     }
-    if (a.chain) {   // the next level's decision reads these after this kernel
+    if (a.chain) {   // this workgroup's sums, read by the next level's scan (a later kernel)
+        __shared__ int64_t s_sum[kEmitBlock / 64];
+        __shared__ int s_mx[kEmitBlock / 64], s_nz[kEmitBlock / 64];
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
             csum += __shfl_xor(csum, d, 64);
             cmax = max(cmax, __shfl_xor(cmax, d, 64));
             cnz += __shfl_xor(cnz, d, 64);
         }
-        if (lane == 0 && csum > 0) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctrl->chain_W), (unsigned long long)csum);
-            atomicMax(&a.ctrl->chain_max, cmax);
-            atomicAdd(&a.ctrl->chain_fnz, cnz);
+        if (lane == 0) {
+            s_sum[wid] = csum;
+            s_mx[wid] = cmax;
+            s_nz[wid] = cnz;
         }
-        if (blockIdx.x == 0 && tid == 0)
-            __hip_atomic_store(&a.ctrl->chain_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kEmitBlock / 64; ++w) {
+                csum += s_sum[w];
+                cmax = max(cmax, s_mx[w]);
+                cnz += s_nz[w];
+            }
+            a.chain_part[2 * blockIdx.x] = csum;
+            a.chain_part[2 * blockIdx.x + 1] = ((int64_t)cmax << 32) | (uint32_t)cnz;
+            if (blockIdx.x == 0) __hip_atomic_store(&a.ctrl->chain_ready, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     // the look-back words of this call are cleared by the next k_pull_prep
 }

@@ -117,9 +117,6 @@ __global__ void k_bfs_init(int32_t n, int32_t root, int32_t* level, int32_t* par
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->chain_ready = 0;
         ctrl->chain_word = 0;
-        ctrl->chain_W = 0;
-        ctrl->chain_max = 0;
-        ctrl->chain_fnz = 0;
         frontier[0] = root;
         ctrl->f = 1;
         ctrl->level = 0;

@@ -55,7 +55,7 @@ struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
         front2, heavy, disc, pmin, bar, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
-    size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, t_colids, t_values, selector;
+    size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose;
     int64_t nb_max, lb1_n, chunk_n;
 };
@@ -100,6 +100,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
         L.p_ydense = take(size_t(m) * 4);
         L.p_lbp = take(size_t(pull_emit_blocks((int32_t)m) + 1) * 8);
         L.p_part = take(size_t(pull_blocks((int32_t)m, nnz) + 2) * 4);
+        L.p_chain = take(size_t(pull_emit_blocks((int32_t)m)) * 16);
     }
     if (L.transpose) {
         L.t_colids = take(size_t(nnz + 1) * 4);
@@ -221,6 +222,7 @@ struct spmspv_matrix {
     uint32_t* p_xdense = nullptr;
     uint32_t* p_ybits = nullptr;
     uint32_t* p_ydense = nullptr;
+    int64_t* p_chain = nullptr;         // direction-switching BFS: the pull emit's per-workgroup column sums
     uint64_t* p_lbp = nullptr;
     int32_t* p_part = nullptr;
     uint32_t ydense_ident = 0;
@@ -351,6 +353,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
         sa.sel = A->selector;
         sa.has_pull = 1;
         sa.xbits = A->p_xbits;
+        sa.chain_part = A->p_chain;
+        sa.chain_nparts = pull_emit_blocks((int32_t)A->m);
     }
     // f known on the host: one workgroup per tile, narrow tiles unless that
     // would take more than two workgroups per compute unit.  f on the device
@@ -480,6 +484,7 @@ int enqueue_pull(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     if (bfs && gate) {   // level of a direction-switching BFS (square A)
         pa.chain = 1;
         pa.colptr = A->colptr;
+        pa.chain_part = A->p_chain;
         pa.x_index = xmode == XV_INDEX ? 1 : 0;
     }
     const bool early = semiring == SR_OR_AND || (semiring == SR_MIN_SELECT2ND && xmode == XV_INDEX && A->rows_sorted);
@@ -860,6 +865,7 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         A->p_ydense = reinterpret_cast<uint32_t*>(A->ws + L.p_ydense);
         A->p_lbp = reinterpret_cast<uint64_t*>(A->ws + L.p_lbp);
         A->p_part = reinterpret_cast<int32_t*>(A->ws + L.p_part);
+        A->p_chain = reinterpret_cast<int64_t*>(A->ws + L.p_chain);
         // every pull region up to the transpose starts at zero (ydense = identity of + and or)
         const size_t zb = L.p_xbits, ze = L.transpose ? L.t_colids : L.total;
         if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + zb), 0u, int64_t((ze - zb) / 4), s)) != hipSuccess)

@@ -232,9 +232,37 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         if (a.chain && __hip_atomic_load(&a.ctrl->chain_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             __shared__ int s_dir;
             if (blockIdx.x == 0) {
-                const int32_t W = (int32_t)__hip_atomic_load(&a.ctrl->chain_W, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t mx = ld_ctrl(&a.ctrl->chain_max), nz = ld_ctrl(&a.ctrl->chain_fnz);
+                // the frontier's column sums from the emit's per-workgroup partials
+                int64_t ws = 0;
+                int32_t wm = 0, wz = 0;
+                for (int b = tid; b < a.chain_nparts; b += BLOCK) {
+                    ws += a.chain_part[2 * b];
+                    const int64_t mz = a.chain_part[2 * b + 1];
+                    wm = max(wm, (int32_t)(mz >> 32));
+                    wz += (int32_t)(uint32_t)mz;
+                }
+                __shared__ int64_t s_ws[BLOCK / kWave];
+                __shared__ int32_t s_wm[BLOCK / kWave], s_wz[BLOCK / kWave];
+#pragma unroll
+                for (int d = kWave / 2; d >= 1; d >>= 1) {
+                    ws += __shfl_xor(ws, d, kWave);
+                    wm = max(wm, __shfl_xor(wm, d, kWave));
+                    wz += __shfl_xor(wz, d, kWave);
+                }
+                if ((tid & (kWave - 1)) == 0) {
+                    s_ws[tid / kWave] = ws;
+                    s_wm[tid / kWave] = wm;
+                    s_wz[tid / kWave] = wz;
+                }
+                __syncthreads();
+                int64_t Wt = 0;
+                int32_t mx = 0, nz = 0;
+                for (int w = 0; w < BLOCK / kWave; ++w) {
+                    Wt += s_ws[w];
+                    mx = max(mx, s_wm[w]);
+                    nz += s_wz[w];
+                }
+                const int32_t W = (int32_t)Wt;
                 int dir;
                 if (a.chain == 2) {
                     dir = select_step(a.ctrl, a.sel, a.n, a.nnz, a.has_pull, 1, -1, f, W, mx, nz);
