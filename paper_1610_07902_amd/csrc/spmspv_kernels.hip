@@ -202,6 +202,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     } else {
         f = a.f_dev ? ld_ctrl(a.f_dev) : a.f_host;
     }
+    // issued with the frontier length so the two round trips overlap
+    uint32_t chain_ready = 0;
+    if constexpr (CHAIN)
+        chain_ready = a.chain ? __hip_atomic_load(&a.ctrl->chain_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     uint64_t* lb_sum = a.lb1;
     uint64_t* lb_cnt = a.lb1 + a.lb1_n;
 
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         // this frontier's column sums in the control block, so the decision
         // is taken here (workgroup 0, published with one word) and a level
         // that stays pull needs no column tables.
-        if (a.chain && __hip_atomic_load(&a.ctrl->chain_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        if (chain_ready) {
             __shared__ int s_dir;
             if (blockIdx.x == 0) {
                 // the frontier's column sums from the emit's per-workgroup partials
