@@ -178,3 +178,59 @@ def test_pull_identity_kept_across_bfs_graph_replays(spv):
     run_pair(spv, M, A, S, 1, None, flags=spv.X_VAL_IS_INDEX)
     bfs_check(roots[0])
     run_pair(spv, M, A, S, 0, xv)
+
+
+def _two_clusters(nc=20000, deg=32, path=40, seed=13):
+    """Two random clusters joined by a path: a BFS from the first cluster
+    goes push, pull (the cluster), push (the path), pull (the second
+    cluster)."""
+    rng = np.random.default_rng(seed)
+    k = nc * deg // 2
+    parts = []
+    for base in (0, nc + path):
+        r = rng.integers(0, nc, k) + base
+        c = rng.integers(0, nc, k) + base
+        parts.append((r, c))
+    pr = np.arange(nc, nc + path)                       # path vertices
+    parts.append((np.concatenate([[0], pr]), np.concatenate([pr, [nc + path]])))
+    rows = np.concatenate([p[0] for p in parts] + [p[1] for p in parts]).astype(np.int32)
+    cols = np.concatenate([p[1] for p in parts] + [p[0] for p in parts]).astype(np.int32)
+    n = 2 * nc + path
+    colptr, rowids = synth.coo_to_csc(n, n, rows, cols)
+    return synth.CSC(n, n, colptr, rowids, None, "two-clusters")
+
+
+def _heuristic_directions(A, olev):
+    """The frontier-edge rule (push -> pull when 14 W > edges left, pull ->
+    push when 24 f < n) replayed on the oracle's levels."""
+    deg = np.diff(A.colptr).astype(np.int64)
+    left, prev, dirs = int(A.nnz), 0, []
+    for L in range(int(olev.max()) + 1):
+        F = np.nonzero(olev == L)[0]
+        f, W = F.size, int(deg[F].sum())
+        d = (1 if W * 14 > left else 0) if prev == 0 else (0 if f * 24 < A.n else 1)
+        left = max(left - W, 0)
+        dirs.append(d)
+        prev = d
+    return dirs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_direction_switches_back_and_forth(spv, graph):
+    """Pull levels in a row, then push levels, then pull again in one BFS:
+    the scan-free pull chain, its hand-back to push (tables rebuilt, x bits
+    cleared) and a fresh pull phase."""
+    A = _two_clusters()
+    root = 5
+    olev, opar, onl = oracle.bfs(A, root)
+    dirs = "".join(map(str, _heuristic_directions(A, olev)))
+    assert "11" in dirs and "10" in dirs and dirs.count("01") >= 2, dirs   # the graph does exercise it
+    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC)
+    fl = spv.DIRECTION_OPT | (spv.USE_GRAPH if graph else 0)
+    for _ in range(2):
+        lev, par, nl = M.bfs(root, spv.MIN_SELECT2ND_I32, flags=fl)
+        assert nl == onl
+        assert np.array_equal(lev.cpu().numpy(), olev)
+        assert np.array_equal(par.cpu().numpy(), opar)
+        lev2, _, nl2 = M.bfs(root, spv.OR_AND_BOOL, flags=fl)
+        assert nl2 == onl and np.array_equal(lev2.cpu().numpy(), olev)
