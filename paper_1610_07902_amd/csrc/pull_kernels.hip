@@ -385,7 +385,9 @@ __global__ __launch_bounds__(256) void k_pull_bfs(PullArgs a) {
 // -------------------------------------------------------------- emit y
 // Walks ybits in order, kEmitWords words per workgroup, and writes y with a
 // decoupled look-back for the offsets.  Resets ybits / ydense for the next
-// call and clears the x bits this call set.
+// call and clears the x bits this call set; in a direction-switching BFS it
+// writes the new frontier over the x bits instead and leaves per-workgroup
+// sums of its column lengths for the next level's decision.
 constexpr int kEmitBlock = 256;
 constexpr int kEmitWords = 1024;
 

@@ -16,10 +16,12 @@
 //             is reserved with one atomic per (chunk, bucket), which plays
 //             the role of Algorithm 2's per-thread Boffset prefix.
 //   k_merge   (steps c, d) gives each bucket one workgroup and an LDS-resident
-//             sparse accumulator over the bucket's rows.  First touch of a
-//             row is found with an LDS atomic on a row bitmap and counted by
-//             wavefront ballot; only touched accumulator cells are
-//             initialised (Algorithm 1, step 2).  The per-bucket unique
+//             sparse accumulator over the bucket's rows.  Every cell of the
+//             tile is initialised with wide stores (on the GPU cheaper than
+//             the first-touch test that Algorithm 1's partial
+//             initialisation needs); touched rows are marked in an LDS row
+//             bitmap, whose population count is the bucket's number of
+//             unique rows.  The per-bucket unique
 //             counts are prefix-summed across workgroups by decoupled
 //             look-back, and each workgroup writes its rows straight to y
 //             (Algorithm 1, step 3), ascending when sorted output is asked
@@ -230,9 +232,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     bool clear_x = false;   // push level after a pull level: clear the x bits that level left
     if constexpr (CHAIN) {
         // Direction-switching BFS after a pull level: that level's emit left
-        // this frontier's column sums in the control block, so the decision
-        // is taken here (workgroup 0, published with one word) and a level
-        // that stays pull needs no column tables.
+        // per-workgroup sums of this frontier's column lengths, so the
+        // decision is taken here (workgroup 0 adds them up and publishes the
+        // direction in one word) and a level that stays pull needs no column
+        // tables.
         if (chain_ready) {
             __shared__ int s_dir;
             if (blockIdx.x == 0) {
