@@ -35,3 +35,25 @@ def test_profiles_name_the_kernels_bench_reads():
     assert len(tc["source_digest"]) == 16
     for k in ("scan", "scatter", "merge"):
         assert tc["kernels"][k]["fetch_bytes"] > 0 and tc["kernels"][k]["write_bytes"] > 0
+
+
+def test_profile_commands_run_committed_code_with_known_flags():
+    """Every rocprofv3 summary under profiles/ gives the command that made it;
+    each must run bench.py from this repository with options it accepts."""
+    import glob
+    import re
+    sys.path.insert(0, ROOT)
+    import bench
+    parser_src = open(os.path.join(ROOT, "bench.py")).read()
+    known = set(re.findall(r'add_argument\("(--[a-z0-9-]+)"', parser_src))
+    summaries = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")))
+    assert summaries
+    for path in summaries:
+        text = open(path).read()
+        cmds = re.findall(r"python3 \$REPO/(\S+)((?: --?[\w-]+(?: [\w.]+)?)*)", text)
+        assert cmds, f"{os.path.basename(path)} names no command"
+        for script, args in cmds:
+            assert script == "bench.py" and os.path.exists(os.path.join(ROOT, script))
+            for flag in re.findall(r"(--[a-z0-9-]+)", args):
+                assert flag in known, f"{os.path.basename(path)}: bench.py has no {flag}"
+    assert callable(bench.kernel_source_digest)
