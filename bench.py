@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--grid-only", action="store_true", help="only the 3-D grid BFS (256^3)")
     ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
     ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the density sweep (push and pull) on the headline graph (for rocprofv3)")
     ap.add_argument("--bfs-profile", choices=("learned_graph", "learned", "diropt", "push"),
                     help="only BFS from 4 roots of the held-out graph in one level-loop mode (for rocprofv3)")
     args = ap.parse_args()
@@ -106,6 +108,9 @@ def main():
     log(f"generated {A.name}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
     M = spv.Matrix.from_csc(A, device=dev, flags=spv.WITH_TRANSPOSE)
     deg = A.degrees()
+    if args.sweep_only:
+        print(json.dumps({"sweep": sweep(spv, M, A, deg, dev, torch.cuda.current_stream())}))
+        return
     f = synth.density_f(A.n, args.density)
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in range(args.nx)]
     W = np.array([int(deg[x[0]].sum()) for x in xs], np.int64)
