@@ -40,8 +40,12 @@ extern "C" {
 typedef struct spmspv_matrix* spmspv_handle;
 
 /* Semirings (Algorithm 1's Mult / Add pair).
- *   PLUS_TIMES_F32     : Mult = a*x (fp32, rounded), Add = + (fp32).
- *                        A values float, x float, y float.
+ *   PLUS_TIMES_F32     : Mult = a*x (fp32, rounded), Add = +.
+ *                        A values float, x float, y float.  Each product
+ *                        is rounded to fp32; a row's products are summed
+ *                        in fp64 (in any order) and the sum is rounded to
+ *                        fp32 once, so |y - exact| <= 2^-24 |exact| plus
+ *                        k * 2^-53 * sum|terms| for a row of k terms.
  *   MIN_SELECT2ND_I32  : Mult = select2nd(a, x) = x, Add = min.
  *                        A values ignored, x int32, y int32.
  *   OR_AND_BOOL        : Mult = (a != 0) AND (x != 0), Add = OR.
@@ -120,7 +124,9 @@ enum spmspv_flags {
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any
- * output index set; fp32 plus-times sums may differ in rounding order.   */
+ * output index set; fp32 plus-times sums may differ in rounding order.
+ * Plus-times calls merge in fp64 cells: a schedule tile above 2^14 rows
+ * runs as 2^14 for them.                                                 */
 typedef struct {
     int direction;      /* 0 = push (vector-driven, Algorithm 1); 1 = pull
                            (matrix-driven: scan every row of A against x;
@@ -334,9 +340,11 @@ int spmspv_run_batch(spmspv_handle A, int semiring, int flags, int nbatch, const
                      int64_t y_capacity, int64_t* h_nnz_total, void* stream);
 
 /* Schedule for batched calls (tile_log2 is the starting tile; NULL restores
- * the handle's schedule) and the effective one for nbatch vectors.       */
+ * the handle's schedule) and the effective one for nbatch vectors of the
+ * given semiring (plus-times merges in fp64 cells, so its tiles hold at
+ * most 2^14 rows; see spmspv_schedule).                                   */
 int spmspv_set_batch_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
-int spmspv_get_batch_schedule(spmspv_handle A, int nbatch, spmspv_schedule* h_sched);
+int spmspv_get_batch_schedule(spmspv_handle A, int semiring, int nbatch, spmspv_schedule* h_sched);
 
 /* Multi-source BFS: nsrc independent searches from h_roots[0..nsrc) run as
  * one batched SpMSpV per level (the frontiers of all sources form one

@@ -112,7 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_batch_attach.argtypes = [vp, ci, i64, i64, ci, vp, sz, vp]
     lib.spmspv_run_batch.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.spmspv_set_batch_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
-    lib.spmspv_get_batch_schedule.argtypes = [vp, ci, ctypes.POINTER(Schedule)]
+    lib.spmspv_get_batch_schedule.argtypes = [vp, ci, ci, ctypes.POINTER(Schedule)]
     lib.msbfs_run.argtypes = [vp, ci, ci, vp, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_autotune.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_double), ci, ci, vp, vp, vp, vp,
                                     ctypes.POINTER(TuneEntry), vp]
@@ -267,9 +267,9 @@ def spmspv_set_batch_schedule(handle, sched: Optional[Schedule] = None):
     _check(load_library().spmspv_set_batch_schedule(handle, ctypes.byref(sched) if sched is not None else None))
 
 
-def spmspv_get_batch_schedule(handle, nbatch) -> Schedule:
+def spmspv_get_batch_schedule(handle, nbatch, semiring=0) -> Schedule:
     sc = Schedule()
-    _check(load_library().spmspv_get_batch_schedule(handle, int(nbatch), ctypes.byref(sc)))
+    _check(load_library().spmspv_get_batch_schedule(handle, int(semiring), int(nbatch), ctypes.byref(sc)))
     return sc
 
 

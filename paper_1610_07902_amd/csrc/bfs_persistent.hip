@@ -64,12 +64,18 @@ __device__ __forceinline__ void stcu(uint32_t* p, uint32_t v) {
 // cache maintenance, so the barrier only has to wait for this workgroup's
 // own memory operations to complete: no L2 write-back or invalidation (which
 // on a multi-die GPU would touch the whole L2 of a die at every barrier).
+// That wait is explicit: a workgroup-scope fence does not wait for vector
+// memory operations on gfx950 (the waves of a workgroup share one CU), so
+// every wave waits for its own outstanding loads, stores and atomics
+// (s_waitcnt vmcnt(0)) before the workgroup barrier, and only then does
+// thread 0 publish the arrival.
 // A wait past kSpinLimit polls sets ERR_SPIN and returns false; the caller
 // then leaves the kernel, so every later barrier of the others times out
 // too and no wave can hang.
 __device__ bool grid_sync(uint32_t* bar, uint32_t& gen, uint32_t* err) {
     __shared__ int s_ok;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wait_vmem();
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;

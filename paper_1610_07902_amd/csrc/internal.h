@@ -10,6 +10,12 @@ namespace spv {
 
 constexpr int kWave = 64;
 
+// Wait until every vector memory operation this wave has issued (loads,
+// stores, atomics) has completed: s_waitcnt with vmcnt = 0 and the other
+// counters at their maximum (gfx9 encoding: vmcnt bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Device error bits (Ctrl::err), sticky until the host reads them.
 enum : uint32_t {
     ERR_X_RANGE = 1u,          // an x index outside [0, n)
@@ -159,7 +165,6 @@ struct MergeArgs {
     int64_t y_cap;
     int64_t* d_nnz_y;        // nullable
     uint32_t* visited;       // BFS: visited bitmap, updated with new vertices
-    const uint32_t* heavy;   // [m/32] rows with at least kHeavyRow stored entries
     int set_f;               // BFS: publish nnz(y) as the next frontier length
     int gate;                // 1: skip when ctrl->dir selects pull
     // Batched calls (key = vector * nbx + bucket)
@@ -226,7 +231,7 @@ hipError_t launch_fill_ident(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int pull_emit_blocks(int32_t m);
 int pull_blocks(int32_t m, int64_t nnz);
 
-size_t merge_lds_bytes(int tile_log2);
+size_t merge_lds_bytes(int tile_log2, int semiring);
 size_t scatter_lds_bytes(int nb, int chunk, bool batch = false);
 constexpr int kMaxBatch = 1024;    // vectors per batched call
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
@@ -253,12 +258,17 @@ constexpr int kScanItems = 2;         // host-known f: one tile per workgroup
 constexpr int kScanItemsWide = 8;     // device-known f or batched: looping grid
 constexpr int kScanTile = kScanBlock * kScanItems;   // smallest tile (sizes look-back arrays)
 constexpr int kMergeItems = 8;
-constexpr int kHeavyRow = 2048;    // rows with this many stored entries may be collapsed per wave
 constexpr int kMergeList = 8192;   // rows staged per round of the in-order bitmap walk (largest tiles)
-constexpr int kTileLog2Cap = 15;   // widest merge tile (2^15 rows) the LDS holds
-// Rows the merge's LDS list holds: the whole tile up to 2^14 rows.
-__host__ __device__ inline int merge_list_cap(int tile_log2) {
-    return tile_log2 <= 14 ? (1 << tile_log2) : kMergeList;
+constexpr int kTileLog2Cap = 15;   // widest merge tile (2^15 rows of 4-byte cells) the LDS holds
+constexpr int kTileLog2Wide = 14;  // widest plus-times tile (2^14 rows of 8-byte fp64 cells)
+// Rows the merge's LDS list holds: the whole tile while its cells take at
+// most 64 KB, else kMergeList per round of the walk.
+__host__ __device__ inline int merge_list_cap(int tile_log2, bool wide) {
+    return tile_log2 + (wide ? 3 : 2) <= 16 ? (1 << tile_log2) : kMergeList;
+}
+// Tile of a call: plus-times merges in fp64 cells, so at most 2^14 rows.
+__host__ __device__ inline int tile_for(int tile_log2, int semiring) {
+    return semiring == SR_PLUS_TIMES && tile_log2 > kTileLog2Wide ? kTileLog2Wide : tile_log2;
 }
 
 // Persistent BFS levels for small frontiers on low-degree graphs.
@@ -284,7 +294,6 @@ hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int3
                              hipStream_t s);
 hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
-hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s);
 hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
 hipError_t launch_pr_init(int32_t n, const int32_t* colptr, float d, float* rank, int32_t* x_idx, float* x_val,
                           Ctrl* ctrl, hipStream_t s);

@@ -192,19 +192,6 @@ __global__ void k_gen_x(int32_t n, uint64_t thresh, uint64_t seed, int32_t* x_id
     }
 }
 
-// heavy bit of row r = (rcp[r+1] - rcp[r] >= thresh); one thread per 32-row word.
-__global__ void k_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy) {
-    const int64_t nw = ((int64_t)m + 31) >> 5;
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t bits = 0;
-        for (int b = 0; b < 32; ++b) {
-            const int64_t r = w * 32 + b;
-            if (r < m && rcp[r + 1] - rcp[r] >= thresh) bits |= 1u << b;
-        }
-        heavy[w] = bits;
-    }
-}
-
 // Direction of the next BFS level from the frontier just scanned (the
 // frontier-edge rule of heuristic_step), unless the scan of this level
 // already took the decision.
@@ -252,12 +239,6 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(k_validate_colptr, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, colptr, n, nnz,
                        ctrl);
-    return hipGetLastError();
-}
-
-hipError_t launch_heavy_rows(const int32_t* rcp, int32_t m, int32_t thresh, uint32_t* heavy, hipStream_t s) {
-    hipLaunchKernelGGL(k_heavy_rows, dim3(grid_for((m + 31) / 32, kSetupBlock)), dim3(kSetupBlock), 0, s, rcp, m,
-                       thresh, heavy);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
-        front2, heavy, disc, pmin, bar, total;
+        front2, disc, pmin, bar, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose;
@@ -86,7 +86,6 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
     L.front2 = take(size_t(m) * 4);
-    L.heavy = take(size_t((m + 31) / 32) * 4);
     L.disc = take(size_t((m + 31) / 32) * 4 * 3);
     L.pmin = take(size_t(m) * 4);
     L.bar = take(160 * 4);
@@ -192,7 +191,6 @@ struct spmspv_matrix {
     uint64_t* lb3 = nullptr;
     uint2* buckets = nullptr;
     uint32_t* visited = nullptr;
-    uint32_t* heavy = nullptr;
     uint32_t* disc = nullptr;           // persistent BFS: three discovered-at-level bitmaps of m/32 words
     int32_t* pmin = nullptr;            // persistent BFS: smallest frontier in-neighbour
     uint32_t* bar = nullptr;            // persistent BFS: grid barrier words
@@ -244,7 +242,7 @@ int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
     int tl = ceil_log2(A->m) - 8;
     if (tl < kTileLog2Min) tl = kTileLog2Min;
     if (tl > kTileLog2Max) tl = kTileLog2Max;
-    while (tl > kTileLog2Min && merge_lds_bytes(tl) + 1024 > A->lds_max) --tl;
+    while (tl > kTileLog2Min && merge_lds_bytes(tl, SR_MIN_SELECT2ND) + 1024 > A->lds_max) --tl;
     s->direction = 0;
     s->tile_log2 = tl;
     s->scatter_block = 1024;
@@ -290,12 +288,20 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
     if (s->merge_block != 256 && s->merge_block != 512 && s->merge_block != 1024)
         return fail(SPMSPV_EINVAL, "merge_block must be 256, 512 or 1024");
     if (s->merge_variant != 0) return fail(SPMSPV_EUNSUPPORTED, "only the LDS merge variant is built");
-    if (merge_lds_bytes(s->tile_log2) + 1024 > A->lds_max) return fail(SPMSPV_EINVAL, "tile exceeds LDS");
+    if (merge_lds_bytes(s->tile_log2, SR_MIN_SELECT2ND) + 1024 > A->lds_max)
+        return fail(SPMSPV_EINVAL, "tile exceeds LDS");
     if (scatter_lds_bytes((int)nb, sb * si) + 1024 > A->lds_max)
         return fail(SPMSPV_EINVAL, "too many buckets for the scatter LDS histogram");
     return SPMSPV_OK;
 }
 
+// Tile one call merges with: the schedule's tile, narrowed for plus-times
+// (fp64 cells take twice the LDS of the other semirings' cells).
+int call_tile(const spmspv_matrix* A, int tl, int semiring) {
+    tl = tile_for(tl, semiring);
+    while (tl > kTileLog2Min && merge_lds_bytes(tl, semiring) + 1024 > A->lds_max) --tl;
+    return tl;
+}
 
 // Bucketing workgroups one compute unit holds at once (LDS and 2048
 // threads per CU): the scatter grid is at most this many per CU, so every
@@ -319,8 +325,12 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
             int phases = 3, int clear_nb = 0, bool learned_gate = false) {
     spmspv_schedule sc = A->sched;
     if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
+    sc.tile_log2 = call_tile(A, sc.tile_log2, semiring);
     const int nb = (int)((A->m + (int64_t(1) << sc.tile_log2) - 1) >> sc.tile_log2);
     const int chunk = sc.scatter_block * sc.scatter_items;
+    if (scatter_lds_bytes(nb, chunk) + 1024 > A->lds_max)
+        return fail(SPMSPV_EUNSUPPORTED, "too many buckets of 2^" + std::to_string(sc.tile_log2) +
+                                             " rows for the scatter LDS histogram");
     const int chunk_log2 = ceil_log2(chunk);
     const int64_t f_bound = f_dev ? A->n : f_host;
 
@@ -409,7 +419,6 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ma.y_cap = y_cap;
     ma.d_nnz_y = d_nnz_y;
     ma.visited = A->visited;
-    ma.heavy = A->heavy;
     ma.set_f = bfs ? 1 : 0;
     ma.gate = diropt ? 1 : 0;
 
@@ -508,9 +517,10 @@ int class_tile(const spmspv_matrix* A, int c) {
                                                  A->sched.scatter_block * A->sched.scatter_items) + 1024 >
                                    A->lds_max)
         ++tl;
-    while (tl > kTileLog2Min && merge_lds_bytes(tl) + 1024 > A->lds_max) --tl;
+    while (tl > kTileLog2Min && merge_lds_bytes(tl, SR_MIN_SELECT2ND) + 1024 > A->lds_max) --tl;
     return tl;
 }
+
 
 // One multiply whose schedule the selector MLP picks: scan, selector
 // inference on the device, one host read of the class, then the chosen
@@ -543,12 +553,12 @@ int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
 // Shape of a batched call: the narrowest tile at or above the handle's whose
 // nbatch * buckets keys fit the key limit and whose scatter histogram fits
 // LDS with one of the candidate workgroup shapes.
-int batch_shape(const spmspv_matrix* A, int nbatch, spmspv_schedule* out) {
+int batch_shape(const spmspv_matrix* A, int nbatch, int semiring, spmspv_schedule* out) {
     spmspv_schedule sc = A->sched;
     if (A->batch_sched.tile_log2 > 0) sc = A->batch_sched;
     const int shapes[4][2] = {{sc.scatter_block, sc.scatter_items}, {1024, 4}, {512, 4}, {256, 4}};
-    for (int tl = sc.tile_log2; tl <= kTileLog2Max; ++tl) {
-        if (merge_lds_bytes(tl) + 1024 > A->lds_max) break;
+    for (int tl = call_tile(A, sc.tile_log2, semiring); tl <= kTileLog2Max; ++tl) {
+        if (merge_lds_bytes(tl, semiring) + 1024 > A->lds_max) break;
         const int64_t nbx = (A->m + (int64_t(1) << tl) - 1) >> tl;
         const int64_t K = nbx * nbatch;
         if (K > kMaxKeys) continue;
@@ -573,7 +583,7 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     char* w = B.ws;
     const BatchLayout& L = B.L;
     spmspv_schedule sc{};
-    int rc = batch_shape(A, nbatch, &sc);
+    int rc = batch_shape(A, nbatch, semiring, &sc);
     if (rc) return rc;
     const int tl = sc.tile_log2;
     const int nbx = (int)((A->m + (int64_t(1) << tl) - 1) >> tl);
@@ -656,7 +666,6 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     ma.y_cap = y_cap;
     ma.d_nnz_y = nullptr;
     ma.visited = visited;
-    ma.heavy = A->heavy;
     ma.set_f = bfs ? 1 : 0;
     ma.kbase = kcount;
     ma.nbx = nbx;
@@ -824,7 +833,6 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
     A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
     A->front2 = reinterpret_cast<int32_t*>(A->ws + L.front2);
-    A->heavy = reinterpret_cast<uint32_t*>(A->ws + L.heavy);
     A->disc = reinterpret_cast<uint32_t*>(A->ws + L.disc);
     A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
     A->bar = reinterpret_cast<uint32_t*>(A->ws + L.bar);
@@ -853,8 +861,6 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     if ((e = launch_exclusive_scan_i32(A->rcp, m + 1, reinterpret_cast<int32_t*>(A->ws + L.partials), s)) !=
         hipSuccess)
         return bail(hip_fail(e, "row count scan"));
-    if ((e = launch_heavy_rows(A->rcp, (int32_t)m, kHeavyRow, A->heavy, s)) != hipSuccess)
-        return bail(hip_fail(e, "heavy rows"));
     if ((e = reset_persistent_state(A, s)) != hipSuccess || (e = launch_fill_u32(A->bar, 0u, 160, s)) != hipSuccess)
         return bail(hip_fail(e, "persistent BFS state"));
     if (L.pull) {
@@ -1292,10 +1298,11 @@ int spmspv_set_batch_schedule(spmspv_handle A, const spmspv_schedule* h_sched) {
     return SPMSPV_OK;
 }
 
-int spmspv_get_batch_schedule(spmspv_handle A, int nbatch, spmspv_schedule* h_sched) {
+int spmspv_get_batch_schedule(spmspv_handle A, int semiring, int nbatch, spmspv_schedule* h_sched) {
     if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
     if (nbatch < 1 || nbatch > kMaxBatch) return fail(SPMSPV_EINVAL, "nbatch must be in [1, 1024]");
-    return batch_shape(A, nbatch, h_sched);
+    return batch_shape(A, nbatch, semiring, h_sched);
 }
 
 namespace {
@@ -1383,7 +1390,7 @@ int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, i
     BatchCtx& B = A->batch;
     const BatchLayout& L = B.L;
     spmspv_schedule sc{};
-    int rc = batch_shape(A, nsrc, &sc);
+    int rc = batch_shape(A, nsrc, semiring, &sc);
     if (rc) return rc;
     int32_t* roots = reinterpret_cast<int32_t*>(B.ws + L.roots);
     int32_t* front[2] = {reinterpret_cast<int32_t*>(B.ws + L.front0), reinterpret_cast<int32_t*>(B.ws + L.front1)};
@@ -1541,7 +1548,7 @@ int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, 
         return r;
     };
     spmspv_schedule best{};
-    rc = batch_shape(A, nbatch, &best);
+    rc = batch_shape(A, nbatch, semiring, &best);
     if (rc) {
         A->batch_sched = keep;
         return rc;
@@ -1554,7 +1561,7 @@ int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, 
     auto consider = [&](spmspv_schedule c) -> int {
         spmspv_schedule eff{};
         A->batch_sched = c;
-        if (batch_shape(A, nbatch, &eff) != SPMSPV_OK || eff.tile_log2 != c.tile_log2 ||
+        if (batch_shape(A, nbatch, semiring, &eff) != SPMSPV_OK || eff.tile_log2 != c.tile_log2 ||
             eff.scatter_block != c.scatter_block || eff.scatter_items != c.scatter_items) {
             g_last_error.clear();
             return SPMSPV_OK;   // infeasible for this batch

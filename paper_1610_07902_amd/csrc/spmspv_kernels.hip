@@ -692,62 +692,35 @@ __device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) 
 
 
 
-// Tile accumulation.  Measured on gfx950, an LDS float atomic add retires
-// about a third of a lane per cycle per compute unit, some 17 times slower
-// than an integer LDS atomic, while a compare-and-swap retry loop on a
-// 32-bit word sustains about 2.4 lanes per cycle on distinct addresses.
-// So plus-times adds through compare-and-swap, with untouched cells holding
-// kUntouched (a signalling NaN: products and sums of real values are never
-// signalling NaNs, so the swap that replaces it is the row's first touch and
-// only that lane sets the row's bitmap bit).  Rows flagged heavy (hubs; many
-// lanes of one wave may hit the same one, where retries would pile up) start
-// at +0.0 and take the native float atomic plus a bitmap bit.  min and or
-// use their native integer atomics and the bitmap.
-constexpr uint32_t kUntouched = 0x7fa5a5a5u;
+// Tile accumulation.  Measured on gfx950 (random addresses in a 128 KB
+// tile, every lane of 256 workgroups of 1024 threads): an LDS add of a
+// 64-bit float retires about 2 lanes per cycle per compute unit, and keeps
+// that rate when a third of the lanes hit a few dozen hub rows; a 32-bit
+// float add retires about a third of a lane per cycle, and a
+// compare-and-swap loop on a 32-bit word about 1.9 on distinct rows but half
+// a lane once hub rows make lanes retry.  So plus-times accumulates every
+// row in fp64 and rounds it to fp32 once, when y is written: faster, and the
+// rounding error no longer grows with the number of terms of a row (fp32
+// sums of a few hundred thousand terms in arbitrary order drift past 1e-5).
+// An fp64 cell starts at -0.0, which only a sum whose every term is -0.0
+// reproduces: such a product also sets the row's bitmap bit, and every other
+// touched row is the one whose cell is no longer -0.0 (a ballot pass after
+// the accumulation sets its bit).  min and or use their native integer
+// atomics and set the bitmap bit with every entry.
+constexpr uint64_t kNegZero64 = 0x8000000000000000ull;
 
-// Applies K entries held by one thread.  For plus-times the K reads and
-// the K first compare-and-swap attempts are issued back to back, so a wave
-// pays the LDS round trip about twice per K entries; the rare lost races
-// retry one entry at a time.
 template <int SR, int K>
 __device__ __forceinline__ void add_rows(const uint32_t (&r)[K], const uint32_t (&v)[K], const bool (&ok)[K],
-                                         const bool (&hv)[K], uint32_t* spa, uint32_t* bm) {
+                                         uint32_t* spa, uint32_t* bm) {
     if constexpr (SR == SR_PLUS_TIMES) {
-        bool light[K];
-        uint32_t old[K];
+        double* spa64 = reinterpret_cast<double*>(spa);
 #pragma unroll
         for (int u = 0; u < K; ++u) {
-            light[u] = ok[u] && !hv[u];
-            if (ok[u] && hv[u]) {
-                atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
-                atomicAdd(reinterpret_cast<float*>(&spa[r[u]]), __uint_as_float(v[u]));
+            if (ok[u]) {
+                atomicAdd(&spa64[r[u]], (double)__uint_as_float(v[u]));
+                if (v[u] == 0x80000000u) atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
             }
         }
-#pragma unroll
-        for (int u = 0; u < K; ++u) old[u] = light[u] ? spa[r[u]] : 0u;
-        uint32_t got[K];
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            got[u] = old[u];
-            if (light[u]) {
-                const uint32_t nv =
-                    old[u] == kUntouched ? v[u] : __float_as_uint(__uint_as_float(old[u]) + __uint_as_float(v[u]));
-                got[u] = atomicCAS(&spa[r[u]], old[u], nv);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            while (got[u] != old[u]) {   // another lane updated the cell first
-                old[u] = got[u];
-                const uint32_t nv =
-                    old[u] == kUntouched ? v[u] : __float_as_uint(__uint_as_float(old[u]) + __uint_as_float(v[u]));
-                got[u] = atomicCAS(&spa[r[u]], old[u], nv);
-            }
-        }
-        // the lane whose swap replaced kUntouched made the first touch
-#pragma unroll
-        for (int u = 0; u < K; ++u)
-            if (light[u] && old[u] == kUntouched) atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
     } else {
 #pragma unroll
         for (int u = 0; u < K; ++u) {
@@ -755,6 +728,27 @@ __device__ __forceinline__ void add_rows(const uint32_t (&r)[K], const uint32_t 
                 atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
                 accumulate<SR>(&spa[r[u]], v[u]);
             }
+        }
+    }
+}
+
+// Bitmap bits of the fp64 cells a plus-times entry reached (cell no longer
+// -0.0), 64 consecutive cells per wave and step: conflict-free 8-byte LDS
+// reads, one ballot, and lane 0 merges the two bitmap words (nothing else
+// writes them after the accumulation).
+template <int BLOCK>
+__device__ __forceinline__ void touched_bits64(const uint32_t* spa, uint32_t* bm, int rows) {
+    const uint64_t* c64 = reinterpret_cast<const uint64_t*>(spa);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    for (int c0 = wid * kWave; c0 < rows; c0 += BLOCK) {
+        const int c = c0 + lane;
+        const bool t = c < rows && c64[c] != kNegZero64;
+        const uint64_t b = __ballot(t);
+        if (lane == 0) {
+            const int w = c0 >> 5;
+            bm[w] |= (uint32_t)b;
+            if (c0 + 32 < rows) bm[w + 1] |= (uint32_t)(b >> 32);
         }
     }
 }
@@ -779,10 +773,10 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     extern __shared__ uint32_t lds_merge[];
     const int tl = a.tile_log2;
     const int T = 1 << tl;
-    uint32_t* spa = lds_merge;                                       // [T]
-    uint32_t* bm = spa + T;                                          // [T/32]
-    uint32_t* hb = bm + (T >> 5);                                    // [T/32] heavy rows
-    uint16_t* list = reinterpret_cast<uint16_t*>(hb + (T >> 5));     // [merge_list_cap(tl)]
+    constexpr bool kWide = SR == SR_PLUS_TIMES;                      // fp64 cells
+    uint32_t* spa = lds_merge;                                       // [T] cells of 4 or 8 bytes
+    uint32_t* bm = spa + (kWide ? 2 * T : T);                        // [T/32]
+    uint16_t* list = reinterpret_cast<uint16_t*>(bm + (T >> 5));     // [merge_list_cap(tl, kWide)]
     __shared__ int64_t s_excl;
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
@@ -797,17 +791,6 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         bt = b - xb * a.nbx;
     }
     const int row0 = bt << tl;
-    // heavy-row words of this tile, fetched before the control reads
-    constexpr int kHw = (1 << kTileLog2Cap) / 32 / BLOCK;
-    uint32_t hw[kHw];
-    {
-        const int nwt = (min(T, a.m - row0) + 31) >> 5;
-#pragma unroll
-        for (int k = 0; k < kHw; ++k) {
-            const int w = tid + k * BLOCK;
-            hw[k] = w < nwt ? a.heavy[(row0 >> 5) + w] : 0u;
-        }
-    }
     const int W = ld_ctrl(&a.ctrl->W);
     const int cnt_raw = ld_ctrl(&a.cursor[b]);
     int64_t base;
@@ -852,35 +835,22 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
             vv[i] = ent.y;
         }
     }
-#pragma unroll
-    for (int k = 0; k < kHw; ++k) {
-        const int w = tid + k * BLOCK;
-        if (w < nw) {
-            bm[w] = 0u;
-            hb[w] = hw[k];
-        }
-    }
-    if constexpr (SR == SR_PLUS_TIMES) __syncthreads();   // the cell init below reads hb
+    for (int w = tid; w < nw; w += BLOCK) bm[w] = 0u;
     {
+        // whole bitmap words of cells, 16 bytes per store
         uint4* spa4 = reinterpret_cast<uint4*>(spa);
-        for (int q = tid; q < nw * 8; q += BLOCK) {   // 4 cells per store, whole bitmap words
-            uint32_t c[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if constexpr (SR == SR_PLUS_TIMES) {
-                    const int r = q * 4 + k;
-                    c[k] = ((hb[r >> 5] >> (r & 31)) & 1u) ? 0u : kUntouched;
-                } else {
-                    c[k] = identity<SR>();
-                }
-            }
-            spa4[q] = make_uint4(c[0], c[1], c[2], c[3]);
+        if constexpr (kWide) {
+            const uint4 z = make_uint4(0u, 0x80000000u, 0u, 0x80000000u);   // two -0.0 doubles
+            for (int q = tid; q < nw * 16; q += BLOCK) spa4[q] = z;
+        } else {
+            const uint32_t id = identity<SR>();
+            for (int q = tid; q < nw * 8; q += BLOCK) spa4[q] = make_uint4(id, id, id, id);
         }
     }
     __syncthreads();
     bool bad = false;
     if (small) {
-        bool ok[ITEMS], hv[ITEMS];
+        bool ok[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             ok[i] = rr[i] != 0xffffffffu;
@@ -889,9 +859,8 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                 ok[i] = false;
                 bad = true;
             }
-            hv[i] = ok[i] && ((hb[rr[i] >> 5] >> (rr[i] & 31u)) & 1u);
         }
-        add_rows<SR, ITEMS>(rr, vv, ok, hv, spa, bm);
+        add_rows<SR, ITEMS>(rr, vv, ok, spa, bm);
     } else {
         constexpr int kBatch = 8;   // entries per thread in flight per step
         for (int e0 = 0; e0 < cnt; e0 += BLOCK * kBatch) {
@@ -902,7 +871,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                 ent[u] = e < cnt ? a.buckets[base + e] : make_uint2(0xffffffffu, 0u);
             }
             uint32_t r[kBatch], v[kBatch];
-            bool ok[kBatch], hv[kBatch];
+            bool ok[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 r[u] = ent[u].x - (uint32_t)row0;
@@ -912,13 +881,16 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                     ok[u] = false;
                     bad = true;
                 }
-                hv[u] = ok[u] && ((hb[r[u] >> 5] >> (r[u] & 31u)) & 1u);
             }
-            add_rows<SR, kBatch>(r, v, ok, hv, spa, bm);
+            add_rows<SR, kBatch>(r, v, ok, spa, bm);
         }
     }
     if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
     __syncthreads();
+    if constexpr (kWide) {
+        touched_bits64<BLOCK>(spa, bm, rows);
+        __syncthreads();
+    }
     int pc = 0;
     for (int w = tid; w < nw; w += BLOCK) pc += __popc(bm[w]);
     int ucnt;
@@ -951,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
 
     // In-order walk of the bitmap: one word per thread per round, as many
     // words as the LDS list holds (the whole tile up to 16K rows).
-    const int round_words = min(BLOCK, merge_list_cap(tl) >> 5);
+    const int round_words = min(BLOCK, merge_list_cap(tl, kWide) >> 5);
     int64_t carry = 0;
     for (int w0 = 0; w0 < nw; w0 += round_words) {
         const int w = w0 + tid;
@@ -972,7 +944,9 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         for (int t = tid; t < tot; t += BLOCK) {
             const int r = list[t];
             const int64_t o = excl + carry + t;
-            const uint32_t v = spa[r];
+            uint32_t v;
+            if constexpr (kWide) v = __float_as_uint((float)reinterpret_cast<const double*>(spa)[r]);
+            else v = spa[r];
             if (o < a.y_cap) {
                 a.y_idx[o] = row0 + r;
                 if (a.y_val) store_value<SR>(a.y_val, o, v);
@@ -989,9 +963,10 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
 
 }  // namespace
 
-size_t merge_lds_bytes(int tile_log2) {
+size_t merge_lds_bytes(int tile_log2, int semiring) {
+    const bool wide = semiring == SR_PLUS_TIMES;
     const size_t T = size_t(1) << tile_log2;
-    return T * 4 + (T / 32) * 8 + size_t(merge_list_cap(tile_log2)) * 2;
+    return T * (wide ? 8 : 4) + (T / 32) * 4 + size_t(merge_list_cap(tile_log2, wide)) * 2;
 }
 
 size_t scatter_lds_bytes(int nb, int chunk, bool batch) {
@@ -1110,7 +1085,7 @@ hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, i
 
 template <int BLOCK, int SR, bool BFS, bool BATCH>
 static hipError_t merge_one(const MergeArgs& a, hipStream_t s, const LaunchEvents* ev) {
-    const size_t lds = merge_lds_bytes(a.tile_log2);
+    const size_t lds = merge_lds_bytes(a.tile_log2, SR);
     auto kern = k_merge<BLOCK, kMergeItems, SR, BFS, BATCH>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;

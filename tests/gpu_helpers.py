@@ -1,4 +1,6 @@
 """Shared helpers of the GPU parity tests (compare the HIP path with the oracle)."""
+import functools
+
 import numpy as np
 
 # fp32 plus-times contract: |y - y64| <= REL_TOL * sum_k |term_k|; every input
@@ -37,3 +39,14 @@ def compare(semiring, g_idx, g_val, o_idx, o_val, sorted_output=False, terms_abs
     else:
         bad = np.nonzero(gv.astype(np.uint8) != ov.astype(np.uint8))[0]
         assert bad.size == 0, f"{bad.size} bool values differ, e.g. rows {gi[bad[:5]]} gpu {gv[bad[:5]]} oracle {ov[bad[:5]]}"
+
+
+@functools.lru_cache(maxsize=1)
+def rmat24_pattern():
+    """The held-out evaluation graph (R-MAT scale 24, edge factor 16,
+    symmetrised, pattern only: 16,777,216 vertices, 520,757,406 stored
+    entries), generated once per test session."""
+    import synth
+    A = synth.rmat(24, 16, seed=24, symmetrize=True, with_values=False)
+    assert (A.n, A.nnz) == (16777216, 520757406)
+    return A

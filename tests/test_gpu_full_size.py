@@ -29,7 +29,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import compare, to_np
+from gpu_helpers import compare, rmat24_pattern, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -229,8 +229,7 @@ def test_full_size_held_out_bfs_learned_and_heuristic(spv):
     host-read selector and with the frontier-edge heuristic, against the
     queue BFS from one of the evaluation's roots."""
     from paper_1610_07902_amd import selector
-    A = synth.rmat(24, 16, seed=24, symmetrize=True, with_values=False)
-    assert (A.n, A.nnz) == (16777216, 520757406)
+    A = rmat24_pattern()
     P = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
     params, mean, std, _ = selector.load_weights()
     P.load_selector(params, mean, std)
