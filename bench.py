@@ -46,6 +46,8 @@ def algorithmic_bytes(phase, semiring, f, fnz, W, nnz_y):
         return 12 * fnz + W * (4 + vbytes) + 8 * W
     if phase == "merge":    # bucket pairs read, y (index + value) written
         return 8 * W + nnz_y * (4 + xbytes)
+    if phase == "one_launch":   # the three phases' data flow in one kernel
+        return sum(algorithmic_bytes(p, semiring, f, fnz, W, nnz_y) for p in ("scan", "scatter", "merge"))
     raise ValueError(phase)
 
 
@@ -153,11 +155,31 @@ def main():
         print(json.dumps({"metric": METRIC, "value": gteps, "unit": "GTEPS", "ms_per_step": ms / args.steps}))
         return
 
+    eff = spv.spmspv_effective_schedule(M.handle, f)
+    # The same loop with the schedule forced to the other launch mode, for comparison.
+    other = 1 if eff.launch == 2 else 2
+    s = M.schedule
+    s.launch = other
+    try:
+        M.schedule = s
+        for i in range(args.warmup):
+            step(i)
+        ev0.record(stream)
+        for i in range(args.steps):
+            step(i)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        other_ms = ev0.elapsed_time(ev1) / args.steps
+    except spv.SpmspvError:
+        other_ms = None
+    M.schedule = None
+    log(f"launch {other}: {other_ms} ms per step")
+
     # Per-kernel durations: the same loop again with events around each kernel.
     for i in range(args.steps):
         step(i, spv.PROFILE)
     phase_ms, calls = spv.spmspv_profile_read(M.handle)
-    phases = ["scan", "scatter", "merge"]
+    phases = ["one_launch"] if eff.launch == 2 else ["scan", "scatter", "merge"]
     avg_ms = {p: phase_ms[k] / calls for k, p in enumerate(phases)}
     avg_bytes = {p: float(np.mean([algorithmic_bytes(p, 0, f, fnz[r], W[r], nnz_y[r]) for r in steps_idx]))
                  for p in phases}
@@ -183,7 +205,8 @@ def main():
                                f"nnz={A.nnz}), x density {args.density:g} (f={f}), {args.nx} rotating x",
                    "scale": args.scale, "nnz": A.nnz, "f": f, "mean_products": float(W.mean()),
                    "mean_nnz_y": float(nnz_y.mean()),
-                   "schedule": spv.spmspv_effective_schedule(M.handle, f).as_dict()},
+                   "schedule": eff.as_dict(),
+                   "other_launch_mode": {"launch": other, "ms_per_step": other_ms}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(dom, args),
@@ -246,7 +269,7 @@ def copy_calibration(torch):
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for name in ("spmspv_kernels.hip", "internal.h"):
+    for name in ("spmspv_kernels.hip", "fused_kernels.hip", "device_ops.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1610_07902_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -331,15 +354,21 @@ def sweep(spv, M, A, deg, dev, stream):
             xv = [torch.as_tensor(x[1] if sr == 0 else x[0]).to(dev) for x in xs]
             y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
             y_val = torch.empty(A.m, dtype=torch.float32 if sr == 0 else torch.int32, device=dev)
-            rec = {"f": f}
-            for direction in (0, 1):
-                M.schedule = None   # push: the default, sized per call
-                if direction == 1:
+            rec = {"f": f, "push_launch": spv.spmspv_effective_schedule(M.handle, f, 0, sr).launch}
+            # push with the default schedule (sized per call, launch mode by the
+            # expected product count), push forced to each launch mode, pull
+            for key, direction, launch in (("push", 0, 0), ("push_three", 0, 1), ("push_one", 0, 2),
+                                           ("pull", 1, 0)):
+                M.schedule = None
+                if direction == 1 or launch:
                     s = M.schedule
-                    s.direction = 1
+                    s.direction = direction
+                    s.launch = launch
                     M.schedule = s
-                ms = time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, A.m, 64, stream)
-                key = "push" if direction == 0 else "pull"
+                try:
+                    ms = time_calls(spv, M, sr, f, xi, xv, y_idx, y_val, A.m, 64, stream)
+                except spv.SpmspvError:
+                    continue
                 rec[key + "_us"] = round(ms * 1e3, 2)
                 rec[key + "_GTEPS"] = round(W / (ms * 1e-3) / 1e9, 3)
             M.schedule = None

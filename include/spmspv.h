@@ -136,6 +136,14 @@ typedef struct {
     int scatter_items;  /* products per thread per chunk (1..16, power of 2)       */
     int merge_block;    /* threads per merge workgroup (64..1024, power of 2)      */
     int merge_variant;  /* 0 = sparse accumulator in LDS                           */
+    int launch;         /* push calls of spmspv_run / spmspv_run_masked:
+                           0, 1 = three launches (scan, bucketing, merge: the
+                               default, faster on gfx950),
+                           2 = one launch of all three phases (one workgroup
+                               per compute unit, exchanging through tagged
+                               words; needs f <= 4096 per compute unit, at most
+                               1024 buckets and no other work on the device
+                               during the call, else EUNSUPPORTED or EDEVICE) */
 } spmspv_schedule;
 
 /* Bytes of device workspace spmspv_create needs for an m-by-n matrix with
@@ -251,8 +259,10 @@ int spmspv_autotune_batch(spmspv_handle A, int semiring, int flags, int nbatch, 
 int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched);
 int spmspv_set_schedule(spmspv_handle A, const spmspv_schedule* h_sched);
 
-/* The schedule spmspv_run(A, ..., flags, f, ...) would launch with.      */
-int spmspv_effective_schedule(spmspv_handle A, int64_t f, int flags, spmspv_schedule* h_sched);
+/* The schedule spmspv_run(A, semiring, flags, f, ...) would launch with:
+ * the tile that semiring merges with, and for push calls the launch mode
+ * (1 = three launches, 2 = one launch).                                  */
+int spmspv_effective_schedule(spmspv_handle A, int semiring, int64_t f, int flags, spmspv_schedule* h_sched);
 
 /* Statistics of the most recent spmspv_run / BFS level (synchronous):
  * h_out[0] = products W (sum of selected column lengths, the work bound of
@@ -265,7 +275,8 @@ int spmspv_last_stats(spmspv_handle A, int64_t* h_out, void* stream);
 /* Per-kernel timing of calls made with SPMSPV_PROFILE: waits for the
  * recorded events, writes the summed milliseconds of each phase
  * (0 = scan, 1 = bucket scatter, 2 = merge + compaction) to h_ms[3] and the
- * number of profiled calls to *h_calls, then clears the record.           */
+ * number of profiled calls to *h_calls, then clears the record.  A call
+ * made in one launch records its kernel under phase 0 (1 and 2 stay 0).  */
 int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
 
 /* Release the handle (host memory and HIP events only; the caller frees

@@ -59,7 +59,8 @@ class SpmspvError(RuntimeError):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int), ("tile_log2", ctypes.c_int), ("scatter_block", ctypes.c_int),
-                ("scatter_items", ctypes.c_int), ("merge_block", ctypes.c_int), ("merge_variant", ctypes.c_int)]
+                ("scatter_items", ctypes.c_int), ("merge_block", ctypes.c_int), ("merge_variant", ctypes.c_int),
+                ("launch", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,7 +96,7 @@ def load_library(path: str = LIB_PATH):
     lib.bfs_run.argtypes = [vp, ci, ctypes.c_int32, ci, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.spmspv_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
-    lib.spmspv_effective_schedule.argtypes = [vp, i64, ci, ctypes.POINTER(Schedule)]
+    lib.spmspv_effective_schedule.argtypes = [vp, ci, i64, ci, ctypes.POINTER(Schedule)]
     lib.spmspv_last_stats.argtypes = [vp, ctypes.POINTER(i64), vp]
     lib.spmspv_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.spmspv_destroy.argtypes = [vp]
@@ -290,9 +291,9 @@ def spmspv_autotune(handle, semiring, densities, reps, x_idx, x_val, y_idx, y_va
     return [e.as_dict() for e in out]
 
 
-def spmspv_effective_schedule(handle, f, flags=0) -> Schedule:
+def spmspv_effective_schedule(handle, f, flags=0, semiring=0) -> Schedule:
     sc = Schedule()
-    _check(load_library().spmspv_effective_schedule(handle, int(f), int(flags), ctypes.byref(sc)))
+    _check(load_library().spmspv_effective_schedule(handle, int(semiring), int(f), int(flags), ctypes.byref(sc)))
     return sc
 
 

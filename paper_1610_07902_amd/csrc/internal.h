@@ -66,7 +66,10 @@ struct alignas(256) Ctrl {
     // deciding again.
     uint32_t chain_ready;
     uint32_t chain_word;
-    uint32_t pad[27];
+    // One-launch multiply: call counter whose value tags this call's
+    // exchange and look-back words (advanced once per call on the device).
+    uint32_t fused_epoch;
+    uint32_t pad[26];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -270,6 +273,57 @@ __host__ __device__ inline int merge_list_cap(int tile_log2, bool wide) {
 __host__ __device__ inline int tile_for(int tile_log2, int semiring) {
     return semiring == SR_PLUS_TIMES && tile_log2 > kTileLog2Wide ? kTileLog2Wide : tile_log2;
 }
+
+// One-launch multiply (k_fused): scan, bucketing and merge of one y <- A x
+// in a single cooperative launch of one workgroup per compute unit.
+constexpr int kFBlock = 1024;                  // threads per workgroup
+constexpr int kFItems = 8;                     // products per thread per chunk
+constexpr int kFChunk = kFBlock * kFItems;     // largest chunk of products a workgroup bucket-sorts at once
+constexpr int kFSamples = 64;                  // local offsets each source list publishes
+constexpr int kFMaxF = 4096;                   // x entries per source workgroup (f <= grid * kFMaxF)
+constexpr int kFMaxNb = 1024;                  // buckets
+constexpr int kFMaxGrid = 1024;                // workgroups
+constexpr int kFRunGroup = 1024;               // chunk runs a merge workgroup indexes at once
+// Tagged exchange words (64-bit, call tag in bits 63:44), one array each:
+constexpr int kXA = 0;                          // per source: column and product counts (its lists are written)
+constexpr int kXM = kFMaxGrid;                  // per source: longest column
+constexpr int kXD = 2 * kFMaxGrid;              // per workgroup: its chunk runs are written
+constexpr int kXG = 3 * kFMaxGrid;              // per workgroup: every run is written (set by workgroup 0)
+constexpr int kXU = 4 * kFMaxGrid;              // per bucket: unique rows
+constexpr int kXY = 4 * kFMaxGrid + kFMaxNb;    // per bucket: offset in y (set by workgroup 0)
+constexpr int kXWords = 4 * kFMaxGrid + 2 * kFMaxNb;
+struct FusedArgs {
+    const int32_t* colptr;
+    const int32_t* rowids;
+    const float* values;     // nullable (pattern)
+    int32_t m, n;
+    int64_t nnz;
+    const int32_t* x_idx;
+    const void* x_val;
+    int xmode;
+    int32_t f;
+    int tile_log2;
+    int32_t nb;
+    const uint32_t* mask;    // nullable: drop rows whose bit is set
+    Ctrl* ctrl;
+    int32_t* lstart;         // [grid * F] per-source lists of non-empty columns: first entry,
+    int32_t* loff;           //   local exclusive product offset,
+    uint32_t* lxv;           //   x value bits
+    int32_t* samples;        // [grid][kFSamples] local offsets at evenly spaced list positions
+    uint64_t* xw;            // [kXWords] tagged exchange words
+    uint64_t* xrec;          // [2 * rows_cap] tagged chunk records: W, and the chunk's first and last source
+    int64_t* gpoff;          // [kFMaxGrid + 1] product prefix of each source, its column count in bits 60:48
+    int32_t* roff;           // [rows_cap][nb + 1] per-chunk bucket offsets
+    int64_t rows_cap;
+    uint2* buckets;          // [nnz + 1] (row, value bits), chunk k at k * chunk
+    int32_t* y_idx;
+    void* y_val;             // nullable
+    int64_t y_cap;
+    int64_t* d_nnz_y;        // nullable
+};
+size_t fused_lds_bytes(int tile_log2, int semiring, int nb);
+int fused_grid(int num_cu, size_t lds_bytes);
+hipError_t launch_fused(const FusedArgs& a, int semiring, int grid, hipStream_t s, const LaunchEvents* ev = nullptr);
 
 // Persistent BFS levels for small frontiers on low-degree graphs.
 constexpr int kTinyFrontier = 65536;   // vertices per frontier handled by the persistent kernel

@@ -52,12 +52,14 @@ inline int ceil_log2(int64_t v) {
 
 // Offsets of every region inside the caller's workspace.
 struct Layout {
-    size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, buckets, visited, front0, front1,
-        front2, disc, pmin, bar, total;
+    size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
+        front1, front2, disc, pmin, bar, samples, gpoff, roff, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose;
     int64_t nb_max, lb1_n, chunk_n;
+    int64_t rows_cap;   // one-launch multiply: chunk rows of run offsets
+    int32_t fnb;        // one-launch multiply: buckets per row of run offsets
 };
 
 Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
@@ -69,18 +71,27 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
         return at;
     };
     L.nb_max = (m + (1 << kTileLog2Min) - 1) >> kTileLog2Min;
+    // one-launch multiply: chunks of at most kFChunk products, at least one per workgroup
+    L.rows_cap = std::max<int64_t>(kFMaxGrid, (nnz + kFChunk) / kFChunk) + 1;
+    L.fnb = (int32_t)std::min<int64_t>(kFMaxNb, L.nb_max);
     L.lb1_n = (n + kScanTile - 1) / kScanTile + 1;
     L.chunk_n = nnz / kChunkMin + 2;
     L.ctrl = take(sizeof(Ctrl));
     L.rcp = take(size_t(m + 1) * 4);
     L.partials = take(size_t((m + 1) / 4096 + 2) * 4);
-    L.cstart = take(size_t(n) * 4);
-    L.coff = take(size_t(n + 1) * 4);
-    L.cxv = take(size_t(n) * 4);
+    // column tables; the one-launch multiply keeps its per-workgroup column
+    // lists here too (up to kFMaxGrid - 1 slots past n)
+    L.cstart = take(size_t(n + kFMaxGrid + 1) * 4);
+    L.coff = take(size_t(n + kFMaxGrid + 1) * 4);
+    L.cxv = take(size_t(n + kFMaxGrid + 1) * 4);
     L.chunk_col = take(size_t(L.chunk_n) * 4);
     L.lb1 = take(size_t(L.lb1_n) * 16);
     L.cursor = take(size_t(L.nb_max) * 4);
     L.lb3 = take(size_t(L.nb_max) * 8);
+    // one-launch multiply: tagged exchange words and chunk records (zeroed
+    // at create with everything before the buckets; tags are never zero)
+    L.xw = take(size_t(kXWords) * 8);
+    L.xrec = take(size_t(2 * L.rows_cap) * 8);
     L.buckets = take(size_t(nnz + 1) * 8);
     L.visited = take(size_t((m + 31) / 32) * 4);
     L.front0 = take(size_t(m) * 4);
@@ -90,6 +101,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.pmin = take(size_t(m) * 4);
     L.bar = take(160 * 4);
     L.selector = take(size_t(kMlpParams + 2 * kMlpIn) * 4);
+    // one-launch multiply: list samples, source prefix and per-chunk bucket offsets
+    L.samples = take(size_t(kFMaxGrid) * kFSamples * 4);
+    L.gpoff = take(size_t(kFMaxGrid + 1) * 8);
+    L.roff = take(size_t(L.rows_cap) * size_t(L.fnb + 1) * 4);
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
     if (L.pull) {
@@ -195,6 +210,7 @@ struct spmspv_matrix {
     int32_t* pmin = nullptr;            // persistent BFS: smallest frontier in-neighbour
     uint32_t* bar = nullptr;            // persistent BFS: grid barrier words
     int persist_grid = -1;              // co-resident workgroups of the persistent kernel (0 = unavailable)
+    int fused_grid = -1;                // workgroups of the one-launch multiply (0 = unavailable)
     int32_t* front[2] = {nullptr, nullptr};
     int32_t* front2 = nullptr;          // persistent BFS: third frontier list
     int32_t maxdeg = 0;
@@ -249,6 +265,7 @@ int default_schedule(const spmspv_matrix* A, spmspv_schedule* s) {
     s->scatter_items = 8;
     s->merge_block = 1024;
     s->merge_variant = 0;
+    s->launch = 0;
     const int64_t nb = (A->m + (int64_t(1) << tl) - 1) >> tl;
     if (scatter_lds_bytes((int)nb, 8192) + 1024 > A->lds_max) s->scatter_items = 4;
     return SPMSPV_OK;
@@ -288,6 +305,7 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
     if (s->merge_block != 256 && s->merge_block != 512 && s->merge_block != 1024)
         return fail(SPMSPV_EINVAL, "merge_block must be 256, 512 or 1024");
     if (s->merge_variant != 0) return fail(SPMSPV_EUNSUPPORTED, "only the LDS merge variant is built");
+    if (s->launch < 0 || s->launch > 2) return fail(SPMSPV_EINVAL, "launch must be 0 (auto), 1 (three) or 2 (one)");
     if (merge_lds_bytes(s->tile_log2, SR_MIN_SELECT2ND) + 1024 > A->lds_max)
         return fail(SPMSPV_EINVAL, "tile exceeds LDS");
     if (scatter_lds_bytes((int)nb, sb * si) + 1024 > A->lds_max)
@@ -438,6 +456,74 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
         HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s, ev ? &le[1] : nullptr));
         HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s, ev ? &le[2] : nullptr));
     }
+    return SPMSPV_OK;
+}
+
+// One-launch multiply.  Eligible when the device holds one workgroup of it
+// per compute unit, every source workgroup's slice of x fits its list
+// (f <= kFMaxF per workgroup) and the call's buckets fit one row of run
+// offsets.  Returns the grid, or 0 when the call must take three launches.
+int fused_eligible(spmspv_matrix* A, int semiring, int64_t f, int* tl_out, int* nb_out) {
+    const int tl = call_tile(A, A->sched.tile_log2, semiring);
+    const int64_t nb = (A->m + (int64_t(1) << tl) - 1) >> tl;
+    if (nb > A->L.fnb || nb > kFMaxNb) return 0;
+    if (A->fused_grid < 0) {
+        size_t lds = 0;
+        for (int t = kTileLog2Min; t <= kTileLog2Max; ++t)
+            for (int sr = 0; sr < 3; ++sr) {
+                if (merge_lds_bytes(tile_for(t, sr), sr) + 1024 > A->lds_max) continue;
+                lds = std::max(lds, fused_lds_bytes(tile_for(t, sr), sr, kFMaxNb));
+            }
+        A->fused_grid = lds + 1024 <= A->lds_max ? fused_grid(A->num_cu, lds) : 0;
+        (void)hipGetLastError();   // an unavailable attribute leaves no sticky error behind
+    }
+    const int G = A->fused_grid;
+    if (G < 1 || f > (int64_t)G * kFMaxF) return 0;
+    if (fused_lds_bytes(tl, semiring, (int)nb) + 1024 > A->lds_max) return 0;
+    *tl_out = tl;
+    *nb_out = (int)nb;
+    return G;
+}
+
+int enqueue_fused(spmspv_matrix* A, int semiring, int xmode, int64_t f, const int32_t* x_idx, const void* x_val,
+                  int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, const uint32_t* mask, int G, int tl,
+                  int nb, hipStream_t s, hipEvent_t* ev) {
+    FusedArgs a{};
+    a.colptr = A->colptr;
+    a.rowids = A->rowids;
+    a.values = A->values;
+    a.m = (int32_t)A->m;
+    a.n = (int32_t)A->n;
+    a.nnz = A->nnz;
+    a.x_idx = x_idx;
+    a.x_val = x_val;
+    a.xmode = xmode;
+    a.f = (int32_t)f;
+    a.tile_log2 = tl;
+    a.nb = nb;
+    a.mask = mask;
+    a.ctrl = A->ctrl;
+    a.lstart = A->cstart;
+    a.loff = A->coff;
+    a.lxv = A->cxv;
+    a.samples = reinterpret_cast<int32_t*>(A->ws + A->L.samples);
+    a.xw = reinterpret_cast<uint64_t*>(A->ws + A->L.xw);
+    a.xrec = reinterpret_cast<uint64_t*>(A->ws + A->L.xrec);
+    a.gpoff = reinterpret_cast<int64_t*>(A->ws + A->L.gpoff);
+    a.roff = reinterpret_cast<int32_t*>(A->ws + A->L.roff);
+    a.rows_cap = A->L.rows_cap;
+    a.buckets = A->buckets;
+    a.y_idx = y_idx;
+    a.y_val = y_val;
+    a.y_cap = y_cap;
+    a.d_nnz_y = d_nnz_y;
+    // the row width of the offsets array is fixed at create
+    a.nb = nb;
+    if (nb > A->L.fnb) return fail(SPMSPV_EUNSUPPORTED, "too many buckets for the one-launch multiply");
+    const LaunchEvents le{ev ? ev[0] : nullptr, ev ? ev[1] : nullptr};
+    HIP_TRY(launch_fused(a, semiring, G, s, ev ? &le : nullptr));
+    if (ev)
+        for (int k = 2; k < 6; ++k) HIP_TRY(hipEventRecord(ev[k], s));   // the scatter and merge phases take no separate time
     return SPMSPV_OK;
 }
 
@@ -922,13 +1008,21 @@ int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched) {
     return SPMSPV_OK;
 }
 
-int spmspv_effective_schedule(spmspv_handle A, int64_t f, int flags, spmspv_schedule* h_sched) {
+int spmspv_effective_schedule(spmspv_handle A, int semiring, int64_t f, int flags, spmspv_schedule* h_sched) {
     if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
     if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    const spmspv_schedule keep = A->sched;
     const spmspv_schedule* tuned = (flags & SPMSPV_AUTO_SCHEDULE) ? tuned_for(A, f) : nullptr;
-    if (tuned) *h_sched = *tuned;
-    else if (A->sched_default) *h_sched = sized_for_call(A, f);
-    else *h_sched = A->sched;
+    if (tuned) A->sched = *tuned;
+    else if (A->sched_default) A->sched = sized_for_call(A, f);
+    spmspv_schedule e = A->sched;
+    if (e.direction == 0) {
+        e.tile_log2 = call_tile(A, e.tile_log2, semiring);
+        e.launch = e.launch == 2 ? 2 : 1;
+    }
+    A->sched = keep;
+    *h_sched = e;
     return SPMSPV_OK;
 }
 
@@ -996,9 +1090,21 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
         const spmspv_schedule* tuned = (flags & SPMSPV_AUTO_SCHEDULE) ? tuned_for(A, f) : nullptr;
         if (tuned) A->sched = *tuned;
         else if (A->sched_default) A->sched = sized_for_call(A, f);
+        int G = 0, ftl = 0, fnb = 0;
+        if (A->sched.direction == 0 && A->sched.launch == 2) {
+            G = fused_eligible(A, semiring, f, &ftl, &fnb);
+            if (G == 0) {
+                A->sched = keep;
+                return fail(SPMSPV_EUNSUPPORTED, "this call cannot run as one launch (f > 4096 per compute unit, "
+                                                 "more than 1024 buckets, or no co-resident grid)");
+            }
+        }
         if (A->sched.direction == 1)
             rc = enqueue_pull(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false,
                               mask, false, false, s, ev, (flags & SPMSPV_PULL_ROWWISE) != 0);
+        else if (G > 0)
+            rc = enqueue_fused(A, semiring, xmode, f, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, mask, G, ftl,
+                               fnb, s, ev);
         else
             rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask,
                          s, ev);

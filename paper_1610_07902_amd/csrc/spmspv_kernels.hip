@@ -37,6 +37,7 @@
 #include <hip/hip_ext.h>
 
 #include "decide.h"
+#include "device_ops.h"
 
 namespace spv {
 
@@ -115,74 +116,10 @@ __device__ uint64_t lookback(uint64_t* st, int tile, uint64_t agg, uint32_t* err
     return excl;
 }
 
-template <int BLOCK>
-__device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t v, uint64_t* s_tmp, uint64_t& total) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    uint64_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint64_t y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
-    if (lane == kWave - 1) s_tmp[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t acc = 0;
-        for (int w = 0; w < BLOCK / kWave; ++w) {
-            const uint64_t t = s_tmp[w];
-            s_tmp[w] = acc;
-            acc += t;
-        }
-        s_tmp[BLOCK / kWave] = acc;
-    }
-    __syncthreads();
-    const uint64_t r = s_tmp[wid] + x - v;
-    total = s_tmp[BLOCK / kWave];
-    __syncthreads();
-    return r;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ int block_exclusive_i32(int v, int* s_tmp, int& total) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
-    if (lane == kWave - 1) s_tmp[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int w = 0; w < BLOCK / kWave; ++w) {
-            const int t = s_tmp[w];
-            s_tmp[w] = acc;
-            acc += t;
-        }
-        s_tmp[BLOCK / kWave] = acc;
-    }
-    __syncthreads();
-    const int r = s_tmp[wid] + x - v;
-    total = s_tmp[BLOCK / kWave];
-    __syncthreads();
-    return r;
-}
-
 // ------------------------------------------------------------------ step (a)
 // Two look-back chains per tile, one for the product count (sum of column
 // lengths) and one for the number of non-empty columns, each with a 62-bit
 // value: no input, valid or not, can make one overflow into the other.
-template <int XMODE>
-__device__ __forceinline__ uint32_t x_value(const void* x_val, int p, int32_t j) {
-    if constexpr (XMODE == XV_BITS32) return reinterpret_cast<const uint32_t*>(x_val)[p];
-    else if constexpr (XMODE == XV_INDEX) return (uint32_t)j;
-    else if constexpr (XMODE == XV_U8) return reinterpret_cast<const uint8_t*>(x_val)[p] ? 1u : 0u;
-    else return 1u;
-}
-
 template <int BLOCK, int ITEMS, int XMODE, bool BATCH, bool CHAIN>
 __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
     constexpr int TILE = BLOCK * ITEMS;
@@ -417,19 +354,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
 }
 
 // ------------------------------------------------------------------ step (b)
-template <int SR>
-__device__ __forceinline__ uint32_t mult(const float* values, int32_t q, uint32_t xbits) {
-    if constexpr (SR == SR_PLUS_TIMES) {
-        const float av = values ? values[q] : 1.0f;
-        return __float_as_uint(__fmul_rn(av, __uint_as_float(xbits)));
-    } else if constexpr (SR == SR_MIN_SELECT2ND) {
-        return xbits;
-    } else {
-        const uint32_t av = values ? (values[q] != 0.0f ? 1u : 0u) : 1u;
-        return av & (xbits != 0u ? 1u : 0u);
-    }
-}
-
 // One workgroup turns chunks of C = BLOCK * ITEMS consecutive products into
 // bucket runs.  Per chunk: (1) each thread gathers ITEMS products (row id,
 // Mult value) and takes a rank in its bucket from an LDS histogram; (2) the
@@ -670,89 +594,6 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
 }
 
 // ---------------------------------------------------------------- steps (c, d)
-template <int SR>
-__device__ __forceinline__ uint32_t identity() {
-    if constexpr (SR == SR_PLUS_TIMES) return 0u;            // +0.0f
-    else if constexpr (SR == SR_MIN_SELECT2ND) return 0x7fffffffu;
-    else return 0u;
-}
-
-template <int SR>
-__device__ __forceinline__ void accumulate(uint32_t* cell, uint32_t v) {
-    if constexpr (SR == SR_PLUS_TIMES) atomicAdd(reinterpret_cast<float*>(cell), __uint_as_float(v));
-    else if constexpr (SR == SR_MIN_SELECT2ND) atomicMin(reinterpret_cast<int*>(cell), (int)v);
-    else atomicOr(cell, v);
-}
-
-template <int SR>
-__device__ __forceinline__ void store_value(void* y_val, int64_t o, uint32_t v) {
-    if constexpr (SR == SR_OR_AND) reinterpret_cast<uint8_t*>(y_val)[o] = (uint8_t)(v != 0u);
-    else reinterpret_cast<uint32_t*>(y_val)[o] = v;
-}
-
-
-
-// Tile accumulation.  Measured on gfx950 (random addresses in a 128 KB
-// tile, every lane of 256 workgroups of 1024 threads): an LDS add of a
-// 64-bit float retires about 2 lanes per cycle per compute unit, and keeps
-// that rate when a third of the lanes hit a few dozen hub rows; a 32-bit
-// float add retires about a third of a lane per cycle, and a
-// compare-and-swap loop on a 32-bit word about 1.9 on distinct rows but half
-// a lane once hub rows make lanes retry.  So plus-times accumulates every
-// row in fp64 and rounds it to fp32 once, when y is written: faster, and the
-// rounding error no longer grows with the number of terms of a row (fp32
-// sums of a few hundred thousand terms in arbitrary order drift past 1e-5).
-// An fp64 cell starts at -0.0, which only a sum whose every term is -0.0
-// reproduces: such a product also sets the row's bitmap bit, and every other
-// touched row is the one whose cell is no longer -0.0 (a ballot pass after
-// the accumulation sets its bit).  min and or use their native integer
-// atomics and set the bitmap bit with every entry.
-constexpr uint64_t kNegZero64 = 0x8000000000000000ull;
-
-template <int SR, int K>
-__device__ __forceinline__ void add_rows(const uint32_t (&r)[K], const uint32_t (&v)[K], const bool (&ok)[K],
-                                         uint32_t* spa, uint32_t* bm) {
-    if constexpr (SR == SR_PLUS_TIMES) {
-        double* spa64 = reinterpret_cast<double*>(spa);
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            if (ok[u]) {
-                atomicAdd(&spa64[r[u]], (double)__uint_as_float(v[u]));
-                if (v[u] == 0x80000000u) atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            if (ok[u]) {
-                atomicOr(&bm[r[u] >> 5], 1u << (r[u] & 31u));
-                accumulate<SR>(&spa[r[u]], v[u]);
-            }
-        }
-    }
-}
-
-// Bitmap bits of the fp64 cells a plus-times entry reached (cell no longer
-// -0.0), 64 consecutive cells per wave and step: conflict-free 8-byte LDS
-// reads, one ballot, and lane 0 merges the two bitmap words (nothing else
-// writes them after the accumulation).
-template <int BLOCK>
-__device__ __forceinline__ void touched_bits64(const uint32_t* spa, uint32_t* bm, int rows) {
-    const uint64_t* c64 = reinterpret_cast<const uint64_t*>(spa);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    for (int c0 = wid * kWave; c0 < rows; c0 += BLOCK) {
-        const int c = c0 + lane;
-        const bool t = c < rows && c64[c] != kNegZero64;
-        const uint64_t b = __ballot(t);
-        if (lane == 0) {
-            const int w = c0 >> 5;
-            bm[w] |= (uint32_t)b;
-            if (c0 + 32 < rows) bm[w + 1] |= (uint32_t)(b >> 32);
-        }
-    }
-}
-
 // One workgroup per bucket.  The bucket's rows [row0, row0 + T) get an LDS
 // sparse accumulator (T values) and a T-bit touched bitmap.  The whole tile
 // is initialised while the bucket's first entries are in flight (a store
@@ -825,6 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     const int cnt = min(cnt_raw, cap);
     const int nw = (rows + 31) >> 5;
     const bool small = cnt <= BLOCK * ITEMS;
+    const bool sparse = cnt < rows / 8;   // plus-times: mark rows per entry, skip the ballot pass
     uint32_t rr[ITEMS], vv[ITEMS];
     if (small) {   // the whole bucket in registers: issue every load before the tile set-up
 #pragma unroll
@@ -860,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                 bad = true;
             }
         }
-        add_rows<SR, ITEMS>(rr, vv, ok, spa, bm);
+        add_rows<SR, ITEMS>(rr, vv, ok, spa, bm, sparse);
     } else {
         constexpr int kBatch = 8;   // entries per thread in flight per step
         for (int e0 = 0; e0 < cnt; e0 += BLOCK * kBatch) {
@@ -882,12 +724,12 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
                     bad = true;
                 }
             }
-            add_rows<SR, kBatch>(r, v, ok, spa, bm);
+            add_rows<SR, kBatch>(r, v, ok, spa, bm, sparse);
         }
     }
     if (bad) atomicOr(&a.ctrl->err, ERR_BUCKET_OVERFLOW);
     __syncthreads();
-    if constexpr (kWide) {
+    if (kWide && !sparse) {
         touched_bits64<BLOCK>(spa, bm, rows);
         __syncthreads();
     }

@@ -68,13 +68,22 @@ def oracle_x(semiring, S, xv):
     return xv
 
 
-def test_headline_multiply_full_size(spv, s22):
+@pytest.mark.parametrize("launch", [0, 2], ids=["default_three_launches", "one_launch"])
+def test_headline_multiply_full_size(spv, s22, launch):
+    """The benchmark's default schedule (three launches) and the one-launch
+    multiply on the same inputs."""
     A, M = s22
     f = synth.density_f(A.n, 0.01)
     assert f == 41943
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in (0, 1, 17, 63)]
+    if launch:
+        s = M.schedule
+        s.launch = launch
+        M.schedule = s
     eff = spv.spmspv_effective_schedule(M.handle, f, 0)
-    assert (eff.direction, eff.scatter_block * eff.scatter_items) == (0, 4096)
+    assert eff.direction == 0 and eff.launch == (launch or 1)
+    if launch == 0:
+        assert eff.scatter_block * eff.scatter_items == 4096
     stream = torch.cuda.current_stream()
     outs = []
     for S, xv in xs:   # back to back on one stream, each into its own output
@@ -86,6 +95,7 @@ def test_headline_multiply_full_size(spv, s22):
         outs.append((y_idx, y_val, d_nnz))
     torch.cuda.synchronize()
     assert M.last_stats()["err"] == 0
+    M.schedule = None
     for (S, xv), (y_idx, y_val, d_nnz) in zip(xs, outs):
         oi, ov, W = oracle.spmspv(A, S, xv)
         k = int(to_np(d_nnz)[0])

@@ -6,6 +6,10 @@ many buckets and scatter chunks with ragged tails; the edge cases cover
 empty input, empty columns, rectangular matrices, unit vectors, permutation
 matrices, a hub row, bucket sizes above the register-resident limit,
 unsorted row ids, small output capacity and invalid input.
+
+Every test runs twice: with the three-launch pipeline (scan, bucketing,
+merge) and with the one-launch cooperative kernel (schedule field launch =
+1 and 2).
 """
 import numpy as np
 import pytest
@@ -30,11 +34,34 @@ def spv():
     return spv
 
 
+LAUNCH = {"mode": 1}
+
+
+@pytest.fixture(scope="module", autouse=True, params=[1, 2], ids=["three_launches", "one_launch"])
+def launch(request):
+    LAUNCH["mode"] = request.param
+    yield request.param
+    LAUNCH["mode"] = 1
+
+
+def make(spv, A, **kw):
+    """Matrix handle whose push calls take the module's launch mode."""
+    M = spv.Matrix.from_csc(A, **kw)
+    set_launch(M)
+    return M
+
+
+def set_launch(M):
+    s = M.schedule
+    s.launch = LAUNCH["mode"]
+    M.schedule = s
+
+
 @pytest.fixture(scope="module")
-def c1(spv):
+def c1(spv, launch):
     """R-MAT scale 14, edge factor 16, directed, fp32 values (0, 1]."""
     A = synth.rmat(14, seed=1)
-    return A, spv.Matrix.from_csc(A)
+    return A, make(spv, A)
 
 
 def dev(a, dtype=None):
@@ -95,7 +122,7 @@ def test_schedule_invariance(spv, c1, sched):
     """Int results and index sets do not depend on the schedule."""
     A, M = c1
     tl, sb, si, mb = sched
-    s = spv.Schedule(0, tl, sb, si, mb, 0)
+    s = spv.Schedule(0, tl, sb, si, mb, 0, LAUNCH["mode"])
     M.schedule = s
     try:
         assert M.schedule.as_dict() == s.as_dict()
@@ -105,6 +132,7 @@ def test_schedule_invariance(spv, c1, sched):
             run_and_compare(spv, M, A, S, spv.PLUS_TIMES_F32, xv)
     finally:
         M.schedule = None
+        set_launch(M)
 
 
 @pytest.mark.parametrize("sb", [256, 512])
@@ -113,8 +141,8 @@ def test_more_buckets_than_scatter_threads(spv, sb):
     two buckets (the looped reservation), with 512 for one (the reservation
     that overlaps the LDS sort)."""
     A = synth.rmat(17, seed=17, symmetrize=True)
-    M = spv.Matrix.from_csc(A)
-    M.schedule = spv.Schedule(0, 8, sb, 4, 256, 0)
+    M = make(spv, A)
+    M.schedule = spv.Schedule(0, 8, sb, 4, 256, 0, LAUNCH["mode"])
     assert (A.m + 255) // 256 == 512
     for f in (40, 2000, 60000):
         S, xv = synth.sparse_x(A.n, f, seed=900 + f)
@@ -142,7 +170,7 @@ def test_rectangular(spv, shape):
     cols = rng.integers(0, n, nt).astype(np.int32)
     colptr, rowids = synth.coo_to_csc(m, n, rows, cols, drop_self=False)
     A = synth.CSC(m, n, colptr, rowids, synth.values(rowids.size, 3))
-    M = spv.Matrix.from_csc(A)
+    M = make(spv, A)
     for f in sorted({1, max(1, n // 10), n}):
         S, xv = synth.sparse_x(n, f, seed=f)
         run_and_compare(spv, M, A, S, spv.PLUS_TIMES_F32, xv, sorted_output=True)
@@ -163,7 +191,7 @@ def test_permutation_matrix_bit_exact(spv):
     n = 100000
     perm = np.random.default_rng(3).permutation(n).astype(np.int32)
     A = synth.CSC(n, n, np.arange(n + 1, dtype=np.int32), perm, synth.values(n, 5))
-    M = spv.Matrix.from_csc(A)
+    M = make(spv, A)
     S, xv = synth.sparse_x(n, 40000, seed=9)
     gi, gv, nnz = M.spmspv(dev(S), dev(xv), sorted_output=True)
     o = np.argsort(perm[S])
@@ -180,14 +208,13 @@ def test_hub_row_and_large_buckets(spv):
     cols = np.concatenate([np.arange(n), rng.integers(0, n, 6 * n)]).astype(np.int32)
     colptr, rowids = synth.coo_to_csc(n, n, rows, cols, drop_self=False)
     A = synth.CSC(n, n, colptr, rowids, synth.values(rowids.size, 8))
-    M = spv.Matrix.from_csc(A)
+    M = make(spv, A)
     for tl in (8, 12):
-        M.schedule = spv.Schedule(0, tl, 256, 8, 256, 0)
+        M.schedule = spv.Schedule(0, tl, 256, 8, 256, 0, LAUNCH["mode"])
         S, xv = synth.sparse_x(n, n, seed=2)
         run_and_compare(spv, M, A, S, spv.PLUS_TIMES_F32, xv)
         run_and_compare(spv, M, A, S, spv.MIN_SELECT2ND_I32, S.astype(np.int32), sorted_output=True)
         run_and_compare(spv, M, A, S, spv.OR_AND_BOOL, np.ones(n, np.uint8))
-    M.schedule = None
 
 
 def test_unsorted_rowids_and_zero_values(spv):
@@ -200,7 +227,7 @@ def test_unsorted_rowids_and_zero_values(spv):
     vals = A.values.copy()
     vals[rng.random(vals.size) < 0.3] = 0.0
     B = synth.CSC(A.m, A.n, A.colptr, rowids, vals)
-    M = spv.Matrix.from_csc(B)
+    M = make(spv, B)
     S, xv = synth.sparse_x(A.n, 1500, seed=6)
     run_and_compare(spv, M, B, S, spv.PLUS_TIMES_F32, xv)
     run_and_compare(spv, M, B, S, spv.OR_AND_BOOL, (rng.random(S.size) < 0.5).astype(np.uint8), sorted_output=True)
@@ -209,7 +236,7 @@ def test_unsorted_rowids_and_zero_values(spv):
 
 def test_pattern_matrix(spv):
     A = synth.rmat(13, seed=2, with_values=False)
-    M = spv.Matrix.from_csc(A)
+    M = make(spv, A)
     S, xv = synth.sparse_x(A.n, 800, seed=3)
     run_and_compare(spv, M, A, S, spv.PLUS_TIMES_F32, xv)
     run_and_compare(spv, M, A, S, spv.OR_AND_BOOL, None, flags=spv.X_ALL_TRUE)
@@ -256,18 +283,33 @@ def test_invalid_inputs(spv, c1):
 
 
 def test_duplicate_x_is_memory_safe(spv):
-    """Duplicated x indices break the distinctness precondition; buckets may
-    overflow, which the device reports while staying inside the workspace."""
+    """Duplicated x indices break the distinctness precondition.  The three
+    launches' buckets may overflow, which the device reports while staying
+    inside the workspace; the one launch has no per-bucket capacity and
+    combines the repeated products like any others (as the oracle does),
+    reporting an error only when the products outnumber A's stored entries."""
     n = 4096
     colptr = np.arange(n + 1, dtype=np.int32)
     A = synth.CSC(n, n, colptr, np.arange(n, dtype=np.int32), np.ones(n, np.float32))   # identity
-    M = spv.Matrix.from_csc(A)
+    M = make(spv, A)
     S = np.full(3000, 7, np.int32)   # the same column 3000 times: row 7's bucket holds 2^tile_log2 slots
     y = torch.empty(n, dtype=torch.int32, device="cuda")
     yv = torch.empty(n, dtype=torch.float32, device="cuda")
-    with pytest.raises(spv.SpmspvError) as e:
-        spv.spmspv_run(M.handle, 0, 0, S.size, dev(S), dev(np.ones(S.size, np.float32)), y, yv, n)
-    assert e.value.status == spv.EDEVICE
+    if LAUNCH["mode"] == 1:
+        with pytest.raises(spv.SpmspvError) as e:
+            spv.spmspv_run(M.handle, 0, 0, S.size, dev(S), dev(np.ones(S.size, np.float32)), y, yv, n)
+        assert e.value.status == spv.EDEVICE
+    else:
+        nnz = spv.spmspv_run(M.handle, 0, 0, S.size, dev(S), dev(np.ones(S.size, np.float32)), y, yv, n)
+        assert nnz == 1 and int(y[0]) == 7 and float(yv[0]) == 3000.0
+        # column 0 with ten entries selected n times: more products than A stores
+        cp = np.concatenate([[0], np.arange(10, n + 10)]).astype(np.int32)
+        ri = np.concatenate([np.arange(10), np.arange(1, n)]).astype(np.int32)
+        M5 = make(spv, synth.CSC(n, n, cp, ri, np.ones(ri.size, np.float32)))
+        S5 = np.zeros(n, np.int32)
+        with pytest.raises(spv.SpmspvError) as e:
+            spv.spmspv_run(M5.handle, 0, 0, S5.size, dev(S5), dev(np.ones(S5.size, np.float32)), y, yv, n)
+        assert e.value.status == spv.EDEVICE
     S2, xv = synth.sparse_x(n, 100, seed=1)
     run_and_compare(spv, M, A, S2, spv.PLUS_TIMES_F32, xv)
 
@@ -288,6 +330,8 @@ def test_profile_and_stats(spv, c1):
     for _ in range(5):
         M.spmspv(dev(S), dev(xv), flags=spv.PROFILE)
     ms, calls = spv.spmspv_profile_read(M.handle)
-    assert calls == 5 and all(t > 0 for t in ms)
+    assert calls == 5 and ms[0] > 0
+    if LAUNCH["mode"] == 1:
+        assert all(t > 0 for t in ms)
     st = M.last_stats()
     assert st["W"] == int(A.degrees()[S].sum()) and st["maxlen"] == int(A.degrees()[S].max())
