@@ -283,6 +283,25 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
 
+/* ---- allocation-free multiply.  For callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, hosts that forbid
+ * allocation): y <- A x as spmspv_create followed by spmspv_run would
+ * compute it, with no handle and no workspace argument.  The workspace lives
+ * in a device array of the library's own, 64 MiB per device, held until the
+ * process ends, so the call allocates nothing: matrices whose
+ * spmspv_workspace_size(m, n, nnz, 0) exceeds 64 MiB are refused with
+ * EINVAL (about nnz <= 5M with m, n <= 1M; *h_scratch_bytes, when
+ * non-NULL, receives the size needed).  Arguments and results are those of
+ * spmspv_create and spmspv_run (flags: SORTED_OUTPUT, X_VAL_IS_INDEX,
+ * X_ALL_TRUE); each call also sizes the buckets from A (one pass over the
+ * row ids), which a handle does once.  Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * host threads) race and must be ordered by the caller.                  */
+int spmspv_run_static(int64_t m, int64_t n, int64_t nnz, const int32_t* colptr, const int32_t* rowids,
+                      const float* values, int semiring, int flags, int64_t f, const int32_t* x_idx,
+                      const void* x_val, int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y,
+                      int64_t* h_nnz_y, size_t* h_scratch_bytes, void* stream);
+
 /* ---- data-driven PageRank (the Introduction names PageRank among the
  * data-driven SpMSpV uses, where a vertex stops sending updates once its
  * value has converged; the paper gives no formula, this is the delta form):

@@ -47,7 +47,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
-    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule",
+    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static",
 )
 
 
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_status_string.argtypes = [ci]
     lib.spmspv_status_string.restype = ctypes.c_char_p
     lib.spmspv_run_masked.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
+    lib.spmspv_run_static.argtypes = [i64, i64, i64, vp, vp, vp, ci, ci, i64, vp, vp, vp, vp, i64, vp,
+                                      ctypes.POINTER(i64), ctypes.POINTER(sz), vp]
     lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
     lib.spmspv_selector_classes.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.spmspv_class_tile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int32)]
@@ -187,6 +189,23 @@ def spmspv_run_masked(handle, semiring, flags, f, x_idx, x_val, mask, y_idx, y_v
                                             _ptr(y_idx), _ptr(y_val), y_capacity, _ptr(d_nnz_y),
                                             ctypes.byref(h) if sync else None, _stream(stream)))
     return h.value if sync else None
+
+
+def spmspv_run_static(m, n, nnz, colptr, rowids, values, semiring, flags, f, x_idx, x_val, y_idx, y_val,
+                      y_capacity, d_nnz_y=None, sync=True, stream=None) -> Optional[int]:
+    """Allocation-free y <- A x (no handle, no workspace: the library's own
+    device scratch).  Returns nnz(y) when sync."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run_static(m, n, nnz, _ptr(colptr), _ptr(rowids), _ptr(values), semiring, flags,
+                                            f, _ptr(x_idx), _ptr(x_val), _ptr(y_idx), _ptr(y_val), y_capacity,
+                                            _ptr(d_nnz_y), ctypes.byref(h) if sync else None, None,
+                                            _stream(stream)))
+    return h.value if sync else None
+
+
+def spmspv_static_scratch_need(m, n, nnz) -> int:
+    """Scratch bytes spmspv_run_static needs for an m x n matrix with nnz entries."""
+    return spmspv_workspace_size(m, n, nnz, 0)
 
 
 def spmspv_selector_load(handle, params, mean, std, stream=None):

@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <string>
+#include <atomic>
+#include <mutex>
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -830,6 +832,38 @@ hipEvent_t* profile_slot(spmspv_matrix* A) {
     return &A->prof_ev[size_t(A->prof_used++) * 6];
 }
 
+// Point a handle at matrix arrays and a workspace laid out by make_layout.
+void bind_workspace(spmspv_matrix* A, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
+                    const int32_t* rowids, const float* values, char* ws, int flags) {
+    A->m = m;
+    A->n = n;
+    A->nnz = nnz;
+    A->colptr = colptr;
+    A->rowids = rowids;
+    A->values = values;
+    A->L = make_layout(m, n, nnz, flags);
+    A->ws = ws;
+    const Layout& L = A->L;
+    A->ctrl = reinterpret_cast<Ctrl*>(A->ws + L.ctrl);
+    A->rcp = reinterpret_cast<int32_t*>(A->ws + L.rcp);
+    A->cstart = reinterpret_cast<int32_t*>(A->ws + L.cstart);
+    A->coff = reinterpret_cast<int32_t*>(A->ws + L.coff);
+    A->cxv = reinterpret_cast<uint32_t*>(A->ws + L.cxv);
+    A->chunk_col = reinterpret_cast<int32_t*>(A->ws + L.chunk_col);
+    A->lb1 = reinterpret_cast<uint64_t*>(A->ws + L.lb1);
+    A->cursor = reinterpret_cast<int32_t*>(A->ws + L.cursor);
+    A->lb3 = reinterpret_cast<uint64_t*>(A->ws + L.lb3);
+    A->buckets = reinterpret_cast<uint2*>(A->ws + L.buckets);
+    A->visited = reinterpret_cast<uint32_t*>(A->ws + L.visited);
+    A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
+    A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
+    A->front2 = reinterpret_cast<int32_t*>(A->ws + L.front2);
+    A->disc = reinterpret_cast<uint32_t*>(A->ws + L.disc);
+    A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
+    A->bar = reinterpret_cast<uint32_t*>(A->ws + L.bar);
+    A->selector = reinterpret_cast<float*>(A->ws + L.selector);
+}
+
 int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -848,6 +882,58 @@ hipError_t reset_persistent_state(spmspv_matrix* A, hipStream_t s) {
 int clear_err(spmspv_matrix* A, hipStream_t s) {
     HIP_TRY(launch_fill_u32(&A->ctrl->err, 0u, 1, s));
     HIP_TRY(reset_persistent_state(A, s));
+    return SPMSPV_OK;
+}
+
+}  // namespace
+
+// Allocation-free multiply (spmspv_run_static): the workspace a handle's
+// workspace argument would bring in lives in this file-scope array instead,
+// one copy per device, held until the process ends.  In host code the
+// array's name is only a stand-in: its device address is looked up once per
+// device with hipGetSymbolAddress and every launch takes that address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+
+struct StaticDevice {
+    std::atomic<void*> ptr{nullptr};   // device address of `scratch` on this device
+    int num_cu = 0;
+    size_t lds_max = 0;
+};
+StaticDevice g_static[kStaticMaxDevices];
+std::mutex g_static_mu;
+
+// Address of this device's scratch array (and its unit count and LDS size),
+// found once per device with that device current.
+int static_scratch(int* dev_out, void** ptr_out, StaticDevice** info_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(SPMSPV_EUNSUPPORTED, "device index beyond the static table");
+    StaticDevice& d = g_static[dev];
+    void* p = d.ptr.load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        p = d.ptr.load(std::memory_order_relaxed);
+        if (!p) {
+            int v = 0;
+            d.num_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                           ? v : 256;
+            d.lds_max = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                         v > 0) ? (size_t)v : 65536;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                       "hipGetSymbolAddress(scratch)");
+            d.ptr.store(p, std::memory_order_release);
+        }
+    }
+    *dev_out = dev;
+    *ptr_out = p;
+    *info_out = &d;
     return SPMSPV_OK;
 }
 
@@ -896,33 +982,8 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     auto* A = new spmspv_matrix();
-    A->m = m;
-    A->n = n;
-    A->nnz = nnz;
-    A->colptr = colptr;
-    A->rowids = rowids;
-    A->values = values;
-    A->L = make_layout(m, n, nnz, flags);
-    A->ws = static_cast<char*>(workspace);
+    bind_workspace(A, m, n, nnz, colptr, rowids, values, static_cast<char*>(workspace), flags);
     const Layout& L = A->L;
-    A->ctrl = reinterpret_cast<Ctrl*>(A->ws + L.ctrl);
-    A->rcp = reinterpret_cast<int32_t*>(A->ws + L.rcp);
-    A->cstart = reinterpret_cast<int32_t*>(A->ws + L.cstart);
-    A->coff = reinterpret_cast<int32_t*>(A->ws + L.coff);
-    A->cxv = reinterpret_cast<uint32_t*>(A->ws + L.cxv);
-    A->chunk_col = reinterpret_cast<int32_t*>(A->ws + L.chunk_col);
-    A->lb1 = reinterpret_cast<uint64_t*>(A->ws + L.lb1);
-    A->cursor = reinterpret_cast<int32_t*>(A->ws + L.cursor);
-    A->lb3 = reinterpret_cast<uint64_t*>(A->ws + L.lb3);
-    A->buckets = reinterpret_cast<uint2*>(A->ws + L.buckets);
-    A->visited = reinterpret_cast<uint32_t*>(A->ws + L.visited);
-    A->front[0] = reinterpret_cast<int32_t*>(A->ws + L.front0);
-    A->front[1] = reinterpret_cast<int32_t*>(A->ws + L.front1);
-    A->front2 = reinterpret_cast<int32_t*>(A->ws + L.front2);
-    A->disc = reinterpret_cast<uint32_t*>(A->ws + L.disc);
-    A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
-    A->bar = reinterpret_cast<uint32_t*>(A->ws + L.bar);
-    A->selector = reinterpret_cast<float*>(A->ws + L.selector);
 
     auto bail = [&](int status) {
         delete A;
@@ -1121,6 +1182,70 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
             return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
                                             " (1 = x index range, 2 = duplicate x index, 4 = look-back bound)");
         }
+        if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
+    }
+    return SPMSPV_OK;
+}
+
+int spmspv_run_static(int64_t m, int64_t n, int64_t nnz, const int32_t* colptr, const int32_t* rowids,
+                      const float* values, int semiring, int flags, int64_t f, const int32_t* x_idx,
+                      const void* x_val, int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y,
+                      int64_t* h_nnz_y, size_t* h_scratch_bytes, void* stream) {
+    size_t need = 0;
+    int rc = spmspv_workspace_size(m, n, nnz, 0, &need);
+    if (rc) return rc;
+    if (h_scratch_bytes) *h_scratch_bytes = need;
+    if (need > kStaticScratchBytes)
+        return fail(SPMSPV_EINVAL, "matrix needs " + std::to_string(need) + " bytes of scratch; the static scratch "
+                                   "holds " + std::to_string(kStaticScratchBytes) + " (use spmspv_create)");
+    if (!colptr || (nnz > 0 && !rowids)) return fail(SPMSPV_EINVAL, "NULL matrix");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (f < 0 || f > n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    if (f > 0 && !x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
+    if (y_capacity < 0 || (y_capacity > 0 && !y_idx)) return fail(SPMSPV_EINVAL, "bad y buffer");
+    if (flags & ~(SPMSPV_SORTED_OUTPUT | SPMSPV_X_VAL_IS_INDEX | SPMSPV_X_ALL_TRUE))
+        return fail(SPMSPV_EINVAL, "spmspv_run_static takes only SORTED_OUTPUT, X_VAL_IS_INDEX and X_ALL_TRUE");
+    int xmode = XV_BITS32;
+    if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
+    else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
+    if (f > 0 && !x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    void* ws = nullptr;
+    StaticDevice* info = nullptr;
+    if ((rc = static_scratch(&dev, &ws, &info))) return rc;
+
+    // A handle on the stack over the scratch (no allocation: its host
+    // containers stay empty), set up as spmspv_create sets one up, without
+    // the host read of the longest column (the bucketing grid is sized from
+    // nnz instead).
+    spmspv_matrix M;
+    bind_workspace(&M, m, n, nnz, colptr, rowids, values, static_cast<char*>(ws), 0);
+    M.device = dev;
+    M.num_cu = info->num_cu;
+    M.lds_max = info->lds_max;
+    M.maxdeg = nnz > INT32_MAX ? INT32_MAX : (int32_t)nnz;
+    default_schedule(&M, &M.sched);
+    if ((rc = check_schedule(&M, &M.sched))) return fail(SPMSPV_EUNSUPPORTED, "matrix too tall for the LDS bucket layout");
+    M.sched = sized_for_call(&M, f);
+    const Layout& L = M.L;
+    // The scratch keeps the previous call's contents: clear the control block,
+    // counters and look-back words (a fill kernel, not a memset).
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(M.ws), 0u, int64_t(L.buckets / 4), s));
+    HIP_TRY(launch_validate_colptr(colptr, (int32_t)n, nnz, M.ctrl, s));
+    HIP_TRY(launch_row_counts(rowids, nnz, (int32_t)m, M.rcp, M.ctrl, s));
+    HIP_TRY(launch_exclusive_scan_i32(M.rcp, m + 1, reinterpret_cast<int32_t*>(M.ws + L.partials), s));
+    rc = enqueue(&M, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, nullptr, s,
+                 nullptr);
+    if (rc) return rc;
+    if (h_nnz_y) {
+        Ctrl h{};
+        if ((rc = read_ctrl(&M, &h, s))) return rc;
+        *h_nnz_y = h.nnz_y;
+        if (h.err & (ERR_CSC | ERR_ROW_RANGE)) return fail(SPMSPV_EINVAL, "invalid CSC (colptr or row ids)");
+        if (h.err)
+            return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
+                                            " (1 = x index range, 2 = duplicate x index, 4 = look-back bound)");
         if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
     }
     return SPMSPV_OK;

@@ -14,5 +14,10 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run last within the GPU tier so cheap failures surface first.
-    items.sort(key=lambda it: 1 if it.get_closest_marker("gpu") and "full" in it.name else 0)
+    # Full-size GPU tests run late so cheap failures surface first; the
+    # allocation-free entry point's tests run last of all.
+    def rank(it):
+        if "test_zz_no_alloc" in it.nodeid:
+            return 2
+        return 1 if it.get_closest_marker("gpu") and "full" in it.name else 0
+    items.sort(key=rank)

@@ -62,3 +62,17 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.spmspv_destroy(None) == spv.OK
     assert lib.spmspv_status_string(spv.ECAPACITY).decode() == "output capacity too small"
     assert lib.spmspv_last_error().decode() != ""
+
+
+def test_static_multiply_refuses_oversized_matrix_without_gpu():
+    """The allocation-free multiply checks its scratch limit on the host,
+    before any device call: a matrix whose workspace exceeds the 64 MiB
+    scratch is refused with EINVAL and the size it would need."""
+    spv, lib = _lib()
+    need = ctypes.c_size_t(0)
+    m = n = 1 << 22
+    rc = lib.spmspv_run_static(m, n, 20_000_000, None, None, None, 0, 0, 0, None, None, None, None, 0, None, None,
+                               ctypes.byref(need), None)
+    assert rc == spv.EINVAL
+    assert need.value == spv.spmspv_workspace_size(m, n, 20_000_000, 0) > (64 << 20)
+    assert "static scratch" in lib.spmspv_last_error().decode()
