@@ -231,7 +231,8 @@ def main():
     cpu_s = time.perf_counter() - t_start
     result["cpu_baseline"] = {"value": round(prod / cpu_s / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                               "sample": f"{done} SpMSpV calls (rotating the same {args.nx} x vectors) in {cpu_s:.1f}s, "
-                                        f"fp64 dense-accumulator oracle, one host thread"}
+                                        f"fp64 dense-accumulator oracle, one host thread",
+                              "host": host_info()}
     log(f"cpu oracle: {result['cpu_baseline']['value']} GTEPS over {done} calls")
 
     if args.schedules:
@@ -249,6 +250,25 @@ def main():
         if not args.no_selector_eval:
             result["learned_selector"] = selector_eval(spv, dev, args.selector_scale)
     print(json.dumps(result))
+
+
+def host_info():
+    """The host the oracle ran on: logical CPUs, the ones this process may
+    use, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
 
 
 COPY_BYTES = 256 << 20

@@ -8,8 +8,10 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -380,6 +382,31 @@ def spmspv_destroy(handle):
 
 
 # ------------------------------------------------------------ convenience
+# Handles still open when the interpreter exits are released by an exit
+# handler, which runs while the HIP runtime is fully up (before the C-level
+# exit handlers and library destructors that tear it down), after the
+# device has finished its work; a handle's own __del__ may otherwise run at
+# an arbitrary point of interpreter shutdown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    if not _live:
+        return
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for M in list(_live):
+        try:
+            M.close()
+        except Exception:
+            pass
+
+
 class Matrix:
     """A CSC matrix resident on the GPU with its library handle and workspace.
 
@@ -398,6 +425,7 @@ class Matrix:
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.handle = spmspv_create(self.m, self.n, self.nnz, self.colptr, self.rowids, self.values, self.workspace,
                                     self.ws_bytes, flags)
+        _live.add(self)
         self._d_nnz = torch.zeros(1, dtype=torch.int64, device=device)
 
     @classmethod

@@ -291,3 +291,14 @@ def test_validate_codes():
     bad = A.rowids.copy()
     bad[0] = A.m
     assert oracle.validate(A.m, A.n, A.colptr, bad, np.array([0])) == -2
+    # colptr: must start at 0 and never decrease (the CSC definition)
+    cp = A.colptr.copy()
+    cp[0] = 1
+    assert oracle.validate(A.m, A.n, cp, A.rowids, np.array([0])) == -1
+    j = int(np.argmax(np.diff(A.colptr) > 0))      # a non-empty column: make its end fall below its start
+    cp = A.colptr.copy()
+    cp[j + 1] = cp[j] - 1
+    assert oracle.validate(A.m, A.n, cp, A.rowids, np.array([0])) == -1
+    # a valid colptr with an empty column passes
+    cp = np.concatenate([[0], A.colptr]).astype(np.int32)
+    assert oracle.validate(A.m, A.n + 1, cp, A.rowids, np.array([0, A.n])) == 0
