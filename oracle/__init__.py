@@ -47,6 +47,10 @@ def _bind(lib):
     lib.oracle_spmspv.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp, i64, vp, vp, vp, ctypes.c_int, vp, vp,
                                   vp, vp]
     lib.oracle_spmspv_f32seq.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+    if hasattr(lib, "oracle_spmspv_graphblas"):
+        ci = ctypes.c_int
+        lib.oracle_spmspv_graphblas.argtypes = [ci, i64, i64, vp, vp, vp, i64, vp, vp, ci, vp, vp, i64, ci, ci, vp,
+                                                vp, i64, ci, vp, vp, vp]
     lib.oracle_bfs.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp]
     lib.oracle_bfs.restype = ctypes.c_int
     if hasattr(lib, "oracle_pagerank"):
@@ -114,6 +118,46 @@ def spmspv(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES,
         raise ValueError(f"oracle_spmspv rc={rc}")
     k = nnz.value
     return yi[:k].copy(), yv[:k].copy(), W.value
+
+
+ACCUM_NONE, ACCUM_ADD, ACCUM_FIRST, ACCUM_SECOND = 0, 1, 2, 3
+
+
+def spmspv_graphblas(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES,
+                     mask_idx: Optional[np.ndarray] = None, mask_val: Optional[np.ndarray] = None,
+                     complement: bool = False, w_idx: Optional[np.ndarray] = None,
+                     w_val: Optional[np.ndarray] = None, accum: int = ACCUM_NONE, replace: bool = False,
+                     lib=None):
+    """w<mask, replace> = w accum (A x), the GraphBLAS rules on top of
+    Algorithm 1's product (the masked SpMSpV of the paper's conclusions).
+
+    mask_idx None: every row is in the mask (complement: none is);
+    mask_val None: structural mask, else a row counts only if its value is
+    nonzero.  w_val: plus-times float64, min-select2nd int32, or-and uint8.
+    Returns (y_idx int32 ascending, y_val).
+    """
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    dt = {PLUS_TIMES: np.float64, MIN_SELECT2ND: np.int32, OR_AND: np.uint8}[semiring]
+    xdt = {PLUS_TIMES: np.float32, MIN_SELECT2ND: np.int32, OR_AND: np.uint8}[semiring]
+    xv = np.ascontiguousarray(x_val, xdt)
+    has_mask = mask_idx is not None
+    mi = np.ascontiguousarray(mask_idx if has_mask else np.zeros(0), np.int32)
+    mv = None if mask_val is None else np.ascontiguousarray(mask_val, np.uint8)
+    wi = np.ascontiguousarray(np.zeros(0) if w_idx is None else w_idx, np.int32)
+    wv = np.ascontiguousarray(np.zeros(wi.size) if w_val is None else w_val, dt)
+    yi = np.empty(max(A.m, 1), np.int32)
+    yv = np.empty(max(A.m, 1), dt)
+    nnz = ctypes.c_int64(0)
+    vals = None if A.values is None else np.ascontiguousarray(A.values, np.float32)
+    rc = lib.oracle_spmspv_graphblas(semiring, A.m, A.n, _p(A.colptr), _p(A.rowids), _p(vals), x_idx.size,
+                                     _p(x_idx), _p(xv), int(has_mask), _p(mi), _p(mv), mi.size, int(bool(complement)),
+                                     int(accum), _p(wi), _p(wv), wi.size, int(bool(replace)), _p(yi), _p(yv),
+                                     ctypes.byref(nnz))
+    if rc != 0:
+        raise ValueError(f"oracle_spmspv_graphblas rc={rc}")
+    k = nnz.value
+    return yi[:k].copy(), yv[:k].copy()
 
 
 def spmspv_f32seq(A, x_idx: np.ndarray, x_val: np.ndarray, lib=None):

@@ -13,6 +13,7 @@
  *                        used for rounding pins.
  *   oracle_bfs           FIFO-queue breadth-first search levels, parents by
  *                        the minimum-parent rule.
+ *   oracle_spmspv_graphblas  masked multiply with accumulate / replace.
  *   oracle_pagerank      data-driven (delta) PageRank in fp64.
  *   oracle_mlp_*         fp64 forward / backward of the schedule-selector MLP.
  *
@@ -135,6 +136,112 @@ int oracle_spmspv(int semiring, int64_t m, int64_t n, const int32_t* colptr, con
     *W = work;
     free(seen); free(acc_d); free(acc_i); free(acc_b);
     return 0;
+}
+
+/*
+ * Masked multiply with accumulation, w<mask, replace> = w (accum) (A x): the
+ * generalisation of the BFS visited mask that the paper's conclusions name
+ * as future work, with the mask, accumulate and replace rules of the
+ * GraphBLAS standard.
+ *   t = A x, structural pattern (oracle_spmspv, no mask).
+ *   Mask: has_mask = 0 means every row is in the mask.  Otherwise row i is
+ *     in it when it is listed in mask_idx[0..mask_count) and, for a value
+ *     mask (mask_val != NULL), its listed value is nonzero; `complement`
+ *     inverts membership (with has_mask = 0: no row is in the mask).
+ *   w: w_idx[0..w_count) distinct rows, any order, values w_val (plus-times
+ *     double, min-select2nd int32, or-and uint8).
+ *   accum: 0 none, 1 the semiring's Add, 2 first (w wins), 3 second (t wins).
+ *   z(i) = accum(w(i), t(i)) where both are present and accum != 0;
+ *          t(i) where t(i) is present (accum == 0 or w(i) absent);
+ *          w(i) where only w(i) is present and accum != 0; else absent.
+ *   result(i) = z(i) for rows in the mask; for the other rows w(i) when
+ *     replace == 0, absent when replace != 0.
+ * Output ascending in y_idx / y_val (value type as w's).  Returns 0, or
+ * -1 for an index out of range.
+ */
+int oracle_spmspv_graphblas(int semiring, int64_t m, int64_t n, const int32_t* colptr, const int32_t* rowids,
+                            const float* values, int64_t f, const int32_t* x_idx, const void* x_val, int has_mask,
+                            const int32_t* mask_idx, const uint8_t* mask_val, int64_t mask_count, int complement,
+                            int accum, const int32_t* w_idx, const void* w_val, int64_t w_count, int replace,
+                            int32_t* y_idx, void* y_val, int64_t* nnz_y) {
+    const size_t M = (size_t)(m > 0 ? m : 1);
+    int32_t* t_idx = (int32_t*)malloc(M * sizeof(int32_t));
+    void* t_val = malloc(M * 8);
+    unsigned char* t_has = (unsigned char*)calloc(M, 1);
+    unsigned char* w_has = (unsigned char*)calloc(M, 1);
+    unsigned char* in_mask = (unsigned char*)calloc(M, 1);
+    double* td = (double*)calloc(M, sizeof(double));
+    double* wd = (double*)calloc(M, sizeof(double));
+    int32_t* ti = (int32_t*)calloc(M, sizeof(int32_t));
+    int32_t* wi = (int32_t*)calloc(M, sizeof(int32_t));
+    int rc = 0;
+    int64_t nt = 0, W = 0, count = 0;
+    if (oracle_spmspv(semiring, m, n, colptr, rowids, values, f, x_idx, x_val, NULL, 1, t_idx, t_val, &nt, &W)) {
+        rc = -1;
+        goto done;
+    }
+    for (int64_t r = 0; r < nt; ++r) {
+        const int32_t i = t_idx[r];
+        t_has[i] = 1;
+        if (semiring == OR_PLUS_TIMES) td[i] = ((const double*)t_val)[r];
+        else if (semiring == OR_MIN_SELECT2ND) ti[i] = ((const int32_t*)t_val)[r];
+        else ti[i] = ((const uint8_t*)t_val)[r];
+    }
+    for (int64_t r = 0; r < w_count; ++r) {
+        const int32_t i = w_idx[r];
+        if (i < 0 || i >= m) { rc = -1; goto done; }
+        w_has[i] = 1;
+        if (semiring == OR_PLUS_TIMES) wd[i] = ((const double*)w_val)[r];
+        else if (semiring == OR_MIN_SELECT2ND) wi[i] = ((const int32_t*)w_val)[r];
+        else wi[i] = ((const uint8_t*)w_val)[r];
+    }
+    if (has_mask) {
+        for (int64_t r = 0; r < mask_count; ++r) {
+            const int32_t i = mask_idx[r];
+            if (i < 0 || i >= m) { rc = -1; goto done; }
+            if (!mask_val || mask_val[r] != 0) in_mask[i] = 1;
+        }
+    } else {
+        for (int64_t i = 0; i < m; ++i) in_mask[i] = 1;
+    }
+    if (complement)
+        for (int64_t i = 0; i < m; ++i) in_mask[i] = (unsigned char)!in_mask[i];
+    for (int64_t i = 0; i < m; ++i) {
+        int zp = 0;          /* z(i) present */
+        double zd = 0.0;     /* z(i), plus-times */
+        int32_t zi = 0;      /* z(i), min-select2nd and or-and */
+        if (t_has[i] && w_has[i] && accum != 0) {
+            zp = 1;
+            if (accum == 2) { zd = wd[i]; zi = wi[i]; }
+            else if (accum == 3) { zd = td[i]; zi = ti[i]; }
+            else if (semiring == OR_PLUS_TIMES) zd = wd[i] + td[i];
+            else if (semiring == OR_MIN_SELECT2ND) zi = wi[i] < ti[i] ? wi[i] : ti[i];
+            else zi = (wi[i] || ti[i]) ? 1 : 0;
+        } else if (t_has[i]) {
+            zp = 1; zd = td[i]; zi = ti[i];
+        } else if (w_has[i] && accum != 0) {
+            zp = 1; zd = wd[i]; zi = wi[i];
+        }
+        int out = 0;
+        double od = 0.0;
+        int32_t oi = 0;
+        if (in_mask[i]) {
+            if (zp) { out = 1; od = zd; oi = zi; }
+        } else if (!replace && w_has[i]) {
+            out = 1; od = wd[i]; oi = wi[i];
+        }
+        if (out) {
+            y_idx[count] = (int32_t)i;
+            if (semiring == OR_PLUS_TIMES) ((double*)y_val)[count] = od;
+            else if (semiring == OR_MIN_SELECT2ND) ((int32_t*)y_val)[count] = oi;
+            else ((uint8_t*)y_val)[count] = (uint8_t)(oi != 0);
+            ++count;
+        }
+    }
+    *nnz_y = count;
+done:
+    free(t_idx); free(t_val); free(t_has); free(w_has); free(in_mask); free(td); free(wd); free(ti); free(wi);
+    return rc;
 }
 
 /* Plus-times accumulated in fp32, products rounded to fp32 first, rows
