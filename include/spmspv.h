@@ -283,6 +283,47 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
 
+/* ---- masked multiply with accumulate and replace: w<mask, replace> =
+ * w accum (A x), the generalisation of the BFS visited mask that the
+ * paper's conclusions name as future work, with the rules of the GraphBLAS
+ * standard.
+ *   t = A x over `semiring` (structural pattern, as spmspv_run).
+ *   Mask: mask_idx == NULL: every row is in the mask.  Otherwise the rows
+ *     listed in mask_idx[0..mask_count) (distinct, in [0, m)); with
+ *     mask_val (uint8 [mask_count]) non-NULL a listed row counts only if its
+ *     value is nonzero (a value mask), else every listed row does (a
+ *     structural mask).  SPMSPV_MASK_COMPLEMENT inverts membership (with no
+ *     mask list: no row is in the mask).
+ *   w: w_idx [w_count] strictly ascending rows in [0, m), w_val [w_count]
+ *     (element type of y: float, int32 or uint8).
+ *   accum: NONE, ADD (the semiring's Add: + in fp32, min, or), FIRST (w),
+ *     SECOND (t).  z(i) = accum(w(i), t(i)) where both exist and an
+ *     operator is given; t(i) where t has the row; w(i) where only w has
+ *     it and an operator is given.
+ *   Result: z(i) for rows in the mask; for the other rows w(i), or nothing
+ *     with SPMSPV_MASK_REPLACE.  y is always ascending.
+ * The mask is applied inside the product (products of rows outside it are
+ * dropped before bucketing), then t and w are merged.  flags: VALIDATE
+ * (host checks of x, the mask list and w's order), X_VAL_IS_INDEX,
+ * X_ALL_TRUE.  Device checks report mask or w indices out of range
+ * (EDEVICE) and a w that is not ascending.  Uses the handle's BFS buffers
+ * for its temporaries.  Push direction always.                            */
+enum spmspv_mask_flags {
+    SPMSPV_MASK_COMPLEMENT = 1,
+    SPMSPV_MASK_REPLACE = 2
+};
+enum spmspv_accum {
+    SPMSPV_ACCUM_NONE = 0,
+    SPMSPV_ACCUM_ADD = 1,
+    SPMSPV_ACCUM_FIRST = 2,
+    SPMSPV_ACCUM_SECOND = 3
+};
+int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx,
+                         const void* x_val, const int32_t* mask_idx, const uint8_t* mask_val, int64_t mask_count,
+                         int mask_flags, int accum, const int32_t* w_idx, const void* w_val, int64_t w_count,
+                         int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
+                         void* stream);
+
 /* ---- allocation-free multiply.  For callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, hosts that forbid
  * allocation): y <- A x as spmspv_create followed by spmspv_run would

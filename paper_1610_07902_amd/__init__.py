@@ -49,7 +49,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
-    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static",
+    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas",
 )
 
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_run_masked.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
     lib.spmspv_run_static.argtypes = [i64, i64, i64, vp, vp, vp, ci, ci, i64, vp, vp, vp, vp, i64, vp,
                                       ctypes.POINTER(i64), ctypes.POINTER(sz), vp]
+    lib.spmspv_run_graphblas.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, i64, ci, ci, vp, vp, i64, vp, vp, i64,
+                                         vp, ctypes.POINTER(i64), vp]
     lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
     lib.spmspv_selector_classes.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.spmspv_class_tile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int32)]
@@ -202,6 +204,23 @@ def spmspv_run_static(m, n, nnz, colptr, rowids, values, semiring, flags, f, x_i
                                             f, _ptr(x_idx), _ptr(x_val), _ptr(y_idx), _ptr(y_val), y_capacity,
                                             _ptr(d_nnz_y), ctypes.byref(h) if sync else None, None,
                                             _stream(stream)))
+    return h.value if sync else None
+
+
+MASK_COMPLEMENT, MASK_REPLACE = 1, 2
+ACCUM_NONE, ACCUM_ADD, ACCUM_FIRST, ACCUM_SECOND = 0, 1, 2, 3
+
+
+def spmspv_run_graphblas(handle, semiring, flags, f, x_idx, x_val, mask_idx, mask_val, mask_count, mask_flags,
+                         accum, w_idx, w_val, w_count, y_idx, y_val, y_capacity, d_nnz_y=None, sync=True,
+                         stream=None) -> Optional[int]:
+    """w<mask, replace> = w accum (A x); returns nnz(y) when sync."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run_graphblas(handle, semiring, flags, f, _ptr(x_idx), _ptr(x_val),
+                                               _ptr(mask_idx), _ptr(mask_val), mask_count, mask_flags, accum,
+                                               _ptr(w_idx), _ptr(w_val), w_count, _ptr(y_idx), _ptr(y_val),
+                                               y_capacity, _ptr(d_nnz_y), ctypes.byref(h) if sync else None,
+                                               _stream(stream)))
     return h.value if sync else None
 
 

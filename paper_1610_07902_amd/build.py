@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["spmspv_api.hip", "spmspv_kernels.hip", "setup_kernels.hip", "pull_kernels.hip", "mlp_kernels.hip",
-           "pagerank_kernels.hip", "bfs_persistent.hip", "fused_kernels.hip"]
+           "pagerank_kernels.hip", "bfs_persistent.hip", "fused_kernels.hip",
+           "graphblas_kernels.hip"]
 LIB = os.path.join(HERE, "libspmspv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 

@@ -23,7 +23,9 @@ enum : uint32_t {
                                // hold in A (only possible with duplicate x)
     ERR_SPIN = 4u,             // a look-back wait exceeded its bound
     ERR_CSC = 8u,              // colptr not monotone / wrong ends (create)
-    ERR_ROW_RANGE = 16u        // a row id outside [0, m) (create)
+    ERR_ROW_RANGE = 16u,       // a row id outside [0, m) (create)
+    ERR_INDEX_RANGE = 32u,     // a mask or accumulation input index outside [0, m)
+    ERR_ORDER = 64u            // accumulation input indices not strictly ascending
 };
 
 enum Semiring : int { SR_PLUS_TIMES = 0, SR_MIN_SELECT2ND = 1, SR_OR_AND = 2 };
@@ -69,7 +71,9 @@ struct alignas(256) Ctrl {
     // One-launch multiply: call counter whose value tags this call's
     // exchange and look-back words (advanced once per call on the device).
     uint32_t fused_epoch;
-    uint32_t pad[26];
+    uint32_t pad1;
+    int64_t aux_count;      // masked multiply: length of the masked product before the combine
+    uint32_t pad[22];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
@@ -144,7 +148,9 @@ struct ScatterArgs {
     int64_t xstride;         // > 0: fixed bases, key (x, b) owns slots x * xstride + [rcp[bT], rcp[(b+1)T])
                              // (no counting pass; needs bucket storage of nbatch * nnz)
     uint2* buckets;          // [nnz] (row, value bits)
-    const uint32_t* mask;    // nullable visited bitmap: drop rows whose bit is set
+    const uint32_t* mask;    // nullable row bitmap: drop rows whose bit is set (mask_keep = 0, the BFS
+                             // visited set) or whose bit is clear (mask_keep = 1, a GraphBLAS mask)
+    int mask_keep;
     uint64_t* lb1;           // scan look-back words to clear (two halves of lb1_n)
     int32_t lb1_n;
     int32_t lb1_clear;       // how many of each half to clear
@@ -239,6 +245,29 @@ size_t scatter_lds_bytes(int nb, int chunk, bool batch = false);
 constexpr int kMaxBatch = 1024;    // vectors per batched call
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
                                 hipStream_t s);
+// Masked multiply with accumulate / replace: row bitmap of a mask list, and
+// the merge of the masked product t with the accumulation input w.
+hipError_t launch_mask_bits(const int32_t* idx, const uint8_t* val, int64_t count, int32_t m, uint32_t* bits,
+                            uint32_t* err, hipStream_t s);
+struct CombineArgs {
+    const int32_t* t_idx;    // masked product, ascending
+    const void* t_val;
+    const int64_t* d_nt;     // its length (device)
+    const int32_t* w_idx;    // accumulation input, ascending
+    const void* w_val;
+    int64_t nw;
+    const uint32_t* mbits;   // nullable: mask row bitmap
+    int complement, replace, accum;
+    int32_t* y_idx;
+    void* y_val;
+    int64_t y_cap;
+    int64_t* d_nnz_y;        // nullable
+    Ctrl* ctrl;
+    uint64_t* lb;            // look-back words, zero on entry
+    int32_t lb_n;
+};
+constexpr int kCombineTile = 2048;   // merged entries per workgroup tile
+hipError_t launch_combine(const CombineArgs& a, int semiring, int grid, hipStream_t s);
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
                              uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl,

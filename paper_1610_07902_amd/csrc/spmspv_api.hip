@@ -55,7 +55,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
-        front1, front2, disc, pmin, bar, samples, gpoff, roff, total;
+        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose;
@@ -63,6 +63,8 @@ struct Layout {
     int64_t rows_cap;   // one-launch multiply: chunk rows of run offsets
     int32_t fnb;        // one-launch multiply: buckets per row of run offsets
 };
+
+inline int64_t gb_lb_words(int64_t m) { return (2 * m + kCombineTile - 1) / kCombineTile + 2; }
 
 Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     Layout L{};
@@ -107,6 +109,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.samples = take(size_t(kFMaxGrid) * kFSamples * 4);
     L.gpoff = take(size_t(kFMaxGrid + 1) * 8);
     L.roff = take(size_t(L.rows_cap) * size_t(L.fnb + 1) * 4);
+    // masked multiply: look-back words of the combine (t and w each hold at most m rows)
+    L.gb_lb = take(size_t(gb_lb_words(m)) * 8);
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
     if (L.pull) {
@@ -342,7 +346,7 @@ int64_t scatter_occupancy(const spmspv_matrix* A, int nb, int block, int chunk, 
 int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev, const int32_t* x_idx,
             const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
             const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
-            int phases = 3, int clear_nb = 0, bool learned_gate = false) {
+            int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0) {
     spmspv_schedule sc = A->sched;
     if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
     sc.tile_log2 = call_tile(A, sc.tile_log2, semiring);
@@ -411,6 +415,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ca.cursor = A->cursor;
     ca.buckets = A->buckets;
     ca.mask = mask;
+    ca.mask_keep = mask_keep;
     ca.lb1 = A->lb1;
     ca.lb1_n = (int32_t)A->L.lb1_n;
     ca.lb1_clear = (int32_t)((f_bound + kScanTile - 1) / kScanTile + 1);
@@ -1181,6 +1186,129 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
             clear_err(A, s);
             return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
                                             " (1 = x index range, 2 = duplicate x index, 4 = look-back bound)");
+        }
+        if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
+    }
+    return SPMSPV_OK;
+}
+
+int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx,
+                         const void* x_val, const int32_t* mask_idx, const uint8_t* mask_val, int64_t mask_count,
+                         int mask_flags, int accum, const int32_t* w_idx, const void* w_val, int64_t w_count,
+                         int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
+                         void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    if (f > 0 && !x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
+    if (mask_count < 0 || (mask_count > 0 && !mask_idx)) return fail(SPMSPV_EINVAL, "bad mask list");
+    if (mask_count > A->m) return fail(SPMSPV_EINVAL, "mask longer than m");
+    if (mask_flags & ~(SPMSPV_MASK_COMPLEMENT | SPMSPV_MASK_REPLACE)) return fail(SPMSPV_EINVAL, "unknown mask flag");
+    if (accum < SPMSPV_ACCUM_NONE || accum > SPMSPV_ACCUM_SECOND) return fail(SPMSPV_EINVAL, "unknown accumulate");
+    if (w_count < 0 || w_count > A->m || (w_count > 0 && (!w_idx || !w_val)))
+        return fail(SPMSPV_EINVAL, "bad accumulation input w");
+    if (y_capacity < 0 || (y_capacity > 0 && !y_idx)) return fail(SPMSPV_EINVAL, "bad y buffer");
+    if (flags & ~(SPMSPV_VALIDATE | SPMSPV_SORTED_OUTPUT | SPMSPV_X_VAL_IS_INDEX | SPMSPV_X_ALL_TRUE))
+        return fail(SPMSPV_EINVAL, "spmspv_run_graphblas takes VALIDATE, SORTED_OUTPUT, X_VAL_IS_INDEX, X_ALL_TRUE");
+    int xmode = XV_BITS32;
+    if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
+    else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
+    if (f > 0 && !x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool complement = (mask_flags & SPMSPV_MASK_COMPLEMENT) != 0;
+    const bool replace = (mask_flags & SPMSPV_MASK_REPLACE) != 0;
+    const bool has_mask = mask_idx != nullptr;
+
+    if (flags & SPMSPV_VALIDATE) {
+        // x: distinct, in range; mask: distinct rows in range; w: strictly ascending rows in range
+        std::vector<int32_t> hx((size_t)f), hm((size_t)mask_count), hw((size_t)w_count);
+        if (f) HIP_TRY(hipMemcpyAsync(hx.data(), x_idx, size_t(f) * 4, hipMemcpyDeviceToHost, s));
+        if (mask_count) HIP_TRY(hipMemcpyAsync(hm.data(), mask_idx, size_t(mask_count) * 4, hipMemcpyDeviceToHost, s));
+        if (w_count) HIP_TRY(hipMemcpyAsync(hw.data(), w_idx, size_t(w_count) * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<uint8_t> seen((size_t)std::max(A->n, A->m), 0);
+        for (int32_t j : hx) {
+            if (j < 0 || j >= A->n) return fail(SPMSPV_EINVAL, "x index out of range");
+            if (seen[(size_t)j]) return fail(SPMSPV_EINVAL, "duplicate x index");
+            seen[(size_t)j] = 1;
+        }
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t i : hm) {
+            if (i < 0 || i >= A->m) return fail(SPMSPV_EINVAL, "mask index out of range");
+            if (seen[(size_t)i]) return fail(SPMSPV_EINVAL, "duplicate mask index");
+            seen[(size_t)i] = 1;
+        }
+        for (size_t r = 0; r < hw.size(); ++r) {
+            if (hw[r] < 0 || hw[r] >= A->m) return fail(SPMSPV_EINVAL, "w index out of range");
+            if (r > 0 && hw[r] <= hw[r - 1]) return fail(SPMSPV_EINVAL, "w indices must be strictly ascending");
+        }
+    }
+
+    // (1) the mask's rows as a bitmap (the BFS visited bitmap's storage)
+    uint32_t* bits = nullptr;
+    if (has_mask) {
+        bits = A->visited;
+        HIP_TRY(launch_fill_u32(bits, 0u, (A->m + 31) / 32, s));
+        HIP_TRY(launch_mask_bits(mask_idx, mask_val, mask_count, (int32_t)A->m, bits, &A->ctrl->err, s));
+    }
+    // (2) t = A x restricted to the mask, ascending; straight into y when
+    // there is nothing to accumulate into (then the result is t: rows
+    // outside the mask have no w to keep)
+    const bool direct = w_count == 0;
+    int32_t* t_idx = direct ? y_idx : A->front[0];
+    void* t_val = direct ? y_val : static_cast<void*>(A->front[1]);
+    const int64_t t_cap = direct ? y_capacity : A->m;
+    int64_t* t_count = direct ? d_nnz_y : &A->ctrl->aux_count;
+    const spmspv_schedule keep = A->sched;
+    if (A->sched_default) A->sched = sized_for_call(A, f);
+    A->sched.direction = 0;
+    int rc;
+    if (!has_mask && complement) {
+        // no row is in the mask: t is empty
+        rc = enqueue(A, semiring, xmode, 0, nullptr, x_idx, x_val, t_idx, t_val, t_cap, t_count, false, nullptr, s,
+                     nullptr);
+    } else {
+        rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, t_idx, t_val, t_cap, t_count, false, bits, s,
+                     nullptr, false, -1, 3, 0, false, complement ? 0 : 1);
+    }
+    A->sched = keep;
+    if (rc) return rc;
+    // (3) merge t with w under the accumulate and replace rules
+    if (!direct) {
+        CombineArgs ca{};
+        ca.t_idx = A->front[0];
+        ca.t_val = A->front[1];
+        ca.d_nt = &A->ctrl->aux_count;
+        ca.w_idx = w_idx;
+        ca.w_val = w_val;
+        ca.nw = w_count;
+        ca.mbits = bits;
+        ca.complement = complement ? 1 : 0;
+        ca.replace = replace ? 1 : 0;
+        ca.accum = accum;
+        ca.y_idx = y_idx;
+        ca.y_val = y_val;
+        ca.y_cap = y_capacity;
+        ca.d_nnz_y = d_nnz_y;
+        ca.ctrl = A->ctrl;
+        ca.lb = reinterpret_cast<uint64_t*>(A->ws + A->L.gb_lb);
+        ca.lb_n = (int32_t)gb_lb_words(A->m);
+        HIP_TRY(launch_clear_u64(ca.lb, ca.lb_n, s));
+        int64_t grid = (A->m + w_count + kCombineTile - 1) / kCombineTile;
+        if (grid < 1) grid = 1;
+        if (grid > 2 * A->num_cu) grid = 2 * A->num_cu;   // co-resident: look-back waits stay bounded
+        HIP_TRY(launch_combine(ca, semiring, (int)grid, s));
+    }
+    if (h_nnz_y) {
+        Ctrl h{};
+        rc = read_ctrl(A, &h, s);
+        if (rc) return rc;
+        *h_nnz_y = h.nnz_y;
+        if (h.err) {
+            clear_err(A, s);
+            return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
+                                            " (1 = x index range, 2 = duplicate x index, 4 = look-back bound, "
+                                            "32 = mask or w index range, 64 = w not ascending)");
         }
         if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
     }

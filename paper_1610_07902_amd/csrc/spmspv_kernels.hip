@@ -43,79 +43,6 @@ namespace spv {
 
 namespace {
 
-constexpr uint64_t LB_AGG = 1ull << 62;
-constexpr uint64_t LB_INC = 2ull << 62;
-constexpr uint64_t LB_VAL = (1ull << 62) - 1;
-constexpr int kSpinMax = 1 << 20;
-
-__device__ __forceinline__ uint64_t ld_acquire64(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_release64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Control words written by an earlier kernel (plain stores or atomics) are
-// read with agent-scope atomic loads, never through the scalar cache.
-__device__ __forceinline__ int32_t ld_ctrl(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t* ld_ctrl_ptr(int32_t* const* p) {
-    return reinterpret_cast<int32_t*>(__hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ __forceinline__ void st_ctrl(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_ctrl_u(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-// Decoupled look-back over per-tile state words (status in bits 63:62,
-// value in 61:0).  Called by all 64 lanes of one wave.  Publishes `agg` for
-// `tile`, returns the exclusive prefix and publishes the inclusive one.
-// A wait that exceeds kSpinMax polls sets ERR_SPIN and returns a partial
-// prefix rather than hanging.
-__device__ uint64_t lookback(uint64_t* st, int tile, uint64_t agg, uint32_t* err) {
-    const int lane = threadIdx.x & (kWave - 1);
-    if (tile == 0) {
-        if (lane == 0) st_release64(&st[0], LB_INC | (agg & LB_VAL));
-        return 0;
-    }
-    if (lane == 0) st_release64(&st[tile], LB_AGG | (agg & LB_VAL));
-    uint64_t excl = 0;
-    int base = tile - 1;
-    int spins = 0;
-    for (;;) {
-        const int idx = base - lane;
-        const uint64_t w = idx >= 0 ? ld_acquire64(&st[idx]) : LB_INC;
-        const uint64_t status = w >> 62;
-        const uint64_t inc_mask = __ballot(status == 2);
-        const uint64_t empty_mask = __ballot(status == 0);
-        const uint64_t need = inc_mask ? (((inc_mask & (~inc_mask + 1)) << 1) - 1) : ~0ull;
-        if (empty_mask & need) {
-            if (++spins > kSpinMax) {
-                if (lane == 0) atomicOr(err, ERR_SPIN);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        const uint64_t v = ((need >> lane) & 1ull) ? (w & LB_VAL) : 0ull;
-        excl += wave_sum_u64(v);
-        if (inc_mask) break;
-        base -= kWave;
-    }
-    if (lane == 0) st_release64(&st[tile], LB_INC | ((excl + agg) & LB_VAL));
-    return excl;
-}
-
 // ------------------------------------------------------------------ step (a)
 // Two look-back chains per tile, one for the product count (sum of column
 // lengths) and one for the number of non-empty columns, each with a 62-bit
@@ -482,7 +409,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         for (int i = 0; i < ITEMS; ++i) {
             bk[i] = -1;
             rank[i] = 0;
-            if (qq[i] >= 0 && ((mw[i] >> (row[i] & 31)) & 1u) == 0u) {
+            if (qq[i] >= 0 && (!a.mask || ((mw[i] >> (row[i] & 31)) & 1u) == (uint32_t)a.mask_keep)) {
                 bk[i] = MODE != SC_SINGLE ? xid[i] * a.nbx + (row[i] >> tl) : row[i] >> tl;
                 rank[i] = atomicAdd(&hist[bk[i]], 1);
             }
