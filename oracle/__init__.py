@@ -51,6 +51,9 @@ def _bind(lib):
         ci = ctypes.c_int
         lib.oracle_spmspv_graphblas.argtypes = [ci, i64, i64, vp, vp, vp, i64, vp, vp, ci, vp, vp, i64, ci, ci, vp,
                                                 vp, i64, ci, vp, vp, vp]
+    if hasattr(lib, "oracle_cc"):
+        lib.oracle_cc.argtypes = [i64, vp, vp, vp]
+        lib.oracle_cc.restype = i64
     lib.oracle_bfs.argtypes = [i64, vp, vp, ctypes.c_int32, vp, vp]
     lib.oracle_bfs.restype = ctypes.c_int
     if hasattr(lib, "oracle_pagerank"):
@@ -158,6 +161,17 @@ def spmspv_graphblas(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PL
         raise ValueError(f"oracle_spmspv_graphblas rc={rc}")
     k = nnz.value
     return yi[:k].copy(), yv[:k].copy()
+
+
+def cc(A, lib=None):
+    """Connected components (a data-driven SpMSpV use named in the paper's
+    introduction): label(v) = the smallest vertex that reaches v along edges
+    j -> i of the stored A(i, j); for a symmetric A, the smallest vertex of
+    v's component.  Returns (labels int32 [n], number of components)."""
+    lib = lib or load()
+    lab = np.empty(max(A.n, 1), np.int32)
+    k = lib.oracle_cc(A.n, _p(A.colptr), _p(A.rowids), _p(lab))
+    return lab[: A.n].copy(), int(k)
 
 
 def spmspv_f32seq(A, x_idx: np.ndarray, x_val: np.ndarray, lib=None):

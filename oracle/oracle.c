@@ -14,6 +14,7 @@
  *   oracle_bfs           FIFO-queue breadth-first search levels, parents by
  *                        the minimum-parent rule.
  *   oracle_spmspv_graphblas  masked multiply with accumulate / replace.
+ *   oracle_cc            connected components (smallest reaching vertex).
  *   oracle_pagerank      data-driven (delta) PageRank in fp64.
  *   oracle_mlp_*         fp64 forward / backward of the schedule-selector MLP.
  *
@@ -242,6 +243,42 @@ int oracle_spmspv_graphblas(int semiring, int64_t m, int64_t n, const int32_t* c
 done:
     free(t_idx); free(t_val); free(t_has); free(w_has); free(in_mask); free(td); free(wd); free(ti); free(wi);
     return rc;
+}
+
+/*
+ * Connected components as the paper's introduction lists them among the
+ * data-driven uses of SpMSpV: label(v) = the smallest vertex u from which v
+ * is reachable along edges j -> i (every stored A(i,j)), u = v included.
+ * For a symmetric A that is the smallest vertex of v's component.  Plain
+ * definition: vertices in increasing order; an unlabelled one labels every
+ * unlabelled vertex it reaches (FIFO queue), so each vertex is labelled by
+ * the first, i.e. smallest, vertex that reaches it (a vertex reached only
+ * through an already labelled one is reached by that one's smaller label
+ * too).  Returns the number of components (distinct labels).
+ */
+int64_t oracle_cc(int64_t n, const int32_t* colptr, const int32_t* rowids, int32_t* label) {
+    int32_t* queue = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < n; ++v) label[v] = -1;
+    int64_t comps = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        if (label[u] >= 0) continue;
+        ++comps;
+        int64_t head = 0, tail = 0;
+        label[u] = (int32_t)u;
+        queue[tail++] = (int32_t)u;
+        while (head < tail) {
+            const int32_t j = queue[head++];
+            for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+                const int32_t i = rowids[q];
+                if (label[i] < 0) {
+                    label[i] = (int32_t)u;
+                    queue[tail++] = i;
+                }
+            }
+        }
+    }
+    free(queue);
+    return comps;
 }
 
 /* Plus-times accumulated in fp32, products rounded to fp32 first, rows
