@@ -283,6 +283,18 @@ int spmspv_profile_read(spmspv_handle A, double* h_ms, int64_t* h_calls);
  * its device arrays and workspace).                                       */
 int spmspv_destroy(spmspv_handle A);
 
+/* ---- connected components (the paper's introduction lists them among the
+ * data-driven uses of SpMSpV).  Label propagation: label(v) = v; each step
+ * multiplies x = {(v, label(v)) : v's label changed in the last step (all
+ * vertices with out-edges at first)} over min-select2nd, and every row i
+ * with y(i) < label(i) takes y(i) and joins the next x; it stops when no
+ * label changes.  Result: labels[v] = the smallest vertex that reaches v
+ * along edges j -> i of the stored A(i, j); for a symmetric A (undirected
+ * graph), the smallest vertex of v's component.  labels: int32 [n]
+ * (device).  *h_iters (nullable) = multiplies run.  Square A; uses the
+ * handle's BFS buffers.  Synchronous (one host check per 8 steps).     */
+int cc_run(spmspv_handle A, int flags, int32_t* labels, int32_t* h_iters, void* stream);
+
 /* ---- masked multiply with accumulate and replace: w<mask, replace> =
  * w accum (A x), the generalisation of the BFS visited mask that the
  * paper's conclusions name as future work, with the rules of the GraphBLAS

@@ -49,7 +49,7 @@ EXPORTED = (
     "spmspv_mlp_train_step", "spmspv_batch_workspace_size", "spmspv_batch_attach", "spmspv_run_batch",
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
-    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas",
+    "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas", "cc_run",
 )
 
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_run_masked.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
     lib.spmspv_run_static.argtypes = [i64, i64, i64, vp, vp, vp, ci, ci, i64, vp, vp, vp, vp, i64, vp,
                                       ctypes.POINTER(i64), ctypes.POINTER(sz), vp]
+    lib.cc_run.argtypes = [vp, ci, vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.spmspv_run_graphblas.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, i64, ci, ci, vp, vp, i64, vp, vp, i64,
                                          vp, ctypes.POINTER(i64), vp]
     lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
@@ -205,6 +206,13 @@ def spmspv_run_static(m, n, nnz, colptr, rowids, values, semiring, flags, f, x_i
                                             _ptr(d_nnz_y), ctypes.byref(h) if sync else None, None,
                                             _stream(stream)))
     return h.value if sync else None
+
+
+def cc_run(handle, labels, flags=0, stream=None) -> int:
+    """Connected components into `labels` (int32 [n] device); returns the multiplies run."""
+    it = ctypes.c_int32(0)
+    _check(load_library().cc_run(handle, flags, _ptr(labels), ctypes.byref(it), _stream(stream)))
+    return it.value
 
 
 MASK_COMPLEMENT, MASK_REPLACE = 1, 2
@@ -561,6 +569,14 @@ class Matrix:
         rank = torch.empty(self.n, dtype=torch.float32, device=dev)
         it = pagerank_run(self.handle, damping, tol, max_iter, flags, rank, self._pr_scratch, nbytes)
         return rank, it
+
+    def connected_components(self):
+        """labels[v] = the smallest vertex reaching v (the component's smallest
+        vertex for a symmetric matrix); returns (labels, multiplies)."""
+        import torch
+        labels = torch.empty(self.n, dtype=torch.int32, device=self.colptr.device)
+        it = cc_run(self.handle, labels)
+        return labels, it
 
     def load_selector(self, params, mean, std):
         spmspv_selector_load(self.handle, params, mean, std)

@@ -384,6 +384,10 @@ hipError_t launch_pr_update(int32_t n, const int32_t* colptr, float d, float tol
                             const float* y_val, int32_t* x_idx, float* x_val, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_gen_x(int32_t n, double density, uint64_t seed, int32_t* x_idx, float* x_val, Ctrl* ctrl,
                         hipStream_t s);
+hipError_t launch_cc_init(int32_t n, const int32_t* colptr, int32_t* label, int32_t* x_idx, int32_t* x_val,
+                          Ctrl* ctrl, hipStream_t s);
+hipError_t launch_cc_update(int32_t n, const int32_t* colptr, int32_t* label, const int32_t* y_idx,
+                            const int32_t* y_val, int32_t* x_idx, int32_t* x_val, Ctrl* ctrl, hipStream_t s);
 
 // Schedule-selector MLP (6 -> 64 -> 64 -> 10).
 constexpr int kMlpIn = 6, kMlpH1 = 64, kMlpH2 = 64, kMlpOut = 10;

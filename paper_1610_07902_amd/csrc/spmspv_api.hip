@@ -2044,6 +2044,47 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
     return SPMSPV_OK;
 }
 
+int cc_run(spmspv_handle A, int flags, int32_t* labels, int32_t* h_iters, void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (A->m != A->n) return fail(SPMSPV_EINVAL, "connected components need a square matrix");
+    if (!labels) return fail(SPMSPV_EINVAL, "labels is NULL");
+    if (flags != 0) return fail(SPMSPV_EINVAL, "cc_run takes no flags");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    // x and y lists in the handle's BFS buffers (values are labels, int32)
+    int32_t* x_idx = A->front[0];
+    int32_t* x_val = A->front[1];
+    int32_t* y_idx = A->front2;
+    int32_t* y_val = A->pmin;
+    HIP_TRY(launch_cc_init((int32_t)n, A->colptr, labels, x_idx, x_val, A->ctrl, s));
+    int32_t hf = 1;
+    int64_t done = 0;
+    while (hf > 0 && done <= n) {
+        // kGraphLevels steps per host check; steps after x empties are no-ops
+        for (int k = 0; k < kGraphLevels; ++k) {
+            const int rc = enqueue(A, SR_MIN_SELECT2ND, XV_BITS32, 0, &A->ctrl->f, x_idx, x_val, y_idx, y_val, n,
+                                   nullptr, false, nullptr, s, nullptr);
+            if (rc) return rc;
+            HIP_TRY(launch_cc_update((int32_t)n, A->colptr, labels, y_idx, y_val, x_idx, x_val, A->ctrl, s));
+        }
+        done += kGraphLevels;
+        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // the persistent BFS expects its scratch (y values lived in it) reset
+    HIP_TRY(reset_persistent_state(A, s));
+    Ctrl h{};
+    int rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    if (h.err) {
+        clear_err(A, s);
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (hf > 0) return fail(SPMSPV_EDEVICE, "labels still changing after n steps");
+    if (h_iters) *h_iters = h.level;
+    return SPMSPV_OK;
+}
+
 int spmspv_mlp_param_count(void) { return kMlpParams; }
 
 int spmspv_mlp_forward(const float* params, const float* X, int batch, float* logits, void* stream) {
