@@ -448,7 +448,8 @@ def batch_bench(spv, dev, msbfs=True, reps=5):
     off_d = torch.as_tensor(off).to(dev)
     cat_i = torch.cat(xi_d)
     cat_v = torch.cat(xv_d)
-    M.attach_batch(64, max_f=int(off[-1]), max_products=Wt)
+    # room for nnz(A) products per vector: fixed slices, no counting pass (16 GB of HBM here)
+    M.attach_batch(64, max_f=int(off[-1]), max_products=64 * A.nnz)
     y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
     y_val = torch.empty(A.m, dtype=torch.float32, device=dev)
     d_nnz = torch.zeros(1, dtype=torch.int64, device=dev)

@@ -407,16 +407,23 @@ int spmspv_batch_workspace_size(spmspv_handle A, int max_batch, int64_t max_f, i
 int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t max_products, int flags,
                         void* workspace, size_t ws_bytes, void* stream);
 
-/* y_b <- A x_b for b < nbatch, one scan, two bucketing passes and one merge
+/* y_b <- A x_b for b < nbatch, one scan, the bucketing and one merge
  * launch for the whole batch.  Flags: SPMSPV_X_VAL_IS_INDEX, X_ALL_TRUE
  * and SPMSPV_VALIDATE (host check of x_off and of distinct in-range indices
- * per vector; synchronous) as for spmspv_run.  Without VALIDATE, duplicate
- * indices inside one vector are combined like repeated products.  y is
- * always ascending within a vector.  y_off [nbatch+1] receives the output
- * offsets.  With h_nnz_total non-NULL the call waits and reports the total
- * (ECAPACITY when it exceeds y_capacity, or when the products exceed the
- * workspace's max_products; then y is unspecified).  The bucket tile is the
- * narrowest at or above the schedule's for which nbatch * ceil(m / tile)
+ * per vector; synchronous) as for spmspv_run.  Indices inside one vector
+ * must be distinct, as for spmspv_run.
+ *   Fixed slices: when the workspace's max_products >= nbatch * nnz(A),
+ *   vector b's products for bucket k go to a slice of its own sized by the
+ *   stored entries of k's rows, and the bucketing is one pass.  A repeated
+ *   index can overflow a slice: the run is dropped (memory stays safe) and
+ *   the status is EDEVICE.
+ *   Counted slices: otherwise a counting pass sizes every (vector, bucket)
+ *   key first; repeated indices are then combined like repeated products.
+ * y is always ascending within a vector.  y_off [nbatch+1] receives the
+ * output offsets.  With h_nnz_total non-NULL the call waits and reports the
+ * total (ECAPACITY when it exceeds y_capacity, or when the products exceed
+ * the workspace's max_products; then y is unspecified).  The bucket tile is
+ * the narrowest at or above the schedule's for which nbatch * ceil(m / tile)
  * <= 8192 (EUNSUPPORTED if none).                                        */
 int spmspv_run_batch(spmspv_handle A, int semiring, int flags, int nbatch, const int64_t* x_off,
                      const int32_t* x_idx, const void* x_val, int64_t* y_off, int32_t* y_idx, void* y_val,

@@ -187,6 +187,7 @@ BatchLayout make_batch_layout(int64_t m, int64_t n, int64_t nnz, int max_batch, 
 struct BatchCtx {
     bool bound = false;
     bool bfs = false;
+    bool fixed_last = false;   // the last batched call used fixed slices (no counting pass)
     int max_batch = 0;
     BatchLayout L{};
     char* ws = nullptr;
@@ -767,11 +768,16 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     ma.n_stride = A->n;
     ma.mask_words = L.mask_words;
 
-    // Multi-source BFS frontiers are sets (no repeated index inside one
-    // vector), so with storage for nnz entries per vector (the default size
-    // of its workspace) key (x, b) owns the fixed slice x * nnz + [rcp[bT],
-    // rcp[(b+1)T]) and the counting pass is not needed.
-    const bool fixed = bfs && L.max_products >= (int64_t)nbatch * A->nnz && A->nnz > 0;
+    // With distinct indices inside each vector (a precondition of every
+    // multiply; multi-source BFS frontiers are sets), vector x puts at most
+    // one product per stored entry of A into bucket b, so bucket b's share
+    // is bounded by its rows' entry count rcp[(b+1)T] - rcp[bT] exactly as
+    // in a single call.  When the workspace holds nnz slots per vector, key
+    // (x, b) owns the fixed slice x * nnz + [rcp[bT], rcp[(b+1)T]) and the
+    // counting pass is not needed.  A repeated index can overflow a slice:
+    // the scatter then drops the run and raises an error bit.
+    const bool fixed = L.max_products >= (int64_t)nbatch * A->nnz && A->nnz > 0;
+    A->batch.fixed_last = fixed;
     if (fixed) {
         ca.xstride = A->nnz;
         ma.xstride = A->nnz;
@@ -1672,6 +1678,8 @@ int batch_status(spmspv_matrix* A, hipStream_t s, int64_t* total) {
     if (h.err) {
         clear_err(A, s);
         if (h.err & ERR_X_RANGE) return fail(SPMSPV_EINVAL, "x index or vector offset out of range");
+        if ((h.err & ERR_BUCKET_OVERFLOW) && A->batch.fixed_last)
+            return fail(SPMSPV_EDEVICE, "a bucket slice overflowed: repeated x index within a vector");
         if (h.err & ERR_BUCKET_OVERFLOW)
             return fail(SPMSPV_ECAPACITY, "products exceed the batch workspace's max_products");
         return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));

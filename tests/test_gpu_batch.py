@@ -184,6 +184,56 @@ def test_batch_then_single_calls_agree(spv, rmat14):
     check_batch(spv, M, A, xs, off, idx, val, 1)
 
 
+@pytest.mark.parametrize("semiring", [0, 1, 2])
+def test_fixed_and_counted_slices(spv, rmat14, semiring):
+    """The same batch through fixed slices (a workspace for B * nnz(A)
+    products: one bucketing pass, each (vector, bucket) key in a slice sized
+    by its rows' stored entries) and through counted slices (a workspace for
+    exactly the batch's products: a counting pass first).  Both match the
+    oracle vector by vector, twice in a row."""
+    A = rmat14
+    M = spv.Matrix.from_csc(A)
+    B = 24
+    sizes = synth.log_uniform_sizes(B, A.n / 2, seed=60 + semiring)
+    sizes[0] = A.n                     # a whole-width vector: every slice filled to the brim
+    sizes[9] = 0
+    xs, off, idx, val = make_batch(A, sizes, 300 + semiring)
+    W = int(sum(A.degrees()[x[0]].sum() for x in xs))
+    assert W < B * A.nnz
+    for mp in (B * A.nnz, W):
+        M.attach_batch(B, max_f=int(off[-1]), max_products=mp)
+        for _ in range(2):
+            check_batch(spv, M, A, xs, off, idx, val, semiring)
+
+
+def test_repeated_index_fixed_vs_counted(spv):
+    """A repeated x index breaks the distinctness precondition.  On the
+    identity matrix, 5000 copies of column 7 put 5000 products into a bucket
+    whose rows hold at most 4096 entries: fixed slices report the overflow
+    (EDEVICE) and the handle keeps working; counted slices combine the
+    repeated products as the oracle does."""
+    n = 4096
+    A = synth.CSC(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n, np.float32))
+    M = spv.Matrix.from_csc(A)
+    rng = np.random.default_rng(8)
+    S0 = np.full(5000, 7, np.int32)
+    S1 = np.arange(0, n, 3, dtype=np.int32)
+    xs = [(S0, rng.random(S0.size).astype(np.float32)), (S1, rng.random(S1.size).astype(np.float32))]
+    off = np.array([0, S0.size, S0.size + S1.size], np.int64)
+    idx = np.concatenate([S0, S1])
+    val = np.concatenate([xs[0][1], xs[1][1]])
+    M.attach_batch(2, max_f=int(off[-1]), max_products=2 * n)          # fixed slices
+    with pytest.raises(spv.SpmspvError) as e:
+        M.spmspv_batch(dev(off), dev(idx), dev(val))
+    assert e.value.status == spv.EDEVICE
+    good = [xs[1], (S1[::2].copy(), xs[1][1][::2].copy())]
+    goff = np.array([0, S1.size, S1.size + good[1][0].size], np.int64)
+    check_batch(spv, M, A, good, goff, np.concatenate([g[0] for g in good]),
+                np.concatenate([g[1] for g in good]), 0)
+    M.attach_batch(2, max_f=int(off[-1]), max_products=int(off[-1]))   # counted slices
+    check_batch(spv, M, A, xs, off, idx, val, 0)
+
+
 @pytest.mark.parametrize("semiring", [1, 2])
 def test_msbfs_matches_oracle(spv, rmat14, semiring):
     A = rmat14
