@@ -51,6 +51,13 @@ def _bind(lib):
         ci = ctypes.c_int
         lib.oracle_spmspv_graphblas.argtypes = [ci, i64, i64, vp, vp, vp, i64, vp, vp, ci, vp, vp, i64, ci, ci, vp,
                                                 vp, i64, ci, vp, vp, vp]
+    if hasattr(lib, "oracle_spmspv_left"):
+        lib.oracle_spmspv_left.argtypes = [ctypes.c_int, i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+        lib.oracle_spmspv_left.restype = ctypes.c_int
+    if hasattr(lib, "oracle_spmspv_dcsc"):
+        lib.oracle_spmspv_dcsc.argtypes = [ctypes.c_int, i64, i64, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp,
+                                           vp]
+        lib.oracle_spmspv_dcsc.restype = ctypes.c_int
     if hasattr(lib, "oracle_cc"):
         lib.oracle_cc.argtypes = [i64, vp, vp, vp]
         lib.oracle_cc.restype = i64
@@ -121,6 +128,80 @@ def spmspv(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES,
         raise ValueError(f"oracle_spmspv rc={rc}")
     k = nnz.value
     return yi[:k].copy(), yv[:k].copy(), W.value
+
+
+def _xv(semiring, x_val):
+    dt = {PLUS_TIMES: np.float32, MIN_SELECT2ND: np.int32, OR_AND: np.uint8}[semiring]
+    return np.ascontiguousarray(x_val, dt)
+
+
+def _yv(semiring, size):
+    dt = {PLUS_TIMES: np.float64, MIN_SELECT2ND: np.int32, OR_AND: np.uint8}[semiring]
+    return np.empty(max(size, 1), dt)
+
+
+def spmspv_left(A, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES, lib=None):
+    """Left multiplication y' <- x' A (Background, Notation: the row-vector
+    case): x' over A's rows, y' over its columns, y'(j) = Add over stored
+    A(i,j) with i in x' of Mult(A(i,j), x'(i)).  Column-driven with a dense
+    x'.  Returns (y_idx ascending, y_val) with y_val typed as in spmspv."""
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    xv = _xv(semiring, x_val)
+    yi = np.empty(max(A.n, 1), np.int32)
+    yv = _yv(semiring, A.n)
+    nnz = ctypes.c_int64(0)
+    vals = None if A.values is None else np.ascontiguousarray(A.values, np.float32)
+    rc = lib.oracle_spmspv_left(semiring, A.m, A.n, _p(A.colptr), _p(A.rowids), _p(vals), x_idx.size, _p(x_idx),
+                                _p(xv), _p(yi), _p(yv), ctypes.byref(nnz))
+    if rc != 0:
+        raise ValueError(f"oracle_spmspv_left rc={rc}")
+    k = nnz.value
+    return yi[:k].copy(), yv[:k].copy()
+
+
+def spmspv_dcsc(D, x_idx: np.ndarray, x_val: np.ndarray, semiring: int = PLUS_TIMES, lib=None):
+    """y <- A x with A in DCSC (``synth.DCSC``; Background, Sparse matrix and
+    vector data structures): columns looked up by binary search over the
+    non-empty column ids.  Returns (y_idx ascending, y_val, W)."""
+    lib = lib or load()
+    x_idx = np.ascontiguousarray(x_idx, np.int32)
+    xv = _xv(semiring, x_val)
+    yi = np.empty(max(D.m, 1), np.int32)
+    yv = _yv(semiring, D.m)
+    nnz = ctypes.c_int64(0)
+    W = ctypes.c_int64(0)
+    vals = None if D.values is None else np.ascontiguousarray(D.values, np.float32)
+    rc = lib.oracle_spmspv_dcsc(semiring, D.m, D.n, D.nzc, _p(np.ascontiguousarray(D.jc, np.int32)),
+                                _p(np.ascontiguousarray(D.cp, np.int32)), _p(np.ascontiguousarray(D.rowids, np.int32)),
+                                _p(vals), x_idx.size, _p(x_idx), _p(xv), _p(yi), _p(yv), ctypes.byref(nnz),
+                                ctypes.byref(W))
+    if rc != 0:
+        raise ValueError(f"oracle_spmspv_dcsc rc={rc}")
+    k = nnz.value
+    return yi[:k].copy(), yv[:k].copy(), W.value
+
+
+def to_bitvector(idx: np.ndarray, val: Optional[np.ndarray], length: int):
+    """Bitvector form of a sparse vector (Background, Sparse matrix and
+    vector data structures): a bitmap of `length` bits in uint32 words, bit
+    (i mod 32) of word i div 32 set for every present index i, and the
+    values listed in ascending index order.  Returns (bits, values)."""
+    idx = np.asarray(idx, np.int64)
+    bits = np.zeros((length + 31) // 32, np.uint32)
+    for i in idx.tolist():
+        bits[i >> 5] |= np.uint32(1 << (i & 31))
+    order = np.argsort(idx, kind="stable")
+    return bits, (None if val is None else np.asarray(val)[order])
+
+
+def from_bitvector(bits: np.ndarray, length: int) -> np.ndarray:
+    """Present indices of a bitmap, ascending (bits at or past `length`
+    must be clear)."""
+    b = np.unpackbits(np.ascontiguousarray(bits, "<u4").view(np.uint8), bitorder="little")
+    if b[length:].any():
+        raise ValueError("bit set past the vector length")
+    return np.nonzero(b[:length])[0].astype(np.int32)
 
 
 ACCUM_NONE, ACCUM_ADD, ACCUM_FIRST, ACCUM_SECOND = 0, 1, 2, 3

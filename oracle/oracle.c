@@ -15,6 +15,8 @@
  *                        the minimum-parent rule.
  *   oracle_spmspv_graphblas  masked multiply with accumulate / replace.
  *   oracle_cc            connected components (smallest reaching vertex).
+ *   oracle_spmspv_left   left multiplication y' <- x' A, column-driven.
+ *   oracle_spmspv_dcsc   y <- A x with A in DCSC (non-empty columns only).
  *   oracle_pagerank      data-driven (delta) PageRank in fp64.
  *   oracle_mlp_*         fp64 forward / backward of the schedule-selector MLP.
  *
@@ -279,6 +281,128 @@ int64_t oracle_cc(int64_t n, const int32_t* colptr, const int32_t* rowids, int32
     }
     free(queue);
     return comps;
+}
+
+/*
+ * Left multiplication y' <- x' A (Background, Notation: the row-vector case,
+ * which the paper leaves to symmetry with the column-vector one).  x' is a
+ * sparse row vector over A's m rows and y' one over its n columns:
+ *   y'(j) = Add over the stored A(i,j) whose row i is in x' of
+ *           Mult(A(i,j), x'(i)),
+ * in the operand order of oracle_spmspv (select2nd yields the x entry), so
+ * y' equals A^T x' entry for entry.  Column-driven, unlike oracle_spmspv:
+ * x' is spread into a dense array and every column of A is walked; column j
+ * is in y' exactly when one of its stored rows is in x' (structural
+ * pattern).  Output ascending in y_idx [n] / y_val (plus-times double,
+ * min-select2nd int32, or-and uint8).  Returns 0, -3 for an x index out of
+ * range, -4 for a duplicate x index.
+ */
+int oracle_spmspv_left(int semiring, int64_t m, int64_t n, const int32_t* colptr, const int32_t* rowids,
+                       const float* values, int64_t f, const int32_t* x_idx, const void* x_val, int32_t* y_idx,
+                       void* y_val, int64_t* nnz_y) {
+    unsigned char* has = (unsigned char*)calloc((size_t)(m > 0 ? m : 1), 1);
+    double* xd = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    int32_t* xi = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int rc = 0;
+    for (int64_t p = 0; p < f && rc == 0; ++p) {
+        const int32_t i = x_idx[p];
+        if (i < 0 || i >= m) rc = -3;
+        else if (has[i]) rc = -4;
+        else {
+            has[i] = 1;
+            if (semiring == OR_PLUS_TIMES) xd[i] = (double)((const float*)x_val)[p];
+            else if (semiring == OR_MIN_SELECT2ND) xi[i] = ((const int32_t*)x_val)[p];
+            else xi[i] = ((const uint8_t*)x_val)[p] != 0;
+        }
+    }
+    int64_t count = 0;
+    for (int64_t j = 0; j < n && rc == 0; ++j) {
+        int hit = 0;
+        double sd = 0.0;
+        int32_t si = 0;
+        for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+            const int32_t i = rowids[q];
+            if (!has[i]) continue;
+            if (semiring == OR_PLUS_TIMES) {
+                const double t = (values ? (double)values[q] : 1.0) * xd[i];
+                sd = hit ? sd + t : t;
+            } else if (semiring == OR_MIN_SELECT2ND) {
+                si = (!hit || xi[i] < si) ? xi[i] : si;
+            } else {
+                const int32_t t = (values ? (values[q] != 0.0f) : 1) && xi[i];
+                si = hit ? (si || t) : t;
+            }
+            hit = 1;
+        }
+        if (!hit) continue;
+        y_idx[count] = (int32_t)j;
+        if (semiring == OR_PLUS_TIMES) ((double*)y_val)[count] = sd;
+        else if (semiring == OR_MIN_SELECT2ND) ((int32_t*)y_val)[count] = si;
+        else ((uint8_t*)y_val)[count] = (uint8_t)si;
+        ++count;
+    }
+    *nnz_y = count;
+    free(has); free(xd); free(xi);
+    return rc;
+}
+
+/*
+ * y <- A x with A in DCSC (Background, Sparse matrix and vector data
+ * structures): only the nzc non-empty columns are stored, their ids
+ * ascending in jc[0..nzc) and their entries at [cp[k], cp[k+1]) of rowids /
+ * values.  Each x entry's column is looked up in jc by binary search; a
+ * column absent from jc is empty and selects nothing.  The product is then
+ * formed as in oracle_spmspv (dense accumulator, fp64 for plus-times,
+ * structural pattern), output ascending.  *W = products formed.  Returns 0,
+ * or -3 for an x index outside [0, n).
+ */
+int oracle_spmspv_dcsc(int semiring, int64_t m, int64_t n, int64_t nzc, const int32_t* jc, const int32_t* cp,
+                       const int32_t* rowids, const float* values, int64_t f, const int32_t* x_idx,
+                       const void* x_val, int32_t* y_idx, void* y_val, int64_t* nnz_y, int64_t* W) {
+    unsigned char* seen = (unsigned char*)calloc((size_t)(m > 0 ? m : 1), 1);
+    double* acc_d = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    int32_t* acc_i = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t work = 0;
+    int rc = 0;
+    for (int64_t p = 0; p < f; ++p) {
+        const int32_t j = x_idx[p];
+        if (j < 0 || j >= n) { rc = -3; break; }
+        int64_t lo = 0, hi = nzc;   /* first k with jc[k] >= j */
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (jc[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo == nzc || jc[lo] != j) continue;   /* empty column */
+        for (int64_t q = cp[lo]; q < cp[lo + 1]; ++q) {
+            const int32_t i = rowids[q];
+            ++work;
+            if (semiring == OR_PLUS_TIMES) {
+                const double t = (values ? (double)values[q] : 1.0) * (double)((const float*)x_val)[p];
+                acc_d[i] = seen[i] ? acc_d[i] + t : t;
+            } else if (semiring == OR_MIN_SELECT2ND) {
+                const int32_t t = ((const int32_t*)x_val)[p];
+                acc_i[i] = (!seen[i] || t < acc_i[i]) ? t : acc_i[i];
+            } else {
+                const int32_t t = (values ? (values[q] != 0.0f) : 1) && ((const uint8_t*)x_val)[p] != 0;
+                acc_i[i] = seen[i] ? (acc_i[i] || t) : t;
+            }
+            seen[i] = 1;
+        }
+    }
+    int64_t count = 0;
+    for (int64_t i = 0; i < m && rc == 0; ++i) {
+        if (!seen[i]) continue;
+        y_idx[count] = (int32_t)i;
+        if (semiring == OR_PLUS_TIMES) ((double*)y_val)[count] = acc_d[i];
+        else if (semiring == OR_MIN_SELECT2ND) ((int32_t*)y_val)[count] = acc_i[i];
+        else ((uint8_t*)y_val)[count] = (uint8_t)acc_i[i];
+        ++count;
+    }
+    *nnz_y = count;
+    *W = work;
+    free(seen); free(acc_d); free(acc_i);
+    return rc;
 }
 
 /* Plus-times accumulated in fp32, products rounded to fp32 first, rows

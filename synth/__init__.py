@@ -93,6 +93,49 @@ class CSC:
         return sp.csc_matrix((vals.astype(np.float64), self.rowids, self.colptr), shape=(self.m, self.n))
 
 
+@dataclass
+class DCSC:
+    """A sparse matrix in doubly compressed sparse column form: only the nzc
+    non-empty columns are stored, their ids ascending in jc and their
+    entries at [cp[k], cp[k+1]) of rowids / values (int32 indices)."""
+    m: int
+    n: int
+    jc: np.ndarray              # int32[nzc]
+    cp: np.ndarray              # int32[nzc+1]
+    rowids: np.ndarray          # int32[nnz]
+    values: Optional[np.ndarray]  # float32[nnz] or None (pattern matrix)
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.cp[-1])
+
+    @property
+    def nzc(self) -> int:
+        return int(self.jc.size)
+
+
+def csc_to_dcsc(A: CSC) -> DCSC:
+    """The same matrix with its empty columns dropped (a format change only)."""
+    jc = np.nonzero(np.diff(A.colptr.astype(np.int64)) > 0)[0].astype(np.int32)
+    cp = np.empty(jc.size + 1, np.int32)
+    cp[:-1] = A.colptr[jc]
+    cp[-1] = A.colptr[-1]
+    return DCSC(A.m, A.n, jc, cp, A.rowids, A.values, A.name + "-dcsc")
+
+
+def column_subset(A: CSC, keep: np.ndarray) -> CSC:
+    """A with every column outside `keep` (a boolean mask over columns)
+    emptied: a way to make hypersparse inputs from the generators' graphs."""
+    keep = np.asarray(keep, bool)
+    lens = np.where(keep, np.diff(A.colptr.astype(np.int64)), 0)
+    colptr = np.zeros(A.n + 1, np.int64)
+    colptr[1:] = np.cumsum(lens)
+    sel = np.repeat(keep, np.diff(A.colptr.astype(np.int64)))
+    vals = None if A.values is None else A.values[sel].copy()
+    return CSC(A.m, A.n, colptr.astype(np.int32), A.rowids[sel].copy(), vals, A.name + "-cols")
+
+
 def values(count: int, seed: int, stream: int = _STREAM_A_VALUES) -> np.ndarray:
     out = np.empty(count, np.float32)
     if count:
