@@ -111,7 +111,7 @@ enum spmspv_flags {
     SPMSPV_MSBFS = 1024,       /* spmspv_batch_workspace_size / _attach: also
                                   hold per-source frontiers and visited
                                   bitmaps for msbfs_run                       */
-    SPMSPV_USE_SELECTOR = 512  /* spmspv_run / bfs_run / pagerank_run: a small
+    SPMSPV_USE_SELECTOR = 512, /* spmspv_run / bfs_run / pagerank_run: a small
                                   MLP loaded with spmspv_selector_load picks
                                   the bucket count (or the pull direction)
                                   per call from features the scan computes on
@@ -121,6 +121,17 @@ enum spmspv_flags {
                                   form instead consumes the decision on the
                                   device (direction only, inside the captured
                                   level graph, no host synchronisation)       */
+    SPMSPV_LEFT = 16384        /* spmspv_run / _masked / _graphblas /
+                                  _bitvector: left multiplication y' <- x' A
+                                  (Background, Notation: the row-vector case),
+                                  x' over A's m rows, y' over its n columns,
+                                  y'(j) = Add over stored A(i,j), i in x', of
+                                  Mult(A(i,j), x'(i)) (select2nd yields the x
+                                  entry, as on the right).  Runs the push
+                                  multiply on A^T through the CSR copy, so
+                                  the handle needs SPMSPV_WITH_TRANSPOSE or
+                                  SPMSPV_SYMMETRIC (EUNSUPPORTED otherwise);
+                                  no selector, pull or tuned schedule         */
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any
@@ -168,6 +179,28 @@ int spmspv_workspace_size(int64_t m, int64_t n, int64_t nnz, int flags, size_t* 
 int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
                   const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes, int flags,
                   void* stream);
+
+/* ---- DCSC input (Background, "Sparse matrix and vector data structures":
+ * only the nzc non-empty columns are stored, so the matrix takes O(nzc +
+ * nnz) space instead of CSC's O(n + nnz)).  jc int32[nzc] holds the stored
+ * column ids, strictly ascending in [0, n); cp int32[nzc+1] their starts
+ * (cp[0] = 0, non-decreasing, cp[nzc] = nnz); rowids / values as for CSC.
+ * The handle builds the auxiliary column index the format description
+ * mentions (first stored column of every chunk of about n / nzc ids, in the
+ * workspace), so an x entry finds its column in expected constant time; an
+ * x entry naming a column absent from jc selects nothing.  The workspace
+ * still holds per-x-entry tables sized by n (x may list every column).
+ * Flags: SPMSPV_VALIDATE only (no transpose, so no pull direction and no
+ * SPMSPV_LEFT).  The handle serves spmspv_run / _masked / _graphblas /
+ * _bitvector (three-launch push multiply; no selector), the batched calls,
+ * msbfs_run and bfs_run (bucketing levels only); pagerank_run and cc_run
+ * need per-id column degrees and return EUNSUPPORTED.  Errors as for
+ * spmspv_create, plus EINVAL for nzc outside [0, min(n, nnz)] or nzc == 0
+ * with nnz > 0, and (on the device) jc not strictly ascending in [0, n). */
+int spmspv_dcsc_workspace_size(int64_t m, int64_t n, int64_t nzc, int64_t nnz, int flags, size_t* h_bytes);
+int spmspv_create_dcsc(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nzc, int64_t nnz, const int32_t* jc,
+                       const int32_t* cp, const int32_t* rowids, const float* values, void* workspace,
+                       size_t ws_bytes, int flags, void* stream);
 
 /* y <- A x (Algorithm 1 with Algorithm 2's counting), enqueued on `stream`.
  *   f                 : number of x entries (0 <= f <= n); indices must be
@@ -317,8 +350,9 @@ int cc_run(spmspv_handle A, int flags, int32_t* labels, int32_t* h_iters, void* 
  * The mask is applied inside the product (products of rows outside it are
  * dropped before bucketing), then t and w are merged.  flags: VALIDATE
  * (host checks of x, the mask list and w's order), X_VAL_IS_INDEX,
- * X_ALL_TRUE.  Device checks report mask or w indices out of range
- * (EDEVICE) and a w that is not ascending.  Uses the handle's BFS buffers
+ * X_ALL_TRUE, LEFT (then x lies over A's rows and the mask, w and y over
+ * its columns).  Device checks report mask or w indices out of range
+ * (EDEVICE) and a w that is not ascending.  Uses the handle's list scratch
  * for its temporaries.  Push direction always.                            */
 enum spmspv_mask_flags {
     SPMSPV_MASK_COMPLEMENT = 1,
@@ -334,6 +368,28 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
                          const void* x_val, const int32_t* mask_idx, const uint8_t* mask_val, int64_t mask_count,
                          int mask_flags, int accum, const int32_t* w_idx, const void* w_val, int64_t w_count,
                          int32_t* y_idx, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
+                         void* stream);
+
+/* ---- bitvector x and y (Background, "Sparse matrix and vector data
+ * structures": a bitmap over the vector's length plus the values of the
+ * present indices in ascending index order).  y is produced in the same
+ * format as x (the paper's rule for the output format).
+ *   x_bits  uint32[ceil(len_x / 32)]: bit (i mod 32) of word i / 32 set when
+ *           index i is present; len_x = n (m with SPMSPV_LEFT).  A set bit
+ *           at or past len_x is ignored and reported (EDEVICE with h_nnz_y).
+ *   x_val   the present entries' values, ascending by index (type per
+ *           semiring; NULL with X_VAL_IS_INDEX / X_ALL_TRUE).
+ *   y_bits  uint32[ceil(len_y / 32)], every word written (len_y = m, or n
+ *           with SPMSPV_LEFT); y_val [y_capacity] the present entries'
+ *           values ascending by index (nullable: pattern only).
+ *   d_nnz_y / h_nnz_y as for spmspv_run (ECAPACITY when nnz(y) exceeds
+ *           y_capacity: then y_bits holds only the first y_capacity rows).
+ * Flags: X_VAL_IS_INDEX, X_ALL_TRUE, LEFT, SORTED_OUTPUT (implied).  The
+ * bitmap is expanded to its index list on the device, the product runs as
+ * a device-sized spmspv_run (push, the handle's schedule), and y's ordered
+ * list is packed back; the lists use the handle's list scratch.          */
+int spmspv_run_bitvector(spmspv_handle A, int semiring, int flags, const uint32_t* x_bits, const void* x_val,
+                         uint32_t* y_bits, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
                          void* stream);
 
 /* ---- allocation-free multiply.  For callers that cannot allocate device

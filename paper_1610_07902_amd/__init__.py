@@ -35,6 +35,7 @@ MSBFS = 1024
 AUTO_SCHEDULE = 2048
 PULL_ROWWISE = 4096
 PERSISTENT = 8192
+LEFT = 16384
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10
@@ -50,6 +51,7 @@ EXPORTED = (
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
     "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas", "cc_run",
+    "spmspv_dcsc_workspace_size", "spmspv_create_dcsc", "spmspv_run_bitvector",
 )
 
 
@@ -108,6 +110,9 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_run_static.argtypes = [i64, i64, i64, vp, vp, vp, ci, ci, i64, vp, vp, vp, vp, i64, vp,
                                       ctypes.POINTER(i64), ctypes.POINTER(sz), vp]
     lib.cc_run.argtypes = [vp, ci, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.spmspv_dcsc_workspace_size.argtypes = [i64, i64, i64, i64, ci, ctypes.POINTER(sz)]
+    lib.spmspv_create_dcsc.argtypes = [ctypes.POINTER(vp), i64, i64, i64, i64, vp, vp, vp, vp, vp, sz, ci, vp]
+    lib.spmspv_run_bitvector.argtypes = [vp, ci, ci, vp, vp, vp, vp, i64, vp, ctypes.POINTER(i64), vp]
     lib.spmspv_run_graphblas.argtypes = [vp, ci, ci, i64, vp, vp, vp, vp, i64, ci, ci, vp, vp, i64, vp, vp, i64,
                                          vp, ctypes.POINTER(i64), vp]
     lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
@@ -174,6 +179,30 @@ def spmspv_create(m, n, nnz, colptr, rowids, values, workspace, ws_bytes, flags=
     _check(load_library().spmspv_create(ctypes.byref(h), m, n, nnz, _ptr(colptr), _ptr(rowids), _ptr(values),
                                         _ptr(workspace), ws_bytes, flags, _stream(stream)))
     return h
+
+
+def spmspv_dcsc_workspace_size(m: int, n: int, nzc: int, nnz: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().spmspv_dcsc_workspace_size(m, n, nzc, nnz, flags, ctypes.byref(out)))
+    return out.value
+
+
+def spmspv_create_dcsc(m, n, nzc, nnz, jc, cp, rowids, values, workspace, ws_bytes, flags=0,
+                       stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p(None)
+    _check(load_library().spmspv_create_dcsc(ctypes.byref(h), m, n, nzc, nnz, _ptr(jc), _ptr(cp), _ptr(rowids),
+                                             _ptr(values), _ptr(workspace), ws_bytes, flags, _stream(stream)))
+    return h
+
+
+def spmspv_run_bitvector(handle, semiring, flags, x_bits, x_val, y_bits, y_val, y_capacity, d_nnz_y=None,
+                         sync=True, stream=None) -> Optional[int]:
+    """Bitvector x -> bitvector y (bitmaps as int32/uint32 words); with sync=True returns nnz(y)."""
+    h = ctypes.c_int64(0)
+    _check(load_library().spmspv_run_bitvector(handle, semiring, flags, _ptr(x_bits), _ptr(x_val), _ptr(y_bits),
+                                               _ptr(y_val), y_capacity, _ptr(d_nnz_y),
+                                               ctypes.byref(h) if sync else None, _stream(stream)))
+    return h.value if sync else None
 
 
 def spmspv_run(handle, semiring, flags, f, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y=None, sync=True,
@@ -459,6 +488,27 @@ class Matrix:
     def from_csc(cls, A, flags: int = 0, device="cuda", pattern: bool = False):
         return cls(A.m, A.n, A.colptr, A.rowids, None if pattern else A.values, flags, device)
 
+    @classmethod
+    def from_dcsc(cls, D, flags: int = 0, device="cuda", pattern: bool = False):
+        """A DCSC matrix (non-empty columns only: ids D.jc, starts D.cp)."""
+        import torch
+        self = cls.__new__(cls)
+        self.m, self.n = int(D.m), int(D.n)
+        self.jc = torch.as_tensor(D.jc, dtype=torch.int32).to(device).contiguous()
+        self.colptr = torch.as_tensor(D.cp, dtype=torch.int32).to(device).contiguous()
+        self.rowids = torch.as_tensor(D.rowids, dtype=torch.int32).to(device).contiguous()
+        vals = None if (pattern or D.values is None) else D.values
+        self.values = None if vals is None else torch.as_tensor(vals, dtype=torch.float32).to(device).contiguous()
+        self.nnz = int(self.rowids.numel())
+        self.nzc = int(self.jc.numel())
+        self.ws_bytes = spmspv_dcsc_workspace_size(self.m, self.n, self.nzc, self.nnz, flags)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.handle = spmspv_create_dcsc(self.m, self.n, self.nzc, self.nnz, self.jc, self.colptr, self.rowids,
+                                         self.values, self.workspace, self.ws_bytes, flags)
+        _live.add(self)
+        self._d_nnz = torch.zeros(1, dtype=torch.int64, device=device)
+        return self
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             spmspv_destroy(self.handle)
@@ -483,7 +533,7 @@ class Matrix:
         """y <- A x (rows with a set `mask` bit excluded).  Returns (y_idx, y_val, nnz), trimmed when sync."""
         import torch
         dev = self.colptr.device
-        cap = self.m if y_capacity is None else int(y_capacity)
+        cap = (self.n if flags & LEFT else self.m) if y_capacity is None else int(y_capacity)
         if out is None:
             y_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
             vdt = {PLUS_TIMES_F32: torch.float32, MIN_SELECT2ND_I32: torch.int32, OR_AND_BOOL: torch.uint8}[semiring]
@@ -498,6 +548,19 @@ class Matrix:
             return y_idx, y_val, self._d_nnz
         k = min(nnz, cap)
         return y_idx[:k], y_val[:k], nnz
+
+    def spmspv_bitvector(self, x_bits, x_val=None, semiring: int = PLUS_TIMES_F32, flags: int = 0,
+                         y_capacity: Optional[int] = None):
+        """Bitvector x (uint32-word bitmap + values ascending by index) -> (y_bits, y_val, nnz)."""
+        import torch
+        dev = self.colptr.device
+        ylen = self.n if flags & LEFT else self.m
+        cap = ylen if y_capacity is None else int(y_capacity)
+        y_bits = torch.empty(max((ylen + 31) // 32, 1), dtype=torch.int32, device=dev)
+        vdt = {PLUS_TIMES_F32: torch.float32, MIN_SELECT2ND_I32: torch.int32, OR_AND_BOOL: torch.uint8}[semiring]
+        y_val = torch.empty(max(cap, 1), dtype=vdt, device=dev)
+        nnz = spmspv_run_bitvector(self.handle, semiring, flags, x_bits, x_val, y_bits, y_val, cap, self._d_nnz)
+        return y_bits, y_val[:min(nnz, cap)], nnz
 
     def bfs(self, root: int, semiring: int = MIN_SELECT2ND_I32, parents: bool = True, flags: int = 0):
         import torch

@@ -71,17 +71,26 @@ struct alignas(256) Ctrl {
     // One-launch multiply: call counter whose value tags this call's
     // exchange and look-back words (advanced once per call on the device).
     uint32_t fused_epoch;
-    uint32_t pad1;
+    int32_t maxrow;         // longest row of A (create, with the transpose)
     int64_t aux_count;      // masked multiply: length of the masked product before the combine
-    uint32_t pad[22];
+    int32_t bv_f;           // bitvector call: x entries found in its bitmap
+    uint32_t pad[21];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl must stay 256 bytes");
 
 // Scan phase: gather the selected column ranges, prefix-sum their lengths,
 // compact the non-empty ones and mark where each product chunk starts.
 struct ScanArgs {
-    const int32_t* colptr;
+    const int32_t* colptr;   // CSC: [n+1]; DCSC: the [nzc+1] column starts
     int32_t n;
+    // DCSC (dcsc = 1): column j is the k-th stored one when dc_jc[k] == j,
+    // searched in [dc_aux[j >> dc_shift], dc_aux[(j >> dc_shift) + 1]); a
+    // column absent from dc_jc is empty (with no stored column dc_jc may be
+    // null and is never read).
+    int dcsc;
+    const int32_t* dc_jc;
+    const int32_t* dc_aux;
+    int32_t dc_shift;
     const int32_t* x_idx;
     const void* x_val;
     int xmode;
@@ -376,7 +385,25 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl,
                              hipStream_t s);
 hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);
-hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, int32_t* maxout,
+                                 hipStream_t s);
+
+// Format variants (format_kernels.hip).
+// DCSC column index: aux[c] = first k with jc[k] >= c << shift, c in [0, nchunk].
+hipError_t launch_dcsc_aux(const int32_t* jc, int32_t nzc, int32_t shift, int32_t nchunk, int32_t* aux,
+                           hipStream_t s);
+// ERR_CSC unless jc is strictly ascending inside [0, n).
+hipError_t launch_validate_jc(const int32_t* jc, int32_t nzc, int32_t n, Ctrl* ctrl, hipStream_t s);
+// Bitmap of n bits -> ascending index list out[], its length to *count
+// (ERR_X_RANGE if a bit at or past n is set; such bits are ignored).
+// tile_counts: bits_tiles(n) ints of scratch.
+int64_t bits_tiles(int64_t n);
+hipError_t launch_bits_to_list(const uint32_t* bits, int32_t n, int32_t* out, int32_t* count, int32_t* tile_counts,
+                               Ctrl* ctrl, hipStream_t s);
+// Ascending list of *nnz (device) distinct indices below m -> bitmap of m
+// bits (every word written); entries past cap are not read.
+hipError_t launch_list_to_bits(const int32_t* idx, const int64_t* nnz, int64_t cap, int32_t m, uint32_t* bits,
+                               hipStream_t s);
 hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
 hipError_t launch_pr_init(int32_t n, const int32_t* colptr, float d, float* rank, int32_t* x_idx, float* x_val,
                           Ctrl* ctrl, hipStream_t s);

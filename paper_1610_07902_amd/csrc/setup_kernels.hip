@@ -27,7 +27,7 @@ __global__ void k_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int3
 }
 
 // colptr[0] == 0, colptr monotone, colptr[n] == nnz; also the longest column.
-__global__ void k_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl) {
+__global__ void k_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, int32_t* maxout) {
     int lmax = 0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = colptr[j], b = colptr[j + 1];
@@ -36,7 +36,7 @@ __global__ void k_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz,
         if (j == 0 && a != 0) atomicOr(&ctrl->err, ERR_CSC);
         if (j == n - 1 && (int64_t)b != nnz) atomicOr(&ctrl->err, ERR_CSC);
     }
-    if (lmax > 0) atomicMax(&ctrl->maxdeg, lmax);
+    if (lmax > 0) atomicMax(maxout, lmax);
 }
 
 __device__ int block_scan_excl(int v, int* s) {
@@ -236,9 +236,10 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
     return hipGetLastError();
 }
 
-hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, int32_t* maxout,
+                                 hipStream_t s) {
     hipLaunchKernelGGL(k_validate_colptr, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, colptr, n, nnz,
-                       ctrl);
+                       ctrl, maxout);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
-        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, total;
+        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose;
@@ -66,7 +66,7 @@ struct Layout {
 
 inline int64_t gb_lb_words(int64_t m) { return (2 * m + kCombineTile - 1) / kCombineTile + 2; }
 
-Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
+Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_chunks = 0) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -74,20 +74,26 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
         o = align_up(o + (bytes ? bytes : 1));
         return at;
     };
-    L.nb_max = (m + (1 << kTileLog2Min) - 1) >> kTileLog2Min;
+    // Left multiplication runs A^T (m and n swapped) through the same
+    // regions, so with the transpose present the regions sized by the
+    // output length (mr) or by the x length (nc) take max(m, n).
+    const int64_t mx = std::max(m, n);
+    const bool tr = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
+    const int64_t mr = tr ? mx : m, nc = tr ? mx : n;
+    L.nb_max = (mr + (1 << kTileLog2Min) - 1) >> kTileLog2Min;
     // one-launch multiply: chunks of at most kFChunk products, at least one per workgroup
     L.rows_cap = std::max<int64_t>(kFMaxGrid, (nnz + kFChunk) / kFChunk) + 1;
     L.fnb = (int32_t)std::min<int64_t>(kFMaxNb, L.nb_max);
-    L.lb1_n = (n + kScanTile - 1) / kScanTile + 1;
+    L.lb1_n = (nc + kScanTile - 1) / kScanTile + 1;
     L.chunk_n = nnz / kChunkMin + 2;
     L.ctrl = take(sizeof(Ctrl));
     L.rcp = take(size_t(m + 1) * 4);
     L.partials = take(size_t((m + 1) / 4096 + 2) * 4);
     // column tables; the one-launch multiply keeps its per-workgroup column
     // lists here too (up to kFMaxGrid - 1 slots past n)
-    L.cstart = take(size_t(n + kFMaxGrid + 1) * 4);
-    L.coff = take(size_t(n + kFMaxGrid + 1) * 4);
-    L.cxv = take(size_t(n + kFMaxGrid + 1) * 4);
+    L.cstart = take(size_t(nc + kFMaxGrid + 1) * 4);
+    L.coff = take(size_t(nc + kFMaxGrid + 1) * 4);
+    L.cxv = take(size_t(nc + kFMaxGrid + 1) * 4);
     L.chunk_col = take(size_t(L.chunk_n) * 4);
     L.lb1 = take(size_t(L.lb1_n) * 16);
     L.cursor = take(size_t(L.nb_max) * 4);
@@ -97,7 +103,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.xw = take(size_t(kXWords) * 8);
     L.xrec = take(size_t(2 * L.rows_cap) * 8);
     L.buckets = take(size_t(nnz + 1) * 8);
-    L.visited = take(size_t((m + 31) / 32) * 4);
+    L.visited = take(size_t((mr + 31) / 32) * 4);
     L.front0 = take(size_t(m) * 4);
     L.front1 = take(size_t(m) * 4);
     L.front2 = take(size_t(m) * 4);
@@ -110,7 +116,14 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0) {
     L.gpoff = take(size_t(kFMaxGrid + 1) * 8);
     L.roff = take(size_t(L.rows_cap) * size_t(L.fnb + 1) * 4);
     // masked multiply: look-back words of the combine (t and w each hold at most m rows)
-    L.gb_lb = take(size_t(gb_lb_words(m)) * 8);
+    L.gb_lb = take(size_t(gb_lb_words(mr)) * 8);
+    // bitvector calls (x list, then y list) and the masked multiply's
+    // product t: lists of up to max(m, n) entries
+    L.bv_idx = take(size_t(mx) * 4);
+    L.bv_val = take(size_t(mx) * 4);
+    L.bv_tiles = take(size_t(bits_tiles(mx)) * 4);
+    // DCSC: column index over the stored column ids
+    L.dc_aux = dc_chunks > 0 ? take(size_t(dc_chunks + 1) * 4) : 0;
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
     if (L.pull) {
@@ -255,6 +268,20 @@ struct spmspv_matrix {
     spmspv_schedule batch_sched{};      // batched-call schedule (tile_log2 0 = derive)
     std::vector<spmspv_tune_entry> tuned;   // autotuned schedule per density band
     std::vector<int32_t> forced_classes;    // per-step classes replacing the selector (replay)
+    // Left multiplication reads the CSR copy as the CSC of A^T: its row
+    // counts are A's column counts (bucket bases colptr) and its longest
+    // column is A's longest row.
+    int32_t maxrow = 0;
+    // DCSC input: colptr holds the nzc + 1 starts of the stored columns
+    bool dcsc = false;
+    int64_t nzc = 0;
+    const int32_t* dc_jc = nullptr;     // ids of the stored columns, ascending
+    int32_t* dc_aux = nullptr;          // column index: first stored column of each id chunk
+    int32_t dc_shift = 0;               // id chunk = j >> dc_shift
+    // list scratch of max(m, n) entries (bitvector calls, masked product t)
+    int32_t* bv_idx = nullptr;
+    uint32_t* bv_val = nullptr;
+    int32_t* bv_tiles = nullptr;
 };
 
 namespace {
@@ -347,21 +374,43 @@ int64_t scatter_occupancy(const spmspv_matrix* A, int nb, int block, int chunk, 
 int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev, const int32_t* x_idx,
             const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
             const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
-            int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0) {
+            int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0, bool left = false) {
+    // The operand: A, or for left multiplication A^T through the CSR copy
+    // (y' = x'A is y = A^T x; Background, Notation).  The CSR copy's row
+    // pointer is A^T's column pointer and A's column pointer is A^T's
+    // row-count prefix, which sizes the buckets.
+    const int64_t Om = left ? A->n : A->m, On = left ? A->m : A->n;
+    const int32_t* Ocolptr = left ? A->rowptr : A->colptr;
+    const int32_t* Orowids = left ? reinterpret_cast<const int32_t*>(A->colids) : A->rowids;
+    const float* Ovalues = left ? A->rvalues : A->values;
+    const int32_t* Orcp = left ? A->colptr : A->rcp;
+    const int64_t Omaxdeg = left ? A->maxrow : A->maxdeg;
     spmspv_schedule sc = A->sched;
     if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
     sc.tile_log2 = call_tile(A, sc.tile_log2, semiring);
-    const int nb = (int)((A->m + (int64_t(1) << sc.tile_log2) - 1) >> sc.tile_log2);
     const int chunk = sc.scatter_block * sc.scatter_items;
+    auto buckets_of = [&](int tl) { return (int)((Om + (int64_t(1) << tl) - 1) >> tl); };
+    // A^T of a wide A can have more rows than the schedule's tile covers in
+    // one scatter histogram: widen the tile as far as the merge allows.
+    while (left && scatter_lds_bytes(buckets_of(sc.tile_log2), chunk) + 1024 > A->lds_max &&
+           sc.tile_log2 < call_tile(A, kTileLog2Max, semiring))
+        ++sc.tile_log2;
+    const int nb = buckets_of(sc.tile_log2);
     if (scatter_lds_bytes(nb, chunk) + 1024 > A->lds_max)
         return fail(SPMSPV_EUNSUPPORTED, "too many buckets of 2^" + std::to_string(sc.tile_log2) +
                                              " rows for the scatter LDS histogram");
     const int chunk_log2 = ceil_log2(chunk);
-    const int64_t f_bound = f_dev ? A->n : f_host;
+    const int64_t f_bound = f_dev ? On : f_host;
 
     ScanArgs sa{};
-    sa.colptr = A->colptr;
-    sa.n = (int32_t)A->n;
+    sa.colptr = Ocolptr;
+    sa.n = (int32_t)On;
+    if (A->dcsc && !left) {
+        sa.dcsc = 1;
+        sa.dc_jc = A->dc_jc;
+        sa.dc_aux = A->dc_aux;
+        sa.dc_shift = A->dc_shift;
+    }
     sa.x_idx = x_idx;
     sa.x_val = x_val;
     sa.xmode = xmode;
@@ -401,8 +450,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     if (f_dev && g1 > 2 * A->num_cu) g1 = 2 * A->num_cu;
 
     ScatterArgs ca{};
-    ca.rowids = A->rowids;
-    ca.values = A->values;
+    ca.rowids = Orowids;
+    ca.values = Ovalues;
     ca.ctrl = A->ctrl;
     ca.cstart = A->cstart;
     ca.coff = A->coff;
@@ -411,8 +460,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ca.chunk_log2 = chunk_log2;
     ca.tile_log2 = sc.tile_log2;
     ca.nb = nb;
-    ca.m = (int32_t)A->m;
-    ca.rcp = A->rcp;
+    ca.m = (int32_t)Om;
+    ca.rcp = Orcp;
     ca.cursor = A->cursor;
     ca.buckets = A->buckets;
     ca.mask = mask;
@@ -424,7 +473,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ca.f_host = (int32_t)f_host;
     ca.f_dev = f_dev;
     ca.gate = diropt ? 1 : 0;
-    int64_t wbound = f_dev ? A->nnz : f_host * (int64_t)A->maxdeg;
+    int64_t wbound = f_dev ? A->nnz : f_host * Omaxdeg;
     if (wbound > A->nnz) wbound = A->nnz;
     int64_t g2 = (wbound + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
@@ -435,8 +484,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ma.ctrl = A->ctrl;
     ma.cursor = A->cursor;
     ma.buckets = A->buckets;
-    ma.rcp = A->rcp;
-    ma.m = (int32_t)A->m;
+    ma.rcp = Orcp;
+    ma.m = (int32_t)Om;
     ma.tile_log2 = sc.tile_log2;
     ma.nb = nb;
     ma.lb3 = A->lb3;
@@ -690,6 +739,12 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
 
     ScanArgs sa{};
     sa.colptr = A->colptr;
+    if (A->dcsc) {
+        sa.dcsc = 1;
+        sa.dc_jc = A->dc_jc;
+        sa.dc_aux = A->dc_aux;
+        sa.dc_shift = A->dc_shift;
+    }
     sa.n = (int32_t)A->n;
     sa.x_idx = x_idx;
     sa.x_val = x_val;
@@ -845,14 +900,14 @@ hipEvent_t* profile_slot(spmspv_matrix* A) {
 
 // Point a handle at matrix arrays and a workspace laid out by make_layout.
 void bind_workspace(spmspv_matrix* A, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
-                    const int32_t* rowids, const float* values, char* ws, int flags) {
+                    const int32_t* rowids, const float* values, char* ws, int flags, int64_t dc_chunks = 0) {
     A->m = m;
     A->n = n;
     A->nnz = nnz;
     A->colptr = colptr;
     A->rowids = rowids;
     A->values = values;
-    A->L = make_layout(m, n, nnz, flags);
+    A->L = make_layout(m, n, nnz, flags, dc_chunks);
     A->ws = ws;
     const Layout& L = A->L;
     A->ctrl = reinterpret_cast<Ctrl*>(A->ws + L.ctrl);
@@ -873,6 +928,10 @@ void bind_workspace(spmspv_matrix* A, int64_t m, int64_t n, int64_t nnz, const i
     A->pmin = reinterpret_cast<int32_t*>(A->ws + L.pmin);
     A->bar = reinterpret_cast<uint32_t*>(A->ws + L.bar);
     A->selector = reinterpret_cast<float*>(A->ws + L.selector);
+    A->bv_idx = reinterpret_cast<int32_t*>(A->ws + L.bv_idx);
+    A->bv_val = reinterpret_cast<uint32_t*>(A->ws + L.bv_val);
+    A->bv_tiles = reinterpret_cast<int32_t*>(A->ws + L.bv_tiles);
+    A->dc_aux = dc_chunks > 0 ? reinterpret_cast<int32_t*>(A->ws + L.dc_aux) : nullptr;
 }
 
 int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s) {
@@ -978,23 +1037,47 @@ int spmspv_workspace_size(int64_t m, int64_t n, int64_t nnz, int flags, size_t* 
     return SPMSPV_OK;
 }
 
-int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
-                  const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes, int flags,
-                  void* stream) {
+namespace {
+
+// DCSC column index: chunks of 2^shift column ids, about one stored column
+// per chunk (at most 2 nzc + 1 chunks).
+int dcsc_shift(int64_t n, int64_t nzc) {
+    int sh = 0;
+    while ((n >> sh) > std::max<int64_t>(nzc, 1)) ++sh;
+    return sh;
+}
+int64_t dcsc_chunks(int64_t n, int64_t nzc) { return ((n - 1) >> dcsc_shift(n, nzc)) + 1; }
+
+// spmspv_create and spmspv_create_dcsc.  CSC: jc == nullptr and colptr has
+// n + 1 entries; DCSC: colptr has nzc + 1 entries, the starts of the stored
+// columns jc[0..nzc).
+int create_impl(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, int64_t nzc, const int32_t* jc,
+                const int32_t* colptr, const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes,
+                int flags, void* stream) {
     if (!h_out) return fail(SPMSPV_EINVAL, "h_out is NULL");
     *h_out = nullptr;
+    const bool dcsc = nzc >= 0;
     size_t need = 0;
-    int rc = spmspv_workspace_size(m, n, nnz, flags, &need);
+    int rc = dcsc ? spmspv_dcsc_workspace_size(m, n, nzc, nnz, flags, &need)
+                  : spmspv_workspace_size(m, n, nnz, flags, &need);
     if (rc) return rc;
-    if (!colptr || (nnz > 0 && !rowids) || !workspace) return fail(SPMSPV_EINVAL, "NULL matrix or workspace");
-    if (ws_bytes < need) return fail(SPMSPV_ENOMEM, "workspace smaller than spmspv_workspace_size");
+    if (!colptr || (nnz > 0 && !rowids) || !workspace || (dcsc && nzc > 0 && !jc))
+        return fail(SPMSPV_EINVAL, "NULL matrix or workspace");
+    if (ws_bytes < need) return fail(SPMSPV_ENOMEM, "workspace smaller than the workspace size call's");
     if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
         return fail(SPMSPV_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     auto* A = new spmspv_matrix();
-    bind_workspace(A, m, n, nnz, colptr, rowids, values, static_cast<char*>(workspace), flags);
+    bind_workspace(A, m, n, nnz, colptr, rowids, values, static_cast<char*>(workspace), flags,
+                   dcsc ? dcsc_chunks(n, nzc) : 0);
     const Layout& L = A->L;
+    if (dcsc) {
+        A->dcsc = true;
+        A->nzc = nzc;
+        A->dc_jc = jc;
+        A->dc_shift = dcsc_shift(n, nzc);
+    }
 
     auto bail = [&](int status) {
         delete A;
@@ -1012,8 +1095,16 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
     const size_t zero_end = L.buckets;
     if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws), 0u, int64_t(zero_end / 4), s)) != hipSuccess)
         return bail(hip_fail(e, "zero workspace"));
-    if ((e = launch_validate_colptr(colptr, (int32_t)n, nnz, A->ctrl, s)) != hipSuccess)
+    if ((e = launch_validate_colptr(colptr, (int32_t)(dcsc ? nzc : n), nnz, A->ctrl, &A->ctrl->maxdeg, s)) !=
+        hipSuccess)
         return bail(hip_fail(e, "validate colptr"));
+    if (dcsc) {
+        if ((e = launch_validate_jc(jc, (int32_t)nzc, (int32_t)n, A->ctrl, s)) != hipSuccess)
+            return bail(hip_fail(e, "validate column ids"));
+        if ((e = launch_dcsc_aux(jc, (int32_t)nzc, A->dc_shift, (int32_t)dcsc_chunks(n, nzc), A->dc_aux, s)) !=
+            hipSuccess)
+            return bail(hip_fail(e, "DCSC column index"));
+    }
     if ((e = launch_row_counts(rowids, nnz, (int32_t)m, A->rcp, A->ctrl, s)) != hipSuccess)
         return bail(hip_fail(e, "row counts"));
     if ((e = launch_exclusive_scan_i32(A->rcp, m + 1, reinterpret_cast<int32_t*>(A->ws + L.partials), s)) !=
@@ -1054,6 +1145,9 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
                                    colids_t, tvalues, A->p_part, L.transpose ? nullptr : &A->ctrl->unsorted, s)) !=
             hipSuccess)
             return bail(hip_fail(e, "pull set-up"));
+        // longest row: bounds the products of a left multiplication
+        if ((e = launch_validate_colptr(A->rowptr, (int32_t)m, nnz, A->ctrl, &A->ctrl->maxrow, s)) != hipSuccess)
+            return bail(hip_fail(e, "row lengths"));
     }
     Ctrl h{};
     if ((e = hipMemcpyAsync(&h, A->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -1066,12 +1160,39 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
         return bail(fail(SPMSPV_EINVAL, "invalid CSC detected while sizing buckets"));
     }
     A->maxdeg = h.maxdeg;
+    A->maxrow = h.maxrow;
     A->rows_sorted = A->pull && !L.transpose && h.unsorted == 0;
     default_schedule(A, &A->sched);
     if (check_schedule(A, &A->sched) != SPMSPV_OK)
         return bail(fail(SPMSPV_EUNSUPPORTED, "matrix too tall for the LDS bucket layout"));
     *h_out = A;
     return SPMSPV_OK;
+}
+
+}  // namespace
+
+int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const int32_t* colptr,
+                  const int32_t* rowids, const float* values, void* workspace, size_t ws_bytes, int flags,
+                  void* stream) {
+    return create_impl(h_out, m, n, nnz, -1, nullptr, colptr, rowids, values, workspace, ws_bytes, flags, stream);
+}
+
+int spmspv_dcsc_workspace_size(int64_t m, int64_t n, int64_t nzc, int64_t nnz, int flags, size_t* h_bytes) {
+    if (!h_bytes) return fail(SPMSPV_EINVAL, "h_bytes is NULL");
+    if (flags & ~SPMSPV_VALIDATE) return fail(SPMSPV_EINVAL, "a DCSC handle takes only SPMSPV_VALIDATE");
+    if (nzc < 0 || nzc > n || (nzc == 0 && nnz != 0) || nnz < nzc)
+        return fail(SPMSPV_EINVAL, "need 0 <= nzc <= min(n, nnz), nnz == 0 when nzc == 0");
+    const int rc = spmspv_workspace_size(m, n, nnz, flags, h_bytes);
+    if (rc) return rc;
+    *h_bytes = make_layout(m, n, nnz, flags, dcsc_chunks(n, nzc)).total;
+    return SPMSPV_OK;
+}
+
+int spmspv_create_dcsc(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nzc, int64_t nnz, const int32_t* jc,
+                       const int32_t* cp, const int32_t* rowids, const float* values, void* workspace,
+                       size_t ws_bytes, int flags, void* stream) {
+    if (nzc < 0) return fail(SPMSPV_EINVAL, "nzc must be >= 0");
+    return create_impl(h_out, m, n, nnz, nzc, jc, cp, rowids, values, workspace, ws_bytes, flags, stream);
 }
 
 int spmspv_get_schedule(spmspv_handle A, spmspv_schedule* h_sched) {
@@ -1126,7 +1247,9 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
                       int64_t* h_nnz_y, void* stream) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
-    if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    const bool left = (flags & SPMSPV_LEFT) != 0;
+    const int64_t xlen = left ? A->m : A->n;
+    if (f < 0 || f > xlen) return fail(SPMSPV_EINVAL, left ? "f must be in [0, m]" : "f must be in [0, n]");
     if (f > 0 && !x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
     if (y_capacity < 0 || (y_capacity > 0 && !y_idx)) return fail(SPMSPV_EINVAL, "bad y buffer");
     int xmode = XV_BITS32;
@@ -1135,23 +1258,36 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
     if (f > 0 && !x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
     if ((flags & SPMSPV_PULL_ROWWISE) && semiring == SR_PLUS_TIMES)
         return fail(SPMSPV_EINVAL, "SPMSPV_PULL_ROWWISE is for min-select2nd and or-and");
+    if (left && !A->pull)
+        return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_LEFT needs a handle created with SPMSPV_WITH_TRANSPOSE or "
+                                         "SPMSPV_SYMMETRIC");
+    if (left && (flags & (SPMSPV_USE_SELECTOR | SPMSPV_PULL_ROWWISE | SPMSPV_AUTO_SCHEDULE)))
+        return fail(SPMSPV_EINVAL, "SPMSPV_LEFT runs the push multiply only (no selector, pull or tuned schedule)");
+    if (A->dcsc && (flags & SPMSPV_USE_SELECTOR))
+        return fail(SPMSPV_EUNSUPPORTED, "the selector needs a CSC handle");
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     if (flags & SPMSPV_VALIDATE) {
         std::vector<int32_t> hx((size_t)f);
         if (f) HIP_TRY(hipMemcpyAsync(hx.data(), x_idx, size_t(f) * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        std::vector<uint8_t> seen((size_t)A->n, 0);
+        std::vector<uint8_t> seen((size_t)xlen, 0);
         for (int64_t p = 0; p < f; ++p) {
             const int32_t j = hx[(size_t)p];
-            if (j < 0 || j >= A->n) return fail(SPMSPV_EINVAL, "x index out of range");
+            if (j < 0 || j >= xlen) return fail(SPMSPV_EINVAL, "x index out of range");
             if (seen[(size_t)j]) return fail(SPMSPV_EINVAL, "duplicate x index");
             seen[(size_t)j] = 1;
         }
     }
     hipEvent_t* ev = (flags & SPMSPV_PROFILE) ? profile_slot(A) : nullptr;
     int rc;
-    if (flags & SPMSPV_USE_SELECTOR) {
+    if (left) {
+        const spmspv_schedule keep = A->sched;
+        A->sched.direction = 0;
+        rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask, s,
+                     ev, false, -1, 3, 0, false, 0, true);
+        A->sched = keep;
+    } else if (flags & SPMSPV_USE_SELECTOR) {
         if (!A->selector_loaded) return fail(SPMSPV_EINVAL, "no selector weights loaded");
         int cls = 0;
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(&A->ctrl->bfs_mode), 0u, 1, s));
@@ -1164,7 +1300,7 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
         else if (A->sched_default) A->sched = sized_for_call(A, f);
         int G = 0, ftl = 0, fnb = 0;
         if (A->sched.direction == 0 && A->sched.launch == 2) {
-            G = fused_eligible(A, semiring, f, &ftl, &fnb);
+            G = A->dcsc ? 0 : fused_eligible(A, semiring, f, &ftl, &fnb);
             if (G == 0) {
                 A->sched = keep;
                 return fail(SPMSPV_EUNSUPPORTED, "this call cannot run as one launch (f > 4096 per compute unit, "
@@ -1198,6 +1334,53 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
     return SPMSPV_OK;
 }
 
+int spmspv_run_bitvector(spmspv_handle A, int semiring, int flags, const uint32_t* x_bits, const void* x_val,
+                         uint32_t* y_bits, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
+                         void* stream) {
+    if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    if (flags & ~(SPMSPV_SORTED_OUTPUT | SPMSPV_X_VAL_IS_INDEX | SPMSPV_X_ALL_TRUE | SPMSPV_LEFT))
+        return fail(SPMSPV_EINVAL, "spmspv_run_bitvector takes SORTED_OUTPUT, X_VAL_IS_INDEX, X_ALL_TRUE, LEFT");
+    const bool left = (flags & SPMSPV_LEFT) != 0;
+    if (left && !A->pull)
+        return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_LEFT needs a handle created with SPMSPV_WITH_TRANSPOSE or "
+                                         "SPMSPV_SYMMETRIC");
+    if (!x_bits || !y_bits || y_capacity < 0) return fail(SPMSPV_EINVAL, "NULL bitmap or negative capacity");
+    int xmode = XV_BITS32;
+    if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
+    else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
+    if (!x_val && (xmode == XV_BITS32 || xmode == XV_U8)) return fail(SPMSPV_EINVAL, "x_val is NULL");
+    const int64_t xlen = left ? A->m : A->n, ylen = left ? A->n : A->m;
+    const int64_t y_cap = y_val ? std::min(y_capacity, ylen) : ylen;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // (1) x's bitmap -> its ascending index list (the values are already in
+    // that order); its length stays on the device
+    HIP_TRY(launch_bits_to_list(x_bits, (int32_t)xlen, A->bv_idx, &A->ctrl->bv_f, A->bv_tiles, A->ctrl, s));
+    // (2) the multiply on the lists; y's index list reuses x's storage (the
+    // scan has copied what it needs from x before the merge writes y)
+    const spmspv_schedule keep = A->sched;
+    A->sched.direction = 0;
+    const int rc = enqueue(A, semiring, xmode, 0, &A->ctrl->bv_f, A->bv_idx, x_val, A->bv_idx, y_val, y_cap, d_nnz_y,
+                           false, nullptr, s, nullptr, false, -1, 3, 0, false, 0, left);
+    A->sched = keep;
+    if (rc) return rc;
+    // (3) y's ascending index list -> its bitmap
+    HIP_TRY(launch_list_to_bits(A->bv_idx, &A->ctrl->nnz_y, y_cap, (int32_t)ylen, y_bits, s));
+    if (h_nnz_y) {
+        Ctrl h{};
+        const int r = read_ctrl(A, &h, s);
+        if (r) return r;
+        *h_nnz_y = h.nnz_y;
+        if (h.err) {
+            clear_err(A, s);
+            return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err) +
+                                            " (1 = x bit set past the vector length)");
+        }
+        if (h.nnz_y > y_capacity) return fail(SPMSPV_ECAPACITY, "nnz(y) exceeds y_capacity");
+    }
+    return SPMSPV_OK;
+}
+
 int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, const int32_t* x_idx,
                          const void* x_val, const int32_t* mask_idx, const uint8_t* mask_val, int64_t mask_count,
                          int mask_flags, int accum, const int32_t* w_idx, const void* w_val, int64_t w_count,
@@ -1205,17 +1388,24 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
                          void* stream) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
-    if (f < 0 || f > A->n) return fail(SPMSPV_EINVAL, "f must be in [0, n]");
+    // left multiplication: x over A's rows, mask / w / y over its columns
+    const bool left = (flags & SPMSPV_LEFT) != 0;
+    if (left && !A->pull)
+        return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_LEFT needs a handle created with SPMSPV_WITH_TRANSPOSE or "
+                                         "SPMSPV_SYMMETRIC");
+    const int64_t xlen = left ? A->m : A->n, ylen = left ? A->n : A->m;
+    if (f < 0 || f > xlen) return fail(SPMSPV_EINVAL, "f exceeds the length of x");
     if (f > 0 && !x_idx) return fail(SPMSPV_EINVAL, "x_idx is NULL");
     if (mask_count < 0 || (mask_count > 0 && !mask_idx)) return fail(SPMSPV_EINVAL, "bad mask list");
-    if (mask_count > A->m) return fail(SPMSPV_EINVAL, "mask longer than m");
+    if (mask_count > ylen) return fail(SPMSPV_EINVAL, "mask longer than y");
     if (mask_flags & ~(SPMSPV_MASK_COMPLEMENT | SPMSPV_MASK_REPLACE)) return fail(SPMSPV_EINVAL, "unknown mask flag");
     if (accum < SPMSPV_ACCUM_NONE || accum > SPMSPV_ACCUM_SECOND) return fail(SPMSPV_EINVAL, "unknown accumulate");
-    if (w_count < 0 || w_count > A->m || (w_count > 0 && (!w_idx || !w_val)))
+    if (w_count < 0 || w_count > ylen || (w_count > 0 && (!w_idx || !w_val)))
         return fail(SPMSPV_EINVAL, "bad accumulation input w");
     if (y_capacity < 0 || (y_capacity > 0 && !y_idx)) return fail(SPMSPV_EINVAL, "bad y buffer");
-    if (flags & ~(SPMSPV_VALIDATE | SPMSPV_SORTED_OUTPUT | SPMSPV_X_VAL_IS_INDEX | SPMSPV_X_ALL_TRUE))
-        return fail(SPMSPV_EINVAL, "spmspv_run_graphblas takes VALIDATE, SORTED_OUTPUT, X_VAL_IS_INDEX, X_ALL_TRUE");
+    if (flags & ~(SPMSPV_VALIDATE | SPMSPV_SORTED_OUTPUT | SPMSPV_X_VAL_IS_INDEX | SPMSPV_X_ALL_TRUE | SPMSPV_LEFT))
+        return fail(SPMSPV_EINVAL,
+                    "spmspv_run_graphblas takes VALIDATE, SORTED_OUTPUT, X_VAL_IS_INDEX, X_ALL_TRUE, LEFT");
     int xmode = XV_BITS32;
     if (semiring == SR_MIN_SELECT2ND && (flags & SPMSPV_X_VAL_IS_INDEX)) xmode = XV_INDEX;
     else if (semiring == SR_OR_AND) xmode = (flags & SPMSPV_X_ALL_TRUE) ? XV_TRUE : XV_U8;
@@ -1234,18 +1424,18 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
         HIP_TRY(hipStreamSynchronize(s));
         std::vector<uint8_t> seen((size_t)std::max(A->n, A->m), 0);
         for (int32_t j : hx) {
-            if (j < 0 || j >= A->n) return fail(SPMSPV_EINVAL, "x index out of range");
+            if (j < 0 || j >= xlen) return fail(SPMSPV_EINVAL, "x index out of range");
             if (seen[(size_t)j]) return fail(SPMSPV_EINVAL, "duplicate x index");
             seen[(size_t)j] = 1;
         }
         std::fill(seen.begin(), seen.end(), 0);
         for (int32_t i : hm) {
-            if (i < 0 || i >= A->m) return fail(SPMSPV_EINVAL, "mask index out of range");
+            if (i < 0 || i >= ylen) return fail(SPMSPV_EINVAL, "mask index out of range");
             if (seen[(size_t)i]) return fail(SPMSPV_EINVAL, "duplicate mask index");
             seen[(size_t)i] = 1;
         }
         for (size_t r = 0; r < hw.size(); ++r) {
-            if (hw[r] < 0 || hw[r] >= A->m) return fail(SPMSPV_EINVAL, "w index out of range");
+            if (hw[r] < 0 || hw[r] >= ylen) return fail(SPMSPV_EINVAL, "w index out of range");
             if (r > 0 && hw[r] <= hw[r - 1]) return fail(SPMSPV_EINVAL, "w indices must be strictly ascending");
         }
     }
@@ -1254,36 +1444,36 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
     uint32_t* bits = nullptr;
     if (has_mask) {
         bits = A->visited;
-        HIP_TRY(launch_fill_u32(bits, 0u, (A->m + 31) / 32, s));
-        HIP_TRY(launch_mask_bits(mask_idx, mask_val, mask_count, (int32_t)A->m, bits, &A->ctrl->err, s));
+        HIP_TRY(launch_fill_u32(bits, 0u, (ylen + 31) / 32, s));
+        HIP_TRY(launch_mask_bits(mask_idx, mask_val, mask_count, (int32_t)ylen, bits, &A->ctrl->err, s));
     }
     // (2) t = A x restricted to the mask, ascending; straight into y when
     // there is nothing to accumulate into (then the result is t: rows
     // outside the mask have no w to keep)
     const bool direct = w_count == 0;
-    int32_t* t_idx = direct ? y_idx : A->front[0];
-    void* t_val = direct ? y_val : static_cast<void*>(A->front[1]);
-    const int64_t t_cap = direct ? y_capacity : A->m;
+    int32_t* t_idx = direct ? y_idx : A->bv_idx;
+    void* t_val = direct ? y_val : static_cast<void*>(A->bv_val);
+    const int64_t t_cap = direct ? y_capacity : ylen;
     int64_t* t_count = direct ? d_nnz_y : &A->ctrl->aux_count;
     const spmspv_schedule keep = A->sched;
-    if (A->sched_default) A->sched = sized_for_call(A, f);
+    if (A->sched_default && !left) A->sched = sized_for_call(A, f);
     A->sched.direction = 0;
     int rc;
     if (!has_mask && complement) {
         // no row is in the mask: t is empty
         rc = enqueue(A, semiring, xmode, 0, nullptr, x_idx, x_val, t_idx, t_val, t_cap, t_count, false, nullptr, s,
-                     nullptr);
+                     nullptr, false, -1, 3, 0, false, 0, left);
     } else {
         rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, t_idx, t_val, t_cap, t_count, false, bits, s,
-                     nullptr, false, -1, 3, 0, false, complement ? 0 : 1);
+                     nullptr, false, -1, 3, 0, false, complement ? 0 : 1, left);
     }
     A->sched = keep;
     if (rc) return rc;
     // (3) merge t with w under the accumulate and replace rules
     if (!direct) {
         CombineArgs ca{};
-        ca.t_idx = A->front[0];
-        ca.t_val = A->front[1];
+        ca.t_idx = A->bv_idx;
+        ca.t_val = A->bv_val;
         ca.d_nt = &A->ctrl->aux_count;
         ca.w_idx = w_idx;
         ca.w_val = w_val;
@@ -1298,9 +1488,9 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
         ca.d_nnz_y = d_nnz_y;
         ca.ctrl = A->ctrl;
         ca.lb = reinterpret_cast<uint64_t*>(A->ws + A->L.gb_lb);
-        ca.lb_n = (int32_t)gb_lb_words(A->m);
+        ca.lb_n = (int32_t)gb_lb_words(ylen);
         HIP_TRY(launch_clear_u64(ca.lb, ca.lb_n, s));
-        int64_t grid = (A->m + w_count + kCombineTile - 1) / kCombineTile;
+        int64_t grid = (ylen + w_count + kCombineTile - 1) / kCombineTile;
         if (grid < 1) grid = 1;
         if (grid > 2 * A->num_cu) grid = 2 * A->num_cu;   // co-resident: look-back waits stay bounded
         HIP_TRY(launch_combine(ca, semiring, (int)grid, s));
@@ -1366,7 +1556,7 @@ int spmspv_run_static(int64_t m, int64_t n, int64_t nnz, const int32_t* colptr, 
     // The scratch keeps the previous call's contents: clear the control block,
     // counters and look-back words (a fill kernel, not a memset).
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(M.ws), 0u, int64_t(L.buckets / 4), s));
-    HIP_TRY(launch_validate_colptr(colptr, (int32_t)n, nnz, M.ctrl, s));
+    HIP_TRY(launch_validate_colptr(colptr, (int32_t)n, nnz, M.ctrl, &M.ctrl->maxdeg, s));
     HIP_TRY(launch_row_counts(rowids, nnz, (int32_t)m, M.rcp, M.ctrl, s));
     HIP_TRY(launch_exclusive_scan_i32(M.rcp, m + 1, reinterpret_cast<int32_t*>(M.ws + L.partials), s));
     rc = enqueue(&M, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, nullptr, s,
@@ -1406,6 +1596,8 @@ int bfs_run(spmspv_handle A, int semiring, int32_t root, int flags, int32_t* lev
         return fail(SPMSPV_EINVAL, "no selector weights loaded");
     if (diropt && !A->pull)
         return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DIRECTION_OPT needs SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
+    if (A->dcsc && (flags & (SPMSPV_PERSISTENT | SPMSPV_USE_SELECTOR)))
+        return fail(SPMSPV_EUNSUPPORTED, "a DCSC handle runs BFS with the bucketing levels only");
 
 
     auto enqueue_levels = [&](int count, hipStream_t st) -> int {
@@ -1982,6 +2174,7 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
                  size_t scratch_bytes, int32_t* h_iters, void* stream) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (A->m != A->n) return fail(SPMSPV_EINVAL, "PageRank needs a square matrix");
+    if (A->dcsc) return fail(SPMSPV_EUNSUPPORTED, "PageRank needs a CSC handle (column degrees by id)");
     if (A->values) return fail(SPMSPV_EINVAL, "PageRank needs a pattern handle (values NULL)");
     if (!(damping > 0.f && damping < 1.f) || !(tol >= 0.f) || max_iter < 0)
         return fail(SPMSPV_EINVAL, "need 0 < damping < 1, tol >= 0, max_iter >= 0");
@@ -2055,6 +2248,7 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
 int cc_run(spmspv_handle A, int flags, int32_t* labels, int32_t* h_iters, void* stream) {
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (A->m != A->n) return fail(SPMSPV_EINVAL, "connected components need a square matrix");
+    if (A->dcsc) return fail(SPMSPV_EUNSUPPORTED, "connected components need a CSC handle (column degrees by id)");
     if (!labels) return fail(SPMSPV_EINVAL, "labels is NULL");
     if (flags != 0) return fail(SPMSPV_EINVAL, "cc_run takes no flags");
     hipStream_t s = static_cast<hipStream_t>(stream);

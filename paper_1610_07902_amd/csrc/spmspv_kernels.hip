@@ -190,12 +190,35 @@ __global__ __launch_bounds__(BLOCK) void k_scan(ScanArgs a) {
         }
         bool bad = false;
         int32_t b0[ITEMS], b1[ITEMS];
+        if (a.dcsc) {
+            // DCSC: find column j among the stored ones through its chunk of
+            // the column index (a few candidates), else it is empty.
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            // Clamp to a valid column so all gathers issue unconditionally.
-            const int32_t jc = (jj[i] >= 0 && jj[i] < a.n) ? jj[i] : 0;
-            b0[i] = a.colptr[jc];
-            b1[i] = a.colptr[jc + 1];
+            for (int i = 0; i < ITEMS; ++i) {
+                b0[i] = b1[i] = 0;
+                if (p0 + i >= f || jj[i] < 0 || jj[i] >= a.n) continue;
+                const int c = jj[i] >> a.dc_shift;
+                int32_t lo = a.dc_aux[c];
+                const int32_t end = a.dc_aux[c + 1];
+                int32_t hi = end;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (a.dc_jc[mid] < jj[i]) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < end && a.dc_jc[lo] == jj[i]) {
+                    b0[i] = a.colptr[lo];
+                    b1[i] = a.colptr[lo + 1];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                // Clamp to a valid column so all gathers issue unconditionally.
+                const int32_t jc = (jj[i] >= 0 && jj[i] < a.n) ? jj[i] : 0;
+                b0[i] = a.colptr[jc];
+                b1[i] = a.colptr[jc + 1];
+            }
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {

@@ -76,3 +76,28 @@ def test_static_multiply_refuses_oversized_matrix_without_gpu():
     assert rc == spv.EINVAL
     assert need.value == spv.spmspv_workspace_size(m, n, 20_000_000, 0) > (64 << 20)
     assert "static scratch" in lib.spmspv_last_error().decode()
+
+
+def test_format_variants_host_checks():
+    """DCSC sizing and argument checks, and the bitvector / left calls'
+    refusals, all before any device work."""
+    spv, lib = _lib()
+    csc = spv.spmspv_workspace_size(5000, 100000, 20000)
+    dcsc = spv.spmspv_dcsc_workspace_size(5000, 100000, 3000, 20000)
+    assert dcsc > csc                                  # plus the column index over jc
+    for args in ((5000, 100000, 100001, 200000),       # nzc > n
+                 (5000, 100000, 0, 10),                # no stored column but entries
+                 (5000, 100000, 30, 20)):              # more columns than entries
+        with pytest.raises(spv.SpmspvError) as e:
+            spv.spmspv_dcsc_workspace_size(*args)
+        assert e.value.status == spv.EINVAL
+    with pytest.raises(spv.SpmspvError) as e:          # no transpose for a DCSC handle
+        spv.spmspv_dcsc_workspace_size(50, 50, 10, 20, spv.WITH_TRANSPOSE)
+    assert e.value.status == spv.EINVAL
+    h = ctypes.c_void_p(None)
+    rc = lib.spmspv_create_dcsc(ctypes.byref(h), 10, 10, 2, 5, None, None, None, None, None, 0, 0, None)
+    assert rc == spv.EINVAL and h.value is None
+    assert lib.spmspv_run_bitvector(None, 0, 0, None, None, None, None, 0, None, None, None) == spv.EINVAL
+    # the transpose-sized regions grow the workspace of a wide matrix only with a transpose
+    assert spv.spmspv_workspace_size(100, 200000, 1000, spv.WITH_TRANSPOSE) > \
+        spv.spmspv_workspace_size(100, 200000, 1000) + 200000 * 4
