@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--no-msbfs", action="store_true", help="skip the 64-source BFS of the batched workload")
     ap.add_argument("--selector-only", action="store_true", help="only the learned-selector evaluation")
     ap.add_argument("--grid-only", action="store_true", help="only the 3-D grid BFS (256^3)")
+    ap.add_argument("--formats-only", action="store_true",
+                    help="only the format variants and connected components on the headline graph")
     ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
     ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
     ap.add_argument("--sweep-only", action="store_true",
@@ -112,6 +114,9 @@ def main():
     deg = A.degrees()
     if args.sweep_only:
         print(json.dumps({"sweep": sweep(spv, M, A, deg, dev, torch.cuda.current_stream())}))
+        return
+    if args.formats_only:
+        print(json.dumps({"formats": formats_bench(spv, M, A, dev), "cc": cc_bench(spv, M, A, dev)}))
         return
     f = synth.density_f(A.n, args.density)
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in range(args.nx)]
@@ -240,6 +245,8 @@ def main():
     if not args.no_extras:
         result["sweep"] = sweep(spv, M, A, deg, dev, stream)
         result["bfs"] = bfs_bench(spv, M, A, dev)
+        result["formats"] = formats_bench(spv, M, A, dev)
+        result["cc"] = cc_bench(spv, M, A, dev)
         M.close()
         del M, xi_d, xv_d
         torch.cuda.empty_cache()
@@ -394,6 +401,106 @@ def sweep(spv, M, A, deg, dev, stream):
             M.schedule = None
             out[f"{name}@{dens:g}"] = rec
             log(f"sweep {name} density {dens:g}: {rec}")
+    return out
+
+
+def timed_us(fn, reps=32):
+    """Mean duration of `reps` back-to-back calls of fn() (enqueue only)
+    between two events on the current stream, after 4 warm-up calls."""
+    import torch
+    for _ in range(4):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def formats_bench(spv, M, A, dev):
+    """Format variants on the headline graph (R-MAT scale 22, 1 % x,
+    plus-times): left multiplication y' = x'A against the right one; DCSC
+    against CSC on the same matrix, as stored (43 % empty columns) and cut
+    to one column in 16 (hypersparse); bitvector x / y against list x / y
+    (conversions included)."""
+    import torch
+    import synth
+    import oracle
+    out = {}
+    f = synth.density_f(A.n, 1e-2)
+    xs = [synth.sparse_x(A.n, f, seed=7000 + r, sort=True) for r in range(8)]
+    xi = [torch.as_tensor(x[0]).to(dev) for x in xs]
+    xv = [torch.as_tensor(x[1]).to(dev) for x in xs]
+    deg = A.degrees()
+    rdeg = np.bincount(A.rowids, minlength=A.m)
+    W = float(np.mean([int(deg[x[0]].sum()) for x in xs]))
+    Wl = float(np.mean([int(rdeg[x[0]].sum()) for x in xs]))
+    y_idx = torch.empty(max(A.m, A.n), dtype=torch.int32, device=dev)
+    y_val = torch.empty(max(A.m, A.n), dtype=torch.float32, device=dev)
+    k = [0]
+
+    def call(handle, flags, m):
+        r = k[0] % 8
+        k[0] += 1
+        spv.spmspv_run(handle, 0, flags, f, xi[r], xv[r], y_idx, y_val, m, sync=False)
+
+    right = timed_us(lambda: call(M.handle, 0, A.m))
+    left = timed_us(lambda: call(M.handle, spv.LEFT, A.n))
+    out["left"] = {"right_us": round(right, 2), "left_us": round(left, 2),
+                   "right_GTEPS": round(W / right / 1e3, 2), "left_GTEPS": round(Wl / left / 1e3, 2)}
+    log(f"formats: left {out['left']}")
+    # DCSC against CSC
+    for name, B in (("as_stored", A), ("hypersparse_1_in_16",
+                                        synth.column_subset(A, np.random.default_rng(3).random(A.n) < 1 / 16))):
+        D = synth.csc_to_dcsc(B)
+        Mc = M if B is A else spv.Matrix.from_csc(B, device=dev)
+        Md = spv.Matrix.from_dcsc(D, device=dev)
+        Wb = float(np.mean([int(np.diff(B.colptr.astype(np.int64))[x[0]].sum()) for x in xs]))
+        tc = timed_us(lambda: call(Mc.handle, 0, B.m))
+        td = timed_us(lambda: call(Md.handle, 0, B.m))
+        out["dcsc_" + name] = {"nzc": D.nzc, "n": B.n, "nnz": B.nnz, "products": Wb,
+                               "csc_matrix_bytes": 4 * (B.n + 1) + 8 * B.nnz,
+                               "dcsc_matrix_bytes": 4 * (2 * D.nzc + 1) + 8 * B.nnz,
+                               "csc_us": round(tc, 2), "dcsc_us": round(td, 2)}
+        log(f"formats: dcsc {name} {out['dcsc_' + name]}")
+        Md.close()
+        if Mc is not M:
+            Mc.close()
+    # bitvector x / y against list x / y
+    bits = [torch.as_tensor(oracle.to_bitvector(x[0], None, A.n)[0].view(np.int32)).to(dev) for x in xs]
+    y_bits = torch.empty((A.m + 31) // 32, dtype=torch.int32, device=dev)
+
+    def bv():
+        r = k[0] % 8
+        k[0] += 1
+        spv.spmspv_run_bitvector(M.handle, 0, 0, bits[r], xv[r], y_bits, y_val, A.m, sync=False)
+
+    tb = timed_us(bv)
+    tl = timed_us(lambda: call(M.handle, 0, A.m))
+    out["bitvector"] = {"list_us": round(tl, 2), "bitvector_us": round(tb, 2)}
+    log(f"formats: bitvector {out['bitvector']}")
+    return out
+
+
+def cc_bench(spv, M, A, dev):
+    """Connected components by label propagation (min-select2nd SpMSpV of
+    the changed labels each step) on the headline graph."""
+    import torch
+    P = spv.Matrix(A.m, A.n, M.colptr, M.rowids, None, device=dev)
+    P.connected_components()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lab, steps = P.connected_components()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3
+    ncomp = int(torch.unique(lab).numel())
+    P.close()
+    out = {"ms": round(ms, 2), "steps": int(steps), "components": ncomp}
+    log(f"cc: {out}")
     return out
 
 
