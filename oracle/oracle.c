@@ -9,8 +9,8 @@
  * Contents
  *   oracle_spmspv        y <- A x over a semiring, dense accumulator
  *                        (fp64 for plus-times), structural output pattern.
- *   oracle_spmspv_f32seq the same product accumulated in fp32 in x order,
- *                        used for rounding pins.
+ *   oracle_spmspv_f32seq the same product folded in fp32 in product order
+ *                        (the deterministic mode's reference).
  *   oracle_bfs           FIFO-queue breadth-first search levels, parents by
  *                        the minimum-parent rule.
  *   oracle_spmspv_graphblas  masked multiply with accumulate / replace.
@@ -405,8 +405,11 @@ int oracle_spmspv_dcsc(int semiring, int64_t m, int64_t n, int64_t nzc, const in
     return rc;
 }
 
-/* Plus-times accumulated in fp32, products rounded to fp32 first, rows
- * combined in x order.  y_val float[m], y_idx in first-touch order.       */
+/* Plus-times in fp32, the reference of the deterministic mode: each
+ * product is rounded to fp32 (Mult), and each row's products are added one
+ * at a time in fp32 in product order -- x order, then the column's storage
+ * order (Algorithm 1's Add in the order the products are formed).
+ * y_val float[m], y_idx in first-touch order.                             */
 int oracle_spmspv_f32seq(int64_t m, const int32_t* colptr, const int32_t* rowids, const float* values,
                          int64_t f, const int32_t* x_idx, const float* x_val, int32_t* y_idx,
                          float* y_val, int64_t* nnz_y) {
