@@ -121,7 +121,7 @@ enum spmspv_flags {
                                   form instead consumes the decision on the
                                   device (direction only, inside the captured
                                   level graph, no host synchronisation)       */
-    SPMSPV_LEFT = 16384        /* spmspv_run / _masked / _graphblas /
+    SPMSPV_LEFT = 16384,       /* spmspv_run / _masked / _graphblas /
                                   _bitvector: left multiplication y' <- x' A
                                   (Background, Notation: the row-vector case),
                                   x' over A's m rows, y' over its n columns,
@@ -132,6 +132,26 @@ enum spmspv_flags {
                                   the handle needs SPMSPV_WITH_TRANSPOSE or
                                   SPMSPV_SYMMETRIC (EUNSUPPORTED otherwise);
                                   no selector, pull or tuned schedule         */
+    SPMSPV_DETERMINISTIC = 32768 /* spmspv_workspace_size / _create (also
+                                  _dcsc_): add the deterministic mode's
+                                  storage (a second product list of nnz
+                                  entries and a count matrix, about 10.5
+                                  bytes per stored entry).  spmspv_run /
+                                  _masked with plus-times: y(i) is the fp32
+                                  fold of row i's products, each rounded to
+                                  fp32, in product order (x order, then the
+                                  column's storage order), so its bits do
+                                  not depend on the schedule, the bucket
+                                  count or the GPU's timing; y ascending.
+                                  Runs the scan, the product list, a stable
+                                  radix sort by row (Algorithm 2's count
+                                  matrix fixes every run's position) and a
+                                  sequential fold per row (a row with k
+                                  products takes k dependent adds).  Min and
+                                  or are order-free: their calls ignore it.
+                                  EUNSUPPORTED on a handle created without
+                                  it; with LEFT, the order is x' order then
+                                  the row's storage order in the CSR copy   */
 };
 
 /* Launch schedule.  Changing it never changes int / bool results or any

@@ -36,6 +36,7 @@ AUTO_SCHEDULE = 2048
 PULL_ROWWISE = 4096
 PERSISTENT = 8192
 LEFT = 16384
+DETERMINISTIC = 32768
 
 MLP_PARAMS = 5258
 NUM_CLASSES = 10

@@ -277,6 +277,42 @@ struct CombineArgs {
 };
 constexpr int kCombineTile = 2048;   // merged entries per workgroup tile
 hipError_t launch_combine(const CombineArgs& a, int semiring, int grid, hipStream_t s);
+// Deterministic plus-times multiply (det_kernels.hip): the product list in
+// product order, stably sorted by row, folded per row in that order.
+constexpr int kDetBlock = 256;
+constexpr int kDetItems = 16;
+constexpr int kDetTile = kDetBlock * kDetItems;   // list entries per radix block
+constexpr int kDetMaxDigitBits = 11;
+struct DetArgs {
+    Ctrl* ctrl;
+    int32_t m;               // rows of the operand; m itself marks a masked-out product
+    const int32_t* rowids;
+    const float* values;     // nullable (pattern)
+    const int32_t* cstart;   // the scan's column tables
+    const int32_t* coff;
+    const uint32_t* cxv;
+    const int32_t* chunk_col;
+    int chunk_log2;
+    const uint32_t* mask;    // nullable: row bitmap, a product is kept when its bit == mask_keep
+    int mask_keep;
+    uint64_t* lb1;           // the scan's look-back words: the first lb1_clear of each half are
+    int32_t lb1_n;           // cleared for the next call (the bucket scatter's task otherwise)
+    int32_t lb1_clear;
+    int32_t* counts;         // [2^digit_bits * nblk + 1] per-(digit, block) counts, scanned in place
+    int32_t nblk;            // radix blocks of kDetTile entries (an upper bound; blocks past W idle)
+    int32_t* y_idx;
+    float* y_val;
+    int64_t y_cap;
+    int64_t* d_nnz_y;
+};
+// Products -> (row, RN32(a * x)) at their product index; `grid` chunks of
+// 2^chunk_log2 products.
+hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_t s);
+// One stable pass on bits [shift, shift + digit_bits) of the row.
+hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int shift, int digit_bits,
+                           int32_t* partials, hipStream_t s);
+// Fold each row's run of the sorted list and write y ascending.
+hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int32_t* partials, hipStream_t s);
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
                              uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl,

@@ -55,11 +55,13 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
-        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, total;
+        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, det_list,
+        det_counts, det_partials, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
-    bool pull, transpose;
+    bool pull, transpose, det;
     int64_t nb_max, lb1_n, chunk_n;
+    int32_t det_nblk_max;   // deterministic mode: radix blocks of the longest product list
     int64_t rows_cap;   // one-launch multiply: chunk rows of run offsets
     int32_t fnb;        // one-launch multiply: buckets per row of run offsets
 };
@@ -124,6 +126,16 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
     L.bv_tiles = take(size_t(bits_tiles(mx)) * 4);
     // DCSC: column index over the stored column ids
     L.dc_aux = dc_chunks > 0 ? take(size_t(dc_chunks + 1) * 4) : 0;
+    // deterministic plus-times: a second product list (the buckets are the
+    // first) and the radix passes' count matrix with its scan partials
+    L.det = (flags & SPMSPV_DETERMINISTIC) != 0;
+    if (L.det) {
+        L.det_nblk_max = (int32_t)(nnz / kDetTile + 2);
+        const int64_t ncounts = (int64_t(1) << kDetMaxDigitBits) * L.det_nblk_max + 1;
+        L.det_list = take(size_t(nnz + 1) * 8);
+        L.det_counts = take(size_t(ncounts) * 4);
+        L.det_partials = take(size_t(ncounts / 4096 + 2) * 4);
+    }
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
     if (L.pull) {
@@ -513,6 +525,64 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
         HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s, ev ? &le[1] : nullptr));
         HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s, ev ? &le[2] : nullptr));
     }
+    return SPMSPV_OK;
+}
+
+// Deterministic plus-times multiply: the scan, then the product list in
+// product order, its stable sort by row and the sequential fold per row
+// (det_kernels.hip).  y is ascending.
+int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, const void* x_val, int32_t* y_idx,
+                float* y_val, int64_t y_cap, int64_t* d_nnz_y, const uint32_t* mask, int mask_keep, bool left,
+                hipStream_t s) {
+    const Layout& L = A->L;
+    if (!L.det)
+        return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DETERMINISTIC needs a handle whose workspace was sized and "
+                                         "created with SPMSPV_DETERMINISTIC");
+    const int64_t Om = left ? A->n : A->m;
+    const int64_t Omaxdeg = left ? A->maxrow : A->maxdeg;
+    // the scan only (phase 1), on the same operand
+    int rc = enqueue(A, SR_PLUS_TIMES, xmode, f, nullptr, x_idx, x_val, nullptr, nullptr, 0, nullptr, false,
+                     nullptr, s, nullptr, false, -1, 1, 0, false, 0, left);
+    if (rc) return rc;
+    const int chunk_log2 = ceil_log2(A->sched.scatter_block * A->sched.scatter_items);
+    int64_t wbound = f * Omaxdeg;
+    if (wbound > A->nnz) wbound = A->nnz;
+    DetArgs d{};
+    d.ctrl = A->ctrl;
+    d.m = (int32_t)Om;
+    d.rowids = left ? reinterpret_cast<const int32_t*>(A->colids) : A->rowids;
+    d.values = left ? A->rvalues : A->values;
+    d.cstart = A->cstart;
+    d.coff = A->coff;
+    d.cxv = A->cxv;
+    d.chunk_col = A->chunk_col;
+    d.chunk_log2 = chunk_log2;
+    d.mask = mask;
+    d.mask_keep = mask_keep;
+    d.lb1 = A->lb1;
+    d.lb1_n = (int32_t)L.lb1_n;
+    d.lb1_clear = (int32_t)std::min<int64_t>(L.lb1_n, (f + kScanTile - 1) / kScanTile + 1);
+    d.counts = reinterpret_cast<int32_t*>(A->ws + L.det_counts);
+    d.nblk = (int32_t)std::max<int64_t>(1, (wbound + kDetTile - 1) / kDetTile);
+    d.y_idx = y_idx;
+    d.y_val = y_val;
+    d.y_cap = y_cap;
+    d.d_nnz_y = d_nnz_y;
+    int32_t* partials = reinterpret_cast<int32_t*>(A->ws + L.det_partials);
+    uint2* cur = A->buckets;
+    uint2* other = reinterpret_cast<uint2*>(A->ws + L.det_list);
+    const int64_t gchunks = std::max<int64_t>(1, (wbound + (int64_t(1) << chunk_log2) - 1) >> chunk_log2);
+    HIP_TRY(launch_det_gather(d, cur, (int)gchunks, s));
+    // stable LSD passes over the bits of the row (m itself included: it marks masked products)
+    int bits = 1;
+    while ((Om >> bits) > 0) ++bits;
+    const int passes = (bits + kDetMaxDigitBits - 1) / kDetMaxDigitBits;
+    const int dbits = (bits + passes - 1) / passes;
+    for (int p = 0; p < passes; ++p) {
+        HIP_TRY(launch_det_pass(d, cur, other, p * dbits, dbits, partials, s));
+        std::swap(cur, other);
+    }
+    HIP_TRY(launch_det_fold(d, cur, partials, s));
     return SPMSPV_OK;
 }
 
@@ -1179,7 +1249,8 @@ int spmspv_create(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, const
 
 int spmspv_dcsc_workspace_size(int64_t m, int64_t n, int64_t nzc, int64_t nnz, int flags, size_t* h_bytes) {
     if (!h_bytes) return fail(SPMSPV_EINVAL, "h_bytes is NULL");
-    if (flags & ~SPMSPV_VALIDATE) return fail(SPMSPV_EINVAL, "a DCSC handle takes only SPMSPV_VALIDATE");
+    if (flags & ~(SPMSPV_VALIDATE | SPMSPV_DETERMINISTIC))
+        return fail(SPMSPV_EINVAL, "a DCSC handle takes only SPMSPV_VALIDATE and SPMSPV_DETERMINISTIC");
     if (nzc < 0 || nzc > n || (nzc == 0 && nnz != 0) || nnz < nzc)
         return fail(SPMSPV_EINVAL, "need 0 <= nzc <= min(n, nnz), nnz == 0 when nzc == 0");
     const int rc = spmspv_workspace_size(m, n, nnz, flags, h_bytes);
@@ -1281,7 +1352,16 @@ int spmspv_run_masked(spmspv_handle A, int semiring, int flags, int64_t f, const
     }
     hipEvent_t* ev = (flags & SPMSPV_PROFILE) ? profile_slot(A) : nullptr;
     int rc;
-    if (left) {
+    if ((flags & SPMSPV_DETERMINISTIC) && semiring == SR_PLUS_TIMES) {
+        // min and or are order-free: only plus-times takes the ordered fold
+        if (flags & (SPMSPV_USE_SELECTOR | SPMSPV_PULL_ROWWISE))
+            return fail(SPMSPV_EINVAL, "SPMSPV_DETERMINISTIC runs the push multiply only");
+        const spmspv_schedule keep = A->sched;
+        if (A->sched_default && !left) A->sched = sized_for_call(A, f);
+        rc = enqueue_det(A, xmode, f, x_idx, x_val, y_idx, static_cast<float*>(y_val), y_capacity, d_nnz_y, mask, 0,
+                         left, s);
+        A->sched = keep;
+    } else if (left) {
         const spmspv_schedule keep = A->sched;
         A->sched.direction = 0;
         rc = enqueue(A, semiring, xmode, f, nullptr, x_idx, x_val, y_idx, y_val, y_capacity, d_nnz_y, false, mask, s,
