@@ -116,7 +116,8 @@ def main():
         print(json.dumps({"sweep": sweep(spv, M, A, deg, dev, torch.cuda.current_stream())}))
         return
     if args.formats_only:
-        print(json.dumps({"formats": formats_bench(spv, M, A, dev), "cc": cc_bench(spv, M, A, dev)}))
+        print(json.dumps({"formats": formats_bench(spv, M, A, dev), "cc": cc_bench(spv, M, A, dev),
+                          "deterministic": det_bench(spv, A, dev)}))
         return
     f = synth.density_f(A.n, args.density)
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in range(args.nx)]
@@ -248,6 +249,7 @@ def main():
         result["formats"] = formats_bench(spv, M, A, dev)
         result["cc"] = cc_bench(spv, M, A, dev)
         M.close()
+        result["deterministic"] = det_bench(spv, A, dev)
         del M, xi_d, xv_d
         torch.cuda.empty_cache()
         result["batched"] = batch_bench(spv, dev, msbfs=not args.no_msbfs)
@@ -483,6 +485,38 @@ def formats_bench(spv, M, A, dev):
     tl = timed_us(lambda: call(M.handle, 0, A.m))
     out["bitvector"] = {"list_us": round(tl, 2), "bitvector_us": round(tb, 2)}
     log(f"formats: bitvector {out['bitvector']}")
+    return out
+
+
+def det_bench(spv, A, dev):
+    """The deterministic plus-times mode (sequential fp32 fold per row in
+    product order) against the default multiply, on the headline graph."""
+    import torch
+    import synth
+    M = spv.Matrix.from_csc(A, flags=spv.DETERMINISTIC, device=dev)
+    deg = A.degrees()
+    y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
+    y_val = torch.empty(A.m, dtype=torch.float32, device=dev)
+    out = {}
+    for dens in (1e-3, 1e-2, 1e-1):
+        f = synth.density_f(A.n, dens)
+        xs = [synth.sparse_x(A.n, f, seed=9000 + r) for r in range(4)]
+        W = float(np.mean([int(deg[x[0]].sum()) for x in xs]))
+        xi = [torch.as_tensor(x[0]).to(dev) for x in xs]
+        xv = [torch.as_tensor(x[1]).to(dev) for x in xs]
+        k = [0]
+
+        def call(flags):
+            r = k[0] % 4
+            k[0] += 1
+            spv.spmspv_run(M.handle, 0, flags, f, xi[r], xv[r], y_idx, y_val, A.m, sync=False)
+
+        td = timed_us(lambda: call(0), reps=16)
+        tt = timed_us(lambda: call(spv.DETERMINISTIC), reps=16)
+        out[f"{dens:g}"] = {"products": W, "default_us": round(td, 2), "deterministic_us": round(tt, 2),
+                            "deterministic_GTEPS": round(W / tt / 1e3, 2)}
+        log(f"deterministic {dens:g}: {out[f'{dens:g}']}")
+    M.close()
     return out
 
 

@@ -147,7 +147,9 @@ enum spmspv_flags {
                                   radix sort by row (Algorithm 2's count
                                   matrix fixes every run's position) and a
                                   sequential fold per row (a row with k
-                                  products takes k dependent adds).  Min and
+                                  products takes k dependent adds); the call
+                                  waits for the scan once (the product count
+                                  sizes the radix passes).  Min and
                                   or are order-free: their calls ignore it.
                                   EUNSUPPORTED on a handle created without
                                   it; with LEFT, the order is x' order then

@@ -163,39 +163,113 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
 
 __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* list) {
     __shared__ int s_tmp[kDetWaves + 1];
+    __shared__ int s_nlong;
     const int W = ld_ctrl(&a.ctrl->W);
+    if (threadIdx.x == 0) s_nlong = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int64_t total = a.counts[a.nblk];
         __hip_atomic_store(&a.ctrl->nnz_y, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (a.d_nnz_y) *a.d_nnz_y = total;
     }
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
-    if (base >= W) return;
+    if (base >= W) {
+        if (threadIdx.x == 0) a.long_count[blockIdx.x] = 0;
+        return;
+    }
+    // (1) every head's output position (block scans round by round), then
+    // (2) each thread folds its own heads with no further barrier, so a
+    // long run delays only its own thread
     int64_t run = a.counts[blockIdx.x];
+    uint32_t heads = 0;             // bit r: item r of this thread is a head
+    int32_t pos[kDetItems];
+#pragma unroll
     for (int r = 0; r < kDetItems; ++r) {
         const int64_t e = base + r * kDetBlock + threadIdx.x;
         bool head = false;
-        uint32_t row = 0;
         if (e < W) {
-            row = list[e].x;
+            const uint32_t row = list[e].x;
             head = row < (uint32_t)a.m && (e == 0 || list[e - 1].x != row);
         }
         int tot;
         const int pre = block_exclusive_i32<kDetBlock>(head ? 1 : 0, s_tmp, tot);
-        if (head) {
-            float acc = __uint_as_float(list[e].y);
-            for (int64_t k = e + 1; k < W; ++k) {
-                const uint2 v = list[k];
-                if (v.x != row) break;
-                acc = __fadd_rn(acc, __uint_as_float(v.y));
-            }
-            const int64_t pos = run + pre;
-            if (pos < a.y_cap) {
-                a.y_idx[pos] = (int32_t)row;
-                if (a.y_val) a.y_val[pos] = acc;
+        pos[r] = (int32_t)(run + pre);
+        heads |= head ? (1u << r) : 0u;
+        run += tot;
+    }
+#pragma unroll
+    for (int r = 0; r < kDetItems; ++r) {
+        if (!((heads >> r) & 1u)) continue;
+        const int64_t e = base + r * kDetBlock + threadIdx.x;
+        const uint32_t row = list[e].x;
+        // the run folds one add at a time; its entries are loaded sixteen
+        // at a time so the loads overlap (the adds stay in order).  Past
+        // kDetShortRun entries the run goes on in the wave-wide fold.
+        float acc = __uint_as_float(list[e].y);
+        bool more = true;
+        int64_t k = e + 1;
+        for (; more && k < W && k < e + kDetShortRun; k += 16) {
+            uint2 v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = k + u < W ? list[k + u] : make_uint2(~0u, 0u);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                more = more && v[u].x == row;
+                if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
             }
         }
-        run += tot;
+        const int64_t p = pos[r];
+        if (more && k < W && list[k].x == row) {
+            // a long run: more than kDetShortRun + 1 entries (the loop above
+            // folded kDetShortRun after the head), so runs starting in one
+            // block are that far apart and at most kDetLongPerBlock start here
+            const int slot = atomicAdd(&s_nlong, 1);
+            if (slot < kDetLongPerBlock)
+                a.long_runs[(int64_t)blockIdx.x * kDetLongPerBlock + slot] =
+                    make_int4((int)row, (int)__float_as_uint(acc), (int)k, (int)p);
+            else
+                atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
+        } else if (p < a.y_cap) {
+            a.y_idx[p] = (int32_t)row;
+            if (a.y_val) a.y_val[p] = acc;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
+}
+
+// One wave per long run: 64 consecutive entries per step in one load (the
+// next step's load issued before this step's adds), folded in order through
+// lane reads (every lane holds the same accumulator).
+__global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const uint2* list) {
+    const int W = ld_ctrl(&a.ctrl->W);
+    const int nblk_used = (W + kDetTile - 1) / kDetTile;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nwaves = gridDim.x * kDetWaves;
+    const int64_t npairs = (int64_t)nblk_used * kDetLongPerBlock;
+    for (int64_t pr = blockIdx.x * kDetWaves + threadIdx.x / kWave; pr < npairs; pr += nwaves) {
+        const int b = (int)(pr / kDetLongPerBlock), slot = (int)(pr % kDetLongPerBlock);
+        if (slot >= a.long_count[b]) continue;
+        const int4 rec = a.long_runs[pr];
+        const uint32_t row = (uint32_t)rec.x;
+        float acc = __uint_as_float((uint32_t)rec.y);
+        int64_t k = rec.z;
+        uint2 v = k + lane < W ? list[k + lane] : make_uint2(~0u, 0u);
+        bool more = true;
+        while (more) {
+            const uint2 next = k + kWave + lane < W ? list[k + kWave + lane] : make_uint2(~0u, 0u);
+            const uint64_t match = __ballot(v.x == row);
+            // entries of the run in this step: the lanes before the first mismatch
+            const int n = (~match == 0ull) ? kWave : __ffsll((unsigned long long)~match) - 1;
+            const int vb = (int)v.y;
+            for (int u = 0; u < n; ++u) acc = __fadd_rn(acc, __int_as_float(__builtin_amdgcn_readlane(vb, u)));
+            more = n == kWave;
+            k += kWave;
+            v = next;
+        }
+        if (lane == 0 && rec.w < a.y_cap) {
+            a.y_idx[rec.w] = (int32_t)row;
+            if (a.y_val) a.y_val[rec.w] = acc;
+        }
     }
 }
 
@@ -222,6 +296,7 @@ hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int32_t* partial
     hipError_t e = launch_exclusive_scan_i32(a.counts, int64_t(a.nblk) + 1, partials, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_det_fold, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
+    hipLaunchKernelGGL(k_det_fold_long, dim3(2048), dim3(kDetBlock), 0, s, a, list);
     return hipGetLastError();
 }
 

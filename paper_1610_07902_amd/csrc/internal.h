@@ -283,6 +283,8 @@ constexpr int kDetBlock = 256;
 constexpr int kDetItems = 16;
 constexpr int kDetTile = kDetBlock * kDetItems;   // list entries per radix block
 constexpr int kDetMaxDigitBits = 11;
+constexpr int kDetShortRun = 128;   // a run longer than this continues in the wave-wide fold
+constexpr int kDetLongPerBlock = kDetTile / kDetShortRun;   // long runs starting in one radix block, at most
 struct DetArgs {
     Ctrl* ctrl;
     int32_t m;               // rows of the operand; m itself marks a masked-out product
@@ -299,7 +301,10 @@ struct DetArgs {
     int32_t lb1_n;           // cleared for the next call (the bucket scatter's task otherwise)
     int32_t lb1_clear;
     int32_t* counts;         // [2^digit_bits * nblk + 1] per-(digit, block) counts, scanned in place
-    int32_t nblk;            // radix blocks of kDetTile entries (an upper bound; blocks past W idle)
+    int32_t nblk;            // radix blocks of kDetTile entries
+    int4* long_runs;         // [nblk][kDetLongPerBlock] runs longer than kDetShortRun, by the block of
+                             // their first entry: (row, acc bits, next entry, y position)
+    int32_t* long_count;     // [nblk] long runs of each block
     int32_t* y_idx;
     float* y_val;
     int64_t y_cap;

@@ -56,7 +56,7 @@ inline int ceil_log2(int64_t v) {
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
         front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, det_list,
-        det_counts, det_partials, total;
+        det_counts, det_partials, det_long, det_long_count, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose, det;
@@ -135,6 +135,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
         L.det_list = take(size_t(nnz + 1) * 8);
         L.det_counts = take(size_t(ncounts) * 4);
         L.det_partials = take(size_t(ncounts / 4096 + 2) * 4);
+        L.det_long = take(size_t(L.det_nblk_max) * kDetLongPerBlock * 16);
+        L.det_long_count = take(size_t(L.det_nblk_max) * 4);
     }
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
@@ -539,14 +541,18 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
         return fail(SPMSPV_EUNSUPPORTED, "SPMSPV_DETERMINISTIC needs a handle whose workspace was sized and "
                                          "created with SPMSPV_DETERMINISTIC");
     const int64_t Om = left ? A->n : A->m;
-    const int64_t Omaxdeg = left ? A->maxrow : A->maxdeg;
     // the scan only (phase 1), on the same operand
     int rc = enqueue(A, SR_PLUS_TIMES, xmode, f, nullptr, x_idx, x_val, nullptr, nullptr, 0, nullptr, false,
                      nullptr, s, nullptr, false, -1, 1, 0, false, 0, left);
     if (rc) return rc;
     const int chunk_log2 = ceil_log2(A->sched.scatter_block * A->sched.scatter_items);
-    int64_t wbound = f * Omaxdeg;
-    if (wbound > A->nnz) wbound = A->nnz;
+    // The radix passes' count matrix has a row per radix block: size it by
+    // the product count itself (one host read after the scan) rather than by
+    // f * (longest column), which on a skewed graph is the whole matrix.
+    int32_t Wh = 0;
+    HIP_TRY(hipMemcpyAsync(&Wh, &A->ctrl->W, sizeof(Wh), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t wbound = Wh;
     DetArgs d{};
     d.ctrl = A->ctrl;
     d.m = (int32_t)Om;
@@ -564,6 +570,8 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
     d.lb1_clear = (int32_t)std::min<int64_t>(L.lb1_n, (f + kScanTile - 1) / kScanTile + 1);
     d.counts = reinterpret_cast<int32_t*>(A->ws + L.det_counts);
     d.nblk = (int32_t)std::max<int64_t>(1, (wbound + kDetTile - 1) / kDetTile);
+    d.long_runs = reinterpret_cast<int4*>(A->ws + L.det_long);
+    d.long_count = reinterpret_cast<int32_t*>(A->ws + L.det_long_count);
     d.y_idx = y_idx;
     d.y_val = y_val;
     d.y_cap = y_cap;
@@ -574,8 +582,10 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
     const int64_t gchunks = std::max<int64_t>(1, (wbound + (int64_t(1) << chunk_log2) - 1) >> chunk_log2);
     HIP_TRY(launch_det_gather(d, cur, (int)gchunks, s));
     // stable LSD passes over the bits of the row (m itself included: it marks masked products)
+    // bits of the largest key: m - 1, or m itself when a mask marks products with it
+    const int64_t top = mask ? Om : Om - 1;
     int bits = 1;
-    while ((Om >> bits) > 0) ++bits;
+    while ((top >> bits) > 0) ++bits;
     const int passes = (bits + kDetMaxDigitBits - 1) / kDetMaxDigitBits;
     const int dbits = (bits + passes - 1) / passes;
     for (int p = 0; p < passes; ++p) {
