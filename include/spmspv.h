@@ -158,8 +158,8 @@ enum spmspv_flags {
 
 /* Launch schedule.  Changing it never changes int / bool results or any
  * output index set; fp32 plus-times sums may differ in rounding order.
- * Plus-times calls merge in fp64 cells: a schedule tile above 2^14 rows
- * runs as 2^14 for them.                                                 */
+ * Plus-times calls merge in fp64 cells: with merge_variant 0 a schedule
+ * tile above 2^14 rows runs as 2^14 for them.                            */
 typedef struct {
     int direction;      /* 0 = push (vector-driven, Algorithm 1); 1 = pull
                            (matrix-driven: scan every row of A against x;
@@ -168,7 +168,17 @@ typedef struct {
     int scatter_block;  /* threads per bucketing workgroup (64..1024, power of 2)  */
     int scatter_items;  /* products per thread per chunk (1..16, power of 2)       */
     int merge_block;    /* threads per merge workgroup (64..1024, power of 2)      */
-    int merge_variant;  /* 0 = sparse accumulator in LDS                           */
+    int merge_variant;  /* 0 = sparse accumulator in LDS, one workgroup per bucket
+                           (tile_log2 8..15);
+                           1 = sparse accumulator in HBM (Algorithm 1 step 2
+                               with the SPA in memory): a dense m-long array of
+                               cells and a touched-row bitmap in the workspace,
+                               updated with global atomics by several
+                               workgroups per bucket, then walked in row order
+                               and left empty; any bucket width (tile_log2
+                               8..30).  Push calls of spmspv_run / _masked /
+                               _graphblas / _bitvector and bfs_run; batched
+                               calls merge in LDS                          */
     int launch;         /* push calls of spmspv_run / spmspv_run_masked:
                            0, 1 = three launches (scan, bucketing, merge: the
                                default, faster on gfx950),
@@ -556,8 +566,17 @@ int spmspv_force_classes(spmspv_handle A, const int32_t* h_classes, int32_t coun
  * in the order above; synchronous).                                      */
 int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream);
 
-/* tile_log2 that class `cls` (0..8) runs with on this handle; -1 for 9.   */
+/* tile_log2 that class `cls` (0..8) runs with on this handle, before the
+ * LDS merge's narrowing; -1 for 9.  Class c is push with 2^(c+4) buckets
+ * (tile ceil(log2 m) - c - 4, at least 2^8 rows).                        */
 int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2);
+
+/* The whole schedule class `cls` (0..9) runs with for `semiring`: its tile
+ * and merge variant (variant 1, the HBM accumulator, when the tile is wider
+ * than the semiring's LDS accumulator holds, so all nine push classes are
+ * distinct schedules on any graph), or the pull direction for 9
+ * (EUNSUPPORTED without a row form).                                      */
+int spmspv_class_schedule(spmspv_handle A, int semiring, int cls, spmspv_schedule* h_sched);
 
 /* Number of selector parameters (5258). */
 int spmspv_mlp_param_count(void);

@@ -52,7 +52,7 @@ EXPORTED = (
     "spmspv_set_batch_schedule", "spmspv_get_batch_schedule", "msbfs_run", "spmspv_autotune",
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
     "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas", "cc_run",
-    "spmspv_dcsc_workspace_size", "spmspv_create_dcsc", "spmspv_run_bitvector",
+    "spmspv_dcsc_workspace_size", "spmspv_create_dcsc", "spmspv_run_bitvector", "spmspv_class_schedule",
 )
 
 
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_selector_load.argtypes = [vp, vp, vp, vp, vp]
     lib.spmspv_selector_classes.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.spmspv_class_tile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int32)]
+    lib.spmspv_class_schedule.argtypes = [vp, ci, ci, ctypes.POINTER(Schedule)]
     lib.spmspv_mlp_param_count.argtypes = []
     lib.spmspv_mlp_forward.argtypes = [vp, vp, ci, vp, vp]
     lib.spmspv_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp, vp, ci, vp, vp, vp]
@@ -296,6 +297,12 @@ def spmspv_selector_features(handle, stream=None) -> list:
 def spmspv_force_classes(handle, classes=()):
     arr = (ctypes.c_int32 * max(len(classes), 1))(*[int(c) for c in classes])
     _check(load_library().spmspv_force_classes(handle, arr, len(classes)))
+
+
+def spmspv_class_schedule(handle, semiring: int, cls: int) -> Schedule:
+    out = Schedule()
+    _check(load_library().spmspv_class_schedule(handle, int(semiring), int(cls), ctypes.byref(out)))
+    return out
 
 
 def spmspv_class_tile(handle, cls: int) -> int:

@@ -193,7 +193,24 @@ struct MergeArgs {
     int64_t* yoff;           // [nbatch+1] out: start of each vector's y
     int64_t n_stride;        // BFS: level / parent entries per vector
     int32_t mask_words;      // BFS: visited words per vector
+    // Merge through the HBM sparse accumulator (merge variant 1): dense
+    // cells for every row, empty between calls (plus-times fp64 at -0.0,
+    // min-select2nd int32 at INT32_MAX, or-and value bits clear) and the
+    // touched-row bitmap (clear between calls).
+    double* h_f64;
+    int32_t* h_i32;
+    uint32_t* h_orbits;
+    uint32_t* h_touched;
+    int32_t h_split;         // workgroups per bucket in the accumulation
 };
+// Merge variant 1: rows per output tile of the in-order walk.
+constexpr int kHTileRows = 65536;
+inline int64_t hmerge_tiles(int64_t m) { return (m + kHTileRows - 1) / kHTileRows; }
+// Accumulate every bucket entry into the HBM cells, then walk the touched
+// rows in order, writing y (and the BFS outputs) and emptying the cells.
+// Uses lb3[0, hmerge_tiles(m)) as look-back words (zero on entry).
+hipError_t launch_hbm_merge(const MergeArgs& a, int semiring, bool bfs, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s);
 
 // Pull (matrix-driven) direction over the CSR form of A.
 struct PullArgs {

@@ -39,6 +39,7 @@ int hip_fail(hipError_t e, const char* where) {
 
 constexpr int kTileLog2Min = 8;
 constexpr int kTileLog2Max = 15;
+constexpr int kTileLog2MaxHbm = 30;   // merge variant 1: any bucket width
 constexpr int kChunkMin = 256;
 constexpr size_t kAlign = 256;
 constexpr int kProfileSlots = 1024;
@@ -56,12 +57,13 @@ inline int ceil_log2(int64_t v) {
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
         front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, det_list,
-        det_counts, det_partials, det_long, det_long_count, total;
+        det_counts, det_partials, det_long, det_long_count, h_f64, h_i32, h_orbits, h_touched, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
     bool pull, transpose, det;
     int64_t nb_max, lb1_n, chunk_n;
     int32_t det_nblk_max;   // deterministic mode: radix blocks of the longest product list
+    int64_t h_rows;         // merge variant 1: rows of the HBM accumulator
     int64_t rows_cap;   // one-launch multiply: chunk rows of run offsets
     int32_t fnb;        // one-launch multiply: buckets per row of run offsets
 };
@@ -126,6 +128,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
     L.bv_tiles = take(size_t(bits_tiles(mx)) * 4);
     // DCSC: column index over the stored column ids
     L.dc_aux = dc_chunks > 0 ? take(size_t(dc_chunks + 1) * 4) : 0;
+    // merge variant 1: the HBM sparse accumulator over every row
+    L.h_f64 = take(size_t(mr) * 8);
+    L.h_i32 = take(size_t(mr) * 4);
+    L.h_orbits = take(size_t((mr + 31) / 32) * 4);
+    L.h_touched = take(size_t((mr + 31) / 32) * 4);
+    L.h_rows = mr;
     // deterministic plus-times: a second product list (the buckets are the
     // first) and the radix passes' count matrix with its scan partials
     L.det = (flags & SPMSPV_DETERMINISTIC) != 0;
@@ -345,16 +353,18 @@ int check_schedule(const spmspv_matrix* A, const spmspv_schedule* s) {
     if (s->direction != 0 && s->direction != 1) return fail(SPMSPV_EINVAL, "direction must be 0 (push) or 1 (pull)");
     if (s->direction == 1 && !A->pull)
         return fail(SPMSPV_EUNSUPPORTED, "pull needs a handle created with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC");
-    if (s->tile_log2 < kTileLog2Min || s->tile_log2 > kTileLog2Max)
-        return fail(SPMSPV_EINVAL, "tile_log2 out of [8, 15]");
+    if (s->merge_variant != 0 && s->merge_variant != 1)
+        return fail(SPMSPV_EINVAL, "merge_variant must be 0 (LDS) or 1 (HBM)");
+    const int tmax = s->merge_variant == 1 ? kTileLog2MaxHbm : kTileLog2Max;
+    if (s->tile_log2 < kTileLog2Min || s->tile_log2 > tmax)
+        return fail(SPMSPV_EINVAL, s->merge_variant == 1 ? "tile_log2 out of [8, 30]" : "tile_log2 out of [8, 15]");
     const int64_t nb = (A->m + (int64_t(1) << s->tile_log2) - 1) >> s->tile_log2;
     const int sb = s->scatter_block, si = s->scatter_items;
     if (!scatter_shape_supported(sb, si)) return fail(SPMSPV_EINVAL, "unsupported scatter_block / scatter_items pair");
     if (s->merge_block != 256 && s->merge_block != 512 && s->merge_block != 1024)
         return fail(SPMSPV_EINVAL, "merge_block must be 256, 512 or 1024");
-    if (s->merge_variant != 0) return fail(SPMSPV_EUNSUPPORTED, "only the LDS merge variant is built");
     if (s->launch < 0 || s->launch > 2) return fail(SPMSPV_EINVAL, "launch must be 0 (auto), 1 (three) or 2 (one)");
-    if (merge_lds_bytes(s->tile_log2, SR_MIN_SELECT2ND) + 1024 > A->lds_max)
+    if (s->merge_variant == 0 && merge_lds_bytes(s->tile_log2, SR_MIN_SELECT2ND) + 1024 > A->lds_max)
         return fail(SPMSPV_EINVAL, "tile exceeds LDS");
     if (scatter_lds_bytes((int)nb, sb * si) + 1024 > A->lds_max)
         return fail(SPMSPV_EINVAL, "too many buckets for the scatter LDS histogram");
@@ -388,7 +398,8 @@ int64_t scatter_occupancy(const spmspv_matrix* A, int nb, int block, int chunk, 
 int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int32_t* f_dev, const int32_t* x_idx,
             const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
             const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
-            int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0, bool left = false) {
+            int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0, bool left = false,
+            int variant = -1) {
     // The operand: A, or for left multiplication A^T through the CSR copy
     // (y' = x'A is y = A^T x; Background, Notation).  The CSR copy's row
     // pointer is A^T's column pointer and A's column pointer is A^T's
@@ -401,13 +412,17 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     const int64_t Omaxdeg = left ? A->maxrow : A->maxdeg;
     spmspv_schedule sc = A->sched;
     if (tile_log2 >= 0) sc.tile_log2 = tile_log2;
-    sc.tile_log2 = call_tile(A, sc.tile_log2, semiring);
+    if (variant >= 0) sc.merge_variant = variant;
+    // merge variant 1 (HBM accumulator) takes any tile; the LDS merge's is
+    // narrowed to what its accumulator holds for this semiring
+    const bool hbm = sc.merge_variant == 1;
+    if (!hbm) sc.tile_log2 = call_tile(A, sc.tile_log2, semiring);
     const int chunk = sc.scatter_block * sc.scatter_items;
     auto buckets_of = [&](int tl) { return (int)((Om + (int64_t(1) << tl) - 1) >> tl); };
     // A^T of a wide A can have more rows than the schedule's tile covers in
     // one scatter histogram: widen the tile as far as the merge allows.
     while (left && scatter_lds_bytes(buckets_of(sc.tile_log2), chunk) + 1024 > A->lds_max &&
-           sc.tile_log2 < call_tile(A, kTileLog2Max, semiring))
+           sc.tile_log2 < (hbm ? kTileLog2MaxHbm : call_tile(A, kTileLog2Max, semiring)))
         ++sc.tile_log2;
     const int nb = buckets_of(sc.tile_log2);
     if (scatter_lds_bytes(nb, chunk) + 1024 > A->lds_max)
@@ -443,6 +458,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     sa.cursor = A->cursor;
     sa.lb3 = A->lb3;
     sa.nb = clear_nb > nb ? clear_nb : nb;
+    if (hbm && sa.nb < hmerge_tiles(Om)) sa.nb = (int32_t)hmerge_tiles(Om);   // its walk's look-back words
     sa.bump_level = bfs ? 1 : 0;
     // A direction-switching BFS level: after a pull level the scan takes the
     // decision itself (see the pull emit's chain mode).
@@ -510,6 +526,11 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ma.visited = A->visited;
     ma.set_f = bfs ? 1 : 0;
     ma.gate = diropt ? 1 : 0;
+    ma.h_f64 = reinterpret_cast<double*>(A->ws + A->L.h_f64);
+    ma.h_i32 = reinterpret_cast<int32_t*>(A->ws + A->L.h_i32);
+    ma.h_orbits = reinterpret_cast<uint32_t*>(A->ws + A->L.h_orbits);
+    ma.h_touched = reinterpret_cast<uint32_t*>(A->ws + A->L.h_touched);
+    ma.h_split = std::max(1, std::min(1024, 4 * A->num_cu / nb));   // about four workgroups per CU
 
     // With profiling, each kernel's own start and end timestamps go to a pair
     // of events (scan, scatter, merge).
@@ -525,7 +546,13 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     }
     if (phases & 2) {
         HIP_TRY(launch_scatter(ca, semiring, sc.scatter_block, sc.scatter_items, (int)g2, s, ev ? &le[1] : nullptr));
-        HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s, ev ? &le[2] : nullptr));
+        if (hbm) {   // two kernels: profile them between plain event markers
+            if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+            HIP_TRY(launch_hbm_merge(ma, semiring, bfs, s));
+            if (ev) HIP_TRY(hipEventRecord(ev[5], s));
+        } else {
+            HIP_TRY(launch_merge(ma, semiring, sc.merge_block, bfs, s, ev ? &le[2] : nullptr));
+        }
     }
     return SPMSPV_OK;
 }
@@ -601,6 +628,7 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
 // (f <= kFMaxF per workgroup) and the call's buckets fit one row of run
 // offsets.  Returns the grid, or 0 when the call must take three launches.
 int fused_eligible(spmspv_matrix* A, int semiring, int64_t f, int* tl_out, int* nb_out) {
+    if (A->sched.merge_variant != 0) return 0;   // the one launch merges in LDS only
     const int tl = call_tile(A, A->sched.tile_log2, semiring);
     const int64_t nb = (A->m + (int64_t(1) << tl) - 1) >> tl;
     if (nb > A->L.fnb || nb > kFMaxNb) return 0;
@@ -732,16 +760,23 @@ int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s);
 
 // Tile of a selector class c < 9: 2^(c+4) buckets over m rows, clamped to
 // what LDS and the scatter histogram can hold.
+// Selector class c < 9: push with 2^(c+4) buckets, i.e. the tile
+// ceil_log2(m) - (c + 4) (at least 2^8 rows, widened while the scatter's
+// bucket histogram would not fit LDS).  A tile wider than the semiring's LDS
+// accumulator runs the HBM merge (variant 1), so every class is a schedule
+// of its own on any graph size.
 int class_tile(const spmspv_matrix* A, int c) {
     int tl = ceil_log2(A->m) - (c + 4);
     if (tl < kTileLog2Min) tl = kTileLog2Min;
-    if (tl > kTileLog2Max) tl = kTileLog2Max;
-    while (tl < kTileLog2Max && scatter_lds_bytes((int)((A->m + (int64_t(1) << tl) - 1) >> tl),
-                                                 A->sched.scatter_block * A->sched.scatter_items) + 1024 >
-                                   A->lds_max)
+    while (tl < kTileLog2MaxHbm && scatter_lds_bytes((int)((A->m + (int64_t(1) << tl) - 1) >> tl),
+                                                    A->sched.scatter_block * A->sched.scatter_items) + 1024 >
+                                      A->lds_max)
         ++tl;
-    while (tl > kTileLog2Min && merge_lds_bytes(tl, SR_MIN_SELECT2ND) + 1024 > A->lds_max) --tl;
     return tl;
+}
+int class_variant(const spmspv_matrix* A, int c, int semiring) {
+    const int tl = class_tile(A, c);
+    return call_tile(A, tl, semiring) < tl ? 1 : 0;
 }
 
 
@@ -768,9 +803,9 @@ int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
         return enqueue_pull(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs,
                             mask, false, false, s, nullptr);
     }
-    const int tl = class_tile(A, h.cls < 9 ? h.cls : 8);
+    const int c = h.cls < 9 ? h.cls : 8;
     return enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
-                   nullptr, false, tl, 2, 0);
+                   nullptr, false, class_tile(A, c), 2, 0, false, 0, false, class_variant(A, c, semiring));
 }
 
 // Shape of a batched call: the narrowest tile at or above the handle's whose
@@ -790,6 +825,7 @@ int batch_shape(const spmspv_matrix* A, int nbatch, int semiring, spmspv_schedul
             if (scatter_lds_bytes((int)K, sh[0] * sh[1], true) + 1024 > A->lds_max) continue;
             *out = sc;
             out->tile_log2 = tl;
+            out->merge_variant = 0;   // batched keys merge in LDS
             out->scatter_block = sh[0];
             out->scatter_items = sh[1];
             return SPMSPV_OK;
@@ -1192,6 +1228,15 @@ int create_impl(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, int64_t
         return bail(hip_fail(e, "row count scan"));
     if ((e = reset_persistent_state(A, s)) != hipSuccess || (e = launch_fill_u32(A->bar, 0u, 160, s)) != hipSuccess)
         return bail(hip_fail(e, "persistent BFS state"));
+    // the HBM accumulator starts (and is left after every call) empty
+    if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(A->ws + L.h_f64), 0x8000000000000000ull, L.h_rows, s)) !=
+            hipSuccess ||
+        (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + L.h_i32), 0x7fffffffu, L.h_rows, s)) != hipSuccess ||
+        (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + L.h_orbits), 0u, (L.h_rows + 31) / 32, s)) !=
+            hipSuccess ||
+        (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + L.h_touched), 0u, (L.h_rows + 31) / 32, s)) !=
+            hipSuccess)
+        return bail(hip_fail(e, "HBM accumulator"));
     if (L.pull) {
         A->pull = true;
         A->p_xbits = reinterpret_cast<uint32_t*>(A->ws + L.p_xbits);
@@ -1292,7 +1337,7 @@ int spmspv_effective_schedule(spmspv_handle A, int semiring, int64_t f, int flag
     else if (A->sched_default) A->sched = sized_for_call(A, f);
     spmspv_schedule e = A->sched;
     if (e.direction == 0) {
-        e.tile_log2 = call_tile(A, e.tile_log2, semiring);
+        if (e.merge_variant == 0) e.tile_log2 = call_tile(A, e.tile_log2, semiring);
         e.launch = e.launch == 2 ? 2 : 1;
     }
     A->sched = keep;
@@ -1884,6 +1929,25 @@ int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream) {
     const int rc = read_ctrl(A, &h, static_cast<hipStream_t>(stream));
     if (rc) return rc;
     for (int c = 0; c < kMlpIn; ++c) h_out[c] = h.features[c];
+    return SPMSPV_OK;
+}
+
+int spmspv_class_schedule(spmspv_handle A, int semiring, int cls, spmspv_schedule* h_sched) {
+    if (!A || !h_sched) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (cls < 0 || cls > 9) return fail(SPMSPV_EINVAL, "class must be in [0, 9]");
+    if (semiring < 0 || semiring > 2) return fail(SPMSPV_EINVAL, "unknown semiring");
+    spmspv_schedule e = A->sched;
+    if (cls == 9) {
+        if (!A->pull) return fail(SPMSPV_EUNSUPPORTED, "pull needs a handle with a row form");
+        e.direction = 1;
+    } else {
+        e.direction = 0;
+        e.tile_log2 = class_tile(A, cls);
+        e.merge_variant = class_variant(A, cls, semiring);
+        if (e.merge_variant == 0) e.tile_log2 = call_tile(A, e.tile_log2, semiring);
+    }
+    e.launch = 1;
+    *h_sched = e;
     return SPMSPV_OK;
 }
 

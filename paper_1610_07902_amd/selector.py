@@ -24,7 +24,8 @@ from typing import List, Optional
 import numpy as np
 
 from . import (MIN_SELECT2ND_I32, OR_AND_BOOL, PLUS_TIMES_F32, PULL_ROWWISE, X_ALL_TRUE, X_VAL_IS_INDEX,
-               MLP_PARAMS, NUM_CLASSES, Schedule, spmspv_mlp_forward, spmspv_mlp_train_step, spmspv_run_masked)
+               MLP_PARAMS, NUM_CLASSES, Schedule, spmspv_class_schedule, spmspv_mlp_forward, spmspv_mlp_train_step,
+               spmspv_run_masked)
 
 IN, H1, H2, OUT = 6, 64, 64, NUM_CLASSES
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.json")
@@ -75,14 +76,9 @@ class Samples:
         return s
 
 
-def class_schedule(M, c: int) -> Schedule:
-    s = M.schedule
-    if c == OUT - 1:
-        s.direction = 1
-    else:
-        s.direction = 0
-        s.tile_log2 = M.class_tile(c)
-    return s
+def class_schedule(M, c: int, semiring: int = MIN_SELECT2ND_I32) -> Schedule:
+    """The library's schedule for class c (push tile and merge variant, or pull)."""
+    return spmspv_class_schedule(M.handle, semiring, c)
 
 
 def time_classes(M, semiring: int, x_idx, x_val, flags: int, mask, reps: int = 3, bfs_step: bool = False):
@@ -99,7 +95,7 @@ def time_classes(M, semiring: int, x_idx, x_val, flags: int, mask, reps: int = 3
     stats = None
     for c in range(OUT):
         try:
-            M.schedule = class_schedule(M, c)
+            M.schedule = class_schedule(M, c, semiring)
         except Exception:   # the handle has no row form: pull unavailable
             continue
         fl = flags | (PULL_ROWWISE if (c == OUT - 1 and bfs_step) else 0)
