@@ -765,7 +765,7 @@ def selector_eval(spv, dev, scale=24, nroots=16, reps=2):
     roots = synth.roots(A, nroots, seed=2000)
     del A
     out = {"graph": f"R-MAT scale {scale} ef16 symmetrised (held out)", "n": P.n, "nnz": P.nnz, "roots": nroots,
-           "training": meta}
+           "training": meta, "weights_match_kernels": selector.weights_current(meta)}
 
     def run_bfs(flags):
         P.bfs(int(roots[0]), spv.MIN_SELECT2ND_I32, parents=True, flags=flags)

@@ -29,6 +29,26 @@ from . import (MIN_SELECT2ND_I32, OR_AND_BOOL, PLUS_TIMES_F32, PULL_ROWWISE, X_A
 
 IN, H1, H2, OUT = 6, 64, 64, NUM_CLASSES
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.json")
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_digest() -> str:
+    """Digest of the library's device sources (every .hip and .h under
+    csrc/).  Weights are trained on timings of these kernels; a weights file
+    whose digest differs was trained on other kernels and is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def weights_current(meta: dict) -> bool:
+    """True when weights (their meta) were trained on the current kernels."""
+    return meta.get("kernel_digest") == kernel_digest()
 
 
 def encode(raw: np.ndarray) -> np.ndarray:
@@ -244,9 +264,11 @@ def regret(times: np.ndarray, choice: np.ndarray) -> float:
 
 
 def save_weights(params, mean, std, meta: Optional[dict] = None, path: str = WEIGHTS_PATH):
+    meta = dict(meta or {})
+    meta["kernel_digest"] = kernel_digest()
     with open(path, "w") as fh:
         json.dump({"params": [float(v) for v in params], "mean": [float(v) for v in mean],
-                   "std": [float(v) for v in std], "meta": meta or {}}, fh)
+                   "std": [float(v) for v in std], "meta": meta}, fh)
 
 
 def load_weights(path: str = WEIGHTS_PATH):

@@ -74,3 +74,20 @@ def test_init_params_layout():
     assert p.dtype == np.float32 and p.size == 5258
     # biases start at zero: b1 after W1 (64*6), b2 after W2, b3 last
     assert np.all(p[384:448] == 0) and np.all(p[448 + 4096:448 + 4096 + 64] == 0) and np.all(p[-10:] == 0)
+
+
+def test_weights_are_tied_to_the_kernel_sources(tmp_path):
+    """The committed weights carry the digest of the device sources they were
+    trained on and it matches the sources in the tree (retrain after any
+    kernel change); a weights file from other kernels is recognised as
+    stale."""
+    sel = selector()
+    _, _, _, meta = sel.load_weights()
+    assert meta.get("kernel_digest") == sel.kernel_digest(), "selector weights trained on other kernels: retrain"
+    assert sel.weights_current(meta)
+    stale = dict(meta, kernel_digest="0" * 16)
+    assert not sel.weights_current(stale)
+    p, m, s, _ = sel.load_weights()
+    out = tmp_path / "w.json"
+    sel.save_weights(p, m, s, {"samples": 1}, str(out))
+    assert sel.load_weights(str(out))[3]["kernel_digest"] == sel.kernel_digest()
