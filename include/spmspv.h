@@ -309,6 +309,23 @@ int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, in
  * spmspv_autotune).                                                       */
 int spmspv_tuned_schedule(spmspv_handle A, int64_t f, spmspv_schedule* h_sched);
 
+/* Persisted tuning tables.  spmspv_tuning_save writes the handle's table
+ * (after spmspv_autotune; EINVAL before) to the text file `path`, keyed by
+ * the device (name, gfx architecture, compute units), the library's device
+ * sources (spmspv_source_digest) and the matrix (m, n, nnz and a hash of
+ * 4096 evenly spaced entries of its column pointers and of its row ids);
+ * format version 1.  spmspv_tuning_load installs a saved table on a handle
+ * whose device, library and matrix all match (then AUTO_SCHEDULE calls use
+ * it), else EUNSUPPORTED and the handle is unchanged; EINVAL for a missing,
+ * malformed or other-version file.  Both read a few device values and
+ * wait for `stream`.                                                      */
+int spmspv_tuning_save(spmspv_handle A, const char* path, void* stream);
+int spmspv_tuning_load(spmspv_handle A, const char* path, void* stream);
+
+/* Digest of the device sources this library was built from (16 hex
+ * digits; the selector's weights and tuning tables record it).            */
+const char* spmspv_source_digest(void);
+
 /* Tune the batched-call schedule on one given batch (arguments as for
  * spmspv_run_batch), keep the fastest with spmspv_set_batch_schedule's
  * effect, and report it and its time per call.  Synchronous.             */

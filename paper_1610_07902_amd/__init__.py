@@ -53,6 +53,7 @@ EXPORTED = (
     "spmspv_tuned_schedule", "spmspv_autotune_batch", "pagerank_scratch_size", "pagerank_run",
     "spmspv_selector_features", "spmspv_force_classes", "spmspv_effective_schedule", "spmspv_run_static", "spmspv_run_graphblas", "cc_run",
     "spmspv_dcsc_workspace_size", "spmspv_create_dcsc", "spmspv_run_bitvector", "spmspv_class_schedule",
+    "spmspv_tuning_save", "spmspv_tuning_load", "spmspv_source_digest",
 )
 
 
@@ -120,6 +121,10 @@ def load_library(path: str = LIB_PATH):
     lib.spmspv_selector_classes.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.spmspv_class_tile.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int32)]
     lib.spmspv_class_schedule.argtypes = [vp, ci, ci, ctypes.POINTER(Schedule)]
+    lib.spmspv_tuning_save.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.spmspv_tuning_load.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.spmspv_source_digest.argtypes = []
+    lib.spmspv_source_digest.restype = ctypes.c_char_p
     lib.spmspv_mlp_param_count.argtypes = []
     lib.spmspv_mlp_forward.argtypes = [vp, vp, ci, vp, vp]
     lib.spmspv_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, vp, vp, ci, vp, vp, vp]
@@ -297,6 +302,18 @@ def spmspv_selector_features(handle, stream=None) -> list:
 def spmspv_force_classes(handle, classes=()):
     arr = (ctypes.c_int32 * max(len(classes), 1))(*[int(c) for c in classes])
     _check(load_library().spmspv_force_classes(handle, arr, len(classes)))
+
+
+def spmspv_tuning_save(handle, path: str, stream=None):
+    _check(load_library().spmspv_tuning_save(handle, os.fsencode(path), _stream(stream)))
+
+
+def spmspv_tuning_load(handle, path: str, stream=None):
+    _check(load_library().spmspv_tuning_load(handle, os.fsencode(path), _stream(stream)))
+
+
+def spmspv_source_digest() -> str:
+    return load_library().spmspv_source_digest().decode()
 
 
 def spmspv_class_schedule(handle, semiring: int, cls: int) -> Schedule:
@@ -629,6 +646,12 @@ class Matrix:
         yi = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
         yv = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
         return spmspv_autotune(self.handle, semiring, densities, reps, xi, xv, yi, yv)
+
+    def save_tuning(self, path: str):
+        spmspv_tuning_save(self.handle, path)
+
+    def load_tuning(self, path: str):
+        spmspv_tuning_load(self.handle, path)
 
     def pagerank(self, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 100, flags: int = 0):
         """Data-driven PageRank on a pattern handle; returns (rank float32 tensor, multiplies)."""

@@ -440,6 +440,8 @@ hipError_t launch_bfs_persistent(const PersistArgs& a, bool min_semiring, int gr
 
 // Set-up kernels (spmspv_create, bfs_run).
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+// Evenly spaced samples of a device array (first and last included), K >= 2.
+hipError_t launch_sample_i32(const int32_t* a, int64_t count, int32_t* out, int32_t K, hipStream_t s);
 hipError_t launch_row_counts(const int32_t* rowids, int64_t nnz, int32_t m, int32_t* counts, Ctrl* ctrl,
                              hipStream_t s);
 hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* partials, hipStream_t s);

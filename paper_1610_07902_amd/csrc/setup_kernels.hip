@@ -236,6 +236,19 @@ hipError_t launch_exclusive_scan_i32(int32_t* data, int64_t count, int32_t* part
     return hipGetLastError();
 }
 
+// out[k] = a[k * (count - 1) / (K - 1)] for k < K (K >= 2, count >= 1):
+// evenly spaced samples of a device array, first and last included.
+__global__ void k_sample_i32(const int32_t* a, int64_t count, int32_t* out, int32_t K) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x)
+        out[k] = count > 0 ? a[(int64_t)k * (count - 1) / (K - 1)] : 0;
+}
+
+hipError_t launch_sample_i32(const int32_t* a, int64_t count, int32_t* out, int32_t K, hipStream_t s) {
+    if (K < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_i32, dim3((K + 255) / 256), dim3(256), 0, s, a, count, out, K);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate_colptr(const int32_t* colptr, int32_t n, int64_t nnz, Ctrl* ctrl, int32_t* maxout,
                                  hipStream_t s) {
     hipLaunchKernelGGL(k_validate_colptr, dim3(grid_for(n, kSetupBlock)), dim3(kSetupBlock), 0, s, colptr, n, nnz,

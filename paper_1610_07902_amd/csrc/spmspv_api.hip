@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 #include <vector>
+#include <fstream>
+#include <sstream>
 
 #include "spmspv.h"
 #include "internal.h"
@@ -2192,6 +2194,7 @@ int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, in
                 spmspv_schedule c = best;
                 c.direction = 0;
                 c.tile_log2 = tl;
+                c.merge_variant = 0;
                 if ((rc = consider(c))) return rc;
             }
             for (const auto& sh : shapes) {
@@ -2208,6 +2211,14 @@ int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, in
                 if ((rc = consider(c))) return rc;
             }
         }
+        // wide buckets through the HBM accumulator (16 to 1024 buckets)
+        for (int tl = std::max(kTileLog2Max + 1, ceil_log2(A->m) - 10); tl <= ceil_log2(A->m) - 4; ++tl) {
+            spmspv_schedule c = best;
+            c.direction = 0;
+            c.tile_log2 = tl;
+            c.merge_variant = 1;
+            if ((rc = consider(c))) return rc;
+        }
         if (A->pull) {
             spmspv_schedule c = best;
             c.direction = 1;
@@ -2217,6 +2228,136 @@ int spmspv_autotune(spmspv_handle A, int semiring, const double* h_densities, in
         e.us = best_us;
         table.push_back(e);
         if (h_out) h_out[d] = e;
+    }
+    A->tuned = table;
+    return SPMSPV_OK;
+}
+
+// ---- persisted tuning tables
+#ifndef SPMSPV_SOURCE_DIGEST
+#define SPMSPV_SOURCE_DIGEST "unknown"
+#endif
+
+const char* spmspv_source_digest(void) { return SPMSPV_SOURCE_DIGEST; }
+
+extern "C++" {
+namespace {
+
+constexpr int kTuningVersion = 1;
+constexpr int kSignatureSamples = 4096;
+
+std::string device_key(const spmspv_matrix* A) {
+    hipDeviceProp_t p{};
+    if (hipGetDeviceProperties(&p, A->device) != hipSuccess) return "unknown";
+    std::string name(p.name);
+    for (char& c : name)
+        if (c == '\n' || c == '\r') c = ' ';
+    return name + "|" + p.gcnArchName + "|" + std::to_string(p.multiProcessorCount);
+}
+
+// FNV-1a over m, n, nnz and evenly spaced samples of colptr and rowids.
+int graph_signature(spmspv_matrix* A, hipStream_t s, uint64_t* out) {
+    const int K = kSignatureSamples;
+    // the batch of samples goes through the handle's list scratch (max(m, n) entries)
+    const int Kc = (int)std::min<int64_t>(K, std::max<int64_t>(2, std::max(A->m, A->n) / 2));
+    int32_t* d = A->bv_idx;
+    std::vector<int32_t> h(2 * (size_t)Kc);
+    const int64_t ncol = (A->dcsc ? A->nzc : A->n) + 1;
+    HIP_TRY(launch_sample_i32(A->colptr, ncol, d, Kc, s));
+    HIP_TRY(launch_sample_i32(A->rowids, A->nnz, d + Kc, Kc, s));
+    HIP_TRY(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            x ^= (v >> (8 * b)) & 0xffu;
+            x *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)A->m);
+    mix((uint64_t)A->n);
+    mix((uint64_t)A->nnz);
+    mix(A->dcsc ? 1u : 0u);
+    for (int32_t v : h) mix((uint32_t)v);
+    *out = x;
+    return SPMSPV_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+int spmspv_tuning_save(spmspv_handle A, const char* path, void* stream) {
+    if (!A || !path) return fail(SPMSPV_EINVAL, "NULL argument");
+    if (A->tuned.empty()) return fail(SPMSPV_EINVAL, "the handle has not been autotuned");
+    uint64_t sig = 0;
+    const int rc = graph_signature(A, static_cast<hipStream_t>(stream), &sig);
+    if (rc) return rc;
+    std::ofstream f(path);
+    if (!f) return fail(SPMSPV_EINVAL, std::string("cannot write ") + path);
+    char hex[24];
+    snprintf(hex, sizeof(hex), "%016llx", (unsigned long long)sig);
+    f << "spmspv-tuning " << kTuningVersion << "\n";
+    f << "device " << device_key(A) << "\n";
+    f << "library " << SPMSPV_SOURCE_DIGEST << "\n";
+    f << "graph " << A->m << " " << A->n << " " << A->nnz << " " << hex << "\n";
+    f << "entries " << A->tuned.size() << "\n";
+    f.precision(17);
+    for (const auto& e : A->tuned) {
+        const spmspv_schedule& c = e.sched;
+        f << e.density << " " << c.direction << " " << c.tile_log2 << " " << c.scatter_block << " "
+          << c.scatter_items << " " << c.merge_block << " " << c.merge_variant << " " << c.launch << " " << e.us
+          << " " << e.default_us << "\n";
+    }
+    f.flush();
+    if (!f) return fail(SPMSPV_EINVAL, std::string("write failed: ") + path);
+    return SPMSPV_OK;
+}
+
+int spmspv_tuning_load(spmspv_handle A, const char* path, void* stream) {
+    if (!A || !path) return fail(SPMSPV_EINVAL, "NULL argument");
+    std::ifstream f(path);
+    if (!f) return fail(SPMSPV_EINVAL, std::string("cannot read ") + path);
+    std::string line, word;
+    auto next = [&](const char* key, std::string* rest) -> bool {
+        if (!std::getline(f, line)) return false;
+        const std::string k(key);
+        if (line.compare(0, k.size() + 1, k + " ") != 0) return false;
+        *rest = line.substr(k.size() + 1);
+        return true;
+    };
+    std::string v, dev, lib, graph, count;
+    if (!next("spmspv-tuning", &v) || std::atoi(v.c_str()) != kTuningVersion)
+        return fail(SPMSPV_EINVAL, "not a tuning table of version " + std::to_string(kTuningVersion));
+    if (!next("device", &dev) || !next("library", &lib) || !next("graph", &graph) || !next("entries", &count))
+        return fail(SPMSPV_EINVAL, "malformed tuning table header");
+    if (dev != device_key(A)) return fail(SPMSPV_EUNSUPPORTED, "tuning table is for another device: " + dev);
+    if (lib != SPMSPV_SOURCE_DIGEST)
+        return fail(SPMSPV_EUNSUPPORTED, "tuning table was measured on other kernels (" + lib + ")");
+    uint64_t sig = 0;
+    int rc = graph_signature(A, static_cast<hipStream_t>(stream), &sig);
+    if (rc) return rc;
+    {
+        std::istringstream g(graph);
+        long long m = -1, n = -1, nnz = -1;
+        std::string hex;
+        g >> m >> n >> nnz >> hex;
+        if (m != A->m || n != A->n || nnz != A->nnz || std::strtoull(hex.c_str(), nullptr, 16) != sig)
+            return fail(SPMSPV_EUNSUPPORTED, "tuning table is for another matrix");
+    }
+    const int k = std::atoi(count.c_str());
+    if (k < 1 || k > 64) return fail(SPMSPV_EINVAL, "bad entry count in tuning table");
+    std::vector<spmspv_tune_entry> table;
+    for (int i = 0; i < k; ++i) {
+        if (!std::getline(f, line)) return fail(SPMSPV_EINVAL, "truncated tuning table");
+        std::istringstream r(line);
+        spmspv_tune_entry e{};
+        spmspv_schedule& c = e.sched;
+        if (!(r >> e.density >> c.direction >> c.tile_log2 >> c.scatter_block >> c.scatter_items >> c.merge_block >>
+              c.merge_variant >> c.launch >> e.us >> e.default_us))
+            return fail(SPMSPV_EINVAL, "malformed tuning table entry");
+        if (!(e.density > 0.0 && e.density <= 1.0)) return fail(SPMSPV_EINVAL, "bad density in tuning table");
+        if ((rc = check_schedule(A, &c))) return rc;
+        table.push_back(e);
     }
     A->tuned = table;
     return SPMSPV_OK;

@@ -29,21 +29,15 @@ from . import (MIN_SELECT2ND_I32, OR_AND_BOOL, PLUS_TIMES_F32, PULL_ROWWISE, X_A
 
 IN, H1, H2, OUT = 6, 64, 64, NUM_CLASSES
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.json")
-CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
 def kernel_digest() -> str:
     """Digest of the library's device sources (every .hip and .h under
-    csrc/).  Weights are trained on timings of these kernels; a weights file
-    whose digest differs was trained on other kernels and is stale."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+    csrc/, the one build.py compiles into the library).  Weights are trained
+    on timings of these kernels; a weights file whose digest differs was
+    trained on other kernels and is stale."""
+    from .build import source_digest
+    return source_digest()
 
 
 def weights_current(meta: dict) -> bool:

@@ -85,7 +85,10 @@ def main():
     params, mean, std, hist = selector.train(samples, epochs=args.epochs)
     T = samples.T
     pred = selector.predict(params, mean, std, samples.X)
-    meta = {"samples": len(samples.raw), "epochs": args.epochs, "final_loss": hist[-1],
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    meta = {"device": props.name, "arch": getattr(props, "gcnArchName", ""),
+            "samples": len(samples.raw), "epochs": args.epochs, "final_loss": hist[-1],
             "train_accuracy": float((pred == T.argmin(1)).mean()),
             "train_regret": selector.regret(T, pred),
             "label_histogram": np.bincount(T.argmin(1), minlength=10).tolist(),

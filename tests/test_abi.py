@@ -101,3 +101,9 @@ def test_format_variants_host_checks():
     # the transpose-sized regions grow the workspace of a wide matrix only with a transpose
     assert spv.spmspv_workspace_size(100, 200000, 1000, spv.WITH_TRANSPOSE) > \
         spv.spmspv_workspace_size(100, 200000, 1000) + 200000 * 4
+
+
+def test_library_records_its_source_digest():
+    spv, lib = _lib()
+    from paper_1610_07902_amd import build
+    assert spv.spmspv_source_digest() == build.source_digest(), "library built from other sources: rebuild"

@@ -130,3 +130,56 @@ def test_default_schedule_sizes_the_scatter_chunk(spv, rmat15):
     M.schedule = None
     eff = spv.spmspv_effective_schedule(M.handle, 10)
     assert (eff.scatter_block, eff.scatter_items) == (256, 4)
+
+
+def test_tuning_table_persists_and_reloads(spv, rmat15, tmp_path):
+    """A saved table reloads onto a new handle over the same matrix (same
+    schedules, AUTO_SCHEDULE calls still match the oracle) and is refused,
+    leaving the handle untouched, for another matrix, other kernels, another
+    device, another format version or a damaged file."""
+    A = rmat15
+    M = spv.Matrix.from_csc(A)
+    path = str(tmp_path / "tuning.txt")
+    with pytest.raises(spv.SpmspvError) as e:
+        M.save_tuning(path)                                  # nothing tuned yet
+    assert e.value.status == spv.EINVAL
+    dens = (1e-3, 1e-1)
+    M.autotune(0, dens, reps=2)
+    M.save_tuning(path)
+    text = open(path).read().splitlines()
+    assert text[0] == "spmspv-tuning 1" and text[2] == "library " + spv.spmspv_source_digest()
+    N = spv.Matrix.from_csc(A)
+    N.load_tuning(path)
+    for d in dens:
+        f = synth.density_f(A.n, d)
+        assert spv.spmspv_tuned_schedule(N.handle, f).as_dict() == spv.spmspv_tuned_schedule(M.handle, f).as_dict()
+        S, xv = synth.sparse_x(A.n, f, seed=70)
+        gi, gv, _ = N.spmspv(dev(S), dev(xv), sorted_output=True, flags=spv.AUTO_SCHEDULE)
+        oi, ov, _ = oracle.spmspv(A, S, xv, 0, sorted_output=True)
+        compare(0, gi, gv, oi, ov, sorted_output=True)
+    # another matrix of the same shape and size
+    B = synth.rmat(15, 16, seed=42, symmetrize=True)
+    O = spv.Matrix.from_csc(B)
+    with pytest.raises(spv.SpmspvError) as e:
+        O.load_tuning(path)
+    assert e.value.status == spv.EUNSUPPORTED
+    with pytest.raises(spv.SpmspvError):
+        spv.spmspv_tuned_schedule(O.handle, 100)            # still untuned
+    # edited keys, another version, a damaged file, a missing one
+    for k, line, status in ((2, "library 0000000000000000", spv.EUNSUPPORTED),
+                            (1, "device some other GPU|gfx000|1", spv.EUNSUPPORTED),
+                            (0, "spmspv-tuning 2", spv.EINVAL),
+                            (5, "0.5 0 12", spv.EINVAL)):
+        bad = list(text)
+        bad[k] = line
+        p2 = str(tmp_path / f"bad{k}.txt")
+        open(p2, "w").write("\n".join(bad) + "\n")
+        with pytest.raises(spv.SpmspvError) as e:
+            N.load_tuning(p2)
+        assert e.value.status == status, (k, e.value)
+    with pytest.raises(spv.SpmspvError) as e:
+        N.load_tuning(str(tmp_path / "missing.txt"))
+    assert e.value.status == spv.EINVAL
+    # the good table is still installed on N
+    f = synth.density_f(A.n, 1e-1)
+    assert spv.spmspv_tuned_schedule(N.handle, f).as_dict() == spv.spmspv_tuned_schedule(M.handle, f).as_dict()
