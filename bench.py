@@ -180,6 +180,7 @@ def main():
         other_ms = None
     M.schedule = None
     log(f"launch {other}: {other_ms} ms per step")
+    concurrent = None if args.profile_only else concurrent_bench(spv, M, A, f, xi_d, xv_d, W, dev)
 
     # Per-kernel durations: the same loop again with events around each kernel.
     for i in range(args.steps):
@@ -212,7 +213,8 @@ def main():
                    "scale": args.scale, "nnz": A.nnz, "f": f, "mean_products": float(W.mean()),
                    "mean_nnz_y": float(nnz_y.mean()),
                    "schedule": eff.as_dict(),
-                   "other_launch_mode": {"launch": other, "ms_per_step": other_ms}},
+                   "other_launch_mode": {"launch": other, "ms_per_step": other_ms},
+                   "concurrent_streams": concurrent},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(dom, args),
@@ -259,6 +261,40 @@ def main():
         if not args.no_selector_eval:
             result["learned_selector"] = selector_eval(spv, dev, args.selector_scale)
     print(json.dumps(result))
+
+
+def concurrent_bench(spv, M, A, f, xi_d, xv_d, W, dev, nstreams=4, steps=256):
+    """The headline multiplies issued round-robin on several streams, one
+    handle (workspace) per stream over the same matrix arrays: independent
+    multiplies overlap their latency-bound phases.  Reported beside the
+    headline, which runs one multiply at a time."""
+    import torch
+    nx = len(xi_d)
+    handles = [M] + [spv.Matrix(A.m, A.n, M.colptr, M.rowids, M.values, device=dev) for _ in range(nstreams - 1)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+    ys = [(torch.empty(A.m, dtype=torch.int32, device=dev), torch.empty(A.m, dtype=torch.float32, device=dev))
+          for _ in range(nstreams)]
+
+    def run(n):
+        for i in range(n):
+            k = i % nstreams
+            r = i % nx
+            spv.spmspv_run(handles[k].handle, 0, 0, f, xi_d[r], xv_d[r], ys[k][0], ys[k][1], A.m, sync=False,
+                           stream=streams[k])
+
+    run(4 * nstreams)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    products = int(W[np.arange(steps) % nx].sum())
+    for h in handles[1:]:
+        h.close()
+    out = {"streams": nstreams, "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 4),
+           "GTEPS": round(products / dt / 1e9, 2)}
+    log(f"concurrent streams: {out}")
+    return out
 
 
 def host_info():

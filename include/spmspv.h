@@ -584,14 +584,12 @@ int spmspv_force_classes(spmspv_handle A, const int32_t* h_classes, int32_t coun
 int spmspv_selector_features(spmspv_handle A, float* h_out, void* stream);
 
 /* tile_log2 that class `cls` (0..8) runs with on this handle, before the
- * LDS merge's narrowing; -1 for 9.  Class c is push with 2^(c+4) buckets
- * (tile ceil(log2 m) - c - 4, at least 2^8 rows).                        */
+ * plus-times narrowing; -1 for 9.  Class c is push with 2^(c+4) buckets
+ * (tile ceil(log2 m) - c - 4, between 2^8 and 2^15 rows).                */
 int spmspv_class_tile(spmspv_handle A, int cls, int32_t* h_tile_log2);
 
-/* The whole schedule class `cls` (0..9) runs with for `semiring`: its tile
- * and merge variant (variant 1, the HBM accumulator, when the tile is wider
- * than the semiring's LDS accumulator holds, so all nine push classes are
- * distinct schedules on any graph), or the pull direction for 9
+/* The whole schedule class `cls` (0..9) runs with for `semiring` (its LDS
+ * tile, narrowed for plus-times' fp64 cells), or the pull direction for 9
  * (EUNSUPPORTED without a row form).                                      */
 int spmspv_class_schedule(spmspv_handle A, int semiring, int cls, spmspv_schedule* h_sched);
 

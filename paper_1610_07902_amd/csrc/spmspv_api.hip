@@ -764,21 +764,23 @@ int read_ctrl(spmspv_matrix* A, Ctrl* h, hipStream_t s);
 // what LDS and the scatter histogram can hold.
 // Selector class c < 9: push with 2^(c+4) buckets, i.e. the tile
 // ceil_log2(m) - (c + 4) (at least 2^8 rows, widened while the scatter's
-// bucket histogram would not fit LDS).  A tile wider than the semiring's LDS
-// accumulator runs the HBM merge (variant 1), so every class is a schedule
-// of its own on any graph size.
+// bucket histogram would not fit LDS), merged in LDS: a tile wider than the
+// semiring's LDS accumulator runs as the widest one it holds.  (The HBM
+// merge would realise the wider tiles, but its global atomics made those
+// classes several times slower than the widest LDS tile on the scale-24
+// graph -- 1.2 ms against 0.22 ms on a 2,290-vertex frontier -- and a
+// network trained on smaller graphs, where the same classes were LDS tiles,
+// cannot foresee that; it stays a schedule the caller or the autotuner
+// chooses.)
 int class_tile(const spmspv_matrix* A, int c) {
     int tl = ceil_log2(A->m) - (c + 4);
     if (tl < kTileLog2Min) tl = kTileLog2Min;
-    while (tl < kTileLog2MaxHbm && scatter_lds_bytes((int)((A->m + (int64_t(1) << tl) - 1) >> tl),
-                                                    A->sched.scatter_block * A->sched.scatter_items) + 1024 >
-                                      A->lds_max)
+    if (tl > kTileLog2Max) tl = kTileLog2Max;
+    while (tl < kTileLog2Max && scatter_lds_bytes((int)((A->m + (int64_t(1) << tl) - 1) >> tl),
+                                                 A->sched.scatter_block * A->sched.scatter_items) + 1024 >
+                                   A->lds_max)
         ++tl;
     return tl;
-}
-int class_variant(const spmspv_matrix* A, int c, int semiring) {
-    const int tl = class_tile(A, c);
-    return call_tile(A, tl, semiring) < tl ? 1 : 0;
 }
 
 
@@ -807,7 +809,7 @@ int run_selected(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, cons
     }
     const int c = h.cls < 9 ? h.cls : 8;
     return enqueue(A, semiring, xmode, f_host, f_dev, x_idx, x_val, y_idx, y_val, y_cap, d_nnz_y, bfs, mask, s,
-                   nullptr, false, class_tile(A, c), 2, 0, false, 0, false, class_variant(A, c, semiring));
+                   nullptr, false, class_tile(A, c), 2, 0, false, 0, false, 0);
 }
 
 // Shape of a batched call: the narrowest tile at or above the handle's whose
@@ -1944,9 +1946,8 @@ int spmspv_class_schedule(spmspv_handle A, int semiring, int cls, spmspv_schedul
         e.direction = 1;
     } else {
         e.direction = 0;
-        e.tile_log2 = class_tile(A, cls);
-        e.merge_variant = class_variant(A, cls, semiring);
-        if (e.merge_variant == 0) e.tile_log2 = call_tile(A, e.tile_log2, semiring);
+        e.merge_variant = 0;
+        e.tile_log2 = call_tile(A, class_tile(A, cls), semiring);
     }
     e.launch = 1;
     *h_sched = e;

@@ -4,7 +4,9 @@
 
 Training graphs (the reading of the selector's training set): R-MAT scales
 18, 20 and 22 (edge factor 16, symmetrised), a 2D 5-point grid 1024^2 and 3D
-7-point grids 64^3 and 128^3.  Samples: every BFS level from a few seeded
+7-point grids 64^3, 128^3 and 192^3 (large enough that the pull direction's
+cost per level, which grows with the unvisited vertices, is seen at the
+sizes where it loses to push).  Samples: every BFS level from a few seeded
 roots (min-select2nd, as a BFS step runs it: frontier expanded with the
 visited vertices masked) plus standalone multiplies across densities for
 plus-times and min-select2nd.  Each sample times all ten classes; the label
@@ -43,6 +45,7 @@ def graphs(quick: bool):
     yield "grid2d-1024", synth.grid(1024, 1024, 1)
     yield "grid3d-64", synth.grid(64, 64, 64)
     yield "grid3d-128", synth.grid(128, 128, 128)
+    yield "grid3d-192", synth.grid(192, 192, 192)
 
 
 def collect(quick: bool = False, roots_per_graph: int = 4, reps: int = 3, log=print) -> selector.Samples:

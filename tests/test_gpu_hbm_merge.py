@@ -4,8 +4,8 @@ against the oracle: every semiring over bucket widths from 2^8 rows to one
 bucket for the whole matrix; semirings alternating on one handle (the cells
 must be left empty for the next call, whatever its semiring); BFS, masks,
 the GraphBLAS rules, left multiplication and bitvector calls through it; the
-selector's classes, now distinct schedules on large graphs; and the
-benchmark's scale-22 graph with 16 buckets.
+bucket counts of the selector's widest classes as explicit HBM schedules;
+and the benchmark's scale-22 graph with 16 buckets.
 
 Index sets and int32 / bool values bit-exact; fp32 within 1e-5 of the fp64
 oracle (values positive)."""
@@ -157,11 +157,10 @@ def test_masked_graphblas_left_bitvector(spv, r16):
     M.schedule = None
 
 
-def test_selector_classes_are_distinct_schedules(spv):
-    """On a matrix with 2^22 rows every push class is a schedule of its own:
-    tiles 2^18 .. 2^10, the widest through the HBM accumulator (above 2^14
-    rows for plus-times' fp64 cells, above 2^15 for the others); each class
-    matches the oracle."""
+def test_selector_classes_and_explicit_hbm_schedules(spv):
+    """On a matrix with 2^22 rows the selector's classes are LDS tiles (2^15
+    at most, 2^14 for plus-times); the same bucket counts as explicit HBM
+    schedules (tiles 2^18 .. 2^16) give the same results."""
     rng = np.random.default_rng(8)
     m, n = 1 << 22, 4096
     colptr, rowids = synth.coo_to_csc(m, n, rng.integers(0, m, 400000).astype(np.int32),
@@ -170,35 +169,19 @@ def test_selector_classes_are_distinct_schedules(spv):
     M = spv.Matrix.from_csc(A, flags=spv.WITH_TRANSPOSE)
     S, xv = synth.sparse_x(n, 300, seed=10)
     oi, ov, _ = oracle.spmspv(A, S, xv, 0, sorted_output=True)
-    seen = set()
     for c in range(9):
         s = spv.spmspv_class_schedule(M.handle, 0, c)
-        assert s.tile_log2 == 18 - c and s.merge_variant == (1 if s.tile_log2 > 14 else 0)
+        assert s.merge_variant == 0 and s.tile_log2 == min(18 - c, 14)
         s1 = spv.spmspv_class_schedule(M.handle, 1, c)
-        assert s1.merge_variant == (1 if s1.tile_log2 > 15 else 0)
-        seen.add((s.tile_log2, s.merge_variant))
+        assert s1.merge_variant == 0 and s1.tile_log2 == min(18 - c, 15)
         M.schedule = s
         gi, gv, _ = M.spmspv(dev(S), dev(xv), sorted_output=True)
         compare(0, gi, gv, oi, ov, sorted_output=True)
-    assert len(seen) == 9
+    for tl in (18, 17, 16):
+        hbm(spv, M, tl)
+        gi, gv, _ = M.spmspv(dev(S), dev(xv), sorted_output=True)
+        compare(0, gi, gv, oi, ov, sorted_output=True)
     assert spv.spmspv_class_schedule(M.handle, 0, 9).direction == 1
-    M.close()
-
-
-def test_selector_bfs_through_the_hbm_classes(spv):
-    """A constant selector picking class 0 (16 buckets: tiles of 2^16 rows,
-    the HBM accumulator) and class 2 on a 2^20-vertex graph."""
-    A = synth.rmat(20, 4, seed=93, symmetrize=True)
-    M = spv.Matrix.from_csc(A, flags=spv.SYMMETRIC, pattern=True)
-    for cls in (0, 2):
-        p = np.zeros(oracle.mlp_param_count(), np.float32)
-        p[-10 + cls] = 5.0
-        M.load_selector(p, np.zeros(6, np.float32), np.ones(6, np.float32))
-        root = int(synth.roots(A, 1, seed=cls)[0])
-        lev, par, nl = M.bfs(root, semiring=1, flags=spv.USE_SELECTOR)
-        olev, opar, onl = oracle.bfs(A, root)
-        assert nl == onl and np.array_equal(to_np(lev), olev) and np.array_equal(to_np(par), opar)
-        assert set(M.selector_classes()) == {cls}
     M.close()
 
 
