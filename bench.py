@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--selector-only", action="store_true", help="only the learned-selector evaluation")
     ap.add_argument("--grid-only", action="store_true", help="only the 3-D grid BFS (256^3)")
     ap.add_argument("--formats-only", action="store_true",
-                    help="only the format variants and connected components on the headline graph")
+                    help="only the format variants, masked multiplies, connected components and the deterministic mode on the headline graph")
     ap.add_argument("--no-selector-eval", action="store_true", help="skip the learned-selector evaluation")
     ap.add_argument("--selector-scale", type=int, default=24, help="R-MAT scale of the held-out graph")
     ap.add_argument("--sweep-only", action="store_true",
@@ -116,8 +116,8 @@ def main():
         print(json.dumps({"sweep": sweep(spv, M, A, deg, dev, torch.cuda.current_stream())}))
         return
     if args.formats_only:
-        print(json.dumps({"formats": formats_bench(spv, M, A, dev), "cc": cc_bench(spv, M, A, dev),
-                          "deterministic": det_bench(spv, A, dev)}))
+        print(json.dumps({"formats": formats_bench(spv, M, A, dev), "masked": masked_bench(spv, M, A, dev),
+                          "cc": cc_bench(spv, M, A, dev), "deterministic": det_bench(spv, A, dev)}))
         return
     f = synth.density_f(A.n, args.density)
     xs = [synth.sparse_x(A.n, f, seed=1000 + r) for r in range(args.nx)]
@@ -249,6 +249,7 @@ def main():
         result["sweep"] = sweep(spv, M, A, deg, dev, stream)
         result["bfs"] = bfs_bench(spv, M, A, dev)
         result["formats"] = formats_bench(spv, M, A, dev)
+        result["masked"] = masked_bench(spv, M, A, dev)
         result["cc"] = cc_bench(spv, M, A, dev)
         M.close()
         result["deterministic"] = det_bench(spv, A, dev)
@@ -521,6 +522,62 @@ def formats_bench(spv, M, A, dev):
     tl = timed_us(lambda: call(M.handle, 0, A.m))
     out["bitvector"] = {"list_us": round(tl, 2), "bitvector_us": round(tb, 2)}
     log(f"formats: bitvector {out['bitvector']}")
+    return out
+
+
+def masked_bench(spv, M, A, dev):
+    """Masked multiplies on the headline graph (1 % x, plus-times) against
+    the unmasked one: the bitmap mask (rows with a set bit dropped, half of
+    them) and the GraphBLAS form w<mask> = w + A x with a structural mask
+    list of half the rows and a w of m/8 entries, without and with replace.
+    GTEPS counts the unmasked products (the work the call is asked for)."""
+    import torch
+    import synth
+    f = synth.density_f(A.n, 1e-2)
+    xs = [synth.sparse_x(A.n, f, seed=8000 + r) for r in range(8)]
+    xi = [torch.as_tensor(x[0]).to(dev) for x in xs]
+    xv = [torch.as_tensor(x[1]).to(dev) for x in xs]
+    deg = A.degrees()
+    W = float(np.mean([int(deg[x[0]].sum()) for x in xs]))
+    rng = np.random.default_rng(11)
+    drop = rng.random(A.m) < 0.5
+    nwords = (A.m + 31) // 32
+    packed = np.zeros(nwords * 4, np.uint8)
+    packed[: (A.m + 7) // 8] = np.packbits(drop, bitorder="little")
+    mask_bits = torch.as_tensor(packed.view(np.int32)).to(dev)
+    mi = torch.as_tensor(np.sort(rng.permutation(A.m)[: A.m // 2]).astype(np.int32)).to(dev)
+    wi_np = np.sort(rng.permutation(A.m)[: A.m // 8]).astype(np.int32)
+    wi = torch.as_tensor(wi_np).to(dev)
+    wv = torch.as_tensor(synth.values(wi_np.size, 5)).to(dev)
+    y_idx = torch.empty(A.m, dtype=torch.int32, device=dev)
+    y_val = torch.empty(A.m, dtype=torch.float32, device=dev)
+    k = [0]
+
+    def nxt():
+        r = k[0] % 8
+        k[0] += 1
+        return r
+
+    def plain():
+        r = nxt()
+        spv.spmspv_run(M.handle, 0, 0, f, xi[r], xv[r], y_idx, y_val, A.m, sync=False)
+
+    def bitmap():
+        r = nxt()
+        spv.spmspv_run_masked(M.handle, 0, 0, f, xi[r], xv[r], mask_bits, y_idx, y_val, A.m, sync=False)
+
+    def graphblas(mflags):
+        r = nxt()
+        spv.spmspv_run_graphblas(M.handle, 0, 0, f, xi[r], xv[r], mi, None, A.m // 2, mflags, spv.ACCUM_ADD,
+                                 wi, wv, wi_np.size, y_idx, y_val, A.m, sync=False)
+
+    out = {"products": W, "mask_rows": A.m // 2, "w_entries": int(wi_np.size)}
+    for name, fn in (("unmasked", plain), ("bitmap_mask", bitmap),
+                     ("graphblas_accum_add", lambda: graphblas(0)),
+                     ("graphblas_accum_add_replace", lambda: graphblas(spv.MASK_REPLACE))):
+        t = timed_us(fn)
+        out[name] = {"us": round(t, 2), "GTEPS": round(W / t / 1e3, 2)}
+    log(f"masked: {out}")
     return out
 
 

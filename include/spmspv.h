@@ -489,8 +489,9 @@ int pagerank_run(spmspv_handle A, float damping, float tol, int max_iter, int fl
 /* ---- batched calls (many x against one A in one launch sequence).
  * x is the concatenation of nbatch vectors: vector b occupies positions
  * [x_off[b], x_off[b+1]) of x_idx / x_val (x_off int64, device, x_off[0]
- * = 0).  Its products are bucketed by key (b, row range), with exact bucket
- * sizes from a counting pass (Algorithm 2's role), and merged per key; the
+ * = 0).  Its products are bucketed by key (b, row range), into fixed or
+ * counted slices (below; the counting pass plays Algorithm 2's role), and
+ * merged per key; the
  * results come out one vector after another, each ascending, vector b at
  * [y_off[b], y_off[b+1]) of y_idx / y_val.  Every x, y and offset array is
  * device memory.  The batch workspace is a second caller-owned buffer. */

@@ -272,9 +272,12 @@ constexpr int kMaxBatch = 1024;    // vectors per batched call
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
                                 hipStream_t s);
 // Masked multiply with accumulate / replace: row bitmap of a mask list, and
-// the merge of the masked product t with the accumulation input w.
-hipError_t launch_mask_bits(const int32_t* idx, const uint8_t* val, int64_t count, int32_t m, uint32_t* bits,
-                            uint32_t* err, hipStream_t s);
+// the merge of the masked product t with the accumulation input w.  The
+// list is first set into a byte map (plain byte stores), which is then
+// packed into the bitmap and cleared, so `bytes` (at least 32 * ceil(m / 32)
+// bytes) is all zero before and after.
+hipError_t launch_mask_bits(const int32_t* idx, const uint8_t* val, int64_t count, int32_t m, uint8_t* bytes,
+                            uint32_t* bits, uint32_t* err, hipStream_t s);
 struct CombineArgs {
     const int32_t* t_idx;    // masked product, ascending
     const void* t_val;

@@ -58,7 +58,7 @@ inline int ceil_log2(int64_t v) {
 // Offsets of every region inside the caller's workspace.
 struct Layout {
     size_t ctrl, rcp, partials, cstart, coff, cxv, chunk_col, lb1, cursor, lb3, xw, xrec, buckets, visited, front0,
-        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, bv_idx, bv_val, bv_tiles, dc_aux, det_list,
+        front1, front2, disc, pmin, bar, samples, gpoff, roff, gb_lb, gb_bytes, bv_idx, bv_val, bv_tiles, dc_aux, det_list,
         det_counts, det_partials, det_long, det_long_count, h_f64, h_i32, h_orbits, h_touched, total;
     // pull direction (present with SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC)
     size_t p_xbits, p_xdense, p_ybits, p_ydense, p_lbp, p_part, p_chain, t_colids, t_values, selector;
@@ -123,6 +123,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
     L.roff = take(size_t(L.rows_cap) * size_t(L.fnb + 1) * 4);
     // masked multiply: look-back words of the combine (t and w each hold at most m rows)
     L.gb_lb = take(size_t(gb_lb_words(mr)) * 8);
+    // masked multiply: byte map of the mask list (zero between calls)
+    L.gb_bytes = take(size_t((mr + 31) / 32) * 32);
     // bitvector calls (x list, then y list) and the masked multiply's
     // product t: lists of up to max(m, n) entries
     L.bv_idx = take(size_t(mx) * 4);
@@ -1241,6 +1243,9 @@ int create_impl(spmspv_handle* h_out, int64_t m, int64_t n, int64_t nnz, int64_t
         (e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + L.h_touched), 0u, (L.h_rows + 31) / 32, s)) !=
             hipSuccess)
         return bail(hip_fail(e, "HBM accumulator"));
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(A->ws + L.gb_bytes), 0u, (L.h_rows + 31) / 32 * 8, s)) !=
+        hipSuccess)
+        return bail(hip_fail(e, "mask byte map"));
     if (L.pull) {
         A->pull = true;
         A->p_xbits = reinterpret_cast<uint32_t*>(A->ws + L.p_xbits);
@@ -1583,8 +1588,8 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
     uint32_t* bits = nullptr;
     if (has_mask) {
         bits = A->visited;
-        HIP_TRY(launch_fill_u32(bits, 0u, (ylen + 31) / 32, s));
-        HIP_TRY(launch_mask_bits(mask_idx, mask_val, mask_count, (int32_t)ylen, bits, &A->ctrl->err, s));
+        HIP_TRY(launch_mask_bits(mask_idx, mask_val, mask_count, (int32_t)ylen,
+                                 reinterpret_cast<uint8_t*>(A->ws + A->L.gb_bytes), bits, &A->ctrl->err, s));
     }
     // (2) t = A x restricted to the mask, ascending; straight into y when
     // there is nothing to accumulate into (then the result is t: rows
@@ -1631,7 +1636,9 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
         HIP_TRY(launch_clear_u64(ca.lb, ca.lb_n, s));
         int64_t grid = (ylen + w_count + kCombineTile - 1) / kCombineTile;
         if (grid < 1) grid = 1;
-        if (grid > 2 * A->num_cu) grid = 2 * A->num_cu;   // co-resident: look-back waits stay bounded
+        // co-resident (four 33 KB workgroups fit one compute unit's LDS):
+        // look-back waits stay bounded
+        if (grid > 4 * A->num_cu) grid = 4 * A->num_cu;
         HIP_TRY(launch_combine(ca, semiring, (int)grid, s));
     }
     if (h_nnz_y) {

@@ -159,3 +159,34 @@ def test_errors_and_capacity(spv, c1):
     gi, gv, nnz = M.spmspv(dev(S), dev(xv), sorted_output=True)
     ti, tv, _ = oracle.spmspv(A, S, xv, sorted_output=True)
     assert np.array_equal(to_np(gi), ti)
+
+
+@pytest.mark.parametrize("semiring", [0, 1])
+def test_pairs_across_tile_boundaries(spv, semiring):
+    """w holds every row of t plus others, so a w entry and its t partner
+    sit next to each other all through the merged order and many pairs
+    straddle a 2048-entry tile boundary; one case makes the merged length an
+    exact multiple of the tile."""
+    A = synth.rmat(16, 16, seed=5, symmetrize=True)
+    M = spv.Matrix.from_csc(A)
+    rng = np.random.default_rng(40 + semiring)
+    for f, exact in ((3000, False), (40, True), (200, True)):
+        S, xv0 = synth.sparse_x(A.n, f, seed=int(rng.integers(1 << 30)))
+        xv = xv0 if semiring == 0 else values_for(rng, semiring, f)
+        ti, _, _ = oracle.spmspv(A, S, xv, semiring, sorted_output=True)
+        others = np.setdiff1d(np.arange(A.m, dtype=np.int32), ti)
+        if exact:
+            total = 2048 * ((2 * ti.size) // 2048 + 1)
+            extra = total - 2 * ti.size
+        else:
+            extra = ti.size
+        wi = np.sort(np.concatenate([ti, rng.choice(others, extra, replace=False)])).astype(np.int32)
+        if exact:
+            assert ti.size + wi.size == total
+        wv = values_for(rng, semiring, wi.size)
+        for accum in (0, 1, 2, 3):
+            for replace in (False, True):
+                mi = rng.permutation(A.m)[: A.m // 2].astype(np.int32)
+                check(spv, M, A, semiring, S, xv, mi, None, False, replace, accum, wi, wv)
+                check(spv, M, A, semiring, S, xv, None, None, False, replace, accum, wi, wv)
+    M.close()
