@@ -547,7 +547,18 @@ int spmspv_get_batch_schedule(spmspv_handle A, int semiring, int nbatch, spmspv_
  * batch; source x's visited bitmap masks its own products).  level and
  * parent are [nsrc][n] int32 (parent nullable; NULL for OR_AND), with the
  * conventions of bfs_run per source.  Needs a batch workspace attached with
- * SPMSPV_MSBFS and max_batch >= nsrc.  Synchronous.                      */
+ * SPMSPV_MSBFS and max_batch >= nsrc.  Synchronous.
+ *   flags: SPMSPV_DIRECTION_OPT on a handle with a row form
+ *   (SPMSPV_WITH_TRANSPOSE or SPMSPV_SYMMETRIC; for MIN_SELECT2ND the rows
+ *   must be ascending, as a symmetric handle's sorted columns are) switches
+ *   all searches to the pull direction once the frontiers' summed column
+ *   lengths exceed the sources' unexplored edges / 14 (the frontier-edge
+ *   rule summed over sources; the Conclusions name direction switching as
+ *   future work): one step then scans each vertex's in-neighbours against
+ *   one-bit-per-source frontier masks for every source at once, and the
+ *   searches stay pull to the end.  Same levels and parents (the smallest
+ *   frontier in-neighbour).  Without a usable row form the flag is
+ *   ignored.  One host read per level.                                    */
 int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, int flags, int32_t* level,
               int32_t* parent, int32_t* h_num_levels, void* stream);
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["spmspv_api.hip", "spmspv_kernels.hip", "setup_kernels.hip", "pull_kernels.hip", "mlp_kernels.hip",
            "pagerank_kernels.hip", "bfs_persistent.hip", "fused_kernels.hip",
            "graphblas_kernels.hip", "cc_kernels.hip", "format_kernels.hip", "det_kernels.hip",
-           "hbm_merge_kernels.hip"]
+           "hbm_merge_kernels.hip", "msbfs_kernels.hip"]
 LIB = os.path.join(HERE, "libspmspv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 

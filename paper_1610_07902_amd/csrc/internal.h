@@ -339,6 +339,32 @@ hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int sh
 // Fold each row's run of the sorted list and write y ascending.
 hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int32_t* partials, hipStream_t s);
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
+// Multi-source BFS in the pull direction (msbfs_kernels.hip): frontier and
+// seen masks with one bit per source, G = ceil(nsrc / 64) 64-bit words per
+// vertex (vertex-major).
+constexpr int kMsLong = 64;   // rows longer than this are scanned by a whole wave
+struct MsArgs {
+    int32_t n;
+    int G;
+    int nsrc;
+    const int32_t* rowptr;   // row form: in-neighbours of each vertex, ascending
+    const uint32_t* colids;
+    const uint64_t* fcur;    // [n * G] frontier masks of the current level
+    uint64_t* fnext;         // [n * G] next level's (every word written)
+    uint64_t* seen;          // [n * G]
+    int32_t* level;          // [nsrc][n]
+    int32_t* parent;         // [nsrc][n], nullable
+    int32_t lvl;             // level of the vertices found now
+    const int32_t* long_rows;
+    const int32_t* long_count;
+    unsigned long long* found_total;   // += bits set in fnext
+};
+hipError_t launch_ms_long_rows(const int32_t* rowptr, int32_t n, int32_t* rows, int32_t* count, hipStream_t s);
+hipError_t launch_ms_to_pull(const MsArgs& a, const uint32_t* visited, int32_t mask_words, const int32_t* front,
+                             const int64_t* xoff, uint64_t* fm, hipStream_t s);
+hipError_t launch_ms_pull(const MsArgs& a, bool parent, int num_cu, hipStream_t s);
+hipError_t launch_ms_degsum(const int32_t* front, const int64_t* xoff, int nsrc, const int32_t* colptr, int32_t n,
+                            unsigned long long* out, hipStream_t s);
 hipError_t launch_msbfs_init(int32_t n, int nsrc, const int32_t* roots, int32_t* level, int32_t* parent,
                              uint32_t* visited, int32_t mask_words, int32_t* frontier, int64_t* xoff, Ctrl* ctrl,
                              hipStream_t s);

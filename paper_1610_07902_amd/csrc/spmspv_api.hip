@@ -174,9 +174,10 @@ constexpr int kMaxKeys = 8192;   // (vector, bucket) keys per batched call
 
 struct BatchLayout {
     size_t cstart, coff, cxid, cxv, chunk_col, lb1, kcount, partials, cursor, lb3, buckets, visited, front0, front1,
-        xoff0, xoff1, roots, total;
+        xoff0, xoff1, roots, ms_f0, ms_f1, ms_seen, ms_long, ms_cnt, total;
     int64_t max_f, max_products, chunk_n, lb1_n;
     int32_t mask_words;
+    int32_t ms_groups;   // multi-source pull: 64-bit mask words per vertex
 };
 
 BatchLayout make_batch_layout(int64_t m, int64_t n, int64_t nnz, int max_batch, int64_t max_f,
@@ -218,6 +219,14 @@ BatchLayout make_batch_layout(int64_t m, int64_t n, int64_t nnz, int max_batch, 
         L.xoff0 = take(size_t(max_batch + 1) * 8);
         L.xoff1 = take(size_t(max_batch + 1) * 8);
         L.roots = take(size_t(max_batch) * 4);
+        // pull levels (SPMSPV_DIRECTION_OPT): frontier masks (two levels) and
+        // seen masks, one bit per source; the list of long rows; counters
+        L.ms_groups = (max_batch + 63) / 64;
+        L.ms_f0 = take(size_t(n) * L.ms_groups * 8);
+        L.ms_f1 = take(size_t(n) * L.ms_groups * 8);
+        L.ms_seen = take(size_t(n) * L.ms_groups * 8);
+        L.ms_long = take(size_t(nnz / kMsLong + 2) * 4);
+        L.ms_cnt = take(64);
     }
     L.total = o;
     return L;
@@ -227,6 +236,7 @@ struct BatchCtx {
     bool bound = false;
     bool bfs = false;
     bool fixed_last = false;   // the last batched call used fixed slices (no counting pass)
+    bool ms_long_ready = false;   // the long-row list of the pull levels is built
     int max_batch = 0;
     BatchLayout L{};
     char* ws = nullptr;
@@ -1994,6 +2004,7 @@ int spmspv_batch_attach(spmspv_handle A, int max_batch, int64_t max_f, int64_t m
     A->batch.max_batch = max_batch;
     A->batch.L = make_batch_layout(A->m, A->n, A->nnz, max_batch, max_f, max_products, bfs);
     A->batch.ws = static_cast<char*>(workspace);
+    A->batch.ms_long_ready = false;
     // The first scan looks back over these words; later calls clear them in
     // their first bucketing pass.  (The counters and merge look-back words
     // are cleared by every scan.)
@@ -2095,9 +2106,108 @@ int spmspv_run_batch(spmspv_handle A, int semiring, int flags, int nbatch, const
     return SPMSPV_OK;
 }
 
+// Multi-source BFS with the direction chosen per level for all sources
+// together, by the frontier-edge rule summed over the sources: push (the
+// batched SpMSpV) while the frontiers' column lengths m_f stay below the
+// sources' unexplored edges m_u / alpha, then pull levels on one-bit-per-
+// source masks until every frontier is empty.  The searches stay pull once
+// switched: late levels cost one read of the seen masks, less than the
+// batched push launches.  One host read per level (the switch test, the
+// frontier total); the state starts as k_msbfs_init left it.
+int msbfs_diropt(spmspv_matrix* A, int semiring, int nsrc, int32_t* level, int32_t* parent, int32_t* h_num_levels,
+                 hipStream_t s) {
+    BatchCtx& B = A->batch;
+    const BatchLayout& L = B.L;
+    int32_t* front[2] = {reinterpret_cast<int32_t*>(B.ws + L.front0), reinterpret_cast<int32_t*>(B.ws + L.front1)};
+    int64_t* xoff[2] = {reinterpret_cast<int64_t*>(B.ws + L.xoff0), reinterpret_cast<int64_t*>(B.ws + L.xoff1)};
+    uint64_t* fm[2] = {reinterpret_cast<uint64_t*>(B.ws + L.ms_f0), reinterpret_cast<uint64_t*>(B.ws + L.ms_f1)};
+    int32_t* long_count = reinterpret_cast<int32_t*>(B.ws + L.ms_cnt);
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(B.ws + L.ms_cnt + 16);
+    const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
+    const int G = (nsrc + 63) / 64;
+    const double alpha = 14.0;
+    if (!B.ms_long_ready) {
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(long_count), 0u, 1, s));
+        HIP_TRY(launch_ms_long_rows(A->rowptr, (int32_t)A->n, reinterpret_cast<int32_t*>(B.ws + L.ms_long),
+                                    long_count, s));
+        B.ms_long_ready = true;
+    }
+    // push levels while the frontier-edge rule says so
+    double m_u = (double)nsrc * (double)A->nnz;
+    int32_t hf = nsrc;
+    int64_t lv = 0;   // the current frontier's position in the level sequence
+    bool pull = false;
+    for (;;) {
+        if (lv > A->n + 1) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+        HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 0ull, 1, s));
+        HIP_TRY(launch_ms_degsum(front[lv & 1], xoff[lv & 1], nsrc, A->colptr, (int32_t)A->n, counter, s));
+        unsigned long long mf = 0;
+        HIP_TRY(hipMemcpyAsync(&mf, counter, sizeof(mf), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&hf, &A->ctrl->f, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hf <= 0) break;
+        m_u -= (double)mf;
+        if ((double)mf * alpha > m_u) {
+            pull = true;
+            break;
+        }
+        const int rc = enqueue_batch(A, semiring, xmode, nsrc, xoff[lv & 1], front[lv & 1], nullptr,
+                                     xoff[(lv + 1) & 1], front[(lv + 1) & 1], nullptr, L.max_f, true, s);
+        if (rc) return rc;
+        ++lv;
+    }
+    Ctrl h{};
+    int rc = read_ctrl(A, &h, s);
+    if (rc) return rc;
+    int32_t levels = h.level;
+    if (pull && hf > 0) {
+        // level of the current frontier: the scans have counted the push levels
+        int32_t cur = h.level;
+        MsArgs ma{};
+        ma.n = (int32_t)A->n;
+        ma.G = G;
+        ma.nsrc = nsrc;
+        ma.rowptr = A->rowptr;
+        ma.colids = A->colids;
+        ma.level = level;
+        ma.parent = semiring == SR_MIN_SELECT2ND ? parent : nullptr;
+        ma.long_rows = reinterpret_cast<const int32_t*>(B.ws + L.ms_long);
+        ma.long_count = long_count;
+        ma.found_total = counter;
+        ma.seen = reinterpret_cast<uint64_t*>(B.ws + L.ms_seen);
+        int cf = 0;
+        ma.fcur = fm[cf];
+        HIP_TRY(launch_fill_u64(fm[cf], 0ull, A->n * G, s));
+        HIP_TRY(launch_ms_to_pull(ma, reinterpret_cast<const uint32_t*>(B.ws + L.visited), L.mask_words, front[lv & 1],
+                                  xoff[lv & 1], fm[cf], s));
+        for (int64_t step = 0;; ++step) {
+            if (step > A->n + 1) return fail(SPMSPV_EDEVICE, "BFS did not terminate");
+            ma.fcur = fm[cf];
+            ma.fnext = fm[cf ^ 1];
+            ma.lvl = cur + 1;
+            HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(counter), 0ull, 1, s));
+            HIP_TRY(launch_ms_pull(ma, ma.parent != nullptr, A->num_cu, s));
+            unsigned long long found = 0;
+            HIP_TRY(hipMemcpyAsync(&found, counter, sizeof(found), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ++cur;   // the frontier was not empty
+            if (found == 0) break;
+            cf ^= 1;
+        }
+        levels = cur;
+    }
+    if (h.err) {
+        clear_err(A, s);
+        if (h.err & ERR_BUCKET_OVERFLOW)
+            return fail(SPMSPV_ECAPACITY, "a level's products exceed the batch workspace's max_products");
+        return fail(SPMSPV_EDEVICE, "device error bits " + std::to_string(h.err));
+    }
+    if (h_num_levels) *h_num_levels = levels;
+    return SPMSPV_OK;
+}
+
 int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, int flags, int32_t* level,
               int32_t* parent, int32_t* h_num_levels, void* stream) {
-    (void)flags;
     if (!A) return fail(SPMSPV_EINVAL, "NULL handle");
     if (!A->batch.bound || !A->batch.bfs)
         return fail(SPMSPV_EINVAL, "no batch workspace attached with SPMSPV_MSBFS");
@@ -2122,6 +2232,10 @@ int msbfs_run(spmspv_handle A, int semiring, int nsrc, const int32_t* h_roots, i
     HIP_TRY(launch_msbfs_init((int32_t)A->n, nsrc, roots, level, parent, reinterpret_cast<uint32_t*>(B.ws + L.visited),
                               L.mask_words, front[0], xoff[0], A->ctrl, s));
     const int xmode = semiring == SR_MIN_SELECT2ND ? XV_INDEX : XV_TRUE;
+    // Direction switching needs the row form, and for parents ascending rows
+    // (the first frontier in-neighbour found is then the smallest).
+    if ((flags & SPMSPV_DIRECTION_OPT) && A->pull && (semiring == SR_OR_AND || A->rows_sorted))
+        return msbfs_diropt(A, semiring, nsrc, level, parent, h_num_levels, s);
     // Levels are enqueued kGraphLevels at a time; levels after the frontiers
     // empty are no-ops.  One host check of the total frontier per batch.
     int32_t hf = nsrc;
