@@ -268,6 +268,8 @@ int pull_blocks(int32_t m, int64_t nnz);
 
 size_t merge_lds_bytes(int tile_log2, int semiring);
 size_t scatter_lds_bytes(int nb, int chunk, bool batch = false);
+// Scatter workgroups resident per compute unit (registers, LDS, threads).
+int scatter_resident(int semiring, int block, int items, int nb, bool batch);
 constexpr int kMaxBatch = 1024;    // vectors per batched call
 hipError_t launch_scatter_batch(const ScatterArgs& a, int semiring, int block, int items, int grid, bool count,
                                 hipStream_t s);

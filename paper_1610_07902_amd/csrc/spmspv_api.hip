@@ -393,15 +393,17 @@ int call_tile(const spmspv_matrix* A, int tl, int semiring) {
     return tl;
 }
 
-// Bucketing workgroups one compute unit holds at once (LDS and 2048
-// threads per CU): the scatter grid is at most this many per CU, so every
-// workgroup of the grid is resident and short chunks overlap their memory
-// round trips across workgroups.
-int64_t scatter_occupancy(const spmspv_matrix* A, int nb, int block, int chunk, bool batch) {
-    const size_t lds = scatter_lds_bytes(nb, chunk, batch) + 1024;
+// Bucketing workgroups one compute unit holds at once (registers, LDS and
+// threads, as the runtime computes it for the kernel): the scatter grid is at
+// most this many per CU, so every workgroup of the grid is resident and short
+// chunks overlap their memory round trips across workgroups.  (A grid sized
+// by LDS alone once put a third of the workgroups, each with its share of the
+// chunks, in a second round: 96 -> 114 us at 10 % density on scale 22.)
+int64_t scatter_occupancy(const spmspv_matrix* A, int semiring, int nb, int block, int items, bool batch) {
+    const size_t lds = scatter_lds_bytes(nb, block * items, batch) + 1024;
     int64_t by_lds = (int64_t)(A->lds_max / (lds ? lds : 1));
-    int64_t by_threads = 2048 / block;
-    int64_t occ = by_lds < by_threads ? by_lds : by_threads;
+    int64_t occ = scatter_resident(semiring, block, items, nb, batch);
+    if (by_lds < occ) occ = by_lds;
     return occ < 1 ? 1 : occ;
 }
 
@@ -521,7 +523,8 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     if (wbound > A->nnz) wbound = A->nnz;
     int64_t g2 = (wbound + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
-    const int64_t g2max = int64_t(A->num_cu) * scatter_occupancy(A, nb, sc.scatter_block, chunk, false);
+    const int64_t g2max =
+        int64_t(A->num_cu) * scatter_occupancy(A, semiring, nb, sc.scatter_block, sc.scatter_items, false);
     if (g2 > g2max) g2 = g2max;
 
     MergeArgs ma{};
@@ -930,7 +933,8 @@ int enqueue_batch(spmspv_matrix* A, int semiring, int xmode, int nbatch, const i
     ca.mask_words = L.mask_words;
     int64_t g2 = (L.max_products + chunk - 1) / chunk;
     if (g2 < 1) g2 = 1;
-    const int64_t g2max = int64_t(A->num_cu) * scatter_occupancy(A, K, sc.scatter_block, chunk, true);
+    const int64_t g2max =
+        int64_t(A->num_cu) * scatter_occupancy(A, semiring, K, sc.scatter_block, sc.scatter_items, true);
     if (g2 > g2max) g2 = g2max;
 
     MergeArgs ma{};

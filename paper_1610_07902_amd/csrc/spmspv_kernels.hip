@@ -39,6 +39,11 @@
 #include "decide.h"
 #include "device_ops.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace spv {
 
 namespace {
@@ -330,8 +335,11 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     int32_t* hist = reinterpret_cast<int32_t*>(lds_scatter);   // [nb] counts, then global slot base
     int32_t* loff = hist + nb;                                  // [nb] chunk-local bucket offsets
     uint32_t* region = lds_scatter + 2 * nb + 2;                // 8-byte aligned
-    int32_t* s_off = reinterpret_cast<int32_t*>(region);        // [C+1] column table (phase 1)
-    int32_t* s_start = s_off + (C + 1);
+    // Column table (phase 1): product offset of each column inside the chunk
+    // (16 bits: the first column is cut to start at the chunk, the others
+    // start inside it), its first entry in A and its x value.
+    uint16_t* s_off = reinterpret_cast<uint16_t*>(region);      // [C+2]
+    int32_t* s_start = reinterpret_cast<int32_t*>(s_off + (C + 2));
     uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_start + (C + 1));
     int32_t* s_xid = reinterpret_cast<int32_t*>(s_xv + (C + 1)); // batched: vector of each column
     uint16_t* col_of = reinterpret_cast<uint16_t*>(s_xv + (MODE != SC_SINGLE ? 2 : 1) * (C + 1));   // [C] (phase 1)
@@ -373,8 +381,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         const int ncols = pend - p0 + 1;
         __syncthreads();  // the previous chunk is done with hist, loff and the shared region
         for (int k = tid; k < ncols; k += BLOCK) {
-            s_off[k] = a.coff[p0 + k] - q0;
-            s_start[k] = a.cstart[p0 + k];
+            const int off = a.coff[p0 + k] - q0;   // <= 0 only for k == 0
+            const int st = a.cstart[p0 + k];
+            s_off[k] = (uint16_t)(k == 0 ? 0 : off);
+            s_start[k] = k == 0 ? st - off : st;
             s_xv[k] = a.cxv[p0 + k];
             if constexpr (MODE != SC_SINGLE) s_xid[k] = a.cxid[p0 + k];
         }
@@ -388,7 +398,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         // line instead of one per lane.  All row-id / value / mask loads are
         // issued together (indices clamped into range); ranks are taken in
         // LDS.
-        int32_t row[ITEMS], bk[ITEMS], rank[ITEMS], qq[ITEMS], xid[ITEMS];
+        int32_t row[ITEMS], rank[ITEMS], qq[ITEMS], xid[ITEMS];
         uint32_t xcol[ITEMS];
         {
             const int rq0 = tid * ITEMS;
@@ -428,14 +438,14 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
             mw[i] = a.mask ? a.mask[(int64_t)xid[i] * a.mask_words + ((uint32_t)row[i] >> 5)] : 0u;
+        // A product's bucket (key) is recomputed from its row where needed;
+        // rank < 0 marks a product that is dropped (past the chunk, masked).
+        auto bucket = [&](int i) { return MODE != SC_SINGLE ? xid[i] * a.nbx + (row[i] >> tl) : row[i] >> tl; };
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            bk[i] = -1;
-            rank[i] = 0;
-            if (qq[i] >= 0 && (!a.mask || ((mw[i] >> (row[i] & 31)) & 1u) == (uint32_t)a.mask_keep)) {
-                bk[i] = MODE != SC_SINGLE ? xid[i] * a.nbx + (row[i] >> tl) : row[i] >> tl;
-                rank[i] = atomicAdd(&hist[bk[i]], 1);
-            }
+            rank[i] = -1;
+            if (qq[i] >= 0 && (!a.mask || ((mw[i] >> (row[i] & 31)) & 1u) == (uint32_t)a.mask_keep))
+                rank[i] = atomicAdd(&hist[bucket(i)], 1);
         }
         __syncthreads();
         if constexpr (MODE == SC_COUNT) {
@@ -474,9 +484,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
-                if (bk[i] >= 0) {
-                    stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
-                    if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+                if (rank[i] >= 0) {
+                    const int bi = bucket(i);
+                    stage[loff[bi] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+                    if constexpr (MODE == SC_BATCH) skey[loff[bi] + rank[i]] = bi;
                 }
             if (n > 0) {
                 if (base + g + n > top) {
@@ -522,9 +533,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             // (3) counting sort into the LDS buffer
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
-                if (bk[i] >= 0) {
-                    stage[loff[bk[i]] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
-                    if constexpr (MODE == SC_BATCH) skey[loff[bk[i]] + rank[i]] = bk[i];
+                if (rank[i] >= 0) {
+                    const int bi = bucket(i);
+                    stage[loff[bi] + rank[i]] = make_uint2((uint32_t)row[i], val[i]);
+                    if constexpr (MODE == SC_BATCH) skey[loff[bi] + rank[i]] = bi;
                 }
             __syncthreads();
         }
@@ -539,7 +551,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (bk[i] >= 0 && rank[i] == 0) hist[bk[i]] = 0;
+            if (rank[i] == 0) hist[bucket(i)] = 0;
     }
 }
 
@@ -763,7 +775,7 @@ size_t merge_lds_bytes(int tile_log2, int semiring) {
 
 size_t scatter_lds_bytes(int nb, int chunk, bool batch) {
     // column table (+ the per-product column map) in phase 1, sort buffer in phase 3
-    const size_t table = size_t(chunk + 1) * (batch ? 16 : 12) + size_t(chunk) * 2,
+    const size_t table = size_t(chunk + 2) * 2 + size_t(chunk + 1) * (batch ? 12 : 8) + size_t(chunk) * 2,
                  sortbuf = size_t(chunk) * (batch ? 12 : 8);
     return size_t(2 * nb + 2) * 4 + (table > sortbuf ? table : sortbuf);
 }
@@ -860,6 +872,63 @@ static hipError_t scatter_shape(const ScatterArgs& a, int semiring, int block, i
         if (items == 8) return scatter_sr<1024, 8, MODE>(a, semiring, grid, s, ev);
     }
     return hipErrorInvalidValue;
+}
+
+// Workgroups of one scatter instantiation a compute unit holds at once, as
+// the runtime computes it from the kernel's registers, LDS and threads.
+template <int BLOCK, int ITEMS, int SR, int MODE>
+static int resident_one(size_t lds) {
+    auto kern = k_scatter<BLOCK, ITEMS, SR, MODE>;
+    if (allow_lds(kern, lds) != hipSuccess) return 1;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern), BLOCK, lds) !=
+        hipSuccess)
+        return 1;
+    return n;
+}
+
+template <int BLOCK, int ITEMS, int MODE>
+static int resident_sr(int semiring, size_t lds) {
+    switch (semiring) {
+        case SR_PLUS_TIMES: return resident_one<BLOCK, ITEMS, SR_PLUS_TIMES, MODE>(lds);
+        case SR_MIN_SELECT2ND: return resident_one<BLOCK, ITEMS, SR_MIN_SELECT2ND, MODE>(lds);
+        default: return resident_one<BLOCK, ITEMS, SR_OR_AND, MODE>(lds);
+    }
+}
+
+template <int MODE>
+static int resident_shape(int semiring, int block, int items, size_t lds) {
+    if (block == 256) {
+        if (items == 4) return resident_sr<256, 4, MODE>(semiring, lds);
+        if (items == 8) return resident_sr<256, 8, MODE>(semiring, lds);
+        if (items == 16) return resident_sr<256, 16, MODE>(semiring, lds);
+    } else if (block == 512) {
+        if (items == 4) return resident_sr<512, 4, MODE>(semiring, lds);
+        if (items == 8) return resident_sr<512, 8, MODE>(semiring, lds);
+    } else if (block == 1024) {
+        if (items == 4) return resident_sr<1024, 4, MODE>(semiring, lds);
+        if (items == 8) return resident_sr<1024, 8, MODE>(semiring, lds);
+    }
+    return 1;
+}
+
+int scatter_resident(int semiring, int block, int items, int nb, bool batch) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, bool>, int> cache;
+    const auto key = std::make_tuple(semiring, block, items, nb, batch);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const size_t lds = scatter_lds_bytes(nb, block * items, batch);
+    int n = batch ? std::min(resident_shape<SC_BATCH>(semiring, block, items, lds),
+                             resident_shape<SC_COUNT>(semiring, block, items, lds))
+                  : resident_shape<SC_SINGLE>(semiring, block, items, lds);
+    if (n < 1) n = 1;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = n;
+    return n;
 }
 
 hipError_t launch_scatter(const ScatterArgs& a, int semiring, int block, int items, int grid, hipStream_t s,
