@@ -10,8 +10,9 @@
 // mask has the source's bit: with ascending rows that is the smallest
 // frontier in-neighbour, the parent the push direction's min-select2nd
 // gives.  The scan stops once every unseen source is found.  Rows of up to
-// kMsLong entries are scanned by one thread each, eight entries in flight;
-// longer rows by one wave, 64 entries per step.
+// kMsLong entries are scanned by one thread each, eight entries in flight
+// (levels and parents then stored source by source for the wave's 64
+// vertices); longer rows by one wave, 64 entries per step.
 //
 // Switching a search from push to pull converts its state once: the
 // per-source visited bitmaps become the seen masks (transposed), the
@@ -43,58 +44,78 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// Levels (and parents) of the sources in `bits` (group g) newly reaching v
-// through u.
-template <bool PARENT>
-__device__ __forceinline__ void record(const MsArgs& a, int g, int32_t v, uint64_t bits, uint32_t u) {
-    while (bits) {
-        const int s = __ffsll((unsigned long long)bits) - 1;
-        bits &= bits - 1ull;
-        const int64_t at = (int64_t)(64 * g + s) * a.n + v;
-        a.level[at] = a.lvl;
-        if (PARENT) a.parent[at] = (int32_t)u;
-    }
-}
+// One wave covers 64 consecutive vertices.  A vertex's parent for each
+// newly found source is kept in LDS (slot [source][lane] of its wave) while
+// its row is scanned; afterwards the wave stores source by source, so each
+// store instruction writes consecutive vertices of one source's level and
+// parent rows instead of 64 scattered words.
+constexpr int kMsShortBlock = 128;
 
 template <bool PARENT>
-__global__ __launch_bounds__(kMsBlock) void k_ms_pull_short(MsArgs a) {
+__global__ __launch_bounds__(kMsShortBlock) void k_ms_pull_short(MsArgs a) {
+    __shared__ uint32_t s_par[PARENT ? kMsShortBlock / kWave : 1][64][kWave];
     const int g = blockIdx.y;
     const uint64_t valid = group_valid(a.nsrc, g);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = PARENT ? threadIdx.x / kWave : 0;
     uint32_t cnt = 0;
-    for (int64_t v = (int64_t)blockIdx.x * kMsBlock + threadIdx.x; v < a.n; v += (int64_t)gridDim.x * kMsBlock) {
-        const int32_t b = a.rowptr[v], e = a.rowptr[v + 1];
-        if (e - b > kMsLong) continue;   // k_ms_pull_long's row
-        const int64_t at = v * a.G + g;
-        const uint64_t seen = a.seen[at];
-        const uint64_t unseen = valid & ~seen;
+    for (int64_t base = (int64_t)blockIdx.x * kMsShortBlock; base < a.n;
+         base += (int64_t)gridDim.x * kMsShortBlock) {
+        const int64_t v = base + threadIdx.x;
         uint64_t found = 0ull;
-        if (unseen) {
-            for (int32_t k = b; k < e; k += kMsUnroll) {
-                uint32_t u[kMsUnroll];
-                uint64_t fu[kMsUnroll];
+        bool mine = false;   // this thread owns v's words in this kernel
+        if (v < a.n) {
+            const int32_t b = a.rowptr[v], e = a.rowptr[v + 1];
+            mine = e - b <= kMsLong;   // longer rows are k_ms_pull_long's
+            if (mine) {
+                const int64_t at = v * a.G + g;
+                const uint64_t seen = a.seen[at];
+                const uint64_t unseen = valid & ~seen;
+                if (unseen) {
+                    for (int32_t k = b; k < e; k += kMsUnroll) {
+                        uint32_t u[kMsUnroll];
+                        uint64_t fu[kMsUnroll];
 #pragma unroll
-                for (int q = 0; q < kMsUnroll; ++q) u[q] = k + q < e ? a.colids[k + q] : 0u;
+                        for (int q = 0; q < kMsUnroll; ++q) u[q] = k + q < e ? a.colids[k + q] : 0u;
 #pragma unroll
-                for (int q = 0; q < kMsUnroll; ++q) fu[q] = k + q < e ? a.fcur[(int64_t)u[q] * a.G + g] : 0ull;
+                        for (int q = 0; q < kMsUnroll; ++q)
+                            fu[q] = k + q < e ? a.fcur[(int64_t)u[q] * a.G + g] : 0ull;
 #pragma unroll
-                for (int q = 0; q < kMsUnroll; ++q) {
-                    const uint64_t nf = fu[q] & unseen & ~found;
-                    if (nf) {
-                        record<PARENT>(a, g, (int32_t)v, nf, u[q]);
-                        found |= nf;
+                        for (int q = 0; q < kMsUnroll; ++q) {
+                            uint64_t nf = fu[q] & unseen & ~found;
+                            found |= nf;
+                            if (PARENT) {
+                                while (nf) {
+                                    const int sb = __ffsll((unsigned long long)nf) - 1;
+                                    nf &= nf - 1ull;
+                                    s_par[wv][sb][lane] = u[q];
+                                }
+                            }
+                        }
+                        if (found == unseen) break;
                     }
                 }
-                if (found == unseen) break;
+                a.fnext[at] = found;
+                if (found) {
+                    a.seen[at] = seen | found;
+                    cnt += (uint32_t)__popcll(found);
+                }
             }
         }
-        a.fnext[at] = found;
-        if (found) {
-            a.seen[at] = seen | found;
-            cnt += (uint32_t)__popcll(found);
+        // source-major stores of this wave's new levels and parents
+        uint64_t any = wave_or64(found);   // uniform
+        while (any) {
+            const int sb = __ffsll((unsigned long long)any) - 1;
+            any &= any - 1ull;
+            if ((found >> sb) & 1ull) {
+                const int64_t o = (int64_t)(64 * g + sb) * a.n + v;
+                a.level[o] = a.lvl;
+                if (PARENT) a.parent[o] = (int32_t)s_par[wv][sb][lane];
+            }
         }
     }
     cnt = wave_sum_u32(cnt);
-    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(a.found_total, (unsigned long long)cnt);
+    if (lane == 0 && cnt) atomicAdd(a.found_total, (unsigned long long)cnt);
 }
 
 template <bool PARENT>
@@ -234,12 +255,15 @@ hipError_t launch_ms_to_pull(const MsArgs& a, const uint32_t* visited, int32_t m
 }
 
 hipError_t launch_ms_pull(const MsArgs& a, bool parent, int num_cu, hipStream_t s) {
-    const dim3 gs(grid_for_n(a.n, 16384), a.G), gl((unsigned)(8 * num_cu), a.G);
+    int64_t gshort = (a.n + kMsShortBlock - 1) / kMsShortBlock;
+    if (gshort > 32768) gshort = 32768;
+    if (gshort < 1) gshort = 1;
+    const dim3 gs((unsigned)gshort, a.G), gl((unsigned)(8 * num_cu), a.G);
     if (parent) {
-        hipLaunchKernelGGL(k_ms_pull_short<true>, gs, dim3(kMsBlock), 0, s, a);
+        hipLaunchKernelGGL(k_ms_pull_short<true>, gs, dim3(kMsShortBlock), 0, s, a);
         hipLaunchKernelGGL(k_ms_pull_long<true>, gl, dim3(kMsBlock), 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_ms_pull_short<false>, gs, dim3(kMsBlock), 0, s, a);
+        hipLaunchKernelGGL(k_ms_pull_short<false>, gs, dim3(kMsShortBlock), 0, s, a);
         hipLaunchKernelGGL(k_ms_pull_long<false>, gl, dim3(kMsBlock), 0, s, a);
     }
     return hipGetLastError();

@@ -914,8 +914,10 @@ static int resident_shape(int semiring, int block, int items, size_t lds) {
 
 int scatter_resident(int semiring, int block, int items, int nb, bool batch) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, bool>, int> cache;
-    const auto key = std::make_tuple(semiring, block, items, nb, batch);
+    static std::map<std::tuple<int, int, int, int, int, bool>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    const auto key = std::make_tuple(dev, semiring, block, items, nb, batch);
     {
         std::lock_guard<std::mutex> g(mu);
         const auto it = cache.find(key);
