@@ -237,34 +237,57 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
     if (threadIdx.x == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
 }
 
-// One wave per long run: 64 consecutive entries per step in one load (the
-// next step's load issued before this step's adds), folded in order through
-// lane reads (every lane holds the same accumulator).
+// One wave per long run.  The wave keeps kLongDepth steps of 64 consecutive
+// entries in flight (one coalesced load per step, issued kLongDepth steps
+// ahead); each step's values go to the wave's LDS row and one lane adds them
+// in order from there, so the run costs its dependent adds and little more.
+// (Folding through lane reads cost about 90 cycles per entry, a 16K-entry
+// hub row 0.6 ms; one thread per run with sixteen loads ahead left the
+// memory latency exposed.)
+constexpr int kLongDepth = 4;
+
 __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const uint2* list) {
+    __shared__ __attribute__((aligned(16))) float s_v[kDetWaves][kWave];
     const int W = ld_ctrl(&a.ctrl->W);
     const int nblk_used = (W + kDetTile - 1) / kDetTile;
     const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
     const int nwaves = gridDim.x * kDetWaves;
     const int64_t npairs = (int64_t)nblk_used * kDetLongPerBlock;
-    for (int64_t pr = blockIdx.x * kDetWaves + threadIdx.x / kWave; pr < npairs; pr += nwaves) {
+    auto load = [&](int64_t k) { return k + lane < W ? list[k + lane] : make_uint2(~0u, 0u); };
+    for (int64_t pr = blockIdx.x * kDetWaves + wv; pr < npairs; pr += nwaves) {
         const int b = (int)(pr / kDetLongPerBlock), slot = (int)(pr % kDetLongPerBlock);
         if (slot >= a.long_count[b]) continue;
         const int4 rec = a.long_runs[pr];
         const uint32_t row = (uint32_t)rec.x;
         float acc = __uint_as_float((uint32_t)rec.y);
         int64_t k = rec.z;
-        uint2 v = k + lane < W ? list[k + lane] : make_uint2(~0u, 0u);
+        uint2 ring[kLongDepth];
+#pragma unroll
+        for (int d = 0; d < kLongDepth; ++d) ring[d] = load(k + (int64_t)d * kWave);
         bool more = true;
         while (more) {
-            const uint2 next = k + kWave + lane < W ? list[k + kWave + lane] : make_uint2(~0u, 0u);
+            const uint2 v = ring[0];
+#pragma unroll
+            for (int d = 0; d + 1 < kLongDepth; ++d) ring[d] = ring[d + 1];
+            ring[kLongDepth - 1] = load(k + (int64_t)kLongDepth * kWave);
             const uint64_t match = __ballot(v.x == row);
             // entries of the run in this step: the lanes before the first mismatch
             const int n = (~match == 0ull) ? kWave : __ffsll((unsigned long long)~match) - 1;
-            const int vb = (int)v.y;
-            for (int u = 0; u < n; ++u) acc = __fadd_rn(acc, __int_as_float(__builtin_amdgcn_readlane(vb, u)));
+            s_v[wv][lane] = __uint_as_float(v.y);
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                for (int u = 0; u < n; u += 4) {
+                    const float4 q = *reinterpret_cast<const float4*>(&s_v[wv][u]);
+                    acc = __fadd_rn(acc, q.x);
+                    if (u + 1 < n) acc = __fadd_rn(acc, q.y);
+                    if (u + 2 < n) acc = __fadd_rn(acc, q.z);
+                    if (u + 3 < n) acc = __fadd_rn(acc, q.w);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
             more = n == kWave;
             k += kWave;
-            v = next;
         }
         if (lane == 0 && rec.w < a.y_cap) {
             a.y_idx[rec.w] = (int32_t)row;
