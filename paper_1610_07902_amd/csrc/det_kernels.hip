@@ -277,12 +277,16 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const ui
             s_v[wv][lane] = __uint_as_float(v.y);
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) {
-                for (int u = 0; u < n; u += 4) {
-                    const float4 q = *reinterpret_cast<const float4*>(&s_v[wv][u]);
-                    acc = __fadd_rn(acc, q.x);
-                    if (u + 1 < n) acc = __fadd_rn(acc, q.y);
-                    if (u + 2 < n) acc = __fadd_rn(acc, q.z);
-                    if (u + 3 < n) acc = __fadd_rn(acc, q.w);
+                // all 64 values into registers first, then the dependent adds
+                float4 q[kWave / 4];
+#pragma unroll
+                for (int j = 0; j < kWave / 4; ++j) q[j] = *reinterpret_cast<const float4*>(&s_v[wv][4 * j]);
+#pragma unroll
+                for (int j = 0; j < kWave / 4; ++j) {
+                    if (4 * j < n) acc = __fadd_rn(acc, q[j].x);
+                    if (4 * j + 1 < n) acc = __fadd_rn(acc, q[j].y);
+                    if (4 * j + 2 < n) acc = __fadd_rn(acc, q[j].z);
+                    if (4 * j + 3 < n) acc = __fadd_rn(acc, q[j].w);
                 }
             }
             __builtin_amdgcn_wave_barrier();
