@@ -432,11 +432,13 @@ int spmspv_run_graphblas(spmspv_handle A, int semiring, int flags, int64_t f, co
  *           with SPMSPV_LEFT); y_val [y_capacity] the present entries'
  *           values ascending by index (nullable: pattern only).
  *   d_nnz_y / h_nnz_y as for spmspv_run (ECAPACITY when nnz(y) exceeds
- *           y_capacity: then y_bits holds only the first y_capacity rows).
+ *           y_capacity: y_bits still holds every row of y, y_val the
+ *           values of the first y_capacity rows).
  * Flags: X_VAL_IS_INDEX, X_ALL_TRUE, LEFT, SORTED_OUTPUT (implied).  The
  * bitmap is expanded to its index list on the device, the product runs as
- * a device-sized spmspv_run (push, the handle's schedule), and y's ordered
- * list is packed back; the lists use the handle's list scratch.          */
+ * a device-sized spmspv_run (push, the handle's schedule), and the merge
+ * writes y's bitmap from its tiles' bitmaps of touched rows; the index
+ * lists use the handle's list scratch.                                   */
 int spmspv_run_bitvector(spmspv_handle A, int semiring, int flags, const uint32_t* x_bits, const void* x_val,
                          uint32_t* y_bits, void* y_val, int64_t y_capacity, int64_t* d_nnz_y, int64_t* h_nnz_y,
                          void* stream);

@@ -11,8 +11,8 @@
 //            ascending index order.  The multiply itself runs on index lists:
 //            the input bitmap is expanded to its ascending index list (two
 //            kernels: per-tile bit counts, then each tile emits at the sum of
-//            the counts before it) and the ascending output list is packed
-//            back into a bitmap.
+//            the counts before it); the output bitmap is written by the merge
+//            from its tiles' touched-row bitmaps.
 
 #include "device_ops.h"
 
@@ -105,27 +105,6 @@ __global__ __launch_bounds__(kFmtBlock) void k_bits_emit(const uint32_t* bits, i
     if (tile == ntiles - 1 && threadIdx.x == 0) *count = base + tile_total;
 }
 
-// One thread per list entry; the first entry of each word packs the word's
-// entries (consecutive in the ascending list) and stores it.  Words without
-// entries were cleared before.
-__global__ void k_list_to_bits(const int32_t* idx, const int64_t* nnz_p, int64_t cap, int32_t m, uint32_t* bits) {
-    int64_t nnz = *nnz_p;
-    if (nnz > cap) nnz = cap;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = idx[p];
-        if (i < 0 || i >= m) continue;
-        const int32_t w = i >> 5;
-        if (p > 0 && (idx[p - 1] >> 5) == w) continue;
-        uint32_t word = 0u;
-        for (int64_t q = p; q < nnz && q < p + 32; ++q) {
-            const int32_t r = idx[q];
-            if ((r >> 5) != w) break;
-            word |= 1u << (r & 31);
-        }
-        bits[w] = word;
-    }
-}
-
 inline int grid_of(int64_t count, int block) {
     int64_t g = (count + block - 1) / block;
     if (g < 1) g = 1;
@@ -160,14 +139,6 @@ hipError_t launch_bits_to_list(const uint32_t* bits, int32_t n, int32_t* out, in
     hipLaunchKernelGGL(k_bits_count, dim3((unsigned)nt), dim3(kFmtBlock), 0, s, bits, n, tile_counts, ctrl);
     hipLaunchKernelGGL(k_bits_emit, dim3((unsigned)nt), dim3(kFmtBlock), 0, s, bits, n, tile_counts, (int32_t)nt, out,
                        count);
-    return hipGetLastError();
-}
-
-hipError_t launch_list_to_bits(const int32_t* idx, const int64_t* nnz, int64_t cap, int32_t m, uint32_t* bits,
-                               hipStream_t s) {
-    const hipError_t e = launch_fill_u32(bits, 0u, ((int64_t)m + 31) / 32, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_list_to_bits, dim3(grid_of(m, 256)), dim3(256), 0, s, idx, nnz, cap, m, bits);
     return hipGetLastError();
 }
 

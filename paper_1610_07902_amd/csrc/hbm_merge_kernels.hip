@@ -72,6 +72,7 @@ __global__ __launch_bounds__(kHBlock) void k_hmerge_out(MergeArgs a) {
     for (int i = 0; i < kHWords; ++i) {
         bits[i] = w0 + i < nwords ? a.h_touched[w0 + i] : 0u;
         cnt += __popc(bits[i]);
+        if (!BFS && a.y_bits && w0 + i < nwords) a.y_bits[w0 + i] = bits[i];
     }
     int tile_total;
     const int pre = block_exclusive_i32<kHBlock>(cnt, s_tmp, tile_total);

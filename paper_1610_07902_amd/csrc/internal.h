@@ -202,6 +202,9 @@ struct MergeArgs {
     uint32_t* h_orbits;
     uint32_t* h_touched;
     int32_t h_split;         // workgroups per bucket in the accumulation
+    // bitvector output (single calls, not BFS or batched): every word of y's
+    // bitmap is written from the tiles' touched-row bitmaps; nullable
+    uint32_t* y_bits;
 };
 // Merge variant 1: rows per output tile of the in-order walk.
 constexpr int kHTileRows = 65536;
@@ -491,10 +494,6 @@ hipError_t launch_validate_jc(const int32_t* jc, int32_t nzc, int32_t n, Ctrl* c
 int64_t bits_tiles(int64_t n);
 hipError_t launch_bits_to_list(const uint32_t* bits, int32_t n, int32_t* out, int32_t* count, int32_t* tile_counts,
                                Ctrl* ctrl, hipStream_t s);
-// Ascending list of *nnz (device) distinct indices below m -> bitmap of m
-// bits (every word written); entries past cap are not read.
-hipError_t launch_list_to_bits(const int32_t* idx, const int64_t* nnz, int64_t cap, int32_t m, uint32_t* bits,
-                               hipStream_t s);
 hipError_t launch_decide(Ctrl* ctrl, int32_t n, int64_t nnz, hipStream_t s);
 hipError_t launch_pr_init(int32_t n, const int32_t* colptr, float d, float* rank, int32_t* x_idx, float* x_val,
                           Ctrl* ctrl, hipStream_t s);

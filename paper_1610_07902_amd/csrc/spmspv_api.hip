@@ -415,7 +415,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
             const void* x_val, int32_t* y_idx, void* y_val, int64_t y_cap, int64_t* d_nnz_y, bool bfs,
             const uint32_t* mask, hipStream_t s, hipEvent_t* ev, bool diropt = false, int tile_log2 = -1,
             int phases = 3, int clear_nb = 0, bool learned_gate = false, int mask_keep = 0, bool left = false,
-            int variant = -1) {
+            int variant = -1, uint32_t* y_bits = nullptr) {
     // The operand: A, or for left multiplication A^T through the CSR copy
     // (y' = x'A is y = A^T x; Background, Notation).  The CSR copy's row
     // pointer is A^T's column pointer and A's column pointer is A^T's
@@ -548,6 +548,7 @@ int enqueue(spmspv_matrix* A, int semiring, int xmode, int64_t f_host, const int
     ma.h_orbits = reinterpret_cast<uint32_t*>(A->ws + A->L.h_orbits);
     ma.h_touched = reinterpret_cast<uint32_t*>(A->ws + A->L.h_touched);
     ma.h_split = std::max(1, std::min(1024, 4 * A->num_cu / nb));   // about four workgroups per CU
+    ma.y_bits = bfs ? nullptr : y_bits;
 
     // With profiling, each kernel's own start and end timestamps go to a pair
     // of events (scan, scatter, merge).
@@ -1514,16 +1515,16 @@ int spmspv_run_bitvector(spmspv_handle A, int semiring, int flags, const uint32_
     // (1) x's bitmap -> its ascending index list (the values are already in
     // that order); its length stays on the device
     HIP_TRY(launch_bits_to_list(x_bits, (int32_t)xlen, A->bv_idx, &A->ctrl->bv_f, A->bv_tiles, A->ctrl, s));
-    // (2) the multiply on the lists; y's index list reuses x's storage (the
-    // scan has copied what it needs from x before the merge writes y)
+    // (2) the multiply on the lists, y's bitmap written by the merge from its
+    // tiles' touched-row bitmaps (every word, so no clearing pass); y's index
+    // list goes to x's storage (the scan has copied what it needs from x
+    // before the merge writes y)
     const spmspv_schedule keep = A->sched;
     A->sched.direction = 0;
     const int rc = enqueue(A, semiring, xmode, 0, &A->ctrl->bv_f, A->bv_idx, x_val, A->bv_idx, y_val, y_cap, d_nnz_y,
-                           false, nullptr, s, nullptr, false, -1, 3, 0, false, 0, left);
+                           false, nullptr, s, nullptr, false, -1, 3, 0, false, 0, left, -1, y_bits);
     A->sched = keep;
     if (rc) return rc;
-    // (3) y's ascending index list -> its bitmap
-    HIP_TRY(launch_list_to_bits(A->bv_idx, &A->ctrl->nnz_y, y_cap, (int32_t)ylen, y_bits, s));
     if (h_nnz_y) {
         Ctrl h{};
         const int r = read_ctrl(A, &h, s);

@@ -606,7 +606,15 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         cap = a.rcp[min(row0 + T, a.m)] - a.rcp[row0];
     }
     __syncthreads();
+    // a tile with no entries still writes its (empty) words of y's bitmap
+    auto zero_bits = [&]() {
+        if (!BFS && !BATCH && a.y_bits) {
+            const int zw = (min(T, a.m - row0) + 31) >> 5;
+            for (int w = tid; w < zw; w += BLOCK) a.y_bits[(row0 >> 5) + w] = 0u;
+        }
+    };
     if (W == 0) {
+        zero_bits();
         if (tid == 0) {
             if (BATCH && bt == 0) a.yoff[xb] = 0;
             if (b == a.nb - 1) {
@@ -620,6 +628,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
     }
     const int rows = min(T, a.m - row0);
     if (cnt_raw == 0 && b != a.nb - 1 && (!BATCH || bt != 0)) {
+        zero_bits();
         if (tid == 0) st_release64(&a.lb3[b], (b == 0 ? LB_INC : LB_AGG));
         return;
     }
@@ -733,6 +742,7 @@ __global__ __launch_bounds__(BLOCK) void k_merge(MergeArgs a) {
         const int w = w0 + tid;
         const bool mine = tid < round_words && w < nw;
         const uint32_t bits = mine ? bm[w] : 0u;
+        if (!BFS && !BATCH && a.y_bits && mine) a.y_bits[(row0 >> 5) + w] = bits;
         int tot;
         const int pos = block_exclusive_i32<BLOCK>(__popc(bits), s_tmp, tot);
         if (BFS && bits) visited[(row0 >> 5) + w] |= bits;
