@@ -147,13 +147,19 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
     __shared__ int s_tmp[kDetWaves + 1];
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
-    int cnt = 0;
+    // every row and its predecessor's first, then the comparisons
+    uint32_t rw[kDetItems], pv[kDetItems];
+#pragma unroll
     for (int i = 0; i < kDetItems; ++i) {
         const int64_t e = base + i * kDetBlock + threadIdx.x;
-        if (e < W) {
-            const uint32_t r = list[e].x;
-            if (r < (uint32_t)a.m && (e == 0 || list[e - 1].x != r)) ++cnt;
-        }
+        rw[i] = e < W ? list[e].x : ~0u;
+        pv[i] = (e < W && e > 0) ? list[e - 1].x : ~0u;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kDetItems; ++i) {
+        const int64_t e = base + i * kDetBlock + threadIdx.x;
+        if (e < W && rw[i] < (uint32_t)a.m && (e == 0 || pv[i] != rw[i])) ++cnt;
     }
     int total;
     block_exclusive_i32<kDetBlock>(cnt, s_tmp, total);
@@ -161,71 +167,115 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[a.nblk] = 0;
 }
 
+// The block's kDetTile entries are staged in LDS.  (1) Heads (first entry
+// of each row's run) get their output ordinals from wave ballots and one
+// table of per-round, per-wave head counts; (2) each thread folds its own
+// heads' runs in order from LDS (a run that reaches the block's end goes on
+// from global memory), with no further barrier, so a long run delays only
+// its own thread.  Past kDetShortRun entries after its head a run is handed
+// to k_det_fold_long.
 __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* list) {
-    __shared__ int s_tmp[kDetWaves + 1];
+    __shared__ uint2 s_e[kDetTile];
+    __shared__ uint64_t s_bal[kDetItems][kDetWaves];   // heads of each round, per wave
     __shared__ int s_nlong;
+    __shared__ uint32_t s_prev;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int W = ld_ctrl(&a.ctrl->W);
-    if (threadIdx.x == 0) s_nlong = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         const int64_t total = a.counts[a.nblk];
         __hip_atomic_store(&a.ctrl->nnz_y, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (a.d_nnz_y) *a.d_nnz_y = total;
     }
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     if (base >= W) {
-        if (threadIdx.x == 0) a.long_count[blockIdx.x] = 0;
+        if (tid == 0) a.long_count[blockIdx.x] = 0;
         return;
     }
-    // (1) every head's output position (block scans round by round), then
-    // (2) each thread folds its own heads with no further barrier, so a
-    // long run delays only its own thread
-    int64_t run = a.counts[blockIdx.x];
-    uint32_t heads = 0;             // bit r: item r of this thread is a head
-    int32_t pos[kDetItems];
+    const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);
 #pragma unroll
     for (int r = 0; r < kDetItems; ++r) {
-        const int64_t e = base + r * kDetBlock + threadIdx.x;
-        bool head = false;
-        if (e < W) {
-            const uint32_t row = list[e].x;
-            head = row < (uint32_t)a.m && (e == 0 || list[e - 1].x != row);
-        }
-        int tot;
-        const int pre = block_exclusive_i32<kDetBlock>(head ? 1 : 0, s_tmp, tot);
-        pos[r] = (int32_t)(run + pre);
-        heads |= head ? (1u << r) : 0u;
-        run += tot;
+        const int i = r * kDetBlock + tid;
+        if (i < n_in) s_e[i] = list[base + i];
     }
+    if (tid == 0) {
+        s_nlong = 0;
+        s_prev = base > 0 ? list[base - 1].x : ~0u;
+    }
+    __syncthreads();
+    // (1) item r of thread t is entry r * kDetBlock + t
+    uint32_t heads = 0;   // bit r: item r is a head
 #pragma unroll
     for (int r = 0; r < kDetItems; ++r) {
+        const int i = r * kDetBlock + tid;
+        bool head = false;
+        if (i < n_in) {
+            const uint32_t row = s_e[i].x;
+            const uint32_t prev = i == 0 ? s_prev : s_e[i - 1].x;
+            head = row < (uint32_t)a.m && (base + i == 0 || prev != row);
+        }
+        const uint64_t bal = __ballot(head);
+        if (lane == 0) s_bal[r][wave] = bal;
+        heads |= head ? (1u << r) : 0u;
+    }
+    __syncthreads();
+    // (2) folds, one add at a time in entry order; a head's ordinal is the
+    // heads of earlier rounds, of lower waves in its round and of lower lanes
+    // in its wave
+    int64_t run = a.counts[blockIdx.x];
+    const uint64_t lower = (1ull << lane) - 1ull;
+#pragma unroll 1
+    for (int r = 0; r < kDetItems; ++r) {
+        int64_t p = run;
+        for (int w = 0; w < kDetWaves; ++w) {
+            const uint64_t bw = s_bal[r][w];
+            run += __popcll(bw);
+            if (w < wave) p += __popcll(bw);
+            else if (w == wave) p += __popcll(bw & lower);
+        }
         if (!((heads >> r) & 1u)) continue;
-        const int64_t e = base + r * kDetBlock + threadIdx.x;
-        const uint32_t row = list[e].x;
-        // the run folds one add at a time; its entries are loaded sixteen
-        // at a time so the loads overlap (the adds stay in order).  Past
-        // kDetShortRun entries the run goes on in the wave-wide fold.
-        float acc = __uint_as_float(list[e].y);
+        const int i = r * kDetBlock + tid;
+        const uint32_t row = s_e[i].x;
+        float acc = __uint_as_float(s_e[i].y);
         bool more = true;
-        int64_t k = e + 1;
-        for (; more && k < W && k < e + kDetShortRun; k += 16) {
-            uint2 v[16];
+        const int64_t qlim = base + i + kDetShortRun + 1;   // the short fold's end
+        const int64_t qend = min((int64_t)W, qlim);
+        const int64_t lend = min(qend, base + n_in);
+        int64_t q = base + i + 1;
+        for (; more && q < lend; q += 8) {   // from LDS, eight reads ahead of the adds
+            uint2 v[8];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = k + u < W ? list[k + u] : make_uint2(~0u, 0u);
+            for (int u = 0; u < 8; ++u) v[u] = q + u < lend ? s_e[q + u - base] : make_uint2(~0u, 0u);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                more = more && v[u].x == row;
-                if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
+            for (int u = 0; u < 8; ++u) {
+                if (q + u < lend) {
+                    more = more && v[u].x == row;
+                    if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
+                }
             }
         }
-        const int64_t p = pos[r];
-        if (more && k < W && list[k].x == row) {
-            // a long run: more than kDetShortRun + 1 entries (the loop above
-            // folded kDetShortRun after the head), so runs starting in one
+        if (more) q = lend;
+        for (; more && q < qend; q += 8) {   // past the block: from global memory
+            uint2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = q + u < qend ? list[q + u] : make_uint2(~0u, 0u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (q + u < qend) {
+                    more = more && v[u].x == row;
+                    if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
+                }
+            }
+        }
+        if (more) q = qend;
+        const bool longrun = more && q == qlim && q < W &&
+                             (q - base < n_in ? s_e[q - base].x : list[q].x) == row;
+        if (longrun) {
+            // more than kDetShortRun + 1 entries, so runs starting in one
             // block are that far apart and at most kDetLongPerBlock start here
             const int slot = atomicAdd(&s_nlong, 1);
             if (slot < kDetLongPerBlock)
                 a.long_runs[(int64_t)blockIdx.x * kDetLongPerBlock + slot] =
-                    make_int4((int)row, (int)__float_as_uint(acc), (int)k, (int)p);
+                    make_int4((int)row, (int)__float_as_uint(acc), (int)q, (int)p);
             else
                 atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
         } else if (p < a.y_cap) {
@@ -234,7 +284,7 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
+    if (tid == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
 }
 
 // One wave per long run.  The wave keeps kLongDepth steps of 64 consecutive
