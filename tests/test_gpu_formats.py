@@ -383,6 +383,16 @@ def test_bitvector_ragged_left_dcsc_and_errors(spv):
     with pytest.raises(spv.SpmspvError) as e:
         run_bv(spv, M, 0, oracle.to_bitvector(S2, None, A.n)[0], xv2, A.m, cap=oi.size - 1)
     assert e.value.status == spv.ECAPACITY
+    # with too small a capacity the bitmap still holds every row of y and the
+    # values the first capacity rows
+    cap = oi.size // 2
+    y_bits = torch.full(((A.m + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+    y_val = torch.empty(cap, dtype=torch.float32, device="cuda")
+    xb = dev(oracle.to_bitvector(S2, None, A.n)[0].view(np.int32))
+    spv.spmspv_run_bitvector(M.handle, 0, 0, xb, dev(xv2), y_bits, y_val, cap, sync=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(y_bits).view(np.uint32), oracle.to_bitvector(oi, None, A.m)[0])
+    compare(0, torch.as_tensor(oi[:cap]), y_val, oi[:cap], ov[:cap], sorted_output=True)
     gb, gv, nnz = run_bv(spv, M, 0, oracle.to_bitvector(S2, None, A.n)[0], xv2, A.m, cap=oi.size)
     assert nnz == oi.size and np.array_equal(gb, oracle.to_bitvector(oi, None, A.m)[0])
     M.close()
