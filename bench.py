@@ -918,6 +918,10 @@ def selector_eval(spv, dev, scale=24, nroots=16, reps=2):
     out["default_over_hindsight"] = round(out["default_push_ms"] / out["hindsight_strict_ms"], 3)
     log(f"selector eval hindsight strict {out['hindsight_strict_ms']} ms, single class "
         f"{out['hindsight_single_class']} {out['hindsight_single_ms']} ms, choice regret {out['learned_choice_regret']}")
+    # PageRank's steps are standalone plus-times multiplies: the network
+    # trained on those
+    mparams, mmean, mstd, _ = selector.load_weights(kind="multiply")
+    P.load_selector(mparams, mmean, mstd)
     for name, fl in (("pagerank_default", 0), ("pagerank_learned", spv.USE_SELECTOR),
                      ("pagerank_learned_on_device", spv.USE_SELECTOR | spv.USE_GRAPH)):
         P.pagerank(0.85, 1e-6, 100, flags=fl)

@@ -70,6 +70,19 @@ class Samples:
         self.times += other.times
         self.tags += other.tags
 
+    def subset(self, keep) -> "Samples":
+        out = Samples()
+        for r, t, g, k in zip(self.raw, self.times, self.tags, keep):
+            if k:
+                out.add(r, t, g)
+        return out
+
+    @property
+    def bfs_steps(self) -> np.ndarray:
+        """Samples taken inside a BFS: fewer unvisited vertices than n."""
+        X = self.X
+        return X[:, 5] < X[:, 3]
+
     @property
     def X(self) -> np.ndarray:
         return np.array(self.raw).reshape(-1, IN)
@@ -205,12 +218,40 @@ def labels(T: np.ndarray, tie: float = 0.03) -> np.ndarray:
     return score.argmax(1).astype(np.int32)
 
 
-def train(samples: Samples, epochs: int = 300, lr: float = 1e-3, batch: int = 128, seed: int = 0):
-    """Adam on softmax cross-entropy towards the fastest class, on the GPU.
-    Returns (params, mean, std, loss history)."""
+# Scale augmentation of BFS steps: every sample taken inside a BFS (fewer
+# unvisited vertices than n) also enters with its size features (f, W,
+# longest column, n, unvisited) multiplied by these factors and nnz/n kept,
+# with the same timings.  A BFS step's direction choice depends on ratios of
+# these quantities (frontier edges against unexplored edges; the pull step
+# probes only a bitmap of the frontier), so the copies carry the training
+# graphs' decisions to graphs several times larger than any of them, where
+# the network would otherwise extrapolate.  Standalone multiplies are not
+# copied: a plus-times pull step reads a dense value array of n entries,
+# which stops fitting in cache as n grows, so their choice does not carry
+# over to larger graphs.
+AUGMENT_SCALES = (2.0, 4.0)
+SIZE_FEATURES = np.array([1.0, 1.0, 1.0, 1.0, 0.0, 1.0])
+
+
+def augmented(raw: np.ndarray, times: np.ndarray, scales=AUGMENT_SCALES):
+    """The samples and the scaled copies of the BFS-step samples (raw
+    features, times)."""
+    bfs = raw[:, 5] < raw[:, 3]
+    Xs, Ts = [raw], [times]
+    for sc in scales:
+        Xs.append(raw[bfs] * np.where(SIZE_FEATURES > 0, sc, 1.0)[None, :])
+        Ts.append(times[bfs])
+    return np.concatenate(Xs), np.concatenate(Ts)
+
+
+def train(samples: Samples, epochs: int = 300, lr: float = 1e-3, batch: int = 128, seed: int = 0,
+          scales=AUGMENT_SCALES):
+    """Adam on softmax cross-entropy towards the fastest class, on the GPU,
+    over the samples and their scaled copies.  Returns (params, mean, std,
+    loss history)."""
     import torch
-    X = encode(samples.X)
-    T = samples.T
+    raw, T = augmented(samples.X, samples.T, scales)
+    X = encode(raw)
     y = labels(T)
     mean = X.mean(0)
     std = X.std(0)
@@ -257,16 +298,30 @@ def regret(times: np.ndarray, choice: np.ndarray) -> float:
     return float(times[np.arange(times.shape[0]), choice].sum() / best.sum())
 
 
-def save_weights(params, mean, std, meta: Optional[dict] = None, path: str = WEIGHTS_PATH):
+def save_weights(params, mean, std, meta: Optional[dict] = None, path: str = WEIGHTS_PATH, multiply=None):
+    """The BFS-step network at the top level; `multiply` = (params, mean,
+    std) of the network for standalone multiplies (PageRank's steps)."""
     meta = dict(meta or {})
     meta["kernel_digest"] = kernel_digest()
+    d = {"params": [float(v) for v in params], "mean": [float(v) for v in mean],
+         "std": [float(v) for v in std], "meta": meta}
+    if multiply is not None:
+        mp, mm, ms = multiply
+        d["multiply"] = {"params": [float(v) for v in mp], "mean": [float(v) for v in mm],
+                         "std": [float(v) for v in ms]}
     with open(path, "w") as fh:
-        json.dump({"params": [float(v) for v in params], "mean": [float(v) for v in mean],
-                   "std": [float(v) for v in std], "meta": meta}, fh)
+        json.dump(d, fh)
 
 
-def load_weights(path: str = WEIGHTS_PATH):
+def load_weights(path: str = WEIGHTS_PATH, kind: str = "bfs"):
+    """(params, mean, std, meta) of the BFS-step network (kind "bfs") or of
+    the standalone-multiply network (kind "multiply"; the BFS one when the
+    file has no second network).  The same six inputs and ten classes: a BFS
+    step is a masked multiply whose pull step stops at the first frontier
+    neighbour, a standalone plus-times multiply reads every stored entry in
+    the pull direction, and the inputs cannot tell the two apart."""
     with open(path) as fh:
         d = json.load(fh)
-    return (np.array(d["params"], np.float32), np.array(d["mean"], np.float32), np.array(d["std"], np.float32),
-            d.get("meta", {}))
+    net = d["multiply"] if kind == "multiply" and "multiply" in d else d
+    return (np.array(net["params"], np.float32), np.array(net["mean"], np.float32),
+            np.array(net["std"], np.float32), d.get("meta", {}))

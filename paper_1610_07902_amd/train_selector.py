@@ -10,8 +10,10 @@ sizes where it loses to push).  Samples: every BFS level from a few seeded
 roots (min-select2nd, as a BFS step runs it: frontier expanded with the
 visited vertices masked) plus standalone multiplies across densities for
 plus-times and min-select2nd.  Each sample times all ten classes; the label
-is the fastest.  The network is trained by spmspv_mlp_train_step and the
-weights are written as JSON next to this file.
+is the fastest.  Two networks of the same shape are trained by
+spmspv_mlp_train_step, one on the BFS steps (for bfs_run) and one on the
+standalone multiplies (for pagerank_run), and written as JSON next to this
+file.
 """
 from __future__ import annotations
 
@@ -85,18 +87,28 @@ def main():
     samples = collect(args.quick, args.roots)
     if args.samples:
         samples.save(args.samples)
-    params, mean, std, hist = selector.train(samples, epochs=args.epochs)
-    T = samples.T
-    pred = selector.predict(params, mean, std, samples.X)
+    # one network for BFS steps (with scale-augmented copies), one for
+    # standalone multiplies
+    bfs = samples.subset(samples.bfs_steps)
+    mul = samples.subset(~samples.bfs_steps)
+    params, mean, std, hist = selector.train(bfs, epochs=args.epochs)
+    mp, mm, ms, mhist = selector.train(mul, epochs=args.epochs, scales=())
     import torch
     props = torch.cuda.get_device_properties(0)
+    Tb, Tm = bfs.T, mul.T
+    pb = selector.predict(params, mean, std, bfs.X)
+    pm = selector.predict(mp, mm, ms, mul.X)
     meta = {"device": props.name, "arch": getattr(props, "gcnArchName", ""),
-            "samples": len(samples.raw), "epochs": args.epochs, "final_loss": hist[-1],
-            "train_accuracy": float((pred == T.argmin(1)).mean()),
-            "train_regret": selector.regret(T, pred),
-            "label_histogram": np.bincount(T.argmin(1), minlength=10).tolist(),
+            "samples": len(samples.raw), "bfs_samples": len(bfs.raw), "multiply_samples": len(mul.raw),
+            "epochs": args.epochs, "final_loss": hist[-1], "multiply_final_loss": mhist[-1],
+            "train_accuracy": float((pb == Tb.argmin(1)).mean()),
+            "train_regret": selector.regret(Tb, pb),
+            "multiply_train_accuracy": float((pm == Tm.argmin(1)).mean()),
+            "multiply_train_regret": selector.regret(Tm, pm),
+            "label_histogram": np.bincount(Tb.argmin(1), minlength=10).tolist(),
+            "multiply_label_histogram": np.bincount(Tm.argmin(1), minlength=10).tolist(),
             "seconds": round(time.time() - t0, 1), "quick": args.quick}
-    selector.save_weights(params, mean, std, meta, args.out)
+    selector.save_weights(params, mean, std, meta, args.out, multiply=(mp, mm, ms))
     print(json.dumps(meta))
 
 

@@ -65,7 +65,12 @@ def test_committed_weights_file_is_well_formed():
     assert np.all(np.isfinite(params)) and np.all(std > 0)
     assert meta.get("samples", 0) > 0 and not meta.get("quick", True)
     with open(sel.WEIGHTS_PATH) as fh:
-        assert set(json.load(fh)) == {"params", "mean", "std", "meta"}
+        d = json.load(fh)
+    assert set(d) == {"params", "mean", "std", "meta", "multiply"}
+    mp, mm, ms, _ = sel.load_weights(kind="multiply")
+    assert mp.shape == (5258,) and mm.shape == (6,) and ms.shape == (6,)
+    assert np.all(np.isfinite(mp)) and np.all(ms > 0)
+    assert meta.get("bfs_samples", 0) > 0 and meta.get("multiply_samples", 0) > 0
 
 
 def test_init_params_layout():
@@ -91,3 +96,21 @@ def test_weights_are_tied_to_the_kernel_sources(tmp_path):
     out = tmp_path / "w.json"
     sel.save_weights(p, m, s, {"samples": 1}, str(out))
     assert sel.load_weights(str(out))[3]["kernel_digest"] == sel.kernel_digest()
+
+
+def test_scale_augmentation_copies():
+    """Training copies of BFS steps (unvisited < n): size features scaled,
+    nnz/n kept, timings repeated; standalone multiplies are not copied."""
+    from paper_1610_07902_amd import selector
+    raw = np.array([[10.0, 300.0, 40.0, 1000.0, 8.0, 900.0],     # a BFS step
+                    [1.0, 2.0, 2.0, 50.0, 3.0, 50.0],            # a standalone multiply
+                    [5.0, 90.0, 30.0, 400.0, 6.0, 399.0]])       # a BFS step
+    times = np.arange(30, dtype=np.float64).reshape(3, 10)
+    X, T = selector.augmented(raw, times, scales=(2.0, 4.0))
+    assert X.shape == (7, 6) and T.shape == (7, 10)
+    assert np.array_equal(X[:3], raw) and np.array_equal(T[:3], times)
+    b = raw[[0, 2]]
+    assert np.array_equal(X[3:5, [0, 1, 2, 3, 5]], 2.0 * b[:, [0, 1, 2, 3, 5]])
+    assert np.array_equal(X[5:7, [0, 1, 2, 3, 5]], 4.0 * b[:, [0, 1, 2, 3, 5]])
+    assert np.array_equal(X[3:, 4], np.tile(b[:, 4], 2))
+    assert np.array_equal(T[3:], np.tile(times[[0, 2]], (2, 1)))
