@@ -389,6 +389,15 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             if constexpr (MODE != SC_SINGLE) s_xid[k] = a.cxid[p0 + k];
         }
         __syncthreads();
+        // Keys this chunk can touch: every bucket of a single call; in a
+        // batch, the buckets of the vectors its columns belong to (columns
+        // are in vector order), so the per-key loops below skip the other
+        // vectors' keys.
+        int klo = 0, khi = nb;
+        if constexpr (MODE != SC_SINGLE) {
+            klo = s_xid[0] * a.nbx;
+            khi = min(nb, (s_xid[ncols - 1] + 1) * a.nbx);
+        }
 
         // (1) gather + rank.  Column map: each thread finds the column of
         // its ITEMS consecutive products (one binary search, then a forward
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         __syncthreads();
         if constexpr (MODE == SC_COUNT) {
             // Algorithm 2's per-bucket counts, accumulated over workgroups.
-            for (int b = tid; b < nb; b += BLOCK) {
+            for (int b = klo + tid; b < khi; b += BLOCK) {
                 const int n = hist[b];
                 if (n) {
                     atomicAdd(&a.kcount[b], n);
@@ -500,12 +509,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
             __syncthreads();
         } else {
             int carry = 0;
-            for (int b0 = 0; b0 < nb; b0 += BLOCK) {
+            for (int b0 = klo; b0 < khi; b0 += BLOCK) {
                 const int b = b0 + tid;
-                const int n = b < nb ? hist[b] : 0;
+                const int n = b < khi ? hist[b] : 0;
                 int tot;
                 const int e = block_exclusive_i32<BLOCK>(n, s_tmp, tot);
-                if (b < nb) {
+                if (b < khi) {
                     loff[b] = carry + e;
                     if (n > 0) {
                         int base, cap;
