@@ -29,7 +29,7 @@ constexpr int kMaxDigits = 1 << kDetMaxDigitBits;
 constexpr int kDetWaves = kDetBlock / kWave;
 
 __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* list) {
-    extern __shared__ int32_t s_off[];   // coff of the chunk's columns (chunk + 2 entries at most)
+    extern __shared__ int32_t s_off[];   // the chunk's column table, 3 x (chunk + 2) words
     const int W = ld_ctrl(&a.ctrl->W);
     const int fnz = ld_ctrl(&a.ctrl->fnz);
     // The per-call bookkeeping the bucket scatter does on the other paths:
@@ -56,22 +56,56 @@ __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* l
     const int c_lo = a.chunk_col[blockIdx.x];
     const int c_hi = w1 < W ? a.chunk_col[blockIdx.x + 1] : fnz - 1;
     const int ncol = c_hi - c_lo + 1;
-    for (int i = threadIdx.x; i <= ncol; i += kGatherBlock) s_off[i] = a.coff[c_lo + i];
-    __syncthreads();
-    for (int64_t w = w0 + threadIdx.x; w < w1; w += kGatherBlock) {
-        int lo = 0, hi = ncol - 1;   // the last column starting at or before w
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= w) lo = mid;
-            else hi = mid - 1;
+    // the chunk's column table in LDS: product offsets, first entries, x values
+    const int cap = (int)chunk + 2;
+    int32_t* s_st = s_off + cap;
+    uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_st + cap);
+    for (int i = threadIdx.x; i <= ncol; i += kGatherBlock) {
+        s_off[i] = a.coff[c_lo + i];
+        if (i < ncol) {
+            s_st[i] = a.cstart[c_lo + i];
+            s_xv[i] = a.cxv[c_lo + i];
         }
-        const int c = c_lo + lo;
-        const int64_t q = (int64_t)a.cstart[c] + (w - s_off[lo]);
-        int32_t row = a.rowids[q];
-        const float av = a.values ? a.values[q] : 1.0f;
-        const float t = __fmul_rn(av, __uint_as_float(a.cxv[c]));
-        if (a.mask && ((a.mask[row >> 5] >> (row & 31)) & 1u) != (uint32_t)a.mask_keep) row = a.m;
-        list[w] = make_uint2((uint32_t)row, __float_as_uint(t));
+    }
+    __syncthreads();
+    // products eight per thread at a time: every load unconditional (indices
+    // clamped to the chunk's first product), so they are in flight together
+    constexpr int B8 = 8;
+    const int64_t first = (int64_t)s_st[0] + (w0 - s_off[0]);
+    for (int64_t wb = w0 + threadIdx.x; wb < w1; wb += (int64_t)B8 * kGatherBlock) {
+        int64_t q[B8];
+        uint32_t xv[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int64_t w = wb + (int64_t)u * kGatherBlock;
+            int lo = 0, hi = ncol - 1;   // the last column starting at or before w
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            q[u] = w < w1 ? (int64_t)s_st[lo] + (w - s_off[lo]) : first;
+            xv[u] = s_xv[lo];
+        }
+        int32_t row[B8];
+        float av[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) row[u] = a.rowids[q[u]];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) av[u] = a.values ? a.values[q[u]] : 1.0f;
+        uint32_t mw[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) mw[u] = a.mask ? a.mask[row[u] >> 5] : 0u;
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int64_t w = wb + (int64_t)u * kGatherBlock;
+            if (w < w1) {
+                int32_t r = row[u];
+                const float t = __fmul_rn(av[u], __uint_as_float(xv[u]));
+                if (a.mask && ((mw[u] >> (r & 31)) & 1u) != (uint32_t)a.mask_keep) r = a.m;
+                list[w] = make_uint2((uint32_t)r, __float_as_uint(t));
+            }
+        }
     }
 }
 
@@ -82,10 +116,16 @@ __global__ __launch_bounds__(kDetBlock) void k_det_hist(DetArgs a, const uint2* 
     __syncthreads();
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
-#pragma unroll 4
+    const int64_t last = W > 0 ? W - 1 : 0;
+    // every key loaded first (clamped indices, no branch around a load), so
+    // the loads overlap; then the counts
+    uint32_t key[kDetItems];
+#pragma unroll
+    for (int i = 0; i < kDetItems; ++i) key[i] = in[min(base + i * kDetBlock + threadIdx.x, last)].x;
+#pragma unroll
     for (int i = 0; i < kDetItems; ++i) {
         const int64_t e = base + i * kDetBlock + threadIdx.x;
-        if (e < W) atomicAdd(&h[(in[e].x >> shift) & (uint32_t)(nd - 1)], 1);
+        if (e < W) atomicAdd(&h[(key[i] >> shift) & (uint32_t)(nd - 1)], 1);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < nd; d += kDetBlock) a.counts[(int64_t)d * a.nblk + blockIdx.x] = h[d];
@@ -107,15 +147,18 @@ __global__ __launch_bounds__(kDetBlock) void k_det_scatter(DetArgs a, const uint
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint64_t below = (1ull << lane) - 1ull;
+    // the block's entries into registers first (clamped indices), so the
+    // rounds below wait for no memory
+    const int64_t last = W - 1;
+    uint2 its[kDetItems];
+#pragma unroll
+    for (int r = 0; r < kDetItems; ++r) its[r] = in[min(base + r * kDetBlock + threadIdx.x, last)];
+#pragma unroll
     for (int r = 0; r < kDetItems; ++r) {
         const int64_t e = base + r * kDetBlock + threadIdx.x;
         const bool valid = e < W;
-        uint2 it = make_uint2(0u, 0u);
-        int d = 0;
-        if (valid) {
-            it = in[e];
-            d = (int)((it.x >> shift) & (uint32_t)(nd - 1));
-        }
+        const uint2 it = its[r];
+        const int d = valid ? (int)((it.x >> shift) & (uint32_t)(nd - 1)) : 0;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
         for (int bit = 0; bit < dbits; ++bit) {
@@ -148,12 +191,14 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     // every row and its predecessor's first, then the comparisons
+    // unconditional loads (clamped indices), all in flight together
     uint32_t rw[kDetItems], pv[kDetItems];
+    const int64_t last = W > 0 ? W - 1 : 0;
 #pragma unroll
     for (int i = 0; i < kDetItems; ++i) {
         const int64_t e = base + i * kDetBlock + threadIdx.x;
-        rw[i] = e < W ? list[e].x : ~0u;
-        pv[i] = (e < W && e > 0) ? list[e - 1].x : ~0u;
+        rw[i] = list[min(e, last)].x;
+        pv[i] = list[max(min(e, last) - 1, (int64_t)0)].x;
     }
     int cnt = 0;
 #pragma unroll
@@ -167,17 +212,28 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[a.nblk] = 0;
 }
 
-// The block's kDetTile entries are staged in LDS.  (1) Heads (first entry
-// of each row's run) get their output ordinals from wave ballots and one
-// table of per-round, per-wave head counts; (2) each thread folds its own
-// heads' runs in order from LDS (a run that reaches the block's end goes on
-// from global memory), with no further barrier, so a long run delays only
-// its own thread.  Past kDetShortRun entries after its head a run is handed
-// to k_det_fold_long.
+// The block's kDetTile entries are staged in LDS with the kDetShortRun + 1
+// entries after them (a short fold never reads further).  (1) Row boundaries
+// are found with wave ballots; the heads (boundaries of real rows inside the
+// block) are compacted, in entry order, into a list of positions, and the
+// first other boundary (in the halo, or where the masked rows begin) ends the
+// block's last run.  (2) Thread t folds heads t, t + kDetBlock, ...: a run
+// ends where the next head starts, so its adds need no row comparisons, and
+// consecutive heads -- ordinals, so outputs -- sit in consecutive lanes.
+// Past kDetShortRun + 1 entries a run is handed to k_det_fold_long.  (Giving
+// each thread the heads among its own items left the wave waiting on the
+// lane that held most of them: heads evenly spaced by a power of two all
+// fall on one thread.)
 __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* list) {
-    __shared__ uint2 s_e[kDetTile];
-    __shared__ uint64_t s_bal[kDetItems][kDetWaves];   // heads of each round, per wave
-    __shared__ int s_nlong;
+    constexpr int kStage = kDetTile + kDetShortRun + 1;
+    constexpr int kCells = kDetItems * kDetWaves;   // (round, wave) ballots
+    static_assert(kCells == kWave, "one lane per ballot in the head-count scan");
+    static_assert(kDetTile <= 65536, "head positions are 16-bit");
+    __shared__ uint2 s_e[kStage];
+    __shared__ uint16_t s_head[kDetTile];
+    __shared__ uint64_t s_bal[kCells];   // heads of round r, wave w at r * kDetWaves + w
+    __shared__ int s_pre[kCells + 1];    // heads before each ballot, in entry order
+    __shared__ int s_nlong, s_stop;
     __shared__ uint32_t s_prev;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int W = ld_ctrl(&a.ctrl->W);
@@ -191,95 +247,106 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
         if (tid == 0) a.long_count[blockIdx.x] = 0;
         return;
     }
-    const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);
+    const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
+    const int n_st = (int)min((int64_t)kStage, (int64_t)W - base);     // with the halo
+    constexpr int kRounds = (kStage + kDetBlock - 1) / kDetBlock;
+    {
+        // every load unconditional (index clamped into range), so all are in
+        // flight before the first wait; a guarded load compiles to a branch
+        // that waits for its load before the next one is issued
+        uint2 t[kRounds];
 #pragma unroll
-    for (int r = 0; r < kDetItems; ++r) {
-        const int i = r * kDetBlock + tid;
-        if (i < n_in) s_e[i] = list[base + i];
+        for (int r = 0; r < kRounds; ++r) t[r] = list[base + min(r * kDetBlock + tid, n_st - 1)];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const int i = r * kDetBlock + tid;
+            if (i < n_st) s_e[i] = t[r];
+        }
     }
     if (tid == 0) {
         s_nlong = 0;
+        s_stop = n_st;
         s_prev = base > 0 ? list[base - 1].x : ~0u;
     }
     __syncthreads();
-    // (1) item r of thread t is entry r * kDetBlock + t
+    // (1) item r of thread t is entry r * kDetBlock + t; the rounds past
+    // kDetItems cover the halo, where only the first boundary matters
+    const uint64_t lower = (1ull << lane) - 1ull;
     uint32_t heads = 0;   // bit r: item r is a head
+    int stop = n_st;
 #pragma unroll
-    for (int r = 0; r < kDetItems; ++r) {
+    for (int r = 0; r < kRounds; ++r) {
         const int i = r * kDetBlock + tid;
-        bool head = false;
-        if (i < n_in) {
-            const uint32_t row = s_e[i].x;
-            const uint32_t prev = i == 0 ? s_prev : s_e[i - 1].x;
-            head = row < (uint32_t)a.m && (base + i == 0 || prev != row);
+        const int ic = min(i, n_st - 1);
+        const uint32_t row = s_e[ic].x;
+        const uint32_t prev = s_e[max(ic - 1, 0)].x;
+        const bool bound = i < n_st && (i == 0 ? base == 0 || s_prev != row : prev != row);
+        const bool head = bound && i < n_in && row < (uint32_t)a.m;
+        if (bound && !head) stop = min(stop, i);
+        if (r < kDetItems) {
+            const uint64_t bal = __ballot(head);
+            if (lane == 0) s_bal[r * kDetWaves + wave] = bal;
+            heads |= head ? (1u << r) : 0u;
         }
-        const uint64_t bal = __ballot(head);
-        if (lane == 0) s_bal[r][wave] = bal;
-        heads |= head ? (1u << r) : 0u;
+    }
+    if (stop < n_st) atomicMin(&s_stop, stop);
+    __syncthreads();
+    if (wave == 0) {
+        // exclusive scan of the 64 ballots' head counts, (round, wave) order
+        const int c = __popcll(s_bal[lane]);
+        int v = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int u = __shfl_up(v, d);
+            if (lane >= d) v += u;
+        }
+        s_pre[lane] = v - c;
+        if (lane == kWave - 1) s_pre[kCells] = v;
     }
     __syncthreads();
-    // (2) folds, one add at a time in entry order; a head's ordinal is the
-    // heads of earlier rounds, of lower waves in its round and of lower lanes
-    // in its wave
-    int64_t run = a.counts[blockIdx.x];
-    const uint64_t lower = (1ull << lane) - 1ull;
-#pragma unroll 1
+#pragma unroll
     for (int r = 0; r < kDetItems; ++r) {
-        int64_t p = run;
-        for (int w = 0; w < kDetWaves; ++w) {
-            const uint64_t bw = s_bal[r][w];
-            run += __popcll(bw);
-            if (w < wave) p += __popcll(bw);
-            else if (w == wave) p += __popcll(bw & lower);
+        if ((heads >> r) & 1u) {
+            const int cell = r * kDetWaves + wave;
+            s_head[s_pre[cell] + __popcll(s_bal[cell] & lower)] = (uint16_t)(r * kDetBlock + tid);
         }
-        if (!((heads >> r) & 1u)) continue;
-        const int i = r * kDetBlock + tid;
-        const uint32_t row = s_e[i].x;
-        float acc = __uint_as_float(s_e[i].y);
-        bool more = true;
-        const int64_t qlim = base + i + kDetShortRun + 1;   // the short fold's end
-        const int64_t qend = min((int64_t)W, qlim);
-        const int64_t lend = min(qend, base + n_in);
-        int64_t q = base + i + 1;
-        for (; more && q < lend; q += 8) {   // from LDS, eight reads ahead of the adds
-            uint2 v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = q + u < lend ? s_e[q + u - base] : make_uint2(~0u, 0u);
+    }
+    __syncthreads();
+    // (2) folds, one add at a time in entry order
+    const int H = s_pre[kCells];
+    const int last_end = s_stop;
+    const int64_t run0 = a.counts[blockIdx.x];
+    for (int j = tid; j < H; j += kDetBlock) {
+        const int i = s_head[j];
+        const int nxt = s_head[min(j + 1, H - 1)];
+        const int end = j + 1 < H ? nxt : last_end;   // the run is entries [i, end)
+        const uint2 e0 = s_e[i];
+        float acc = __uint_as_float(e0.y);
+        const int last = i + min(end - i, kDetShortRun + 1) - 1;   // the last entry folded here
+        for (int q = i + 1; q <= last; q += 8) {
+            // eight reads ahead of the adds; past the run the pad is -0, which
+            // leaves every sum (either zero included) unchanged
+            float v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                if (q + u < lend) {
-                    more = more && v[u].x == row;
-                    if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
-                }
+                const uint32_t bits = s_e[min(q + u, last)].y;
+                v[u] = q + u <= last ? __uint_as_float(bits) : -0.0f;
             }
-        }
-        if (more) q = lend;
-        for (; more && q < qend; q += 8) {   // past the block: from global memory
-            uint2 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = q + u < qend ? list[q + u] : make_uint2(~0u, 0u);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (q + u < qend) {
-                    more = more && v[u].x == row;
-                    if (more) acc = __fadd_rn(acc, __uint_as_float(v[u].y));
-                }
-            }
+            for (int u = 0; u < 8; ++u) acc = __fadd_rn(acc, v[u]);
         }
-        if (more) q = qend;
-        const bool longrun = more && q == qlim && q < W &&
-                             (q - base < n_in ? s_e[q - base].x : list[q].x) == row;
-        if (longrun) {
+        const int64_t p = run0 + j;
+        if (end - i > kDetShortRun + 1) {
             // more than kDetShortRun + 1 entries, so runs starting in one
             // block are that far apart and at most kDetLongPerBlock start here
             const int slot = atomicAdd(&s_nlong, 1);
             if (slot < kDetLongPerBlock)
                 a.long_runs[(int64_t)blockIdx.x * kDetLongPerBlock + slot] =
-                    make_int4((int)row, (int)__float_as_uint(acc), (int)q, (int)p);
+                    make_int4((int)e0.x, (int)__float_as_uint(acc), (int)(base + last + 1), (int)p);
             else
                 atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
         } else if (p < a.y_cap) {
-            a.y_idx[p] = (int32_t)row;
+            a.y_idx[p] = (int32_t)e0.x;
             if (a.y_val) a.y_val[p] = acc;
         }
     }
@@ -294,7 +361,7 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
 // (Folding through lane reads cost about 90 cycles per entry, a 16K-entry
 // hub row 0.6 ms; one thread per run with sixteen loads ahead left the
 // memory latency exposed.)
-constexpr int kLongDepth = 4;
+constexpr int kLongDepth = 8;
 
 __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const uint2* list) {
     __shared__ __attribute__((aligned(16))) float s_v[kDetWaves][kWave];
@@ -304,44 +371,60 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const ui
     const int wv = threadIdx.x / kWave;
     const int nwaves = gridDim.x * kDetWaves;
     const int64_t npairs = (int64_t)nblk_used * kDetLongPerBlock;
-    auto load = [&](int64_t k) { return k + lane < W ? list[k + lane] : make_uint2(~0u, 0u); };
+    // clamped, unconditional loads (the end of the list is checked where the
+    // rows are compared): a guarded load sits behind a branch, after which the
+    // compiler waits for every load in flight, the prefetched ones too
+    auto load = [&](int64_t k) { return list[min(k + lane, (int64_t)W - 1)]; };
     for (int64_t pr = blockIdx.x * kDetWaves + wv; pr < npairs; pr += nwaves) {
         const int b = (int)(pr / kDetLongPerBlock), slot = (int)(pr % kDetLongPerBlock);
-        if (slot >= a.long_count[b]) continue;
+        // both loads issued together: pr is inside the record array whether or
+        // not the slot holds a run
         const int4 rec = a.long_runs[pr];
+        if (slot >= a.long_count[b]) continue;
         const uint32_t row = (uint32_t)rec.x;
         float acc = __uint_as_float((uint32_t)rec.y);
         int64_t k = rec.z;
-        uint2 ring[kLongDepth];
+        uint2 cur[kLongDepth];
 #pragma unroll
-        for (int d = 0; d < kLongDepth; ++d) ring[d] = load(k + (int64_t)d * kWave);
+        for (int d = 0; d < kLongDepth; ++d) cur[d] = load(k + (int64_t)d * kWave);
         bool more = true;
         while (more) {
-            const uint2 v = ring[0];
+            // a trip: issue the next trip's kLongDepth loads, fold this trip's
+            // kLongDepth steps, then take the loads over (the only wait for
+            // them comes a trip after their issue); steps past the run's end
+            // find no entries and add nothing
+            uint2 nxt[kLongDepth];
 #pragma unroll
-            for (int d = 0; d + 1 < kLongDepth; ++d) ring[d] = ring[d + 1];
-            ring[kLongDepth - 1] = load(k + (int64_t)kLongDepth * kWave);
-            const uint64_t match = __ballot(v.x == row);
-            // entries of the run in this step: the lanes before the first mismatch
-            const int n = (~match == 0ull) ? kWave : __ffsll((unsigned long long)~match) - 1;
-            s_v[wv][lane] = __uint_as_float(v.y);
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-                // all 64 values into registers first, then the dependent adds
-                float4 q[kWave / 4];
+            for (int d = 0; d < kLongDepth; ++d) nxt[d] = load(k + (int64_t)(kLongDepth + d) * kWave);
 #pragma unroll
-                for (int j = 0; j < kWave / 4; ++j) q[j] = *reinterpret_cast<const float4*>(&s_v[wv][4 * j]);
+            for (int d = 0; d < kLongDepth; ++d) {
+                const uint2 v = cur[d];
+                const uint64_t match = __ballot(more & (k + lane < W) & (v.x == row));
+                // entries of the run in this step: the lanes before the first mismatch
+                const int n = (~match == 0ull) ? kWave : __ffsll((unsigned long long)~match) - 1;
+                // lanes past the run hold -0, which leaves every sum unchanged,
+                // so the 64 adds carry no conditions
+                s_v[wv][lane] = lane < n ? __uint_as_float(v.y) : -0.0f;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0 && n > 0) {
+                    // all 64 values into registers first, then the dependent adds
+                    float4 q[kWave / 4];
 #pragma unroll
-                for (int j = 0; j < kWave / 4; ++j) {
-                    if (4 * j < n) acc = __fadd_rn(acc, q[j].x);
-                    if (4 * j + 1 < n) acc = __fadd_rn(acc, q[j].y);
-                    if (4 * j + 2 < n) acc = __fadd_rn(acc, q[j].z);
-                    if (4 * j + 3 < n) acc = __fadd_rn(acc, q[j].w);
+                    for (int j = 0; j < kWave / 4; ++j) q[j] = *reinterpret_cast<const float4*>(&s_v[wv][4 * j]);
+#pragma unroll
+                    for (int j = 0; j < kWave / 4; ++j) {
+                        acc = __fadd_rn(acc, q[j].x);
+                        acc = __fadd_rn(acc, q[j].y);
+                        acc = __fadd_rn(acc, q[j].z);
+                        acc = __fadd_rn(acc, q[j].w);
+                    }
                 }
+                __builtin_amdgcn_wave_barrier();
+                more = more && n == kWave;
+                k += kWave;
             }
-            __builtin_amdgcn_wave_barrier();
-            more = n == kWave;
-            k += kWave;
+#pragma unroll
+            for (int d = 0; d < kLongDepth; ++d) cur[d] = nxt[d];
         }
         if (lane == 0 && rec.w < a.y_cap) {
             a.y_idx[rec.w] = (int32_t)row;
@@ -353,7 +436,12 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const ui
 }  // namespace
 
 hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_t s) {
-    const size_t lds = ((size_t(1) << a.chunk_log2) + 2) * sizeof(int32_t);
+    const size_t lds = 3 * ((size_t(1) << a.chunk_log2) + 2) * sizeof(int32_t);
+    if (lds > 65536) {   // chunks of 8192 products
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_det_gather),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_det_gather, dim3(grid), dim3(kGatherBlock), lds, s, a, list);
     return hipGetLastError();
 }
