@@ -128,20 +128,99 @@ __global__ __launch_bounds__(kDetBlock) void k_det_hist(DetArgs a, const uint2* 
         if (e < W) atomicAdd(&h[(key[i] >> shift) & (uint32_t)(nd - 1)], 1);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < nd; d += kDetBlock) a.counts[(int64_t)d * a.nblk + blockIdx.x] = h[d];
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[(int64_t)nd * a.nblk] = 0;
+    // the block's row of the count matrix: contiguous, so the stores coalesce
+    for (int d = threadIdx.x; d < nd; d += kDetBlock) a.counts[(int64_t)blockIdx.x * nd + d] = h[d];
+}
+
+// Column prefixes of the count matrix within groups of `group` consecutive
+// blocks: counts[b][d] becomes the digit-d entries of the earlier blocks of
+// b's group, gt[g][d] the group's digit-d total.  Thread = digit (the loads
+// of a block row coalesce), grid (groups, digit slices).
+__global__ __launch_bounds__(kDetBlock) void k_det_colscan(DetArgs a, int32_t* gt, int nd, int group) {
+    const int d = blockIdx.y * kDetBlock + threadIdx.x;
+    if (d >= nd) return;
+    const int b0 = blockIdx.x * group;
+    const int b1 = min(b0 + group, a.nblk);
+    int run = 0;
+    for (int b = b0; b < b1; b += 16) {
+        int v[16];
+        // clamped, unconditional loads so that all sixteen are in flight
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = a.counts[(int64_t)min(b + u, b1 - 1) * nd + d];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (b + u < b1) {
+                a.counts[(int64_t)(b + u) * nd + d] = run;
+                run += v[u];
+            }
+        }
+    }
+    gt[(int64_t)blockIdx.x * nd + d] = run;
+}
+
+// gt[g][d] <- (entries of every digit below d) + (digit-d entries of the
+// groups before g): with the in-group prefixes, each (digit, block) run's
+// position in the digit-major order of Algorithm 2's count matrix.  One
+// block; digit d = p * 1024 + thread, so the loads of a group row coalesce.
+// At most kDetMaxGroups groups: all of a thread's totals are loaded at once.
+constexpr int kBaseBlock = 1024;
+__global__ __launch_bounds__(kBaseBlock) void k_det_digit_base(int32_t* gt, int nd, int ngroups) {
+    __shared__ int s_tmp[kBaseBlock / kWave + 1];
+    constexpr int P = kMaxDigits / kBaseBlock;
+    int v[P][kDetMaxGroups];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int d = p * kBaseBlock + threadIdx.x;
+        const int dc = d < nd ? d : 0;
+#pragma unroll
+        for (int g = 0; g < kDetMaxGroups; ++g) v[p][g] = gt[(int64_t)min(g, ngroups - 1) * nd + dc];
+    }
+    int carry = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int d = p * kBaseBlock + threadIdx.x;
+        int tot = 0;
+#pragma unroll
+        for (int g = 0; g < kDetMaxGroups; ++g) tot += g < ngroups ? v[p][g] : 0;
+        if (d >= nd) tot = 0;
+        int total;
+        int run = block_exclusive_i32<kBaseBlock>(tot, s_tmp, total) + carry;
+        carry += total;
+        if (d < nd) {
+#pragma unroll
+            for (int g = 0; g < kDetMaxGroups; ++g) {
+                if (g < ngroups) gt[(int64_t)g * nd + d] = run;
+                run += v[p][g];
+            }
+        }
+    }
+}
+
+// In-place exclusive scan of n int32 values by one block.
+__global__ __launch_bounds__(kBaseBlock) void k_det_scan_small(int32_t* data, int n) {
+    __shared__ int s_tmp[kBaseBlock / kWave + 1];
+    int carry = 0;
+    for (int i0 = 0; i0 < n; i0 += kBaseBlock) {
+        const int i = i0 + threadIdx.x;
+        const int v = i < n ? data[i] : 0;
+        int total;
+        const int e = block_exclusive_i32<kBaseBlock>(v, s_tmp, total);
+        if (i < n) data[i] = carry + e;
+        carry += total;
+    }
 }
 
 __global__ __launch_bounds__(kDetBlock) void k_det_scatter(DetArgs a, const uint2* in, uint2* out, int shift,
-                                                           int dbits) {
+                                                           int dbits, const int32_t* gt, int group) {
     __shared__ int s_run[kMaxDigits];             // next position of each digit's run
     __shared__ int s_wc[kDetWaves][kMaxDigits];   // this round's count per wave and digit
     const int nd = 1 << dbits;
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     if (base >= W) return;
+    const int32_t* grow = gt + (int64_t)(blockIdx.x / group) * nd;
     for (int d = threadIdx.x; d < nd; d += kDetBlock) {
-        s_run[d] = a.counts[(int64_t)d * a.nblk + blockIdx.x];
+        s_run[d] = a.counts[(int64_t)blockIdx.x * nd + d] + grow[d];
         for (int w = 0; w < kDetWaves; ++w) s_wc[w][d] = 0;
     }
     __syncthreads();
@@ -449,17 +528,21 @@ hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_
 hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int shift, int digit_bits,
                            int32_t* partials, hipStream_t s) {
     if (digit_bits < 1 || digit_bits > kDetMaxDigitBits) return hipErrorInvalidValue;
+    const int nd = 1 << digit_bits;
+    const int group = det_group(a.nblk);
+    const int ngroups = (a.nblk + group - 1) / group;
     hipLaunchKernelGGL(k_det_hist, dim3(a.nblk), dim3(kDetBlock), 0, s, a, in, shift, digit_bits);
-    hipError_t e = launch_exclusive_scan_i32(a.counts, (int64_t(1) << digit_bits) * a.nblk + 1, partials, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_det_scatter, dim3(a.nblk), dim3(kDetBlock), 0, s, a, in, out, shift, digit_bits);
+    hipLaunchKernelGGL(k_det_colscan, dim3(ngroups, (nd + kDetBlock - 1) / kDetBlock), dim3(kDetBlock), 0, s, a,
+                       partials, nd, group);
+    hipLaunchKernelGGL(k_det_digit_base, dim3(1), dim3(kBaseBlock), 0, s, partials, nd, ngroups);
+    hipLaunchKernelGGL(k_det_scatter, dim3(a.nblk), dim3(kDetBlock), 0, s, a, in, out, shift, digit_bits,
+                       partials, group);
     return hipGetLastError();
 }
 
-hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int32_t* partials, hipStream_t s) {
+hipError_t launch_det_fold(const DetArgs& a, const uint2* list, hipStream_t s) {
     hipLaunchKernelGGL(k_det_heads, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
-    hipError_t e = launch_exclusive_scan_i32(a.counts, int64_t(a.nblk) + 1, partials, s);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_det_scan_small, dim3(1), dim3(kBaseBlock), 0, s, a.counts, a.nblk + 1);
     hipLaunchKernelGGL(k_det_fold, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
     hipLaunchKernelGGL(k_det_fold_long, dim3(2048), dim3(kDetBlock), 0, s, a, list);
     return hipGetLastError();

@@ -310,6 +310,15 @@ constexpr int kDetTile = kDetBlock * kDetItems;   // list entries per radix bloc
 constexpr int kDetMaxDigitBits = 11;
 constexpr int kDetShortRun = 128;   // a run longer than this continues in the wave-wide fold
 constexpr int kDetLongPerBlock = kDetTile / kDetShortRun;   // long runs starting in one radix block, at most
+// Radix blocks per group of the count matrix's column scan: at least 16,
+// and enough that there are at most kDetMaxGroups groups.
+constexpr int kDetMaxGroups = 32;
+inline int det_group(int nblk) {
+    const int g = (nblk + kDetMaxGroups - 1) / kDetMaxGroups;
+    return g > 16 ? g : 16;
+}
+// int32 entries of the group totals (gt[group][digit])
+constexpr int64_t kDetGroupEntries = int64_t(kDetMaxGroups) << kDetMaxDigitBits;
 struct DetArgs {
     Ctrl* ctrl;
     int32_t m;               // rows of the operand; m itself marks a masked-out product
@@ -325,7 +334,8 @@ struct DetArgs {
     uint64_t* lb1;           // the scan's look-back words: the first lb1_clear of each half are
     int32_t lb1_n;           // cleared for the next call (the bucket scatter's task otherwise)
     int32_t lb1_clear;
-    int32_t* counts;         // [2^digit_bits * nblk + 1] per-(digit, block) counts, scanned in place
+    int32_t* counts;         // radix passes: [nblk][2^digit_bits] per-(block, digit) counts, block rows
+                             // contiguous; the fold: [nblk + 1] heads per block, scanned in place
     int32_t nblk;            // radix blocks of kDetTile entries
     int4* long_runs;         // [nblk][kDetLongPerBlock] runs longer than kDetShortRun, by the block of
                              // their first entry: (row, acc bits, next entry, y position)
@@ -338,11 +348,12 @@ struct DetArgs {
 // Products -> (row, RN32(a * x)) at their product index; `grid` chunks of
 // 2^chunk_log2 products.
 hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_t s);
-// One stable pass on bits [shift, shift + digit_bits) of the row.
+// One stable pass on bits [shift, shift + digit_bits) of the row; `partials`
+// holds kDetGroupEntries int32 (the count matrix's group totals).
 hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int shift, int digit_bits,
                            int32_t* partials, hipStream_t s);
 // Fold each row's run of the sorted list and write y ascending.
-hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int32_t* partials, hipStream_t s);
+hipError_t launch_det_fold(const DetArgs& a, const uint2* list, hipStream_t s);
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 // Multi-source BFS in the pull direction (msbfs_kernels.hip): frontier and
 // seen masks with one bit per source, G = ceil(nsrc / 64) 64-bit words per

@@ -146,7 +146,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
         const int64_t ncounts = (int64_t(1) << kDetMaxDigitBits) * L.det_nblk_max + 1;
         L.det_list = take(size_t(nnz + 1) * 8);
         L.det_counts = take(size_t(ncounts) * 4);
-        L.det_partials = take(size_t(ncounts / 4096 + 2) * 4);
+        L.det_partials = take(size_t(kDetGroupEntries) * 4);
         L.det_long = take(size_t(L.det_nblk_max) * kDetLongPerBlock * 16);
         L.det_long_count = take(size_t(L.det_nblk_max) * 4);
     }
@@ -637,7 +637,7 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
         HIP_TRY(launch_det_pass(d, cur, other, p * dbits, dbits, partials, s));
         std::swap(cur, other);
     }
-    HIP_TRY(launch_det_fold(d, cur, partials, s));
+    HIP_TRY(launch_det_fold(d, cur, s));
     return SPMSPV_OK;
 }
 
