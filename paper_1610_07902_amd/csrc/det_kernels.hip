@@ -24,14 +24,19 @@ namespace spv {
 
 namespace {
 
-constexpr int kGatherBlock = 256;
+constexpr int kGatherBlock = 1024;   // one batch of eight products per thread for 8192-product chunks
 constexpr int kMaxDigits = 1 << kDetMaxDigitBits;
 constexpr int kDetWaves = kDetBlock / kWave;
 
 __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* list) {
     extern __shared__ int32_t s_off[];   // the chunk's column table, 3 x (chunk + 2) words
+    // every word the set-up needs, loaded together: chunk_col holds an entry
+    // past every chunk of the grid (the next one's is used only if it exists)
     const int W = ld_ctrl(&a.ctrl->W);
     const int fnz = ld_ctrl(&a.ctrl->fnz);
+    const int err = ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err));
+    const int c_lo = a.chunk_col[blockIdx.x];
+    const int c_next = a.chunk_col[blockIdx.x + 1];
     // The per-call bookkeeping the bucket scatter does on the other paths:
     // the scan's statistics, and its look-back words cleared for the next call.
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -46,15 +51,14 @@ __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* l
     }
     // a failed look-back leaves the column tables inconsistent: write
     // nothing (the error is reported with the call's status)
-    if (ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err)) & (int32_t)ERR_SPIN) return;
+    if (err & (int32_t)ERR_SPIN) return;
     const int64_t chunk = int64_t(1) << a.chunk_log2;
     const int64_t w0 = (int64_t)blockIdx.x << a.chunk_log2;
     if (w0 >= W) return;
     const int64_t w1 = w0 + chunk < W ? w0 + chunk : (int64_t)W;
     // chunk_col[k] is the column holding product k * chunk, so the chunk's
     // last product lies in a column no later than chunk_col[k + 1]
-    const int c_lo = a.chunk_col[blockIdx.x];
-    const int c_hi = w1 < W ? a.chunk_col[blockIdx.x + 1] : fnz - 1;
+    const int c_hi = w1 < W ? c_next : fnz - 1;
     const int ncol = c_hi - c_lo + 1;
     // the chunk's column table in LDS: product offsets, first entries, x values
     const int cap = (int)chunk + 2;
@@ -72,20 +76,32 @@ __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* l
     // clamped to the chunk's first product), so they are in flight together
     constexpr int B8 = 8;
     const int64_t first = (int64_t)s_st[0] + (w0 - s_off[0]);
+    int top = 1;   // the largest power of two <= ncol
+    while (top * 2 <= ncol) top *= 2;
     for (int64_t wb = w0 + threadIdx.x; wb < w1; wb += (int64_t)B8 * kGatherBlock) {
+        // the last column starting at or before each product: the eight
+        // searches advance in lockstep, the same steps for every lane, with
+        // clamped reads, so each step's eight LDS reads are in flight together
+        // (a search loop per product waits for every read in turn)
+        int lo[B8];
+#pragma unroll
+        for (int u = 0; u < B8; ++u) lo[u] = 0;
+        for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < B8; ++u) {
+                const int64_t w = wb + (int64_t)u * kGatherBlock;
+                const int c = lo[u] + step;
+                const int o = s_off[min(c, ncol - 1)];
+                if (c < ncol && o <= w) lo[u] = c;
+            }
+        }
         int64_t q[B8];
         uint32_t xv[B8];
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
             const int64_t w = wb + (int64_t)u * kGatherBlock;
-            int lo = 0, hi = ncol - 1;   // the last column starting at or before w
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= w) lo = mid;
-                else hi = mid - 1;
-            }
-            q[u] = w < w1 ? (int64_t)s_st[lo] + (w - s_off[lo]) : first;
-            xv[u] = s_xv[lo];
+            q[u] = w < w1 ? (int64_t)s_st[lo[u]] + (w - s_off[lo[u]]) : first;
+            xv[u] = s_xv[lo[u]];
         }
         int32_t row[B8];
         float av[B8];
@@ -210,18 +226,24 @@ __global__ __launch_bounds__(kBaseBlock) void k_det_scan_small(int32_t* data, in
     }
 }
 
-__global__ __launch_bounds__(kDetBlock) void k_det_scatter(DetArgs a, const uint2* in, uint2* out, int shift,
+// The scatter's workgroup: more threads over the same tile, so fewer rounds
+// of ballots and barriers per tile.
+constexpr int kScatBlock = 1024;
+constexpr int kScatItems = kDetTile / kScatBlock;
+constexpr int kScatWaves = kScatBlock / kWave;
+
+__global__ __launch_bounds__(kScatBlock) void k_det_scatter(DetArgs a, const uint2* in, uint2* out, int shift,
                                                            int dbits, const int32_t* gt, int group) {
     __shared__ int s_run[kMaxDigits];             // next position of each digit's run
-    __shared__ int s_wc[kDetWaves][kMaxDigits];   // this round's count per wave and digit
+    __shared__ uint8_t s_wc[kScatWaves][kMaxDigits];   // this round's count per wave and digit (<= 64)
     const int nd = 1 << dbits;
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     if (base >= W) return;
     const int32_t* grow = gt + (int64_t)(blockIdx.x / group) * nd;
-    for (int d = threadIdx.x; d < nd; d += kDetBlock) {
+    for (int d = threadIdx.x; d < nd; d += kScatBlock) {
         s_run[d] = a.counts[(int64_t)blockIdx.x * nd + d] + grow[d];
-        for (int w = 0; w < kDetWaves; ++w) s_wc[w][d] = 0;
+        for (int w = 0; w < kScatWaves; ++w) s_wc[w][d] = 0;
     }
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -229,12 +251,12 @@ __global__ __launch_bounds__(kDetBlock) void k_det_scatter(DetArgs a, const uint
     // the block's entries into registers first (clamped indices), so the
     // rounds below wait for no memory
     const int64_t last = W - 1;
-    uint2 its[kDetItems];
+    uint2 its[kScatItems];
 #pragma unroll
-    for (int r = 0; r < kDetItems; ++r) its[r] = in[min(base + r * kDetBlock + threadIdx.x, last)];
+    for (int r = 0; r < kScatItems; ++r) its[r] = in[min(base + r * kScatBlock + threadIdx.x, last)];
 #pragma unroll
-    for (int r = 0; r < kDetItems; ++r) {
-        const int64_t e = base + r * kDetBlock + threadIdx.x;
+    for (int r = 0; r < kScatItems; ++r) {
+        const int64_t e = base + r * kScatBlock + threadIdx.x;
         const bool valid = e < W;
         const uint2 it = its[r];
         const int d = valid ? (int)((it.x >> shift) & (uint32_t)(nd - 1)) : 0;
@@ -291,26 +313,32 @@ __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2*
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[a.nblk] = 0;
 }
 
+// The fold's workgroup: twice the radix passes' threads over the same tile,
+// so each thread folds half as many runs.
+constexpr int kFoldBlock = 512;
+constexpr int kFoldItems = kDetTile / kFoldBlock;
+constexpr int kFoldWaves = kFoldBlock / kWave;
+
 // The block's kDetTile entries are staged in LDS with the kDetShortRun + 1
 // entries after them (a short fold never reads further).  (1) Row boundaries
 // are found with wave ballots; the heads (boundaries of real rows inside the
 // block) are compacted, in entry order, into a list of positions, and the
 // first other boundary (in the halo, or where the masked rows begin) ends the
-// block's last run.  (2) Thread t folds heads t, t + kDetBlock, ...: a run
+// block's last run.  (2) Thread t folds heads t, t + kFoldBlock, ...: a run
 // ends where the next head starts, so its adds need no row comparisons, and
 // consecutive heads -- ordinals, so outputs -- sit in consecutive lanes.
 // Past kDetShortRun + 1 entries a run is handed to k_det_fold_long.  (Giving
 // each thread the heads among its own items left the wave waiting on the
 // lane that held most of them: heads evenly spaced by a power of two all
 // fall on one thread.)
-__global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* list) {
+__global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2* list) {
     constexpr int kStage = kDetTile + kDetShortRun + 1;
-    constexpr int kCells = kDetItems * kDetWaves;   // (round, wave) ballots
+    constexpr int kCells = kFoldItems * kFoldWaves;   // (round, wave) ballots
     static_assert(kCells == kWave, "one lane per ballot in the head-count scan");
     static_assert(kDetTile <= 65536, "head positions are 16-bit");
     __shared__ uint2 s_e[kStage];
     __shared__ uint16_t s_head[kDetTile];
-    __shared__ uint64_t s_bal[kCells];   // heads of round r, wave w at r * kDetWaves + w
+    __shared__ uint64_t s_bal[kCells];   // heads of round r, wave w at r * kFoldWaves + w
     __shared__ int s_pre[kCells + 1];    // heads before each ballot, in entry order
     __shared__ int s_nlong, s_stop;
     __shared__ uint32_t s_prev;
@@ -328,17 +356,17 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
     }
     const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
     const int n_st = (int)min((int64_t)kStage, (int64_t)W - base);     // with the halo
-    constexpr int kRounds = (kStage + kDetBlock - 1) / kDetBlock;
+    constexpr int kRounds = (kStage + kFoldBlock - 1) / kFoldBlock;
     {
         // every load unconditional (index clamped into range), so all are in
         // flight before the first wait; a guarded load compiles to a branch
         // that waits for its load before the next one is issued
         uint2 t[kRounds];
 #pragma unroll
-        for (int r = 0; r < kRounds; ++r) t[r] = list[base + min(r * kDetBlock + tid, n_st - 1)];
+        for (int r = 0; r < kRounds; ++r) t[r] = list[base + min(r * kFoldBlock + tid, n_st - 1)];
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
-            const int i = r * kDetBlock + tid;
+            const int i = r * kFoldBlock + tid;
             if (i < n_st) s_e[i] = t[r];
         }
     }
@@ -348,23 +376,23 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
         s_prev = base > 0 ? list[base - 1].x : ~0u;
     }
     __syncthreads();
-    // (1) item r of thread t is entry r * kDetBlock + t; the rounds past
-    // kDetItems cover the halo, where only the first boundary matters
+    // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
+    // kFoldItems cover the halo, where only the first boundary matters
     const uint64_t lower = (1ull << lane) - 1ull;
     uint32_t heads = 0;   // bit r: item r is a head
     int stop = n_st;
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
-        const int i = r * kDetBlock + tid;
+        const int i = r * kFoldBlock + tid;
         const int ic = min(i, n_st - 1);
         const uint32_t row = s_e[ic].x;
         const uint32_t prev = s_e[max(ic - 1, 0)].x;
         const bool bound = i < n_st && (i == 0 ? base == 0 || s_prev != row : prev != row);
         const bool head = bound && i < n_in && row < (uint32_t)a.m;
         if (bound && !head) stop = min(stop, i);
-        if (r < kDetItems) {
+        if (r < kFoldItems) {
             const uint64_t bal = __ballot(head);
-            if (lane == 0) s_bal[r * kDetWaves + wave] = bal;
+            if (lane == 0) s_bal[r * kFoldWaves + wave] = bal;
             heads |= head ? (1u << r) : 0u;
         }
     }
@@ -384,10 +412,10 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kDetItems; ++r) {
+    for (int r = 0; r < kFoldItems; ++r) {
         if ((heads >> r) & 1u) {
-            const int cell = r * kDetWaves + wave;
-            s_head[s_pre[cell] + __popcll(s_bal[cell] & lower)] = (uint16_t)(r * kDetBlock + tid);
+            const int cell = r * kFoldWaves + wave;
+            s_head[s_pre[cell] + __popcll(s_bal[cell] & lower)] = (uint16_t)(r * kFoldBlock + tid);
         }
     }
     __syncthreads();
@@ -395,7 +423,7 @@ __global__ __launch_bounds__(kDetBlock) void k_det_fold(DetArgs a, const uint2* 
     const int H = s_pre[kCells];
     const int last_end = s_stop;
     const int64_t run0 = a.counts[blockIdx.x];
-    for (int j = tid; j < H; j += kDetBlock) {
+    for (int j = tid; j < H; j += kFoldBlock) {
         const int i = s_head[j];
         const int nxt = s_head[min(j + 1, H - 1)];
         const int end = j + 1 < H ? nxt : last_end;   // the run is entries [i, end)
@@ -535,7 +563,7 @@ hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int sh
     hipLaunchKernelGGL(k_det_colscan, dim3(ngroups, (nd + kDetBlock - 1) / kDetBlock), dim3(kDetBlock), 0, s, a,
                        partials, nd, group);
     hipLaunchKernelGGL(k_det_digit_base, dim3(1), dim3(kBaseBlock), 0, s, partials, nd, ngroups);
-    hipLaunchKernelGGL(k_det_scatter, dim3(a.nblk), dim3(kDetBlock), 0, s, a, in, out, shift, digit_bits,
+    hipLaunchKernelGGL(k_det_scatter, dim3(a.nblk), dim3(kScatBlock), 0, s, a, in, out, shift, digit_bits,
                        partials, group);
     return hipGetLastError();
 }
@@ -543,7 +571,7 @@ hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int sh
 hipError_t launch_det_fold(const DetArgs& a, const uint2* list, hipStream_t s) {
     hipLaunchKernelGGL(k_det_heads, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
     hipLaunchKernelGGL(k_det_scan_small, dim3(1), dim3(kBaseBlock), 0, s, a.counts, a.nblk + 1);
-    hipLaunchKernelGGL(k_det_fold, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
+    hipLaunchKernelGGL(k_det_fold, dim3(a.nblk), dim3(kFoldBlock), 0, s, a, list);
     hipLaunchKernelGGL(k_det_fold_long, dim3(2048), dim3(kDetBlock), 0, s, a, list);
     return hipGetLastError();
 }
