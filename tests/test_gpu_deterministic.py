@@ -3,8 +3,8 @@ against the oracle's sequential fp32 fold (oracle_spmspv_f32seq: products
 rounded to fp32, each row's products added one at a time in product order),
 bit for bit: R-MAT graphs at several densities with x in random order, under
 every schedule (the bits must not move), a hub row of 300,000 products,
-masks, left multiplication, a DCSC handle, and the benchmark's scale-22
-graph."""
+run lengths at the fold's and the radix tile's limits, masks, left
+multiplication, a DCSC handle, and the benchmark's scale-22 graph."""
 import numpy as np
 import pytest
 
@@ -196,4 +196,34 @@ def test_calls_of_changing_length_in_a_row(spv):
     # and the default path afterwards on the same handle
     gi, gv, _ = M.spmspv(dev(S), dev(xv), sorted_output=True)
     assert np.array_equal(to_np(gi).astype(np.int64), reference(A, S, xv)[0])
+    M.close()
+
+
+def test_run_lengths_around_the_fold_and_tile_limits(spv):
+    """Rows with product counts at and around the short fold's limit (129
+    entries), a radix tile (4096 entries) and a single entry, shuffled so that
+    runs start and end at every offset of the tiles: one product per column,
+    values of both signs over many binades; x in column order and permuted;
+    and under a mask whose dropped rows sort after every real one (their tail
+    starts inside a tile or in the entries staged after it)."""
+    rng = np.random.default_rng(21)
+    lengths = np.array([1, 2, 3, 127, 128, 129, 130, 131, 257, 4095, 4096, 4097])
+    m = 1200
+    rows = np.repeat(np.arange(m, dtype=np.int32), rng.choice(lengths, m))
+    rng.shuffle(rows)
+    n = rows.size
+    colptr = np.arange(n + 1, dtype=np.int32)
+    vals = (rng.random(n) * 2.0 ** rng.integers(-12, 12, n) * rng.choice([-1.0, 1.0], n)).astype(np.float32)
+    A = synth.CSC(m, n, colptr, rows, vals)
+    M = spv.Matrix.from_csc(A, flags=spv.DETERMINISTIC)
+    xv = synth.values(n, 4, stream=78)
+    for S in (np.arange(n, dtype=np.int32), rng.permutation(n).astype(np.int32)):
+        gi, gv = run(spv, M, S, xv)
+        same_bits(gi, gv, *reference(A, S, xv))
+    drop = rng.random(m) < 0.4
+    words = np.zeros((m + 31) // 32, np.uint32)
+    for i in np.nonzero(drop)[0]:
+        words[i >> 5] |= np.uint32(1 << (i & 31))
+    gi, gv = run(spv, M, S, xv, mask=dev(words.view(np.int32)))
+    same_bits(gi, gv, *reference(A, S, xv, drop=drop))
     M.close()
