@@ -128,16 +128,16 @@ __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* l
 __global__ __launch_bounds__(kDetBlock) void k_det_hist(DetArgs a, const uint2* in, int shift, int dbits) {
     __shared__ int h[kMaxDigits];
     const int nd = 1 << dbits;
-    for (int d = threadIdx.x; d < nd; d += kDetBlock) h[d] = 0;
-    __syncthreads();
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     const int64_t last = W > 0 ? W - 1 : 0;
     // every key loaded first (clamped indices, no branch around a load), so
-    // the loads overlap; then the counts
+    // the loads overlap each other and the clearing of the counts
     uint32_t key[kDetItems];
 #pragma unroll
     for (int i = 0; i < kDetItems; ++i) key[i] = in[min(base + i * kDetBlock + threadIdx.x, last)].x;
+    for (int d = threadIdx.x; d < nd; d += kDetBlock) h[d] = 0;
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < kDetItems; ++i) {
         const int64_t e = base + i * kDetBlock + threadIdx.x;
@@ -240,6 +240,12 @@ __global__ __launch_bounds__(kScatBlock) void k_det_scatter(DetArgs a, const uin
     const int W = ld_ctrl(&a.ctrl->W);
     const int64_t base = (int64_t)blockIdx.x * kDetTile;
     if (base >= W) return;
+    // the block's entries into registers first (clamped indices), in flight
+    // together with the run-start loads, so the rounds below wait for no memory
+    const int64_t last = W - 1;
+    uint2 its[kScatItems];
+#pragma unroll
+    for (int r = 0; r < kScatItems; ++r) its[r] = in[min(base + r * kScatBlock + threadIdx.x, last)];
     const int32_t* grow = gt + (int64_t)(blockIdx.x / group) * nd;
     for (int d = threadIdx.x; d < nd; d += kScatBlock) {
         s_run[d] = a.counts[(int64_t)blockIdx.x * nd + d] + grow[d];
@@ -248,12 +254,6 @@ __global__ __launch_bounds__(kScatBlock) void k_det_scatter(DetArgs a, const uin
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint64_t below = (1ull << lane) - 1ull;
-    // the block's entries into registers first (clamped indices), so the
-    // rounds below wait for no memory
-    const int64_t last = W - 1;
-    uint2 its[kScatItems];
-#pragma unroll
-    for (int r = 0; r < kScatItems; ++r) its[r] = in[min(base + r * kScatBlock + threadIdx.x, last)];
 #pragma unroll
     for (int r = 0; r < kScatItems; ++r) {
         const int64_t e = base + r * kScatBlock + threadIdx.x;
