@@ -6,15 +6,18 @@
 //   k_det_gather   product w -> (row, RN32(a * x)) at list position w; the
 //                  scan's column tables give each product's column.
 //   radix passes   a stable LSD sort of that list by row, digits of up to
-//                  11 bits: per-block digit counts, their exclusive scan in
-//                  digit-major order (Algorithm 2's count matrix: every
-//                  (digit, block) run gets its position), then each block
+//                  11 bits: per-block digit counts (a row of the count
+//                  matrix per block), their exclusive scan in digit-major
+//                  order (Algorithm 2's count matrix: every (digit, block)
+//                  run gets its position) from a column scan within groups
+//                  of blocks plus one block of digit bases, then each block
 //                  writes its entries at those positions, ranked stably
 //                  (wave ballots, waves in order, rounds in order).
-//   k_det_heads / k_det_fold  every row's products now form one run in
-//                  product order; the run's first entry folds it
-//                  sequentially and writes y at the run's ordinal, so y is
-//                  ascending.
+//   k_det_heads, k_det_scan_small, k_det_fold, k_det_fold_long
+//                  every row's products now form one run in product order,
+//                  folded sequentially from its first product by one thread
+//                  (by one wave past kDetShortRun + 1 products); y is
+//                  written at the run's ordinal, so y is ascending.
 // A product whose row the mask removes carries row m and sorts after every
 // real row; it is never written.
 
@@ -205,8 +208,10 @@ __global__ __launch_bounds__(kBaseBlock) void k_det_digit_base(int32_t* gt, int 
         if (d < nd) {
 #pragma unroll
             for (int g = 0; g < kDetMaxGroups; ++g) {
-                if (g < ngroups) gt[(int64_t)g * nd + d] = run;
-                run += v[p][g];
+                if (g < ngroups) {
+                    gt[(int64_t)g * nd + d] = run;
+                    run += v[p][g];
+                }
             }
         }
     }
@@ -461,13 +466,15 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     if (tid == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
 }
 
-// One wave per long run.  The wave keeps kLongDepth steps of 64 consecutive
-// entries in flight (one coalesced load per step, issued kLongDepth steps
-// ahead); each step's values go to the wave's LDS row and one lane adds them
-// in order from there, so the run costs its dependent adds and little more.
+// One wave per long run.  The wave works in trips of kLongDepth steps of 64
+// consecutive entries (one coalesced load per step), the next trip's loads
+// issued before the current trip's steps; each step's values go to the
+// wave's LDS row and one lane adds them in order from there, so the run
+// costs its dependent adds and little more.
 // (Folding through lane reads cost about 90 cycles per entry, a 16K-entry
-// hub row 0.6 ms; one thread per run with sixteen loads ahead left the
-// memory latency exposed.)
+// hub row 0.6 ms, and reading the lanes into scalar registers for the adds
+// still cost more than this LDS row; one thread per run with sixteen loads
+// ahead left the memory latency exposed.)
 constexpr int kLongDepth = 8;
 
 __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const uint2* list) {
