@@ -31,15 +31,28 @@ constexpr int kGatherBlock = 1024;   // one batch of eight products per thread f
 constexpr int kMaxDigits = 1 << kDetMaxDigitBits;
 constexpr int kDetWaves = kDetBlock / kWave;
 
+// Radix tiles of the call's product list (at least one).  Every kernel over
+// tiles takes the count from W on the device and loops over the tiles with
+// whatever grid it was given, so the host never reads W back (the scan caps W
+// at nnz, which the workspace's tile arrays are sized for).
+__device__ __forceinline__ int det_tiles(int W) { return W > 0 ? (W + kDetTile - 1) / kDetTile : 1; }
+
+// Radix tiles per group of the count matrix's column scan: at least 16, and
+// enough that there are at most kDetMaxGroups groups.
+__device__ __forceinline__ int det_group(int nt) {
+    const int g = (nt + kDetMaxGroups - 1) / kDetMaxGroups;
+    return g > 16 ? g : 16;
+}
+
 __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* list) {
     extern __shared__ int32_t s_off[];   // the chunk's column table, 3 x (chunk + 2) words
-    // every word the set-up needs, loaded together: chunk_col holds an entry
-    // past every chunk of the grid (the next one's is used only if it exists)
+    // every word the first chunk's set-up needs, loaded together (the grid is
+    // at most the workspace's chunk count, so chunk_col has both entries; they
+    // are used only if the chunks exist)
     const int W = ld_ctrl(&a.ctrl->W);
     const int fnz = ld_ctrl(&a.ctrl->fnz);
     const int err = ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err));
-    const int c_lo = a.chunk_col[blockIdx.x];
-    const int c_next = a.chunk_col[blockIdx.x + 1];
+    int col_c = a.chunk_col[blockIdx.x], col_next = a.chunk_col[blockIdx.x + 1];
     // The per-call bookkeeping the bucket scatter does on the other paths:
     // the scan's statistics, and its look-back words cleared for the next call.
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -56,75 +69,85 @@ __global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* l
     // nothing (the error is reported with the call's status)
     if (err & (int32_t)ERR_SPIN) return;
     const int64_t chunk = int64_t(1) << a.chunk_log2;
-    const int64_t w0 = (int64_t)blockIdx.x << a.chunk_log2;
-    if (w0 >= W) return;
-    const int64_t w1 = w0 + chunk < W ? w0 + chunk : (int64_t)W;
-    // chunk_col[k] is the column holding product k * chunk, so the chunk's
-    // last product lies in a column no later than chunk_col[k + 1]
-    const int c_hi = w1 < W ? c_next : fnz - 1;
-    const int ncol = c_hi - c_lo + 1;
-    // the chunk's column table in LDS: product offsets, first entries, x values
+    const int nchunks = (int)((W + chunk - 1) >> a.chunk_log2);
     const int cap = (int)chunk + 2;
     int32_t* s_st = s_off + cap;
     uint32_t* s_xv = reinterpret_cast<uint32_t*>(s_st + cap);
-    for (int i = threadIdx.x; i <= ncol; i += kGatherBlock) {
-        s_off[i] = a.coff[c_lo + i];
-        if (i < ncol) {
-            s_st[i] = a.cstart[c_lo + i];
-            s_xv[i] = a.cxv[c_lo + i];
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t w0 = (int64_t)c << a.chunk_log2;
+        const int64_t w1 = w0 + chunk < W ? w0 + chunk : (int64_t)W;
+        // chunk_col[k] is the column holding product k * chunk, so the
+        // chunk's last product lies in a column no later than chunk_col[k + 1]
+        // (the last chunk ends at the last non-empty column)
+        if (c != (int)blockIdx.x) {
+            col_c = a.chunk_col[c];
+            col_next = a.chunk_col[c + 1];   // c + 1 <= nchunks
         }
-    }
-    __syncthreads();
-    // products eight per thread at a time: every load unconditional (indices
-    // clamped to the chunk's first product), so they are in flight together
-    constexpr int B8 = 8;
-    const int64_t first = (int64_t)s_st[0] + (w0 - s_off[0]);
-    int top = 1;   // the largest power of two <= ncol
-    while (top * 2 <= ncol) top *= 2;
-    for (int64_t wb = w0 + threadIdx.x; wb < w1; wb += (int64_t)B8 * kGatherBlock) {
-        // the last column starting at or before each product: the eight
-        // searches advance in lockstep, the same steps for every lane, with
-        // clamped reads, so each step's eight LDS reads are in flight together
-        // (a search loop per product waits for every read in turn)
-        int lo[B8];
+        const int c_lo = col_c;
+        const int c_hi = w1 < W ? col_next : fnz - 1;
+        const int ncol = c_hi - c_lo + 1;
+        // the chunk's column table in LDS: product offsets, first entries, x values
+        for (int i = threadIdx.x; i <= ncol; i += kGatherBlock) {
+            s_off[i] = a.coff[c_lo + i];
+            if (i < ncol) {
+                s_st[i] = a.cstart[c_lo + i];
+                s_xv[i] = a.cxv[c_lo + i];
+            }
+        }
+        __syncthreads();
+        // products eight per thread at a time: every load unconditional
+        // (indices clamped to the chunk's first product), so they are in
+        // flight together
+        constexpr int B8 = 8;
+        const int64_t first = (int64_t)s_st[0] + (w0 - s_off[0]);
+        int top = 1;   // the largest power of two <= ncol
+        while (top * 2 <= ncol) top *= 2;
+        for (int64_t wb = w0 + threadIdx.x; wb < w1; wb += (int64_t)B8 * kGatherBlock) {
+            // the last column starting at or before each product: the eight
+            // searches advance in lockstep, the same steps for every lane,
+            // with clamped reads, so each step's eight LDS reads are in flight
+            // together (a search loop per product waits for every read in turn)
+            int lo[B8];
 #pragma unroll
-        for (int u = 0; u < B8; ++u) lo[u] = 0;
-        for (int step = top; step > 0; step >>= 1) {
+            for (int u = 0; u < B8; ++u) lo[u] = 0;
+            for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+                for (int u = 0; u < B8; ++u) {
+                    const int64_t w = wb + (int64_t)u * kGatherBlock;
+                    const int k = lo[u] + step;
+                    const int o = s_off[min(k, ncol - 1)];
+                    if (k < ncol && o <= w) lo[u] = k;
+                }
+            }
+            int64_t q[B8];
+            uint32_t xv[B8];
 #pragma unroll
             for (int u = 0; u < B8; ++u) {
                 const int64_t w = wb + (int64_t)u * kGatherBlock;
-                const int c = lo[u] + step;
-                const int o = s_off[min(c, ncol - 1)];
-                if (c < ncol && o <= w) lo[u] = c;
+                q[u] = w < w1 ? (int64_t)s_st[lo[u]] + (w - s_off[lo[u]]) : first;
+                xv[u] = s_xv[lo[u]];
+            }
+            int32_t row[B8];
+            float av[B8];
+#pragma unroll
+            for (int u = 0; u < B8; ++u) row[u] = a.rowids[q[u]];
+#pragma unroll
+            for (int u = 0; u < B8; ++u) av[u] = a.values ? a.values[q[u]] : 1.0f;
+            uint32_t mw[B8];
+#pragma unroll
+            for (int u = 0; u < B8; ++u) mw[u] = a.mask ? a.mask[row[u] >> 5] : 0u;
+#pragma unroll
+            for (int u = 0; u < B8; ++u) {
+                const int64_t w = wb + (int64_t)u * kGatherBlock;
+                if (w < w1) {
+                    int32_t r = row[u];
+                    const float t = __fmul_rn(av[u], __uint_as_float(xv[u]));
+                    if (a.mask && ((mw[u] >> (r & 31)) & 1u) != (uint32_t)a.mask_keep) r = a.m;
+                    list[w] = make_uint2((uint32_t)r, __float_as_uint(t));
+                }
             }
         }
-        int64_t q[B8];
-        uint32_t xv[B8];
-#pragma unroll
-        for (int u = 0; u < B8; ++u) {
-            const int64_t w = wb + (int64_t)u * kGatherBlock;
-            q[u] = w < w1 ? (int64_t)s_st[lo[u]] + (w - s_off[lo[u]]) : first;
-            xv[u] = s_xv[lo[u]];
-        }
-        int32_t row[B8];
-        float av[B8];
-#pragma unroll
-        for (int u = 0; u < B8; ++u) row[u] = a.rowids[q[u]];
-#pragma unroll
-        for (int u = 0; u < B8; ++u) av[u] = a.values ? a.values[q[u]] : 1.0f;
-        uint32_t mw[B8];
-#pragma unroll
-        for (int u = 0; u < B8; ++u) mw[u] = a.mask ? a.mask[row[u] >> 5] : 0u;
-#pragma unroll
-        for (int u = 0; u < B8; ++u) {
-            const int64_t w = wb + (int64_t)u * kGatherBlock;
-            if (w < w1) {
-                int32_t r = row[u];
-                const float t = __fmul_rn(av[u], __uint_as_float(xv[u]));
-                if (a.mask && ((mw[u] >> (r & 31)) & 1u) != (uint32_t)a.mask_keep) r = a.m;
-                list[w] = make_uint2((uint32_t)r, __float_as_uint(t));
-            }
-        }
+        __syncthreads();   // the next chunk's table reuses the LDS
     }
 }
 
@@ -132,34 +155,40 @@ __global__ __launch_bounds__(kDetBlock) void k_det_hist(DetArgs a, const uint2* 
     __shared__ int h[kMaxDigits];
     const int nd = 1 << dbits;
     const int W = ld_ctrl(&a.ctrl->W);
-    const int64_t base = (int64_t)blockIdx.x * kDetTile;
+    const int nt = det_tiles(W);
     const int64_t last = W > 0 ? W - 1 : 0;
-    // every key loaded first (clamped indices, no branch around a load), so
-    // the loads overlap each other and the clearing of the counts
-    uint32_t key[kDetItems];
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t base = (int64_t)t * kDetTile;
+        // every key loaded first (clamped indices, no branch around a load),
+        // so the loads overlap each other and the clearing of the counts
+        uint32_t key[kDetItems];
 #pragma unroll
-    for (int i = 0; i < kDetItems; ++i) key[i] = in[min(base + i * kDetBlock + threadIdx.x, last)].x;
-    for (int d = threadIdx.x; d < nd; d += kDetBlock) h[d] = 0;
-    __syncthreads();
+        for (int i = 0; i < kDetItems; ++i) key[i] = in[min(base + i * kDetBlock + threadIdx.x, last)].x;
+        for (int d = threadIdx.x; d < nd; d += kDetBlock) h[d] = 0;
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kDetItems; ++i) {
-        const int64_t e = base + i * kDetBlock + threadIdx.x;
-        if (e < W) atomicAdd(&h[(key[i] >> shift) & (uint32_t)(nd - 1)], 1);
+        for (int i = 0; i < kDetItems; ++i) {
+            const int64_t e = base + i * kDetBlock + threadIdx.x;
+            if (e < W) atomicAdd(&h[(key[i] >> shift) & (uint32_t)(nd - 1)], 1);
+        }
+        __syncthreads();
+        // the tile's row of the count matrix: contiguous, so the stores coalesce
+        for (int d = threadIdx.x; d < nd; d += kDetBlock) a.counts[(int64_t)t * nd + d] = h[d];
+        __syncthreads();   // the next tile clears h
     }
-    __syncthreads();
-    // the block's row of the count matrix: contiguous, so the stores coalesce
-    for (int d = threadIdx.x; d < nd; d += kDetBlock) a.counts[(int64_t)blockIdx.x * nd + d] = h[d];
 }
 
-// Column prefixes of the count matrix within groups of `group` consecutive
-// blocks: counts[b][d] becomes the digit-d entries of the earlier blocks of
-// b's group, gt[g][d] the group's digit-d total.  Thread = digit (the loads
-// of a block row coalesce), grid (groups, digit slices).
-__global__ __launch_bounds__(kDetBlock) void k_det_colscan(DetArgs a, int32_t* gt, int nd, int group) {
+// Column prefixes of the count matrix within groups of det_group(tiles)
+// consecutive tiles: counts[b][d] becomes the digit-d entries of the earlier
+// tiles of b's group, gt[g][d] the group's digit-d total.  Thread = digit
+// (the loads of a tile row coalesce), grid (kDetMaxGroups, digit slices).
+__global__ __launch_bounds__(kDetBlock) void k_det_colscan(DetArgs a, int32_t* gt, int nd) {
+    const int nt = det_tiles(ld_ctrl(&a.ctrl->W));
+    const int group = det_group(nt);
     const int d = blockIdx.y * kDetBlock + threadIdx.x;
-    if (d >= nd) return;
     const int b0 = blockIdx.x * group;
-    const int b1 = min(b0 + group, a.nblk);
+    if (d >= nd || b0 >= nt) return;   // the grid covers kDetMaxGroups groups
+    const int b1 = min(b0 + group, nt);
     int run = 0;
     for (int b = b0; b < b1; b += 16) {
         int v[16];
@@ -183,8 +212,11 @@ __global__ __launch_bounds__(kDetBlock) void k_det_colscan(DetArgs a, int32_t* g
 // block; digit d = p * 1024 + thread, so the loads of a group row coalesce.
 // At most kDetMaxGroups groups: all of a thread's totals are loaded at once.
 constexpr int kBaseBlock = 1024;
-__global__ __launch_bounds__(kBaseBlock) void k_det_digit_base(int32_t* gt, int nd, int ngroups) {
+__global__ __launch_bounds__(kBaseBlock) void k_det_digit_base(DetArgs a, int32_t* gt, int nd) {
     __shared__ int s_tmp[kBaseBlock / kWave + 1];
+    const int nt = det_tiles(ld_ctrl(&a.ctrl->W));
+    const int group = det_group(nt);
+    const int ngroups = (nt + group - 1) / group;
     constexpr int P = kMaxDigits / kBaseBlock;
     int v[P][kDetMaxGroups];
 #pragma unroll
@@ -217,9 +249,12 @@ __global__ __launch_bounds__(kBaseBlock) void k_det_digit_base(int32_t* gt, int 
     }
 }
 
-// In-place exclusive scan of n int32 values by one block.
-__global__ __launch_bounds__(kBaseBlock) void k_det_scan_small(int32_t* data, int n) {
+// In-place exclusive scan of the tiles' head counts (tiles + 1 values) by
+// one block.
+__global__ __launch_bounds__(kBaseBlock) void k_det_scan_small(DetArgs a) {
     __shared__ int s_tmp[kBaseBlock / kWave + 1];
+    int32_t* data = a.counts;
+    const int n = det_tiles(ld_ctrl(&a.ctrl->W)) + 1;
     int carry = 0;
     for (int i0 = 0; i0 < n; i0 += kBaseBlock) {
         const int i = i0 + threadIdx.x;
@@ -238,84 +273,93 @@ constexpr int kScatItems = kDetTile / kScatBlock;
 constexpr int kScatWaves = kScatBlock / kWave;
 
 __global__ __launch_bounds__(kScatBlock) void k_det_scatter(DetArgs a, const uint2* in, uint2* out, int shift,
-                                                           int dbits, const int32_t* gt, int group) {
+                                                           int dbits, const int32_t* gt) {
     __shared__ int s_run[kMaxDigits];             // next position of each digit's run
     __shared__ uint8_t s_wc[kScatWaves][kMaxDigits];   // this round's count per wave and digit (<= 64)
     const int nd = 1 << dbits;
     const int W = ld_ctrl(&a.ctrl->W);
-    const int64_t base = (int64_t)blockIdx.x * kDetTile;
-    if (base >= W) return;
-    // the block's entries into registers first (clamped indices), in flight
-    // together with the run-start loads, so the rounds below wait for no memory
-    const int64_t last = W - 1;
-    uint2 its[kScatItems];
-#pragma unroll
-    for (int r = 0; r < kScatItems; ++r) its[r] = in[min(base + r * kScatBlock + threadIdx.x, last)];
-    const int32_t* grow = gt + (int64_t)(blockIdx.x / group) * nd;
-    for (int d = threadIdx.x; d < nd; d += kScatBlock) {
-        s_run[d] = a.counts[(int64_t)blockIdx.x * nd + d] + grow[d];
-        for (int w = 0; w < kScatWaves; ++w) s_wc[w][d] = 0;
-    }
-    __syncthreads();
+    const int nt = det_tiles(W);
+    const int group = det_group(nt);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const uint64_t below = (1ull << lane) - 1ull;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t base = (int64_t)t * kDetTile;
+        if (base >= W) break;   // W == 0: one empty tile
+        // the tile's entries into registers first (clamped indices), in
+        // flight together with the run-start loads, so the rounds below wait
+        // for no memory
+        const int64_t last = W - 1;
+        uint2 its[kScatItems];
 #pragma unroll
-    for (int r = 0; r < kScatItems; ++r) {
-        const int64_t e = base + r * kScatBlock + threadIdx.x;
-        const bool valid = e < W;
-        const uint2 it = its[r];
-        const int d = valid ? (int)((it.x >> shift) & (uint32_t)(nd - 1)) : 0;
-        // lanes of this wave holding the same digit
-        uint64_t peers = __ballot(valid);
-        for (int bit = 0; bit < dbits; ++bit) {
-            const bool one = (d >> bit) & 1;
-            const uint64_t v = __ballot(one);
-            peers &= one ? v : ~v;
-        }
-        const int rank = __popcll(peers & below);
-        const bool leader = valid && rank == 0;
-        if (leader) s_wc[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int off = s_run[d];
-            for (int w = 0; w < wave; ++w) off += s_wc[w][d];
-            out[off + rank] = it;
+        for (int r = 0; r < kScatItems; ++r) its[r] = in[min(base + r * kScatBlock + threadIdx.x, last)];
+        const int32_t* grow = gt + (int64_t)(t / group) * nd;
+        for (int d = threadIdx.x; d < nd; d += kScatBlock) {
+            s_run[d] = a.counts[(int64_t)t * nd + d] + grow[d];
+            for (int w = 0; w < kScatWaves; ++w) s_wc[w][d] = 0;
         }
         __syncthreads();
-        // a wave clears its own entries before (in its program order) it
-        // writes the next round's; others read them only after the next
-        // round's first barrier
-        if (leader) {
-            atomicAdd(&s_run[d], __popcll(peers));
-            s_wc[wave][d] = 0;
+#pragma unroll
+        for (int r = 0; r < kScatItems; ++r) {
+            const int64_t e = base + r * kScatBlock + threadIdx.x;
+            const bool valid = e < W;
+            const uint2 it = its[r];
+            const int d = valid ? (int)((it.x >> shift) & (uint32_t)(nd - 1)) : 0;
+            // lanes of this wave holding the same digit
+            uint64_t peers = __ballot(valid);
+            for (int bit = 0; bit < dbits; ++bit) {
+                const bool one = (d >> bit) & 1;
+                const uint64_t v = __ballot(one);
+                peers &= one ? v : ~v;
+            }
+            const int rank = __popcll(peers & below);
+            const bool leader = valid && rank == 0;
+            if (leader) s_wc[wave][d] = __popcll(peers);
+            __syncthreads();
+            if (valid) {
+                int off = s_run[d];
+                for (int w = 0; w < wave; ++w) off += s_wc[w][d];
+                out[off + rank] = it;
+            }
+            __syncthreads();
+            // a wave clears its own entries before (in its program order) it
+            // writes the next round's; others read them only after the next
+            // round's first barrier
+            if (leader) {
+                atomicAdd(&s_run[d], __popcll(peers));
+                s_wc[wave][d] = 0;
+            }
         }
+        __syncthreads();   // the next tile sets s_run and s_wc afresh
     }
 }
 
 __global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2* list) {
     __shared__ int s_tmp[kDetWaves + 1];
     const int W = ld_ctrl(&a.ctrl->W);
-    const int64_t base = (int64_t)blockIdx.x * kDetTile;
-    // every row and its predecessor's first, then the comparisons
-    // unconditional loads (clamped indices), all in flight together
-    uint32_t rw[kDetItems], pv[kDetItems];
+    const int nt = det_tiles(W);
     const int64_t last = W > 0 ? W - 1 : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[nt] = 0;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t base = (int64_t)t * kDetTile;
+        // every row and its predecessor's first (unconditional loads, clamped
+        // indices, all in flight together), then the comparisons
+        uint32_t rw[kDetItems], pv[kDetItems];
 #pragma unroll
-    for (int i = 0; i < kDetItems; ++i) {
-        const int64_t e = base + i * kDetBlock + threadIdx.x;
-        rw[i] = list[min(e, last)].x;
-        pv[i] = list[max(min(e, last) - 1, (int64_t)0)].x;
-    }
-    int cnt = 0;
+        for (int i = 0; i < kDetItems; ++i) {
+            const int64_t e = base + i * kDetBlock + threadIdx.x;
+            rw[i] = list[min(e, last)].x;
+            pv[i] = list[max(min(e, last) - 1, (int64_t)0)].x;
+        }
+        int cnt = 0;
 #pragma unroll
-    for (int i = 0; i < kDetItems; ++i) {
-        const int64_t e = base + i * kDetBlock + threadIdx.x;
-        if (e < W && rw[i] < (uint32_t)a.m && (e == 0 || pv[i] != rw[i])) ++cnt;
+        for (int i = 0; i < kDetItems; ++i) {
+            const int64_t e = base + i * kDetBlock + threadIdx.x;
+            if (e < W && rw[i] < (uint32_t)a.m && (e == 0 || pv[i] != rw[i])) ++cnt;
+        }
+        int total;
+        block_exclusive_i32<kDetBlock>(cnt, s_tmp, total);   // ends with a barrier
+        if (threadIdx.x == 0) a.counts[t] = total;
     }
-    int total;
-    block_exclusive_i32<kDetBlock>(cnt, s_tmp, total);
-    if (threadIdx.x == 0) a.counts[blockIdx.x] = total;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.counts[a.nblk] = 0;
 }
 
 // The fold's workgroup: twice the radix passes' threads over the same tile,
@@ -349,121 +393,124 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     __shared__ uint32_t s_prev;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int W = ld_ctrl(&a.ctrl->W);
+    const int nt = det_tiles(W);
     if (blockIdx.x == 0 && tid == 0) {
-        const int64_t total = a.counts[a.nblk];
+        const int64_t total = a.counts[nt];
         __hip_atomic_store(&a.ctrl->nnz_y, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (a.d_nnz_y) *a.d_nnz_y = total;
     }
-    const int64_t base = (int64_t)blockIdx.x * kDetTile;
-    if (base >= W) {
-        if (tid == 0) a.long_count[blockIdx.x] = 0;
-        return;
-    }
-    const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
-    const int n_st = (int)min((int64_t)kStage, (int64_t)W - base);     // with the halo
-    constexpr int kRounds = (kStage + kFoldBlock - 1) / kFoldBlock;
-    {
-        // every load unconditional (index clamped into range), so all are in
-        // flight before the first wait; a guarded load compiles to a branch
-        // that waits for its load before the next one is issued
-        uint2 t[kRounds];
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int64_t base = (int64_t)t * kDetTile;
+        if (base >= W) {   // W == 0: one empty tile
+            if (tid == 0) a.long_count[t] = 0;
+            continue;
+        }
+        const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
+        const int n_st = (int)min((int64_t)kStage, (int64_t)W - base);     // with the halo
+        constexpr int kRounds = (kStage + kFoldBlock - 1) / kFoldBlock;
+        {
+            // every load unconditional (index clamped into range), so all are in
+            // flight before the first wait; a guarded load compiles to a branch
+            // that waits for its load before the next one is issued
+            uint2 st[kRounds];
 #pragma unroll
-        for (int r = 0; r < kRounds; ++r) t[r] = list[base + min(r * kFoldBlock + tid, n_st - 1)];
+            for (int r = 0; r < kRounds; ++r) st[r] = list[base + min(r * kFoldBlock + tid, n_st - 1)];
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+                const int i = r * kFoldBlock + tid;
+                if (i < n_st) s_e[i] = st[r];
+            }
+        }
+        if (tid == 0) {
+            s_nlong = 0;
+            s_stop = n_st;
+            s_prev = base > 0 ? list[base - 1].x : ~0u;
+        }
+        __syncthreads();
+        // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
+        // kFoldItems cover the halo, where only the first boundary matters
+        const uint64_t lower = (1ull << lane) - 1ull;
+        uint32_t heads = 0;   // bit r: item r is a head
+        int stop = n_st;
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
             const int i = r * kFoldBlock + tid;
-            if (i < n_st) s_e[i] = t[r];
-        }
-    }
-    if (tid == 0) {
-        s_nlong = 0;
-        s_stop = n_st;
-        s_prev = base > 0 ? list[base - 1].x : ~0u;
-    }
-    __syncthreads();
-    // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
-    // kFoldItems cover the halo, where only the first boundary matters
-    const uint64_t lower = (1ull << lane) - 1ull;
-    uint32_t heads = 0;   // bit r: item r is a head
-    int stop = n_st;
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const int i = r * kFoldBlock + tid;
-        const int ic = min(i, n_st - 1);
-        const uint32_t row = s_e[ic].x;
-        const uint32_t prev = s_e[max(ic - 1, 0)].x;
-        const bool bound = i < n_st && (i == 0 ? base == 0 || s_prev != row : prev != row);
-        const bool head = bound && i < n_in && row < (uint32_t)a.m;
-        if (bound && !head) stop = min(stop, i);
-        if (r < kFoldItems) {
-            const uint64_t bal = __ballot(head);
-            if (lane == 0) s_bal[r * kFoldWaves + wave] = bal;
-            heads |= head ? (1u << r) : 0u;
-        }
-    }
-    if (stop < n_st) atomicMin(&s_stop, stop);
-    __syncthreads();
-    if (wave == 0) {
-        // exclusive scan of the 64 ballots' head counts, (round, wave) order
-        const int c = __popcll(s_bal[lane]);
-        int v = c;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int u = __shfl_up(v, d);
-            if (lane >= d) v += u;
-        }
-        s_pre[lane] = v - c;
-        if (lane == kWave - 1) s_pre[kCells] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kFoldItems; ++r) {
-        if ((heads >> r) & 1u) {
-            const int cell = r * kFoldWaves + wave;
-            s_head[s_pre[cell] + __popcll(s_bal[cell] & lower)] = (uint16_t)(r * kFoldBlock + tid);
-        }
-    }
-    __syncthreads();
-    // (2) folds, one add at a time in entry order
-    const int H = s_pre[kCells];
-    const int last_end = s_stop;
-    const int64_t run0 = a.counts[blockIdx.x];
-    for (int j = tid; j < H; j += kFoldBlock) {
-        const int i = s_head[j];
-        const int nxt = s_head[min(j + 1, H - 1)];
-        const int end = j + 1 < H ? nxt : last_end;   // the run is entries [i, end)
-        const uint2 e0 = s_e[i];
-        float acc = __uint_as_float(e0.y);
-        const int last = i + min(end - i, kDetShortRun + 1) - 1;   // the last entry folded here
-        for (int q = i + 1; q <= last; q += 8) {
-            // eight reads ahead of the adds; past the run the pad is -0, which
-            // leaves every sum (either zero included) unchanged
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t bits = s_e[min(q + u, last)].y;
-                v[u] = q + u <= last ? __uint_as_float(bits) : -0.0f;
+            const int ic = min(i, n_st - 1);
+            const uint32_t row = s_e[ic].x;
+            const uint32_t prev = s_e[max(ic - 1, 0)].x;
+            const bool bound = i < n_st && (i == 0 ? base == 0 || s_prev != row : prev != row);
+            const bool head = bound && i < n_in && row < (uint32_t)a.m;
+            if (bound && !head) stop = min(stop, i);
+            if (r < kFoldItems) {
+                const uint64_t bal = __ballot(head);
+                if (lane == 0) s_bal[r * kFoldWaves + wave] = bal;
+                heads |= head ? (1u << r) : 0u;
             }
+        }
+        if (stop < n_st) atomicMin(&s_stop, stop);
+        __syncthreads();
+        if (wave == 0) {
+            // exclusive scan of the 64 ballots' head counts, (round, wave) order
+            const int c = __popcll(s_bal[lane]);
+            int v = c;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc = __fadd_rn(acc, v[u]);
+            for (int d = 1; d < kWave; d <<= 1) {
+                const int u = __shfl_up(v, d);
+                if (lane >= d) v += u;
+            }
+            s_pre[lane] = v - c;
+            if (lane == kWave - 1) s_pre[kCells] = v;
         }
-        const int64_t p = run0 + j;
-        if (end - i > kDetShortRun + 1) {
-            // more than kDetShortRun + 1 entries, so runs starting in one
-            // block are that far apart and at most kDetLongPerBlock start here
-            const int slot = atomicAdd(&s_nlong, 1);
-            if (slot < kDetLongPerBlock)
-                a.long_runs[(int64_t)blockIdx.x * kDetLongPerBlock + slot] =
-                    make_int4((int)e0.x, (int)__float_as_uint(acc), (int)(base + last + 1), (int)p);
-            else
-                atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
-        } else if (p < a.y_cap) {
-            a.y_idx[p] = (int32_t)e0.x;
-            if (a.y_val) a.y_val[p] = acc;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kFoldItems; ++r) {
+            if ((heads >> r) & 1u) {
+                const int cell = r * kFoldWaves + wave;
+                s_head[s_pre[cell] + __popcll(s_bal[cell] & lower)] = (uint16_t)(r * kFoldBlock + tid);
+            }
         }
+        __syncthreads();
+        // (2) folds, one add at a time in entry order
+        const int H = s_pre[kCells];
+        const int last_end = s_stop;
+        const int64_t run0 = a.counts[t];
+        for (int j = tid; j < H; j += kFoldBlock) {
+            const int i = s_head[j];
+            const int nxt = s_head[min(j + 1, H - 1)];
+            const int end = j + 1 < H ? nxt : last_end;   // the run is entries [i, end)
+            const uint2 e0 = s_e[i];
+            float acc = __uint_as_float(e0.y);
+            const int last = i + min(end - i, kDetShortRun + 1) - 1;   // the last entry folded here
+            for (int q = i + 1; q <= last; q += 8) {
+                // eight reads ahead of the adds; past the run the pad is -0, which
+                // leaves every sum (either zero included) unchanged
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t bits = s_e[min(q + u, last)].y;
+                    v[u] = q + u <= last ? __uint_as_float(bits) : -0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = __fadd_rn(acc, v[u]);
+            }
+            const int64_t p = run0 + j;
+            if (end - i > kDetShortRun + 1) {
+                // more than kDetShortRun + 1 entries, so runs starting in one
+                // block are that far apart and at most kDetLongPerBlock start here
+                const int slot = atomicAdd(&s_nlong, 1);
+                if (slot < kDetLongPerBlock)
+                    a.long_runs[(int64_t)t * kDetLongPerBlock + slot] =
+                        make_int4((int)e0.x, (int)__float_as_uint(acc), (int)(base + last + 1), (int)p);
+                else
+                    atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
+            } else if (p < a.y_cap) {
+                a.y_idx[p] = (int32_t)e0.x;
+                if (a.y_val) a.y_val[p] = acc;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) a.long_count[t] = min(s_nlong, kDetLongPerBlock);
     }
-    __syncthreads();
-    if (tid == 0) a.long_count[blockIdx.x] = min(s_nlong, kDetLongPerBlock);
 }
 
 // One wave per long run.  The wave works in trips of kLongDepth steps of 64
@@ -561,24 +608,22 @@ hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_
 }
 
 hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int shift, int digit_bits,
-                           int32_t* partials, hipStream_t s) {
-    if (digit_bits < 1 || digit_bits > kDetMaxDigitBits) return hipErrorInvalidValue;
+                           int32_t* partials, int grid, hipStream_t s) {
+    if (digit_bits < 1 || digit_bits > kDetMaxDigitBits || grid < 1) return hipErrorInvalidValue;
     const int nd = 1 << digit_bits;
-    const int group = det_group(a.nblk);
-    const int ngroups = (a.nblk + group - 1) / group;
-    hipLaunchKernelGGL(k_det_hist, dim3(a.nblk), dim3(kDetBlock), 0, s, a, in, shift, digit_bits);
-    hipLaunchKernelGGL(k_det_colscan, dim3(ngroups, (nd + kDetBlock - 1) / kDetBlock), dim3(kDetBlock), 0, s, a,
-                       partials, nd, group);
-    hipLaunchKernelGGL(k_det_digit_base, dim3(1), dim3(kBaseBlock), 0, s, partials, nd, ngroups);
-    hipLaunchKernelGGL(k_det_scatter, dim3(a.nblk), dim3(kScatBlock), 0, s, a, in, out, shift, digit_bits,
-                       partials, group);
+    hipLaunchKernelGGL(k_det_hist, dim3(grid), dim3(kDetBlock), 0, s, a, in, shift, digit_bits);
+    hipLaunchKernelGGL(k_det_colscan, dim3(kDetMaxGroups, (nd + kDetBlock - 1) / kDetBlock), dim3(kDetBlock), 0, s,
+                       a, partials, nd);
+    hipLaunchKernelGGL(k_det_digit_base, dim3(1), dim3(kBaseBlock), 0, s, a, partials, nd);
+    hipLaunchKernelGGL(k_det_scatter, dim3(grid), dim3(kScatBlock), 0, s, a, in, out, shift, digit_bits, partials);
     return hipGetLastError();
 }
 
-hipError_t launch_det_fold(const DetArgs& a, const uint2* list, hipStream_t s) {
-    hipLaunchKernelGGL(k_det_heads, dim3(a.nblk), dim3(kDetBlock), 0, s, a, list);
-    hipLaunchKernelGGL(k_det_scan_small, dim3(1), dim3(kBaseBlock), 0, s, a.counts, a.nblk + 1);
-    hipLaunchKernelGGL(k_det_fold, dim3(a.nblk), dim3(kFoldBlock), 0, s, a, list);
+hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int grid, hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_det_heads, dim3(grid), dim3(kDetBlock), 0, s, a, list);
+    hipLaunchKernelGGL(k_det_scan_small, dim3(1), dim3(kBaseBlock), 0, s, a);
+    hipLaunchKernelGGL(k_det_fold, dim3(grid), dim3(kFoldBlock), 0, s, a, list);
     hipLaunchKernelGGL(k_det_fold_long, dim3(2048), dim3(kDetBlock), 0, s, a, list);
     return hipGetLastError();
 }

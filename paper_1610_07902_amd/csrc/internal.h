@@ -310,13 +310,9 @@ constexpr int kDetTile = kDetBlock * kDetItems;   // list entries per radix bloc
 constexpr int kDetMaxDigitBits = 11;
 constexpr int kDetShortRun = 128;   // a run longer than this continues in the wave-wide fold
 constexpr int kDetLongPerBlock = kDetTile / kDetShortRun;   // long runs starting in one radix block, at most
-// Radix blocks per group of the count matrix's column scan: at least 16,
-// and enough that there are at most kDetMaxGroups groups.
+// Groups of radix tiles in the count matrix's column scan, at most (the
+// kernels size the groups from the call's tile count).
 constexpr int kDetMaxGroups = 32;
-inline int det_group(int nblk) {
-    const int g = (nblk + kDetMaxGroups - 1) / kDetMaxGroups;
-    return g > 16 ? g : 16;
-}
 // int32 entries of the group totals (gt[group][digit])
 constexpr int64_t kDetGroupEntries = int64_t(kDetMaxGroups) << kDetMaxDigitBits;
 struct DetArgs {
@@ -334,26 +330,29 @@ struct DetArgs {
     uint64_t* lb1;           // the scan's look-back words: the first lb1_clear of each half are
     int32_t lb1_n;           // cleared for the next call (the bucket scatter's task otherwise)
     int32_t lb1_clear;
-    int32_t* counts;         // radix passes: [nblk][2^digit_bits] per-(block, digit) counts, block rows
-                             // contiguous; the fold: [nblk + 1] heads per block, scanned in place
-    int32_t nblk;            // radix blocks of kDetTile entries
-    int4* long_runs;         // [nblk][kDetLongPerBlock] runs longer than kDetShortRun, by the block of
+    // Per radix tile of kDetTile list entries; the call's tile count,
+    // ceil(W / kDetTile) (at least one), is taken from W on the device.
+    int32_t* counts;         // radix passes: [tiles][2^digit_bits] per-(tile, digit) counts, tile rows
+                             // contiguous; the fold: [tiles + 1] heads per tile, scanned in place
+    int4* long_runs;         // [tiles][kDetLongPerBlock] runs longer than kDetShortRun, by the tile of
                              // their first entry: (row, acc bits, next entry, y position)
-    int32_t* long_count;     // [nblk] long runs of each block
+    int32_t* long_count;     // [tiles] long runs of each tile
     int32_t* y_idx;
     float* y_val;
     int64_t y_cap;
     int64_t* d_nnz_y;
 };
-// Products -> (row, RN32(a * x)) at their product index; `grid` chunks of
+// The launches take any grid (>= 1): each workgroup loops over chunks or
+// tiles, whose count comes from W on the device.
+// Products -> (row, RN32(a * x)) at their product index, by chunks of
 // 2^chunk_log2 products.
 hipError_t launch_det_gather(const DetArgs& a, uint2* list, int grid, hipStream_t s);
 // One stable pass on bits [shift, shift + digit_bits) of the row; `partials`
 // holds kDetGroupEntries int32 (the count matrix's group totals).
 hipError_t launch_det_pass(const DetArgs& a, const uint2* in, uint2* out, int shift, int digit_bits,
-                           int32_t* partials, hipStream_t s);
+                           int32_t* partials, int grid, hipStream_t s);
 // Fold each row's run of the sorted list and write y ascending.
-hipError_t launch_det_fold(const DetArgs& a, const uint2* list, hipStream_t s);
+hipError_t launch_det_fold(const DetArgs& a, const uint2* list, int grid, hipStream_t s);
 hipError_t launch_merge_batch(const MergeArgs& a, int semiring, int block, bool bfs, hipStream_t s);
 // Multi-source BFS in the pull direction (msbfs_kernels.hip): frontier and
 // seen masks with one bit per source, G = ceil(nsrc / 64) 64-bit words per

@@ -591,13 +591,22 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
                      nullptr, s, nullptr, false, -1, 1, 0, false, 0, left);
     if (rc) return rc;
     const int chunk_log2 = ceil_log2(A->sched.scatter_block * A->sched.scatter_items);
-    // The radix passes' count matrix has a row per radix block: size it by
-    // the product count itself (one host read after the scan) rather than by
-    // f * (longest column), which on a skewed graph is the whole matrix.
-    int32_t Wh = 0;
-    HIP_TRY(hipMemcpyAsync(&Wh, &A->ctrl->W, sizeof(Wh), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int64_t wbound = Wh;
+    // The kernels size their work by the call's product count W on the
+    // device (the scan caps W at nnz) and loop over chunks and radix tiles,
+    // so the call needs no host read.  Grids: a workgroup per expected chunk
+    // or tile (f * nnz / n products) and a quarter more, at least one per
+    // compute unit, never more than the workspace holds; the estimate only
+    // sets how many chunks or tiles each workgroup takes.
+    const int64_t nx = left ? A->m : A->n;   // x's length
+    const int64_t w_est = nx > 0 ? (int64_t)((double)f * (double)A->nnz / (double)nx) : 0;
+    auto grid_for = [&](int64_t unit_log2) {
+        const int64_t cap = std::max<int64_t>(1, (A->nnz + (int64_t(1) << unit_log2) - 1) >> unit_log2);
+        const int64_t est = (w_est >> unit_log2) + 1;
+        return (int)std::min<int64_t>(cap, std::max<int64_t>(A->num_cu, est + est / 4));
+    };
+    static_assert((kDetTile & (kDetTile - 1)) == 0, "radix tiles are a power of two");
+    const int tile_grid = grid_for(ceil_log2(kDetTile));
+    const int gather_grid = grid_for(chunk_log2);
     DetArgs d{};
     d.ctrl = A->ctrl;
     d.m = (int32_t)Om;
@@ -614,7 +623,6 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
     d.lb1_n = (int32_t)L.lb1_n;
     d.lb1_clear = (int32_t)std::min<int64_t>(L.lb1_n, (f + kScanTile - 1) / kScanTile + 1);
     d.counts = reinterpret_cast<int32_t*>(A->ws + L.det_counts);
-    d.nblk = (int32_t)std::max<int64_t>(1, (wbound + kDetTile - 1) / kDetTile);
     d.long_runs = reinterpret_cast<int4*>(A->ws + L.det_long);
     d.long_count = reinterpret_cast<int32_t*>(A->ws + L.det_long_count);
     d.y_idx = y_idx;
@@ -624,8 +632,7 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
     int32_t* partials = reinterpret_cast<int32_t*>(A->ws + L.det_partials);
     uint2* cur = A->buckets;
     uint2* other = reinterpret_cast<uint2*>(A->ws + L.det_list);
-    const int64_t gchunks = std::max<int64_t>(1, (wbound + (int64_t(1) << chunk_log2) - 1) >> chunk_log2);
-    HIP_TRY(launch_det_gather(d, cur, (int)gchunks, s));
+    HIP_TRY(launch_det_gather(d, cur, gather_grid, s));
     // stable LSD passes over the bits of the row (m itself included: it marks masked products)
     // bits of the largest key: m - 1, or m itself when a mask marks products with it
     const int64_t top = mask ? Om : Om - 1;
@@ -634,10 +641,10 @@ int enqueue_det(spmspv_matrix* A, int xmode, int64_t f, const int32_t* x_idx, co
     const int passes = (bits + kDetMaxDigitBits - 1) / kDetMaxDigitBits;
     const int dbits = (bits + passes - 1) / passes;
     for (int p = 0; p < passes; ++p) {
-        HIP_TRY(launch_det_pass(d, cur, other, p * dbits, dbits, partials, s));
+        HIP_TRY(launch_det_pass(d, cur, other, p * dbits, dbits, partials, tile_grid, s));
         std::swap(cur, other);
     }
-    HIP_TRY(launch_det_fold(d, cur, s));
+    HIP_TRY(launch_det_fold(d, cur, tile_grid, s));
     return SPMSPV_OK;
 }
 
