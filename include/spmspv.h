@@ -135,8 +135,8 @@ enum spmspv_flags {
     SPMSPV_DETERMINISTIC = 32768 /* spmspv_workspace_size / _create (also
                                   _dcsc_): add the deterministic mode's
                                   storage (a second product list of nnz
-                                  entries and a count matrix, about 10.5
-                                  bytes per stored entry).  spmspv_run /
+                                  entries and a count matrix, about 10
+                                  bytes per stored entry, plus 256 KiB).  spmspv_run /
                                   _masked with plus-times: y(i) is the fp32
                                   fold of row i's products, each rounded to
                                   fp32, in product order (x order, then the
@@ -147,9 +147,10 @@ enum spmspv_flags {
                                   radix sort by row (Algorithm 2's count
                                   matrix fixes every run's position) and a
                                   sequential fold per row (a row with k
-                                  products takes k dependent adds); the call
-                                  waits for the scan once (the product count
-                                  sizes the radix passes).  Min and
+                                  products takes k dependent adds), with no
+                                  host synchronisation inside the call (the
+                                  kernels read the product count on the
+                                  device).  Min and
                                   or are order-free: their calls ignore it.
                                   EUNSUPPORTED on a handle created without
                                   it; with LEFT, the order is x' order then
