@@ -3,7 +3,8 @@ against the oracle's sequential fp32 fold (oracle_spmspv_f32seq: products
 rounded to fp32, each row's products added one at a time in product order),
 bit for bit: R-MAT graphs at several densities with x in random order, under
 every schedule (the bits must not move), a hub row of 300,000 products,
-run lengths at the fold's and the radix tile's limits, masks, left
+run lengths at the fold's and the radix tile's limits, a product count far
+above the grids' estimate (several tiles per workgroup), masks, left
 multiplication, a DCSC handle, and the benchmark's scale-22 graph."""
 import numpy as np
 import pytest
@@ -226,4 +227,28 @@ def test_run_lengths_around_the_fold_and_tile_limits(spv):
         words[i >> 5] |= np.uint32(1 << (i & 31))
     gi, gv = run(spv, M, S, xv, mask=dev(words.view(np.int32)))
     same_bits(gi, gv, *reference(A, S, xv, drop=drop))
+    M.close()
+
+
+def test_product_count_far_above_the_grid_estimate(spv):
+    """The kernels take their chunk and tile counts from the product count on
+    the device and loop over them; the grids come from the expected count
+    f * nnz / n.  Here x selects the only long columns of a mostly empty
+    matrix (3M products where the estimate is ~300), so each workgroup takes
+    several radix tiles and gather chunks in turn."""
+    rng = np.random.default_rng(23)
+    n, m, k, deg = 1_000_000, 200_000, 100, 30_000
+    long_cols = np.sort(rng.choice(n, k, replace=False)).astype(np.int32)
+    colptr = np.zeros(n + 1, np.int64)
+    colptr[long_cols + 1] = deg
+    colptr = np.cumsum(colptr).astype(np.int32)
+    rows = rng.integers(0, m, k * deg).astype(np.int32)
+    vals = (rng.random(k * deg) * 2.0 ** rng.integers(-8, 8, k * deg)).astype(np.float32)
+    A = synth.CSC(m, n, colptr, rows, vals)
+    M = spv.Matrix.from_csc(A, flags=spv.DETERMINISTIC)
+    S = rng.permutation(long_cols).astype(np.int32)
+    xv = synth.values(S.size, 4, stream=79)
+    gi, gv = run(spv, M, S, xv)
+    same_bits(gi, gv, *reference(A, S, xv))
+    assert M.last_stats()["W"] == k * deg
     M.close()
