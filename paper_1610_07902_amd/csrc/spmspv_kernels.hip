@@ -348,12 +348,18 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
     __shared__ int s_tmp[BLOCK / kWave + 1];
     const int tid = threadIdx.x;
 
+    // The control words, loaded together: one round trip before the work
+    // instead of one per word.
+    const int dir = ld_ctrl(&a.ctrl->dir);
+    const int errw = ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err));
+    const int W = ld_ctrl(&a.ctrl->W);
+    const int fnz = ld_ctrl(&a.ctrl->fnz);
     if (MODE != SC_BATCH || a.xstride) {   // the first pass over the products of this call
         if (blockIdx.x == 0 && tid == 0) {
             st_ctrl_u(&a.ctrl->ticket_scan, 0u);
+            st_ctrl(&a.ctrl->fnz_last, fnz);
+            st_ctrl(&a.ctrl->W_last, W);
             st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
-            st_ctrl(&a.ctrl->fnz_last, ld_ctrl(&a.ctrl->fnz));
-            st_ctrl(&a.ctrl->W_last, ld_ctrl(&a.ctrl->W));
         }
         for (int i = blockIdx.x * BLOCK + tid; i < a.lb1_clear; i += gridDim.x * BLOCK) {
             a.lb1[i] = 0;
@@ -361,12 +367,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ScatterArgs a) {
         }
     }
 
-    if (a.gate && ld_ctrl(&a.ctrl->dir) != 0) return;   // this BFS level runs pull
+    if (a.gate && dir != 0) return;   // this BFS level runs pull
     // A failed look-back leaves the column tables inconsistent: scatter
     // nothing (the error is reported with the call's status).
-    if (ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err)) & (int32_t)ERR_SPIN) return;
-    const int W = ld_ctrl(&a.ctrl->W);
-    const int fnz = ld_ctrl(&a.ctrl->fnz);
+    if (errw & (int32_t)ERR_SPIN) return;
     const int nchunks = (int)(((int64_t)W + C - 1) / C);
     if ((int)blockIdx.x >= nchunks) return;
 
