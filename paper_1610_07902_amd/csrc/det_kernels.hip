@@ -44,7 +44,10 @@ __device__ __forceinline__ int det_group(int nt) {
     return g > 16 ? g : 16;
 }
 
-__global__ __launch_bounds__(kGatherBlock) void k_det_gather(DetArgs a, uint2* list) {
+// Eight waves per SIMD (at most 64 registers): two 1024-thread workgroups
+// per compute unit where the chunk's table fits twice in LDS (4096-product
+// chunks); at 66 registers only one fitted.
+__global__ __launch_bounds__(kGatherBlock, 8) void k_det_gather(DetArgs a, uint2* list) {
     extern __shared__ int32_t s_off[];   // the chunk's column table, 3 x (chunk + 2) words
     // every word the first chunk's set-up needs, loaded together (the grid is
     // at most the workspace's chunk count, so chunk_col has both entries; they
@@ -333,7 +336,8 @@ __global__ __launch_bounds__(kScatBlock) void k_det_scatter(DetArgs a, const uin
     }
 }
 
-__global__ __launch_bounds__(kDetBlock) void k_det_heads(DetArgs a, const uint2* list) {
+// Eight waves per SIMD (at most 64 registers; 65 allowed seven).
+__global__ __launch_bounds__(kDetBlock, 8) void k_det_heads(DetArgs a, const uint2* list) {
     __shared__ int s_tmp[kDetWaves + 1];
     const int W = ld_ctrl(&a.ctrl->W);
     const int nt = det_tiles(W);
