@@ -395,6 +395,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     __shared__ int s_pre[kCells + 1];    // heads before each ballot, in entry order
     __shared__ int s_nlong, s_stop;
     __shared__ uint32_t s_prev;
+    __shared__ int64_t s_run0;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int W = ld_ctrl(&a.ctrl->W);
     const int nt = det_tiles(W);
@@ -419,6 +420,13 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
             uint2 st[kRounds];
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) st[r] = list[base + min(r * kFoldBlock + tid, n_st - 1)];
+            // the row before the tile and the tile's first output position,
+            // in the same round trip (clamped index)
+            if (tid == 0) {
+                const uint32_t before = list[base > 0 ? base - 1 : 0].x;
+                s_run0 = a.counts[t];
+                s_prev = base > 0 ? before : ~0u;
+            }
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) {
                 const int i = r * kFoldBlock + tid;
@@ -428,7 +436,6 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
         if (tid == 0) {
             s_nlong = 0;
             s_stop = n_st;
-            s_prev = base > 0 ? list[base - 1].x : ~0u;
         }
         __syncthreads();
         // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
         // (2) folds, one add at a time in entry order
         const int H = s_pre[kCells];
         const int last_end = s_stop;
-        const int64_t run0 = a.counts[t];
+        const int64_t run0 = s_run0;
         for (int j = tid; j < H; j += kFoldBlock) {
             const int i = s_head[j];
             const int nxt = s_head[min(j + 1, H - 1)];
