@@ -60,9 +60,10 @@ __global__ __launch_bounds__(kGatherBlock, 8) void k_det_gather(DetArgs a, uint2
     // the scan's statistics, and its look-back words cleared for the next call.
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st_ctrl_u(&a.ctrl->ticket_scan, 0u);
-        st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
         st_ctrl(&a.ctrl->fnz_last, fnz);
         st_ctrl(&a.ctrl->W_last, W);
+        *a.long_count = 0;   // the fold appends this call's long runs
+        st_ctrl(&a.ctrl->maxlen_last, atomicExch(&a.ctrl->maxlen, 0));
     }
     for (int i = blockIdx.x * kGatherBlock + threadIdx.x; i < a.lb1_clear; i += gridDim.x * kGatherBlock) {
         a.lb1[i] = 0;
@@ -393,7 +394,8 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     __shared__ uint16_t s_head[kDetTile];
     __shared__ uint64_t s_bal[kCells];   // heads of round r, wave w at r * kFoldWaves + w
     __shared__ int s_pre[kCells + 1];    // heads before each ballot, in entry order
-    __shared__ int s_nlong, s_stop;
+    __shared__ int s_stop, s_nlong, s_lbase;
+    __shared__ int4 s_long[kDetLongPerBlock];   // the tile's long runs, then copied to the list
     __shared__ uint32_t s_prev;
     __shared__ int64_t s_run0;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -407,7 +409,6 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         const int64_t base = (int64_t)t * kDetTile;
         if (base >= W) {   // W == 0: one empty tile
-            if (tid == 0) a.long_count[t] = 0;
             continue;
         }
         const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
@@ -434,8 +435,8 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
             }
         }
         if (tid == 0) {
-            s_nlong = 0;
             s_stop = n_st;
+            s_nlong = 0;
         }
         __syncthreads();
         // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
@@ -506,12 +507,11 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
             }
             const int64_t p = run0 + j;
             if (end - i > kDetShortRun + 1) {
-                // more than kDetShortRun + 1 entries, so runs starting in one
-                // block are that far apart and at most kDetLongPerBlock start here
+                // more than kDetShortRun + 1 entries, so at most
+                // kDetLongPerBlock runs start in a tile
                 const int slot = atomicAdd(&s_nlong, 1);
                 if (slot < kDetLongPerBlock)
-                    a.long_runs[(int64_t)t * kDetLongPerBlock + slot] =
-                        make_int4((int)e0.x, (int)__float_as_uint(acc), (int)(base + last + 1), (int)p);
+                    s_long[slot] = make_int4((int)e0.x, (int)__float_as_uint(acc), (int)(base + last + 1), (int)p);
                 else
                     atomicOr(&a.ctrl->err, ERR_SPIN);   // not reached (see above)
             } else if (p < a.y_cap) {
@@ -520,11 +520,20 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
             }
         }
         __syncthreads();
-        if (tid == 0) a.long_count[t] = min(s_nlong, kDetLongPerBlock);
+        // the tile's long runs join the call's list: one reservation per tile
+        // (the list's order does not matter, each run's fold is its own)
+        const int nl = min(s_nlong, kDetLongPerBlock);
+        if (nl > 0) {
+            if (tid == 0) s_lbase = atomicAdd(a.long_count, nl);
+            __syncthreads();
+            if (tid < nl) a.long_runs[s_lbase + tid] = s_long[tid];
+        }
+        __syncthreads();   // the next tile restages the LDS
     }
 }
 
-// One wave per long run.  The wave works in trips of kLongDepth steps of 64
+// One wave per long run of the fold's list, so every run starts at once.
+// The wave works in trips of kLongDepth steps of 64
 // consecutive entries (one coalesced load per step), the next trip's loads
 // issued before the current trip's steps; each step's values go to the
 // wave's LDS row and one lane adds them in order from there, so the run
@@ -538,21 +547,16 @@ constexpr int kLongDepth = 8;
 __global__ __launch_bounds__(kDetBlock) void k_det_fold_long(DetArgs a, const uint2* list) {
     __shared__ __attribute__((aligned(16))) float s_v[kDetWaves][kWave];
     const int W = ld_ctrl(&a.ctrl->W);
-    const int nblk_used = (W + kDetTile - 1) / kDetTile;
+    const int nlong = *a.long_count;   // the fold's list of long runs
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int nwaves = gridDim.x * kDetWaves;
-    const int64_t npairs = (int64_t)nblk_used * kDetLongPerBlock;
     // clamped, unconditional loads (the end of the list is checked where the
     // rows are compared): a guarded load sits behind a branch, after which the
     // compiler waits for every load in flight, the prefetched ones too
     auto load = [&](int64_t k) { return list[min(k + lane, (int64_t)W - 1)]; };
-    for (int64_t pr = blockIdx.x * kDetWaves + wv; pr < npairs; pr += nwaves) {
-        const int b = (int)(pr / kDetLongPerBlock), slot = (int)(pr % kDetLongPerBlock);
-        // both loads issued together: pr is inside the record array whether or
-        // not the slot holds a run
+    for (int pr = blockIdx.x * kDetWaves + wv; pr < nlong; pr += nwaves) {
         const int4 rec = a.long_runs[pr];
-        if (slot >= a.long_count[b]) continue;
         const uint32_t row = (uint32_t)rec.x;
         float acc = __uint_as_float((uint32_t)rec.y);
         int64_t k = rec.z;

@@ -334,9 +334,9 @@ struct DetArgs {
     // ceil(W / kDetTile) (at least one), is taken from W on the device.
     int32_t* counts;         // radix passes: [tiles][2^digit_bits] per-(tile, digit) counts, tile rows
                              // contiguous; the fold: [tiles + 1] heads per tile, scanned in place
-    int4* long_runs;         // [tiles][kDetLongPerBlock] runs longer than kDetShortRun, by the tile of
-                             // their first entry: (row, acc bits, next entry, y position)
-    int32_t* long_count;     // [tiles] long runs of each tile
+    int4* long_runs;         // [tiles * kDetLongPerBlock] runs longer than kDetShortRun, in the order the
+                             // fold appends them: (row, acc bits, next entry, y position)
+    int32_t* long_count;     // [1] long runs in the list (cleared by the gather)
     int32_t* y_idx;
     float* y_val;
     int64_t y_cap;

@@ -148,7 +148,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t nnz, int flags = 0, int64_t dc_
         L.det_counts = take(size_t(ncounts) * 4);
         L.det_partials = take(size_t(kDetGroupEntries) * 4);
         L.det_long = take(size_t(L.det_nblk_max) * kDetLongPerBlock * 16);
-        L.det_long_count = take(size_t(L.det_nblk_max) * 4);
+        L.det_long_count = take(4);
     }
     L.pull = (flags & (SPMSPV_WITH_TRANSPOSE | SPMSPV_SYMMETRIC)) != 0;
     L.transpose = (flags & SPMSPV_WITH_TRANSPOSE) != 0;
