@@ -155,9 +155,14 @@ def test_flag_on_other_semirings_and_without_storage(spv, r16):
         P.spmspv(dev(S), dev(np.ones(S.size, np.float32)), flags=spv.DETERMINISTIC)
     assert e.value.status == spv.EUNSUPPORTED
     P.close()
-    # empty x and a short output capacity
+    # empty x, x of empty columns only (no products: one empty radix tile),
+    # and a short output capacity
     gi, gv = run(spv, M, np.zeros(0, np.int32), np.zeros(0, np.float32))
     assert gi.size == 0
+    iso = np.nonzero(A.degrees() == 0)[0].astype(np.int32)
+    assert iso.size > 0
+    gi, gv = run(spv, M, iso[:50], np.ones(min(50, iso.size), np.float32))
+    assert gi.size == 0 and M.last_stats()["W"] == 0
     S, xv = synth.sparse_x(A.n, 300, seed=14)
     oi, ov = reference(A, S, xv)
     y = torch.empty(A.m, dtype=torch.int32, device="cuda")
