@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
     __shared__ uint16_t s_head[kDetTile];
     __shared__ uint64_t s_bal[kCells];   // heads of round r, wave w at r * kFoldWaves + w
     __shared__ int s_pre[kCells + 1];    // heads before each ballot, in entry order
-    __shared__ int s_stop, s_nlong, s_lbase;
+    __shared__ int s_stop, s_nlong, s_nlong_all, s_lbase;
     __shared__ int4 s_long[kDetLongPerBlock];   // the tile's long runs, then copied to the list
     __shared__ uint32_t s_prev;
     __shared__ int64_t s_run0;
@@ -437,6 +437,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
         if (tid == 0) {
             s_stop = n_st;
             s_nlong = 0;
+            s_nlong_all = 0;
         }
         __syncthreads();
         // (1) item r of thread t is entry r * kFoldBlock + t; the rounds past
@@ -486,6 +487,21 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
         const int H = s_pre[kCells];
         const int last_end = s_stop;
         const int64_t run0 = s_run0;
+        // the tile's long runs are counted first, so that their reservation
+        // in the call's list is in flight while the runs are folded (the
+        // list's order does not matter, each run's fold is its own)
+        {
+            int nlong_t = 0;
+            for (int j = tid; j < H; j += kFoldBlock) {
+                const int end = j + 1 < H ? s_head[min(j + 1, H - 1)] : last_end;
+                nlong_t += end - s_head[j] > kDetShortRun + 1 ? 1 : 0;
+            }
+            if (nlong_t > 0) atomicAdd(&s_nlong_all, nlong_t);
+        }
+        __syncthreads();
+        const int nl = min(s_nlong_all, kDetLongPerBlock);
+        int lbase = 0;   // thread 0: the tile's first position in the list
+        if (tid == 0 && nl > 0) lbase = atomicAdd(a.long_count, nl);
         for (int j = tid; j < H; j += kFoldBlock) {
             const int i = s_head[j];
             const int nxt = s_head[min(j + 1, H - 1)];
@@ -520,11 +536,9 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
             }
         }
         __syncthreads();
-        // the tile's long runs join the call's list: one reservation per tile
-        // (the list's order does not matter, each run's fold is its own)
-        const int nl = min(s_nlong, kDetLongPerBlock);
+        // the tile's long runs join the call's list
         if (nl > 0) {
-            if (tid == 0) s_lbase = atomicAdd(a.long_count, nl);
+            if (tid == 0) s_lbase = lbase;
             __syncthreads();
             if (tid < nl) a.long_runs[s_lbase + tid] = s_long[tid];
         }
