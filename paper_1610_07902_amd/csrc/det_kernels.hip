@@ -6,13 +6,14 @@
 //   k_det_gather   product w -> (row, RN32(a * x)) at list position w; the
 //                  scan's column tables give each product's column.
 //   radix passes   a stable LSD sort of that list by row, digits of up to
-//                  11 bits: per-block digit counts (a row of the count
-//                  matrix per block), their exclusive scan in digit-major
-//                  order (Algorithm 2's count matrix: every (digit, block)
-//                  run gets its position) from a column scan within groups
-//                  of blocks plus one block of digit bases, then each block
-//                  writes its entries at those positions, ranked stably
-//                  (wave ballots, waves in order, rounds in order).
+//                  11 bits: per-tile digit counts (a row of the count
+//                  matrix per radix tile of kDetTile entries), their
+//                  exclusive scan in digit-major order (Algorithm 2's count
+//                  matrix: every (digit, tile) run gets its position) from a
+//                  column scan within groups of tiles plus one workgroup of
+//                  digit bases, then each tile's entries are written at those
+//                  positions, ranked stably (wave ballots, waves in order,
+//                  rounds in order).
 //   k_det_heads, k_det_scan_small, k_det_fold, k_det_fold_long
 //                  every row's products now form one run in product order,
 //                  folded sequentially from its first product by one thread
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(kGatherBlock, 8) void k_det_gather(DetArgs a, uint2
     const int err = ld_ctrl(reinterpret_cast<const int32_t*>(&a.ctrl->err));
     int col_c = a.chunk_col[blockIdx.x], col_next = a.chunk_col[blockIdx.x + 1];
     // The per-call bookkeeping the bucket scatter does on the other paths:
-    // the scan's statistics, and its look-back words cleared for the next call.
+    // the scan's statistics, and its look-back words cleared for the next
+    // call; and this call's list of long runs emptied.
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st_ctrl_u(&a.ctrl->ticket_scan, 0u);
         st_ctrl(&a.ctrl->fnz_last, fnz);
@@ -373,15 +375,16 @@ constexpr int kFoldBlock = 512;
 constexpr int kFoldItems = kDetTile / kFoldBlock;
 constexpr int kFoldWaves = kFoldBlock / kWave;
 
-// The block's kDetTile entries are staged in LDS with the kDetShortRun + 1
+// A tile's kDetTile entries are staged in LDS with the kDetShortRun + 1
 // entries after them (a short fold never reads further).  (1) Row boundaries
 // are found with wave ballots; the heads (boundaries of real rows inside the
-// block) are compacted, in entry order, into a list of positions, and the
+// tile) are compacted, in entry order, into a list of positions, and the
 // first other boundary (in the halo, or where the masked rows begin) ends the
-// block's last run.  (2) Thread t folds heads t, t + kFoldBlock, ...: a run
+// tile's last run.  (2) Thread t folds heads t, t + kFoldBlock, ...: a run
 // ends where the next head starts, so its adds need no row comparisons, and
 // consecutive heads -- ordinals, so outputs -- sit in consecutive lanes.
-// Past kDetShortRun + 1 entries a run is handed to k_det_fold_long.  (Giving
+// Past kDetShortRun + 1 entries a run is handed to k_det_fold_long through
+// the call's list of long runs.  Workgroups loop over tiles.  (Giving
 // each thread the heads among its own items left the wave waiting on the
 // lane that held most of them: heads evenly spaced by a power of two all
 // fall on one thread.)
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(kFoldBlock) void k_det_fold(DetArgs a, const uint2*
         if (base >= W) {   // W == 0: one empty tile
             continue;
         }
-        const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this block's entries
+        const int n_in = (int)min((int64_t)kDetTile, (int64_t)W - base);   // this tile's entries
         const int n_st = (int)min((int64_t)kStage, (int64_t)W - base);     // with the halo
         constexpr int kRounds = (kStage + kFoldBlock - 1) / kFoldBlock;
         {
